@@ -1,0 +1,70 @@
+"""Textbook closed forms that pin the oracle at any size (test infrastructure).
+
+  * QFT: <y|QFT_n|x> = 2^{-n/2} exp(2 pi i (x y mod 2^n) / 2^n);
+  * amplitude amplification with the diffusion written as H X MCZ X H (which
+    is I - 2|s><s|, the negative of the usual Grover reflection): after s
+    iterations each of the m marked states holds (-1)^s sin((2s+1)theta)/sqrt(m)
+    and each unmarked state (-1)^s cos((2s+1)theta)/sqrt(N-m), sin theta =
+    sqrt(m/N); ancillas end in |0>;
+  * coined Hadamard walk on a line (no wrap for few steps on a huge cycle):
+    the position-space recursion, and the number of coin sequences that end at
+    (x, c), which is the number of valid reduced histories when the coin
+    values after the second..last coin flips are the artificial sources.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Sequence, Tuple
+
+
+def qft_amplitude(n: int, x: int, y: int) -> complex:
+    r = (x * y) % (1 << n)
+    ang = 2.0 * math.pi * r / float(1 << n)
+    s = 2.0 ** (-0.5 * n)
+    return complex(s * math.cos(ang), s * math.sin(ang))
+
+
+def aa_amplitude(k: int, iterations: int, marked: Sequence[int], y: int) -> complex:
+    N = 1 << k
+    m = len(marked)
+    if y >> k:                      # an ancilla bit is set
+        return 0j
+    theta = math.asin(math.sqrt(m / N))
+    sign = -1.0 if iterations % 2 else 1.0
+    a = (2 * iterations + 1) * theta
+    if y in set(marked):
+        return complex(sign * math.sin(a) / math.sqrt(m), 0.0)
+    return complex(sign * math.cos(a) / math.sqrt(N - m), 0.0)
+
+
+def aa_success_probability(k: int, iterations: int, m: int) -> float:
+    theta = math.asin(math.sqrt(m / (1 << k)))
+    return math.sin((2 * iterations + 1) * theta) ** 2
+
+
+def walk_amplitudes(steps: int) -> Dict[Tuple[int, int], complex]:
+    """Hadamard walk from position 0, coin 0: each step maps the coin
+    (a0, a1) -> ((a0 + a1)/sqrt2, (a0 - a1)/sqrt2), then moves coin-1
+    amplitude to x+1 and coin-0 amplitude to x-1."""
+    h = 1.0 / math.sqrt(2.0)
+    amp = {(0, 0): 1.0 + 0j}
+    for _ in range(steps):
+        nxt: Dict[Tuple[int, int], complex] = {}
+        for (x, c), a in amp.items():
+            # contribution of coin c to new coins 0 and 1
+            for c2 in (0, 1):
+                f = -h if (c == 1 and c2 == 1) else h
+                x2 = x + (1 if c2 == 1 else -1)
+                nxt[(x2, c2)] = nxt.get((x2, c2), 0j) + f * a
+        amp = nxt
+    return amp
+
+
+def walk_n_valid(steps: int, x: int, c: int) -> int:
+    """Coin sequences c_1..c_steps with c_steps = c and sum(2c_t - 1) = x."""
+    if (x + steps) % 2:
+        return 0
+    ones = (x + steps) // 2 - c
+    if ones < 0 or ones > steps - 1:
+        return 0
+    return math.comb(steps - 1, ones)

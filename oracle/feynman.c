@@ -1,0 +1,706 @@
+/*
+ * oracle/feynman.c -- CPU oracle for the reduced-history Feynman method.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code with the GPU library.
+ *
+ * What it computes (paper, Section IV):
+ *   - the internal-wire formulation (Section II-A): every gate/qubit incidence
+ *     that is not wire-preserving opens a new binary wire segment; wire-
+ *     preserving incidences (diagonal gates, control roles) keep the segment;
+ *   - gate roles (Section II-A): diagonal -> wire-preserving, exactly one
+ *     nonzero per column -> deterministic, otherwise branching;
+ *   - backward source placement (Section IV-A): an artificial source sits on
+ *     the input-side segment of every branching gate whose input segment is
+ *     not a natural input segment; sources are numbered in the output->input
+ *     sweep order, source k being bit k of the history index h;
+ *   - Algorithm 1 (SetBoundaryWires, PropagateKnownValues, SetArtificialSources,
+ *     EvaluateHistory) and Algorithm 2 (AdvanceCheckpoint over the prefix,
+ *     root and suffix regions, in evaluation order from the output);
+ *   - Eq. (8) gate-operation estimate and its argmin over all cut pairs
+ *     (Section IV-C, "Autotuned Partitioning"), in exact 128-bit integers.
+ *
+ * PropagateKnownValues is a fixpoint over local gate relations (each
+ * deterministic gate admits only the (in,out) pairs of its permutation),
+ * swept forward and backward until nothing changes.  This is deliberately a
+ * different mechanism from the GPU's straight-line backward program.
+ *
+ * Readings where the paper leaves the arithmetic open:
+ *   - threshold pruning: a history is dropped iff M < t, where M is the
+ *     product, in evaluation order (output->input), of min(1, |U_g[out,in]|)
+ *     over branching gates g; M never grows, so where the test sits does not
+ *     change the result; t = 0 prunes nothing;
+ *   - a history is valid iff propagation never conflicts, no gate factor is an
+ *     exact zero, and M >= t;
+ *   - cuts c1 <= c2 index evaluation order: prefix [0,c1), root [c1,c2),
+ *     suffix [c2,G); Eq. (8) ties break to the lexicographically smallest
+ *     (c1,c2).
+ *
+ * Bitstrings: ceil(n/64) uint64 words, qubit q is bit q (little-endian).
+ */
+#include <ctype.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXQ 128
+#define ORC_OK 0
+#define ORC_EPARSE 1
+#define ORC_ERANGE 2
+#define ORC_EINVAL 3
+#define ORC_EINTERNAL 4
+
+typedef struct { double re, im; } cplx;
+
+enum { ROLE_PRESERVE = 0, ROLE_DET = 1, ROLE_BRANCH = 2 };
+enum { KIND_DENSE = 0, KIND_MCX = 1, KIND_MCZ = 2 };
+
+typedef struct {
+    int kind;
+    int k;                  /* number of qubits touched */
+    int *q;                 /* q[j] = qubit of local bit j (MCX: q[0] is target) */
+    unsigned char *neg;     /* MCX/MCZ polarity per local qubit */
+    cplx m[64];             /* dense: U[out*dim + in], dim = 2^k, k <= 3 */
+    int role;
+    unsigned char preserve[3];  /* dense: local wire j is preserved */
+    int *in_seg, *out_seg;  /* segment id per local qubit */
+} ogate;
+
+typedef struct {
+    int n, G, A, nseg;
+    ogate *g;               /* time order */
+    int out_seg[ORC_MAXQ];  /* segment carrying each qubit at the output */
+    int *src_seg;           /* [A] segment fixed by source k */
+    int *src_gate;          /* [A] time index of the gate of source k */
+    int *src_eval;          /* [A] evaluation position of that gate */
+} orc_circuit;
+
+/* ------------------------------------------------------------------ */
+/* parsing and gate matrices                                           */
+/* ------------------------------------------------------------------ */
+
+static cplx C(double re, double im) { cplx z = {re, im}; return z; }
+
+static void set_dense(ogate *g, int k) {
+    g->kind = KIND_DENSE;
+    g->k = k;
+    memset(g->m, 0, sizeof(g->m));
+}
+
+#define M_AT(g, out, in) ((g)->m[(out) * (1 << (g)->k) + (in)])
+
+static int build_gate(ogate *g, const char *name, int *qs, unsigned char *ng,
+                      int nq, double ang, int has_ang) {
+    const double h = sqrt(0.5);
+    int need_ang = 0, nq_expect = -1;
+    g->q = (int *)malloc(sizeof(int) * (nq > 0 ? nq : 1));
+    g->neg = (unsigned char *)calloc(nq > 0 ? nq : 1, 1);
+    memcpy(g->q, qs, sizeof(int) * nq);
+    memcpy(g->neg, ng, nq);
+    for (int j = 0; j < nq; ++j)
+        if (ng[j] && strcmp(name, "MCX") && strcmp(name, "MCZ")) return ORC_EPARSE;
+    if (!strcmp(name, "MCX")) {
+        if (nq < 1 || ng[0]) return ORC_EPARSE;
+        g->kind = KIND_MCX; g->k = nq;
+        return has_ang ? ORC_EPARSE : ORC_OK;
+    }
+    if (!strcmp(name, "MCZ")) {
+        if (nq < 1) return ORC_EPARSE;
+        g->kind = KIND_MCZ; g->k = nq;
+        return has_ang ? ORC_EPARSE : ORC_OK;
+    }
+    if (!strcmp(name, "H") || !strcmp(name, "X") || !strcmp(name, "Y") ||
+        !strcmp(name, "Z") || !strcmp(name, "S") || !strcmp(name, "SDG") ||
+        !strcmp(name, "T") || !strcmp(name, "TDG")) nq_expect = 1;
+    else if (!strcmp(name, "P") || !strcmp(name, "RX") || !strcmp(name, "RY") ||
+             !strcmp(name, "RZ")) { nq_expect = 1; need_ang = 1; }
+    else if (!strcmp(name, "CX") || !strcmp(name, "CZ") || !strcmp(name, "SWAP")) nq_expect = 2;
+    else if (!strcmp(name, "CP") || !strcmp(name, "RZZ")) { nq_expect = 2; need_ang = 1; }
+    else if (!strcmp(name, "CCX") || !strcmp(name, "CSWAP")) nq_expect = 3;
+    else return ORC_EPARSE;
+    if (nq != nq_expect || need_ang != has_ang) return ORC_EPARSE;
+    set_dense(g, nq);
+    if (!strcmp(name, "H")) {
+        M_AT(g, 0, 0) = C(h, 0); M_AT(g, 0, 1) = C(h, 0);
+        M_AT(g, 1, 0) = C(h, 0); M_AT(g, 1, 1) = C(-h, 0);
+    } else if (!strcmp(name, "X")) {
+        M_AT(g, 1, 0) = C(1, 0); M_AT(g, 0, 1) = C(1, 0);
+    } else if (!strcmp(name, "Y")) {
+        M_AT(g, 1, 0) = C(0, 1); M_AT(g, 0, 1) = C(0, -1);
+    } else if (!strcmp(name, "Z")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(-1, 0);
+    } else if (!strcmp(name, "S")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(0, 1);
+    } else if (!strcmp(name, "SDG")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(0, -1);
+    } else if (!strcmp(name, "T")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(h, h);
+    } else if (!strcmp(name, "TDG")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(h, -h);
+    } else if (!strcmp(name, "P")) {
+        M_AT(g, 0, 0) = C(1, 0); M_AT(g, 1, 1) = C(cos(ang), sin(ang));
+    } else if (!strcmp(name, "RX")) {
+        double c = cos(0.5 * ang), s = sin(0.5 * ang);
+        M_AT(g, 0, 0) = C(c, 0); M_AT(g, 1, 1) = C(c, 0);
+        M_AT(g, 0, 1) = C(0, -s); M_AT(g, 1, 0) = C(0, -s);
+    } else if (!strcmp(name, "RY")) {
+        double c = cos(0.5 * ang), s = sin(0.5 * ang);
+        M_AT(g, 0, 0) = C(c, 0); M_AT(g, 1, 1) = C(c, 0);
+        M_AT(g, 0, 1) = C(-s, 0); M_AT(g, 1, 0) = C(s, 0);
+    } else if (!strcmp(name, "RZ")) {
+        double c = cos(0.5 * ang), s = sin(0.5 * ang);
+        M_AT(g, 0, 0) = C(c, -s); M_AT(g, 1, 1) = C(c, s);
+    } else if (!strcmp(name, "CX")) {          /* local bit 0 control, bit 1 target */
+        for (int x = 0; x < 4; ++x) {
+            int y = (x & 1) ? (x ^ 2) : x;
+            M_AT(g, y, x) = C(1, 0);
+        }
+    } else if (!strcmp(name, "CZ")) {
+        for (int x = 0; x < 4; ++x) M_AT(g, x, x) = C(x == 3 ? -1 : 1, 0);
+    } else if (!strcmp(name, "SWAP")) {
+        for (int x = 0; x < 4; ++x) {
+            int y = ((x & 1) << 1) | ((x >> 1) & 1);
+            M_AT(g, y, x) = C(1, 0);
+        }
+    } else if (!strcmp(name, "CP")) {
+        for (int x = 0; x < 3; ++x) M_AT(g, x, x) = C(1, 0);
+        M_AT(g, 3, 3) = C(cos(ang), sin(ang));
+    } else if (!strcmp(name, "RZZ")) {
+        double c = cos(0.5 * ang), s = sin(0.5 * ang);
+        for (int x = 0; x < 4; ++x) {
+            int par = (x ^ (x >> 1)) & 1;
+            M_AT(g, x, x) = par ? C(c, s) : C(c, -s);
+        }
+    } else if (!strcmp(name, "CCX")) {         /* bits 0,1 controls, bit 2 target */
+        for (int x = 0; x < 8; ++x) {
+            int y = ((x & 3) == 3) ? (x ^ 4) : x;
+            M_AT(g, y, x) = C(1, 0);
+        }
+    } else if (!strcmp(name, "CSWAP")) {       /* bit 0 control, bits 1,2 swapped */
+        for (int x = 0; x < 8; ++x) {
+            int y = x;
+            if (x & 1) y = (x & 1) | (((x >> 2) & 1) << 1) | (((x >> 1) & 1) << 2);
+            M_AT(g, y, x) = C(1, 0);
+        }
+    }
+    return ORC_OK;
+}
+
+static int is_zero(cplx z) { return z.re == 0.0 && z.im == 0.0; }
+
+/* Role of a gate from its matrix (Section II-A) and, per local wire, whether
+ * every nonzero transition leaves that wire's value unchanged. */
+static void classify(ogate *g) {
+    if (g->kind == KIND_MCX) { g->role = ROLE_DET; return; }
+    if (g->kind == KIND_MCZ) { g->role = ROLE_PRESERVE; return; }
+    int dim = 1 << g->k, offdiag = 0, multi = 0;
+    for (int x = 0; x < dim; ++x) {
+        int nz = 0;
+        for (int y = 0; y < dim; ++y) {
+            if (is_zero(M_AT(g, y, x))) continue;
+            ++nz;
+            if (y != x) offdiag = 1;
+        }
+        if (nz > 1) multi = 1;
+    }
+    g->role = !offdiag ? ROLE_PRESERVE : (multi ? ROLE_BRANCH : ROLE_DET);
+    for (int j = 0; j < g->k; ++j) {
+        int keep = 1;
+        for (int x = 0; x < dim; ++x)
+            for (int y = 0; y < dim; ++y)
+                if (!is_zero(M_AT(g, y, x)) && (((x ^ y) >> j) & 1)) keep = 0;
+        g->preserve[j] = (unsigned char)keep;
+    }
+}
+
+static int local_preserved(const ogate *g, int j) {
+    if (g->kind == KIND_MCX) return j != 0;
+    if (g->kind == KIND_MCZ) return 1;
+    return g->preserve[j];
+}
+
+void orc_free(orc_circuit *c) {
+    if (!c) return;
+    for (int i = 0; i < c->G; ++i) {
+        free(c->g[i].q); free(c->g[i].neg);
+        free(c->g[i].in_seg); free(c->g[i].out_seg);
+    }
+    free(c->g); free(c->src_seg); free(c->src_gate); free(c->src_eval);
+    free(c);
+}
+
+int orc_load(const char *text, orc_circuit **out) {
+    *out = NULL;
+    orc_circuit *c = (orc_circuit *)calloc(1, sizeof(orc_circuit));
+    int cap = 64, rc = ORC_OK;
+    c->g = (ogate *)calloc(cap, sizeof(ogate));
+    c->n = -1;
+    const char *p = text;
+    char line[8192];
+    while (*p) {
+        size_t len = strcspn(p, "\n");
+        if (len >= sizeof(line)) { rc = ORC_EPARSE; break; }
+        memcpy(line, p, len); line[len] = 0;
+        p += len; if (*p == '\n') ++p;
+        char *hash = strchr(line, '#'); if (hash) *hash = 0;
+        char *tok[260]; int nt = 0;
+        for (char *s = strtok(line, " \t\r"); s && nt < 260; s = strtok(NULL, " \t\r")) tok[nt++] = s;
+        if (nt == 0) continue;
+        if (!strcmp(tok[0], "qubits")) {
+            if (nt != 2 || c->n >= 0) { rc = ORC_EPARSE; break; }
+            c->n = atoi(tok[1]);
+            if (c->n < 1 || c->n > ORC_MAXQ) { rc = ORC_ERANGE; break; }
+            continue;
+        }
+        if (c->n < 0) { rc = ORC_EPARSE; break; }
+        int qs[260]; unsigned char ng[260]; int nq = 0, has_ang = 0; double ang = 0;
+        for (int i = 1; i < nt; ++i) {
+            const char *s = tok[i];
+            int neg = 0;
+            if (s[0] == '~') { neg = 1; ++s; }
+            if (s[0] && strspn(s, "0123456789") == strlen(s)) {
+                int q = atoi(s);
+                if (q < 0 || q >= c->n) { rc = ORC_ERANGE; break; }
+                for (int j = 0; j < nq; ++j) if (qs[j] == q) rc = ORC_EPARSE;
+                qs[nq] = q; ng[nq] = (unsigned char)neg; ++nq;
+            } else {
+                char *end;
+                if (neg || i != nt - 1) { rc = ORC_EPARSE; break; }
+                ang = strtod(s, &end);
+                if (*end || !isfinite(ang)) { rc = ORC_EPARSE; break; }
+                has_ang = 1;
+            }
+        }
+        if (rc) break;
+        if (c->G == cap) { cap *= 2; c->g = (ogate *)realloc(c->g, sizeof(ogate) * cap); memset(c->g + c->G, 0, sizeof(ogate) * (cap - c->G)); }
+        ogate *g = &c->g[c->G++];
+        memset(g, 0, sizeof(*g));
+        rc = build_gate(g, tok[0], qs, ng, nq, ang, has_ang);
+        if (rc) break;
+        classify(g);
+    }
+    if (!rc && c->n < 0) rc = ORC_EPARSE;
+    if (rc) { orc_free(c); return rc; }
+
+    /* internal-wire segments (Section II-A) */
+    int cur[ORC_MAXQ];
+    for (int q = 0; q < c->n; ++q) cur[q] = q;   /* segment q = input segment of qubit q */
+    int next = c->n;
+    for (int t = 0; t < c->G; ++t) {
+        ogate *g = &c->g[t];
+        g->in_seg = (int *)malloc(sizeof(int) * g->k);
+        g->out_seg = (int *)malloc(sizeof(int) * g->k);
+        for (int j = 0; j < g->k; ++j) {
+            int q = g->q[j];
+            g->in_seg[j] = cur[q];
+            g->out_seg[j] = local_preserved(g, j) ? cur[q] : next++;
+            cur[q] = g->out_seg[j];
+        }
+    }
+    for (int q = 0; q < c->n; ++q) c->out_seg[q] = cur[q];
+    c->nseg = next;
+
+    /* backward placement: sweep from the output; a branching gate whose
+     * input-side segment is not an input segment gets a source */
+    c->src_seg = (int *)malloc(sizeof(int) * (c->G + 1));
+    c->src_gate = (int *)malloc(sizeof(int) * (c->G + 1));
+    c->src_eval = (int *)malloc(sizeof(int) * (c->G + 1));
+    c->A = 0;
+    for (int t = c->G - 1; t >= 0; --t) {
+        ogate *g = &c->g[t];
+        if (g->role != ROLE_BRANCH) continue;
+        for (int j = 0; j < g->k; ++j) {
+            if (local_preserved(g, j)) continue;
+            if (g->in_seg[j] < c->n) continue;        /* natural input segment */
+            if (c->A >= c->G) { orc_free(c); return ORC_EINTERNAL; }
+            c->src_seg[c->A] = g->in_seg[j];
+            c->src_gate[c->A] = t;
+            c->src_eval[c->A] = c->G - 1 - t;
+            c->A++;
+        }
+    }
+    *out = c;
+    return ORC_OK;
+}
+
+int orc_info(const orc_circuit *c, int *n, int *G, int *A, int *nseg) {
+    *n = c->n; *G = c->G; *A = c->A; *nseg = c->nseg;
+    return ORC_OK;
+}
+
+int orc_sources(const orc_circuit *c, int *eval_pos) {
+    for (int k = 0; k < c->A; ++k) eval_pos[k] = c->src_eval[k];
+    return ORC_OK;
+}
+
+int orc_gate_role(const orc_circuit *c, int t) { return c->g[t].role; }
+
+/* ------------------------------------------------------------------ */
+/* wire-value propagation                                              */
+/* ------------------------------------------------------------------ */
+
+static int getbit(const uint64_t *w, int q) { return (int)((w[q >> 6] >> (q & 63)) & 1u); }
+
+/* set a segment; 0 = ok, -1 = conflict; *changed set when newly known */
+static int setv(signed char *val, int seg, int v, int *changed) {
+    if (val[seg] < 0) { val[seg] = (signed char)v; if (changed) *changed = 1; return 0; }
+    return val[seg] == v ? 0 : -1;
+}
+
+/* Local consistency of one deterministic gate: keep the (in,out) pairs of
+ * its permutation that agree with the known values, fix every wire on which
+ * all surviving pairs agree.  Returns -1 if no pair survives. */
+static int rule_dense(const ogate *g, signed char *val, int *changed) {
+    int dim = 1 << g->k, nsurv = 0;
+    int and_in = dim - 1, or_in = 0, and_out = dim - 1, or_out = 0;
+    for (int x = 0; x < dim; ++x) {
+        int ok = 1;
+        for (int j = 0; j < g->k && ok; ++j) {
+            int v = val[g->in_seg[j]];
+            if (v >= 0 && v != ((x >> j) & 1)) ok = 0;
+        }
+        if (!ok) continue;
+        int y = -1;
+        for (int yy = 0; yy < dim; ++yy) if (!is_zero(M_AT(g, yy, x))) { y = yy; break; }
+        for (int j = 0; j < g->k && ok; ++j) {
+            int v = val[g->out_seg[j]];
+            if (v >= 0 && v != ((y >> j) & 1)) ok = 0;
+        }
+        if (!ok) continue;
+        ++nsurv;
+        and_in &= x; or_in |= x; and_out &= y; or_out |= y;
+    }
+    if (nsurv == 0) return -1;
+    for (int j = 0; j < g->k; ++j) {
+        if (((and_in ^ or_in) >> j & 1) == 0 && val[g->in_seg[j]] < 0)
+            if (setv(val, g->in_seg[j], (and_in >> j) & 1, changed)) return -1;
+        if (((and_out ^ or_out) >> j & 1) == 0 && val[g->out_seg[j]] < 0)
+            if (setv(val, g->out_seg[j], (and_out >> j) & 1, changed)) return -1;
+    }
+    return 0;
+}
+
+/* Multi-controlled X: target_out = target_in XOR [every control matches]. */
+static int rule_mcx(const ogate *g, signed char *val, int *changed) {
+    int tin = g->in_seg[0], tout = g->out_seg[0];
+    int mismatch = 0, unknown = 0, last_unknown = -1;
+    for (int j = 1; j < g->k; ++j) {
+        int v = val[g->in_seg[j]];
+        int want = g->neg[j] ? 0 : 1;
+        if (v < 0) { ++unknown; last_unknown = j; }
+        else if (v != want) mismatch = 1;
+    }
+    int vi = val[tin], vo = val[tout];
+    if (mismatch || unknown == 0) {
+        int flip = mismatch ? 0 : 1;
+        if (vi >= 0 && setv(val, tout, vi ^ flip, changed)) return -1;
+        if (vo >= 0 && setv(val, tin, vo ^ flip, changed)) return -1;
+        return 0;
+    }
+    if (vi < 0 || vo < 0) return 0;
+    if (vi != vo) {            /* every control must match */
+        for (int j = 1; j < g->k; ++j)
+            if (setv(val, g->in_seg[j], g->neg[j] ? 0 : 1, changed)) return -1;
+    } else if (unknown == 1) { /* the one unknown control must mismatch */
+        if (setv(val, g->in_seg[last_unknown], g->neg[last_unknown] ? 1 : 0, changed)) return -1;
+    }
+    return 0;
+}
+
+/* PropagateKnownValues over time indices [t0, t1): sweep backward then
+ * forward until no value changes.  Returns -1 on a conflict. */
+static int propagate(const orc_circuit *c, signed char *val, int t0, int t1) {
+    for (;;) {
+        int changed = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < t1 - t0; ++i) {
+                int t = pass == 0 ? t1 - 1 - i : t0 + i;
+                const ogate *g = &c->g[t];
+                if (g->role != ROLE_DET) continue;
+                int r = g->kind == KIND_MCX ? rule_mcx(g, val, &changed)
+                                            : rule_dense(g, val, &changed);
+                if (r) return -1;
+            }
+        }
+        if (!changed) return 0;
+    }
+}
+
+static int set_boundary(const orc_circuit *c, signed char *val,
+                        const uint64_t *bin, const uint64_t *bout) {
+    memset(val, -1, (size_t)c->nseg);
+    for (int q = 0; q < c->n; ++q) {
+        if (setv(val, q, getbit(bin, q), NULL)) return -1;
+        if (setv(val, c->out_seg[q], getbit(bout, q), NULL)) return -1;
+    }
+    return 0;
+}
+
+/* SetArtificialSources for sources [k0, k0+na) from the bits of hbits. */
+static int set_sources(const orc_circuit *c, signed char *val, int k0, int na, uint64_t hbits) {
+    for (int i = 0; i < na; ++i)
+        if (setv(val, c->src_seg[k0 + i], (int)((hbits >> i) & 1u), NULL)) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* history evaluation                                                  */
+/* ------------------------------------------------------------------ */
+
+typedef struct { cplx amp; double M; } partial;
+
+static cplx cmul(cplx a, cplx b) {
+    cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return r;
+}
+
+static double modulus1(cplx z) {
+    double m = sqrt(z.re * z.re + z.im * z.im);
+    return m > 1.0 ? 1.0 : m;
+}
+
+/* EvaluateHistory restricted to time indices [t0,t1), walked from t1-1 down
+ * to t0 (evaluation order).  Returns 0 ok, 1 zero factor, 2 pruned. */
+static int evaluate(const orc_circuit *c, const signed char *val, int t0, int t1,
+                    double thr, partial *pa, uint64_t *gate_evals) {
+    for (int t = t1 - 1; t >= t0; --t) {
+        const ogate *g = &c->g[t];
+        cplx f;
+        for (int j = 0; j < g->k; ++j) {
+            if (val[g->in_seg[j]] < 0 || val[g->out_seg[j]] < 0) {
+                fprintf(stderr, "oracle: unresolved wire at gate %d\n", t);
+                abort();
+            }
+        }
+        ++*gate_evals;
+        if (g->kind == KIND_MCX) {
+            int match = 1;
+            for (int j = 1; j < g->k; ++j)
+                if (val[g->in_seg[j]] != (g->neg[j] ? 0 : 1)) match = 0;
+            int ti = val[g->in_seg[0]], to = val[g->out_seg[0]];
+            f = (to == (ti ^ match)) ? C(1, 0) : C(0, 0);
+        } else if (g->kind == KIND_MCZ) {
+            int match = 1;
+            for (int j = 0; j < g->k; ++j)
+                if (val[g->in_seg[j]] != (g->neg[j] ? 0 : 1)) match = 0;
+            f = match ? C(-1, 0) : C(1, 0);
+        } else {
+            int x = 0, y = 0;
+            for (int j = 0; j < g->k; ++j) {
+                x |= val[g->in_seg[j]] << j;
+                y |= val[g->out_seg[j]] << j;
+            }
+            f = M_AT(g, y, x);
+        }
+        if (is_zero(f)) return 1;
+        pa->amp = cmul(pa->amp, f);
+        if (g->role == ROLE_BRANCH) {
+            pa->M = pa->M * modulus1(f);
+            if (pa->M < thr) return 2;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Neumaier-compensated accumulation and statistics                    */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double s, c; } nsum;
+static void nadd(nsum *a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+/* SplitMix64 finaliser (Steele, Lea, Flood 2014), used to hash valid sets. */
+static uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    nsum re, im;
+    uint64_t n_valid, sum_h, xor_h, gate_evals;
+} acc_t;
+
+static void acc_history(acc_t *a, cplx amp, uint64_t h) {
+    nadd(&a->re, amp.re); nadd(&a->im, amp.im);
+    a->n_valid += 1; a->sum_h += h; a->xor_h ^= mix64(h);
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 and Algorithm 2 for one (b_in, b_out) pair              */
+/* ------------------------------------------------------------------ */
+
+static void alg1(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
+                 double thr, acc_t *a) {
+    signed char *c0 = (signed char *)malloc((size_t)c->nseg);
+    signed char *ch = (signed char *)malloc((size_t)c->nseg);
+    if (set_boundary(c, c0, bin, bout) == 0 && propagate(c, c0, 0, c->G) == 0) {
+        uint64_t nh = 1ULL << c->A;
+        for (uint64_t h = 0; h < nh; ++h) {
+            memcpy(ch, c0, (size_t)c->nseg);
+            if (set_sources(c, ch, 0, c->A, h)) continue;
+            if (propagate(c, ch, 0, c->G)) continue;
+            partial pa = {{1.0, 0.0}, 1.0};
+            if (evaluate(c, ch, 0, c->G, thr, &pa, &a->gate_evals)) continue;
+            acc_history(a, pa.amp, h);
+        }
+    }
+    free(c0); free(ch);
+}
+
+/* AdvanceCheckpoint: assign the region's sources, propagate inside the
+ * region, multiply the region's factors.  Region = time indices [t0,t1),
+ * sources [k0, k0+na).  Returns 0 on success (dst filled). */
+static int advance(const orc_circuit *c, const signed char *src, signed char *dst,
+                   int t0, int t1, int k0, int na, uint64_t hbits, double thr,
+                   partial *pa, uint64_t *gate_evals) {
+    memcpy(dst, src, (size_t)c->nseg);
+    if (set_sources(c, dst, k0, na, hbits)) return -1;
+    if (propagate(c, dst, t0, t1)) return -1;
+    if (evaluate(c, dst, t0, t1, thr, pa, gate_evals)) return -1;
+    return 0;
+}
+
+static void alg2(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
+                 double thr, int c1, int c2, acc_t *a) {
+    /* eval cuts -> time ranges: prefix = [G-c1, G), root = [G-c2, G-c1), suffix = [0, G-c2) */
+    int G = c->G;
+    int Ap = 0, Ar = 0, As = 0;
+    for (int k = 0; k < c->A; ++k) {
+        int e = c->src_eval[k];
+        if (e < c1) ++Ap; else if (e < c2) ++Ar; else ++As;
+    }
+    size_t ns = (size_t)c->nseg;
+    signed char *s0 = (signed char *)malloc(ns), *sp = (signed char *)malloc(ns);
+    signed char *sr = (signed char *)malloc(ns), *ss = (signed char *)malloc(ns);
+    if (set_boundary(c, s0, bin, bout) == 0 && propagate(c, s0, 0, G) == 0) {
+        for (uint64_t hp = 0; hp < (1ULL << Ap); ++hp) {
+            partial pp = {{1.0, 0.0}, 1.0};
+            if (advance(c, s0, sp, G - c1, G, 0, Ap, hp, thr, &pp, &a->gate_evals)) continue;
+            for (uint64_t hr = 0; hr < (1ULL << Ar); ++hr) {
+                partial pr = pp;
+                if (advance(c, sp, sr, G - c2, G - c1, Ap, Ar, hr, thr, &pr, &a->gate_evals)) continue;
+                for (uint64_t hs = 0; hs < (1ULL << As); ++hs) {
+                    partial ps = pr;
+                    if (advance(c, sr, ss, 0, G - c2, Ap + Ar, As, hs, thr, &ps, &a->gate_evals)) continue;
+                    uint64_t h = hp | (hr << Ap) | (hs << (Ap + Ar));
+                    acc_history(a, ps.amp, h);
+                }
+            }
+        }
+    }
+    free(s0); free(sp); free(sr); free(ss);
+}
+
+/* One transition amplitude.  c1 < 0 selects Algorithm 1.
+ * stats[4] = n_valid, sum_h (mod 2^64), xor of mix64(h), gate evaluations. */
+int orc_pair(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
+             double thr, int c1, int c2, double *amp, uint64_t *stats) {
+    if (!(thr >= 0.0) || !isfinite(thr)) return ORC_EINVAL;
+    if (c->A > 62) return ORC_ERANGE;
+    if (c1 >= 0 && (c1 > c2 || c2 > c->G)) return ORC_EINVAL;
+    acc_t a;
+    memset(&a, 0, sizeof(a));
+    if (c1 < 0) alg1(c, bin, bout, thr, &a);
+    else alg2(c, bin, bout, thr, c1, c2, &a);
+    amp[0] = a.re.s + a.re.c;
+    amp[1] = a.im.s + a.im.c;
+    stats[0] = a.n_valid; stats[1] = a.sum_h; stats[2] = a.xor_h; stats[3] = a.gate_evals;
+    return ORC_OK;
+}
+
+/* Eq. (2) for a batch: amps[j] = sum_i coeff_i * alpha(in_i, out_j), inputs
+ * summed in order; stats[j] = (n_valid, sum_h, xor_h, gate_evals) over the
+ * pairs of output j.  OpenMP over outputs with nthreads threads. */
+int orc_evaluate(const orc_circuit *c, const uint64_t *inputs, const double *coeffs, int S,
+                 const uint64_t *outputs, int M, double thr, int c1, int c2,
+                 double *amps, uint64_t *stats, int nthreads) {
+    if (!(thr >= 0.0) || !isfinite(thr) || S < 0 || M < 0) return ORC_EINVAL;
+    if (c->A > 62) return ORC_ERANGE;
+    if (c1 >= 0 && (c1 > c2 || c2 > c->G)) return ORC_EINVAL;
+    int W = (c->n + 63) / 64;
+    int rc = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int j = 0; j < M; ++j) {
+        double re = 0.0, im = 0.0;
+        uint64_t st[4] = {0, 0, 0, 0};
+        for (int i = 0; i < S; ++i) {
+            double a[2];
+            uint64_t s[4];
+            if (orc_pair(c, inputs + (size_t)i * W, outputs + (size_t)j * W, thr, c1, c2, a, s)) {
+                rc = ORC_EINTERNAL;
+                continue;
+            }
+            double cr = coeffs[2 * i], ci = coeffs[2 * i + 1];
+            re += cr * a[0] - ci * a[1];
+            im += cr * a[1] + ci * a[0];
+            st[0] += s[0]; st[1] += s[1]; st[2] ^= s[2]; st[3] += s[3];
+        }
+        amps[2 * j] = re; amps[2 * j + 1] = im;
+        for (int k = 0; k < 4; ++k) stats[4 * (size_t)j + k] = st[k];
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. (8) and its argmin                                              */
+/* ------------------------------------------------------------------ */
+
+typedef unsigned __int128 u128;
+
+static void region_counts(const orc_circuit *c, int c1, int c2, int *A3) {
+    A3[0] = A3[1] = A3[2] = 0;
+    for (int k = 0; k < c->A; ++k) {
+        int e = c->src_eval[k];
+        A3[e < c1 ? 0 : (e < c2 ? 1 : 2)]++;
+    }
+}
+
+static u128 eq8(int Ap, int Ar, int As, int Gp, int Gr, int Gs) {
+    u128 inner = (u128)Gr + ((u128)1 << As) * (u128)Gs;
+    return ((u128)1 << Ap) * ((u128)Gp + ((u128)1 << Ar) * inner);
+}
+
+int orc_eq8(const orc_circuit *c, int c1, int c2, uint64_t *cost2) {
+    if (c1 < 0 || c1 > c2 || c2 > c->G) return ORC_EINVAL;
+    if (c->A > 100) return ORC_ERANGE;
+    int A3[3];
+    region_counts(c, c1, c2, A3);
+    u128 v = eq8(A3[0], A3[1], A3[2], c1, c2 - c1, c->G - c2);
+    cost2[0] = (uint64_t)v; cost2[1] = (uint64_t)(v >> 64);
+    return ORC_OK;
+}
+
+/* Exhaustive argmin of Eq. (8) over 0 <= c1 <= c2 <= G, smallest (c1,c2) on ties. */
+int orc_eq8_argmin(const orc_circuit *c, int *c1o, int *c2o, uint64_t *cost2) {
+    if (c->A > 100) return ORC_ERANGE;
+    int G = c->G;
+    int *before = (int *)calloc((size_t)G + 1, sizeof(int)); /* sources with eval pos < e */
+    for (int k = 0; k < c->A; ++k) before[c->src_eval[k] + 1]++;
+    for (int e = 1; e <= G; ++e) before[e] += before[e - 1];
+    u128 best = 0; int b1 = 0, b2 = 0, have = 0;
+    for (int c1 = 0; c1 <= G; ++c1)
+        for (int c2 = c1; c2 <= G; ++c2) {
+            int Ap = before[c1], Ar = before[c2] - before[c1], As = c->A - before[c2];
+            u128 v = eq8(Ap, Ar, As, c1, c2 - c1, G - c2);
+            if (!have || v < best) { best = v; b1 = c1; b2 = c2; have = 1; }
+        }
+    free(before);
+    *c1o = b1; *c2o = b2;
+    cost2[0] = (uint64_t)best; cost2[1] = (uint64_t)(best >> 64);
+    return ORC_OK;
+}

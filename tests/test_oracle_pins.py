@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here runs GPU code.  Each test ties the oracle (state vector O1, the
+C Feynman engine O2, the brute-force path sum) to something independent of
+it: the paper's worked examples (tests/golden), textbook closed forms, gate
+identities and invariants.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from oracle import brute_force as bf
+from oracle import closed_forms as cf
+from oracle import statevector as sv
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# gate matrices (O1) against identities that fix each convention
+# --------------------------------------------------------------------------
+
+def _u(text):
+    return sv.unitary(text)
+
+
+def test_gate_identities():
+    I2 = np.eye(2)
+    H = sv.gate_matrix("H", None)
+    X = sv.gate_matrix("X", None)
+    Y = sv.gate_matrix("Y", None)
+    Z = sv.gate_matrix("Z", None)
+    S = sv.gate_matrix("S", None)
+    T = sv.gate_matrix("T", None)
+    assert np.allclose(H @ H, I2)
+    assert np.allclose(S @ S, Z)
+    assert np.allclose(T @ T, S)
+    assert np.allclose(sv.gate_matrix("SDG", None) @ S, I2)
+    assert np.allclose(sv.gate_matrix("TDG", None) @ T, I2)
+    assert np.allclose(H @ Z @ H, X)
+    assert np.allclose(1j * X @ Z, Y)          # Y = i X Z
+    th = 0.731
+    # RX(pi) = -iX, RY(pi) = -iY, RZ(pi) = -iZ; RX = H RZ H
+    assert np.allclose(sv.gate_matrix("RX", math.pi), -1j * X)
+    assert np.allclose(sv.gate_matrix("RY", math.pi), -1j * Y)
+    assert np.allclose(sv.gate_matrix("RZ", math.pi), -1j * Z)
+    assert np.allclose(sv.gate_matrix("RX", th), H @ sv.gate_matrix("RZ", th) @ H)
+    # exp(-i th/2 X) by its series definition
+    assert np.allclose(sv.gate_matrix("RX", th), math.cos(th / 2) * I2 - 1j * math.sin(th / 2) * X)
+    assert np.allclose(sv.gate_matrix("RY", th), math.cos(th / 2) * I2 - 1j * math.sin(th / 2) * Y)
+    assert np.allclose(sv.gate_matrix("P", th), np.diag([1, np.exp(1j * th)]))
+    for name, ang in [("H", None), ("RX", th), ("RY", th), ("RZ", th), ("P", th),
+                      ("CP", th), ("RZZ", th), ("CX", None), ("SWAP", None), ("CCX", None),
+                      ("CSWAP", None), ("CZ", None)]:
+        u = sv.gate_matrix(name, ang)
+        assert np.allclose(u.conj().T @ u, np.eye(len(u))), name
+
+
+def test_two_qubit_conventions():
+    th = 0.4137
+    # CX a b: control a, target b (|a=1,b=0> -> |a=1,b=1>)
+    u = _u("qubits 2\nCX 0 1\n")
+    assert u[0b11, 0b01] == 1 and u[0b01, 0b01] == 0
+    # RZZ(th) = CX . RZ(th) on the target . CX
+    a = _u(f"qubits 2\nRZZ 0 1 {th.hex()}\n")
+    b = _u(f"qubits 2\nCX 0 1\nRZ 1 {th.hex()}\nCX 0 1\n")
+    assert np.allclose(a, b)
+    # CP(pi) = CZ, symmetric in its qubits
+    assert np.allclose(_u(f"qubits 2\nCP 0 1 {math.pi.hex()}\n"), _u("qubits 2\nCZ 0 1\n"))
+    assert np.allclose(_u(f"qubits 2\nCP 1 0 {th.hex()}\n"), _u(f"qubits 2\nCP 0 1 {th.hex()}\n"))
+    # SWAP = three CNOTs
+    assert np.allclose(_u("qubits 2\nSWAP 0 1\n"), _u("qubits 2\nCX 0 1\nCX 1 0\nCX 0 1\n"))
+    # CSWAP c a b = CX b a; CCX c a b; CX b a
+    assert np.allclose(_u("qubits 3\nCSWAP 0 1 2\n"),
+                       _u("qubits 3\nCX 2 1\nCCX 0 1 2\nCX 2 1\n"))
+    # MCX with polarity = X-conjugated CCX; MCZ = H-conjugated MCX on the target
+    assert np.allclose(_u("qubits 3\nMCX 2 ~0 1\n"), _u("qubits 3\nX 0\nCCX 0 1 2\nX 0\n"))
+    assert np.allclose(_u("qubits 3\nMCZ 0 ~1 2\n"), _u("qubits 3\nX 1\nH 2\nCCX 0 1 2\nH 2\nX 1\n"))
+
+
+# --------------------------------------------------------------------------
+# the paper's worked examples
+# --------------------------------------------------------------------------
+
+def test_eq6_three_qubit_example():
+    g = golden("eq6_three_qubit")
+    F = oracle.Feynman(g["circuit"])
+    assert F.A == g["A_backward"]
+    for b, (re, im) in g["expected"].items():
+        b = int(b)
+        want = complex(re, im)
+        amp, nv, *_ = F.pair(g["input"], b)
+        assert abs(amp - want) <= 1e-15
+        assert nv == g["n_valid"].get(str(b), 0)
+        assert abs(sv.amplitudes(g["circuit"], [0], [1], [b])[0] - want) <= 1e-15
+        assert abs(bf.path_sum(g["circuit"], 0, b)[0] - want) <= 1e-15
+
+
+def test_fig2_four_qubit_example():
+    g = golden("fig2_four_qubit")
+    F = oracle.Feynman(g["circuit"])
+    assert F.A == g["A_backward"]
+    assert F.source_eval_positions == g["source_eval_positions"]
+    assert [F.G - 1 - e for e in F.source_eval_positions] == g["source_time_index"]
+    c1, c2 = g["partition"]
+    assert (c1, c2 - c1, F.G - c2) == tuple(g["region_gates"])
+    assert F.region_sources(c1, c2) == tuple(g["region_sources"])
+    assert F.eq8(c1, c2) == g["eq8_partition"]
+    assert F.eq8(0, 0) == g["eq8_plain"]
+    b = lambda v, q: (v >> q) & 1
+    for i in range(16):
+        for o in range(16):
+            a0, a1 = b(i, 0) ^ b(i, 1), b(i, 2)
+            if b(o, 1) != b(i, 3):
+                want, nv_want = 0.0, 0
+            else:
+                e = b(o, 0) * a0 + b(o, 3) * a1 + b(o, 1) + (b(o, 2) ^ a0) * b(i, 1)
+                want, nv_want = (-1) ** e / (2 * math.sqrt(2)), 1
+            for part in (None, (c1, c2)):
+                amp, nv, sh, xh, _ = F.pair(i, o, partition=part)
+                assert abs(amp - want) <= 1e-15
+                assert nv == nv_want
+                if nv:
+                    assert sh == a0 | (a1 << 1)      # source k is bit k of h
+                    assert xh == oracle.mix64(sh)
+
+
+def test_fig3_backward_sources():
+    g = golden("fig3_three_qubit")
+    F = oracle.Feynman(g["circuit"])
+    assert F.A == g["A_backward"]
+    # the two sources are the final Hadamards (evaluation positions 0 and 1)
+    assert sorted(F.source_eval_positions) == [0, 1]
+    U = sv.unitary(g["circuit"])
+    for i in range(8):
+        amps, _ = F.evaluate([i], [1], list(range(8)))
+        assert np.abs(amps - U[:, i]).max() <= 1e-15
+
+
+def test_table1_backward_source_counts():
+    g = golden("table1_sources")
+    assert g["A_backward"]["qft"] == "0"
+    for n in range(2, 13):
+        assert oracle.Feynman(w.qft(n).to_text()).A == 0
+    for k in (3, 4, 5, 6):
+        for s in (1, 2, 3):
+            c, _ = w.amplitude_amplification(k, s, 4 if k > 2 else 1, seed=7 + k)
+            assert oracle.Feynman(c.to_text()).A == 2 * s * k
+    for nv in (4, 6, 8, 12, 24):
+        for p in (1, 2, 3):
+            c, *_ = w.qaoa_maxcut(nv, p, 11, 12)
+            assert oracle.Feynman(c.to_text()).A == p * nv
+    for n_pos in (3, 8, 99):
+        for s in (1, 2, 5, 20):
+            assert oracle.Feynman(w.quantum_walk(n_pos, s).to_text()).A == s - 1
+
+
+# --------------------------------------------------------------------------
+# closed forms (pin O1 and O2 at sizes the state vector cannot reach)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_qft_closed_form_statevector(n):
+    t = w.qft(n).to_text()
+    U = sv.unitary(t)
+    for x in range(1 << n):
+        want = np.array([cf.qft_amplitude(n, x, y) for y in range(1 << n)])
+        assert np.abs(U[:, x] - want).max() <= 1e-13
+
+
+def test_qft20_closed_form_oracle():
+    n = 20
+    F = oracle.Feynman(w.qft(n).to_text())
+    assert F.A == 0
+    rng = np.random.default_rng(5)
+    for _ in range(24):
+        x, y = int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n))
+        amp, nv, *_ = F.pair(x, y)
+        assert nv == 1
+        assert abs(amp - cf.qft_amplitude(n, x, y)) <= 1e-12
+
+
+@pytest.mark.parametrize("k,s", [(2, 1), (3, 1), (3, 2), (4, 3), (5, 3)])
+def test_aa_closed_form_statevector(k, s):
+    m = 1 if k == 2 else 4
+    c, marked = w.amplitude_amplification(k, s, m, seed=3)
+    t = c.to_text()
+    psi = sv.evolve(t, 0)
+    want = np.array([cf.aa_amplitude(k, s, marked, y) for y in range(1 << c.n)])
+    assert np.abs(psi - want).max() <= 1e-12
+    p = sum(abs(psi[y]) ** 2 for y in marked)
+    assert abs(p - cf.aa_success_probability(k, s, m)) <= 1e-12
+
+
+def test_aa_success_probabilities():
+    # sin^2(7 theta), sin theta = sqrt(4/N): values quoted for N = 16, 32
+    assert abs(cf.aa_success_probability(4, 3, 4) - 0.25) <= 1e-12
+    assert abs(cf.aa_success_probability(5, 3, 4) - 0.330078125) <= 1e-9
+
+
+def test_aa_closed_form_oracle_small():
+    c, marked = w.amplitude_amplification(3, 2, 4, seed=3)
+    F = oracle.Feynman(c.to_text())
+    assert F.A == 12
+    outs = list(range(1 << c.n))
+    amps, st = F.evaluate([0], [1], outs, partition=F.eq8_argmin()[:2], threads=4)
+    want = np.array([cf.aa_amplitude(3, 2, marked, y) for y in outs])
+    assert np.abs(amps - want).max() <= 1e-12
+    # every history is valid when the ancilla output bit is 0, none otherwise
+    for y, s in zip(outs, st):
+        assert int(s[0]) == ((1 << F.A) if (y >> 3) == 0 else 0)
+
+
+def test_walk_closed_form_statevector():
+    steps, n_pos = 5, 5
+    t = w.quantum_walk(n_pos, steps).to_text()
+    psi = sv.evolve(t, 0)
+    dp = cf.walk_amplitudes(steps)
+    for (x, c), a in dp.items():
+        assert abs(psi[w.walk_state(n_pos, x, c)] - a) <= 1e-12
+    assert abs(sum(abs(a) ** 2 for a in dp.values()) - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("n_pos,steps", [(6, 5), (99, 4), (99, 7)])
+def test_walk_closed_form_oracle(n_pos, steps):
+    F = oracle.Feynman(w.quantum_walk(n_pos, steps).to_text())
+    assert F.A == steps - 1
+    dp = cf.walk_amplitudes(steps)
+    keys = [(x, c) for x in range(-steps - 2, steps + 3) for c in (0, 1)]
+    outs = [w.walk_state(n_pos, x, c) for x, c in keys]
+    for part in (None, F.eq8_argmin()[:2]):
+        amps, st = F.evaluate([0], [1], outs, partition=part, threads=4)
+        norm = 0.0
+        for (x, c), a, s in zip(keys, amps, st):
+            assert abs(a - dp.get((x, c), 0)) <= 1e-12
+            assert int(s[0]) == cf.walk_n_valid(steps, x, c)
+            norm += abs(a) ** 2
+        assert abs(norm - 1.0) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# O2 against O1 and the brute-force path sum
+# --------------------------------------------------------------------------
+
+def test_config_clifford_t_against_statevector():
+    cfg = w.CONFIGS["clifford_t_10q_40g"]()
+    t = cfg["circuit"].to_text()
+    F = oracle.Feynman(t)
+    amps, st = F.evaluate(cfg["inputs"], [complex(*z) for z in cfg["coeffs"]], cfg["outputs"])
+    ref = sv.amplitudes(t, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]], cfg["outputs"])
+    assert np.abs(amps - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(0, 600, 1))
+def test_random_against_statevector(seed):
+    n = 1 + seed % 6
+    c = w.random_mixed(n, 4 + seed % 11, seed)
+    t = c.to_text()
+    F = oracle.Feynman(t)
+    rng = np.random.default_rng(seed)
+    S = 1 + seed % 3
+    inputs = [int(v) for v in rng.choice(1 << n, size=min(S, 1 << n), replace=False)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in inputs]
+    outs = list(range(1 << n))
+    amps, _ = F.evaluate(inputs, coeffs, outs)
+    ref = sv.amplitudes(t, inputs, coeffs, outs)
+    assert np.abs(amps - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_counts_and_threshold_against_brute_force(seed):
+    n = 1 + seed % 4
+    c = w.random_mixed(n, 3 + seed % 6, 1000 + seed)
+    t = c.to_text()
+    F = oracle.Feynman(t)
+    rng = np.random.default_rng(seed)
+    b_in = int(rng.integers(0, 1 << n))
+    for thr in (0.0, 0.05, 0.3, 0.6):
+        for b_out in range(1 << n):
+            amp, nv, *_ = F.pair(b_in, b_out, threshold=thr)
+            amp_b, nv_b = bf.path_sum(t, b_in, b_out, threshold=thr)
+            assert nv == nv_b, (thr, b_out)
+            assert abs(amp - amp_b) <= 1e-12
