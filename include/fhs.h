@@ -1,0 +1,166 @@
+/*
+ * fhs.h -- reduced-history Feynman amplitudes on one AMD MI355X (gfx950).
+ *
+ * Problem (paper, Section I and Eq. (2)): given a circuit, a sparse input
+ * state psi = sum_i coeff_i |b_in_i> and a list of output bitstrings, compute
+ * exactly the requested amplitudes <b_out_j| C |psi> =
+ * sum_i coeff_i * alpha^{b_in_i, b_out_j}, each transition amplitude being
+ * the reduced sum over artificial-source assignments of Eq. (7).
+ *
+ * Conventions shared by every call:
+ *   - Circuit text: one gate per line in time order after "qubits <n>"
+ *     (gates H X Y Z S SDG T TDG P RX RY RZ CX CZ SWAP CP RZZ CCX CSWAP MCX MCZ,
+ *     angles as C99 hex floats, "~q" marks a control active on 0).
+ *   - Bitstrings: W = ceil(n/64) uint64 words each, little-endian: qubit q is
+ *     bit (q mod 64) of word q/64.  Bits at positions >= n must be zero.
+ *   - Complex numbers: two doubles (re, im), interleaved.
+ *   - Evaluation order runs from the output towards the input (Section IV-A);
+ *     gate position e in evaluation order is time index G-1-e.  Artificial
+ *     source k (k = 0 nearest the output) is bit k of a history index h.
+ *   - Every call returns an fhs_status; none aborts, throws or exits.
+ *     Argument errors are detected before any work is enqueued and leave all
+ *     outputs untouched.
+ *   - Device pointers are HIP device memory owned by the caller; "stream" is
+ *     a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef FHS_H
+#define FHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FHS_OK = 0,
+    FHS_EINVAL = 1,        /* bad argument (NULL pointer, c1 > c2, NaN/negative threshold, bits >= n) */
+    FHS_EUNSUPPORTED = 2,  /* gate or feature outside the supported set */
+    FHS_ERANGE = 3,        /* n > 128, A > 62, or a size that overflows */
+    FHS_ENOMEM = 4,        /* workspace too small, or a host/device allocation failed */
+    FHS_EHIP = 5,          /* a HIP runtime call failed (message in fhs_last_error) */
+    FHS_ESTATE = 6,        /* call order violated (e.g. evaluate before load) */
+    FHS_EPARSE = 7         /* circuit text could not be parsed */
+} fhs_status;
+
+/* Partition modes for fhs_choose_partition (Section IV-C). */
+enum {
+    FHS_PART_NONE = 0,     /* (0,0): no checkpoint, every gate in the suffix */
+    FHS_PART_THIRDS = 1,   /* fixed split, a third of the gates per region (Section V, amplitude amplification) */
+    FHS_PART_EQ8 = 2,      /* argmin of Eq. (8) over all 0 <= c1 <= c2 <= G, smallest (c1,c2) on ties */
+    FHS_PART_MODEL = 3     /* argmin of the loaded cost model's prediction (fhs_load_cost_model) */
+};
+
+typedef struct fhs_program fhs_program;  /* host-side reduced-history program; immutable */
+typedef struct fhs_ctx fhs_ctx;          /* one device, one loaded program; not thread-safe */
+
+typedef struct {
+    uint32_t n_qubits;    /* n */
+    uint32_t n_gates;     /* G */
+    uint32_t n_sources;   /* A: artificial sources from the backward sweep (Section IV-A) */
+    uint32_t n_words;     /* W = ceil(n/64) */
+    uint32_t n_leading;   /* gates before the first source gate, evaluation order */
+    uint32_t n_branch;    /* branching gates, natural ones included */
+} fhs_program_info;
+
+/* Human-readable name of a status code (static storage). */
+const char *fhs_status_string(fhs_status s);
+
+/* ---------------------------------------------------------------------
+ * Host-only calls (no GPU needed)
+ * ------------------------------------------------------------------- */
+
+/* Section II-A and IV-A: parse `text` (len bytes, need not be NUL-terminated),
+ * classify every gate from its matrix (diagonal -> wire-preserving, one
+ * nonzero per column -> deterministic, else branching), mark natural input
+ * segments, place artificial sources by one backward sweep, and emit the
+ * straight-line history program.  *out is owned by the caller and released
+ * with fhs_program_free.  Errors: FHS_EPARSE, FHS_EUNSUPPORTED, FHS_ERANGE
+ * (n > 128 or G >= 2^24).  A > 62 is accepted here (Eq. (8) still works) and
+ * rejected by the evaluate calls. */
+fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out);
+void fhs_program_free(fhs_program *prog);
+fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info);
+
+/* Evaluation positions of the gates that carry sources 0..A-1 (ascending),
+ * written to eval_pos[0..min(A,cap)-1]. */
+fhs_status fhs_program_sources(const fhs_program *prog, uint32_t *eval_pos, uint32_t cap);
+
+/* Eq. (8): Gate_ops = 2^Ap (Gp + 2^Ar (Gr + 2^As Gs)) for cuts c1 <= c2 <= G,
+ * prefix = evaluation positions [0,c1), root [c1,c2), suffix [c2,G).  The
+ * 128-bit result is cost[0] (low word) + 2^64 cost[1].  regions (may be NULL)
+ * receives {Gp, Gr, Gs, Ap, Ar, As}. */
+fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
+                              uint64_t cost[2], uint32_t *regions);
+
+/* Section IV-C: choose cuts.  FHS_PART_NONE, FHS_PART_THIRDS and
+ * FHS_PART_EQ8 need no context; FHS_PART_MODEL needs fhs_choose_partition_ctx. */
+fhs_status fhs_choose_partition(const fhs_program *prog, int mode, uint32_t *c1, uint32_t *c2);
+
+/* ---------------------------------------------------------------------
+ * Device calls
+ * ------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out is released with
+ * fhs_ctx_destroy.  FHS_EHIP when the device cannot be used. */
+fhs_status fhs_ctx_create(int device, fhs_ctx **out);
+void fhs_ctx_destroy(fhs_ctx *ctx);
+
+/* Message for the last failing call on ctx (valid until the next call). */
+const char *fhs_last_error(const fhs_ctx *ctx);
+
+/* Upload the history program to the device (synchronous).  The program may
+ * be freed afterwards.  Resets the partition to (0,0). */
+fhs_status fhs_load_program(fhs_ctx *ctx, const fhs_program *prog);
+
+/* Set the checkpoint cuts (Section IV-C, Algorithm 2) used by fhs_evaluate.
+ * FHS_EINVAL unless c1 <= c2 <= G; FHS_ESTATE before fhs_load_program. */
+fhs_status fhs_set_partition(fhs_ctx *ctx, uint32_t c1, uint32_t c2);
+fhs_status fhs_get_partition(const fhs_ctx *ctx, uint32_t *c1, uint32_t *c2);
+
+/* Upper bound on the prefix-table bytes one fhs_evaluate call may stage in
+ * the workspace (default 1 GiB); output pairs are processed in batches that
+ * fit.  Minimum 1 MiB. */
+fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
+
+/* Bytes of device workspace fhs_evaluate / fhs_evaluate_plain need for M
+ * outputs and S inputs under the current program and partition. */
+fhs_status fhs_workspace_size(const fhs_ctx *ctx, uint32_t M, uint32_t S, size_t *bytes);
+
+/* Batched, checkpointed evaluation (Algorithm 2 on the GPU).
+ *   d_inputs  [S*W]  input bitstrings b_in_i          (device, read)
+ *   d_coeffs  [S*2]  <b_in_i|psi> as (re,im)          (device, read)
+ *   d_outputs [M*W]  requested output bitstrings      (device, read)
+ *   threshold        t >= 0, finite; 0 = exact (Section IV-A, threshold pruning)
+ *   d_amps    [M*2]  <b_out_j|C|psi>                  (device, written)
+ *   d_stats   [M*4]  per output, summed over inputs: number of valid
+ *                    histories, sum of their indices h (mod 2^64), xor of
+ *                    SplitMix64(h), leaf histories walked (device, written)
+ *   d_ws, ws_bytes   workspace of at least fhs_workspace_size bytes, 256-byte
+ *                    aligned (device, scratch; contents undefined afterwards)
+ * Enqueued asynchronously on `stream`: one precheck launch, then per batch of
+ * output pairs a prefix-table build and one persistent root/suffix launch fed
+ * by an atomic work queue, then a deterministic finalize.  The sequence is
+ * captured into a HIP graph and replayed when every argument repeats.
+ * Results are deterministic (bit-identical across runs).  FHS_ERANGE if
+ * A > 62; FHS_ENOMEM if ws_bytes is too small. */
+fhs_status fhs_evaluate(fhs_ctx *ctx,
+                        const uint64_t *d_inputs, const double *d_coeffs, uint32_t S,
+                        const uint64_t *d_outputs, uint32_t M, double threshold,
+                        double *d_amps, uint64_t *d_stats,
+                        void *d_ws, size_t ws_bytes, void *stream);
+
+/* Plain evaluation (Algorithm 1 on the GPU): no checkpoint, a static grid of
+ * one lane per candidate history h over every output pair, no queue, no
+ * graph.  Same arguments, results and error behaviour as fhs_evaluate. */
+fhs_status fhs_evaluate_plain(fhs_ctx *ctx,
+                              const uint64_t *d_inputs, const double *d_coeffs, uint32_t S,
+                              const uint64_t *d_outputs, uint32_t M, double threshold,
+                              double *d_amps, uint64_t *d_stats,
+                              void *d_ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHS_H */

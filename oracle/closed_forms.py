@@ -60,6 +60,35 @@ def walk_amplitudes(steps: int) -> Dict[Tuple[int, int], complex]:
     return amp
 
 
+def _splitmix64_np(h):
+    import numpy as np
+    z = h.astype(np.uint64)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def walk_valid_stats(steps: int, x: int, c: int) -> Tuple[int, int, int]:
+    """(count, sum of h mod 2^64, xor of SplitMix64(h)) over the valid
+    reduced histories of output (x, c).  Source k sits before the coin flip
+    of step steps-k and carries the coin value after step steps-1-k, so a
+    history is valid iff the coin values it assigns contain exactly
+    (x+steps)/2 - c ones: the set is {h < 2^(steps-1) : popcount(h) = ones}."""
+    import numpy as np
+    if (x + steps) % 2:
+        return 0, 0, 0
+    ones = (x + steps) // 2 - c
+    h = np.arange(1 << (steps - 1), dtype=np.uint64)
+    pc = np.zeros(h.shape, dtype=np.int64)
+    for b in range(steps - 1):
+        pc += ((h >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    sel = h[pc == ones]
+    if sel.size == 0:
+        return 0, 0, 0
+    return (int(sel.size), int(sel.sum(dtype=np.uint64)),
+            int(np.bitwise_xor.reduce(_splitmix64_np(sel))))
+
+
 def walk_n_valid(steps: int, x: int, c: int) -> int:
     """Coin sequences c_1..c_steps with c_steps = c and sum(2c_t - 1) = x."""
     if (x + steps) % 2:

@@ -1,0 +1,242 @@
+"""Reduced-history Feynman amplitudes on one AMD MI355X (gfx950).
+
+Thin ctypes binding over the C ABI in include/fhs.h: argument marshalling
+only.  Every step of the computation runs in the native library
+(libfhs.so: host reducer + HIP kernels); PyTorch provides device memory and
+streams.  There is no CPU fallback: if the library is missing, importing the
+native handle raises.
+
+    prog = Program(circuit_text)            # fhs_reduce (host)
+    ctx = Context(device=0)
+    ctx.load(prog)                          # fhs_load_program
+    ctx.set_partition(*prog.choose_partition(PART_EQ8))
+    amps, stats = ctx.evaluate(inputs, coeffs, outputs, threshold=0.0)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhs.so")
+
+PART_NONE, PART_THIRDS, PART_EQ8, PART_MODEL = 0, 1, 2, 3
+
+STATUS = {0: "FHS_OK", 1: "FHS_EINVAL", 2: "FHS_EUNSUPPORTED", 3: "FHS_ERANGE",
+          4: "FHS_ENOMEM", 5: "FHS_EHIP", 6: "FHS_ESTATE", 7: "FHS_EPARSE"}
+
+EXPORTS = [
+    "fhs_status_string", "fhs_reduce", "fhs_program_free", "fhs_program_get_info",
+    "fhs_program_sources", "fhs_partition_cost", "fhs_choose_partition", "fhs_ctx_create",
+    "fhs_ctx_destroy", "fhs_last_error", "fhs_load_program", "fhs_set_partition",
+    "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
+    "fhs_evaluate_plain",
+]
+
+
+class FhsError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}" if msg else STATUS.get(status, str(status)))
+
+
+class ProgramInfo(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_uint32), ("n_gates", ctypes.c_uint32),
+                ("n_sources", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
+                ("n_leading", ctypes.c_uint32), ("n_branch", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The native library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2608_01467_amd._build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        pU32 = ctypes.POINTER(U32)
+        L.fhs_status_string.restype = ctypes.c_char_p
+        L.fhs_status_string.argtypes = [I32]
+        L.fhs_reduce.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(P)]
+        L.fhs_program_free.argtypes = [P]
+        L.fhs_program_free.restype = None
+        L.fhs_program_get_info.argtypes = [P, ctypes.POINTER(ProgramInfo)]
+        L.fhs_program_sources.argtypes = [P, pU32, U32]
+        L.fhs_partition_cost.argtypes = [P, U32, U32, ctypes.POINTER(U64), pU32]
+        L.fhs_choose_partition.argtypes = [P, I32, pU32, pU32]
+        L.fhs_ctx_create.argtypes = [I32, ctypes.POINTER(P)]
+        L.fhs_ctx_destroy.argtypes = [P]
+        L.fhs_ctx_destroy.restype = None
+        L.fhs_last_error.argtypes = [P]
+        L.fhs_last_error.restype = ctypes.c_char_p
+        L.fhs_load_program.argtypes = [P, P]
+        L.fhs_set_partition.argtypes = [P, U32, U32]
+        L.fhs_get_partition.argtypes = [P, pU32, pU32]
+        L.fhs_set_table_budget.argtypes = [P, ctypes.c_size_t]
+        L.fhs_workspace_size.argtypes = [P, U32, U32, ctypes.POINTER(ctypes.c_size_t)]
+        ev = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P, ctypes.c_size_t, P]
+        L.fhs_evaluate.argtypes = ev
+        L.fhs_evaluate_plain.argtypes = ev
+        _lib = L
+    return _lib
+
+
+def _check(st: int, ctx=None) -> None:
+    if st != 0:
+        msg = ""
+        if ctx is not None and ctx._h:
+            msg = lib().fhs_last_error(ctx._h).decode()
+        raise FhsError(st, msg)
+
+
+class Program:
+    """Host-side reduced-history program (fhs_reduce)."""
+
+    def __init__(self, circuit_text: str):
+        b = circuit_text.encode()
+        h = ctypes.c_void_p()
+        _check(lib().fhs_reduce(b, len(b), ctypes.byref(h)))
+        self._h = h
+        info = ProgramInfo()
+        _check(lib().fhs_program_get_info(h, ctypes.byref(info)))
+        self.n = info.n_qubits
+        self.G = info.n_gates
+        self.A = info.n_sources
+        self.W = info.n_words
+        self.L = info.n_leading
+        self.n_branch = info.n_branch
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fhs_program_free(self._h)
+            self._h = None
+
+    @property
+    def source_eval_positions(self) -> list:
+        arr = (ctypes.c_uint32 * max(1, self.A))()
+        _check(lib().fhs_program_sources(self._h, arr, self.A))
+        return list(arr[: self.A])
+
+    def partition_cost(self, c1: int, c2: int) -> Tuple[int, Tuple[int, ...]]:
+        cost = (ctypes.c_uint64 * 2)()
+        reg = (ctypes.c_uint32 * 6)()
+        _check(lib().fhs_partition_cost(self._h, c1, c2, cost, reg))
+        return int(cost[0]) | (int(cost[1]) << 64), tuple(reg)
+
+    def choose_partition(self, mode: int = PART_EQ8) -> Tuple[int, int]:
+        c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().fhs_choose_partition(self._h, mode, ctypes.byref(c1), ctypes.byref(c2)))
+        return c1.value, c2.value
+
+
+def _to_words(values, n: int) -> np.ndarray:
+    w = max(1, (n + 63) // 64)
+    if isinstance(values, np.ndarray) and values.dtype == np.uint64:
+        arr = np.ascontiguousarray(values.reshape(-1, w))
+    else:
+        arr = np.zeros((len(values), w), dtype=np.uint64)
+        for i, v in enumerate(values):
+            v = int(v)
+            if v < 0 or v >> n:
+                raise ValueError(f"bitstring {v:#x} has bits at or above n={n}")
+            for j in range(w):
+                arr[i, j] = (v >> (64 * j)) & ((1 << 64) - 1)
+    return arr
+
+
+class Context:
+    """One device, one loaded program (fhs_ctx)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().fhs_ctx_create(device, ctypes.byref(h))
+        if st != 0:
+            raise FhsError(st, f"cannot create a context on HIP device {device}")
+        self._h = h
+        self._ws = None
+        self.program: Optional[Program] = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fhs_ctx_destroy(self._h)
+            self._h = None
+
+    def load(self, prog: Program) -> None:
+        _check(lib().fhs_load_program(self._h, prog._h), self)
+        self.program = prog
+
+    def set_partition(self, c1: int, c2: int) -> None:
+        _check(lib().fhs_set_partition(self._h, c1, c2), self)
+
+    @property
+    def partition(self) -> Tuple[int, int]:
+        c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().fhs_get_partition(self._h, ctypes.byref(c1), ctypes.byref(c2)), self)
+        return c1.value, c2.value
+
+    def set_table_budget(self, nbytes: int) -> None:
+        _check(lib().fhs_set_table_budget(self._h, nbytes), self)
+
+    def workspace_size(self, M: int, S: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().fhs_workspace_size(self._h, M, S, ctypes.byref(b)), self)
+        return b.value
+
+    def workspace(self, nbytes: int):
+        torch = self._torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def device_bits(self, values):
+        """Bitstrings (ints or uint64 words) -> int64 device tensor [count, W]."""
+        torch = self._torch
+        if isinstance(values, torch.Tensor):
+            return values.contiguous()
+        arr = _to_words(values, self.program.n)
+        return torch.from_numpy(arr.view(np.int64)).to(f"cuda:{self.device}")
+
+    def device_coeffs(self, coeffs):
+        torch = self._torch
+        if isinstance(coeffs, torch.Tensor):
+            return coeffs.contiguous()
+        arr = np.zeros((len(coeffs), 2), dtype=np.float64)
+        for i, z in enumerate(coeffs):
+            z = complex(*z) if isinstance(z, tuple) else complex(z)
+            arr[i] = (z.real, z.imag)
+        return torch.from_numpy(arr).to(f"cuda:{self.device}")
+
+    def evaluate(self, inputs, coeffs, outputs, threshold: float = 0.0, plain: bool = False,
+                 out=None, stream=None):
+        """<b_out|C|psi> for each output.  Returns (amps float64 [M,2],
+        stats int64 [M,4]) on the device; results are complete once the
+        stream (default: torch's current stream) has synchronized."""
+        torch = self._torch
+        d_in = self.device_bits(inputs)
+        d_out = self.device_bits(outputs)
+        d_cf = self.device_coeffs(coeffs)
+        S, M = d_in.shape[0], d_out.shape[0]
+        if out is None:
+            amps = torch.empty((M, 2), dtype=torch.float64, device=d_out.device)
+            stats = torch.empty((M, 4), dtype=torch.int64, device=d_out.device)
+        else:
+            amps, stats = out
+        nbytes = self.workspace_size(M, max(S, 1))
+        ws = self.workspace(nbytes)
+        if stream is None:
+            stream = torch.cuda.current_stream(d_out.device).cuda_stream
+        fn = lib().fhs_evaluate_plain if plain else lib().fhs_evaluate
+        _check(fn(self._h, d_in.data_ptr(), d_cf.data_ptr(), S, d_out.data_ptr(), M,
+                  float(threshold), amps.data_ptr(), stats.data_ptr(), ws.data_ptr(),
+                  ws.numel(), ctypes.c_void_p(stream)), self)
+        return amps, stats

@@ -1,0 +1,78 @@
+// kernels.hpp -- launch parameters shared by the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "program.hpp"
+
+namespace fhs {
+
+// Per-pair precheck results (structure of arrays, P pairs).
+struct PreBufs {
+    uint32_t *st;      // [NW][P] state after the leading source-free gates
+    double2 *amp;      // [P]     partial amplitude (beta_0)
+    double *M;         // [P]     running modulus product
+    uint32_t *ok;      // [P]     1 = consistent so far
+};
+
+// One output pair's finished result.
+struct PairRes {
+    double2 *amp;      // [P]
+    uint64_t *st;      // [P][4] n_valid, sum_h, xor_h, leaves
+};
+
+// Checkpoint table for one batch of pairs (structure of arrays).
+struct Table {
+    uint32_t *st;      // [NW][E]
+    double2 *beta;     // [E]
+    double *M;         // [E]
+    uint32_t *ok;      // [E]
+};
+
+// Per-item partial sums.
+struct Partials {
+    double2 *amp;      // [items]
+    uint64_t *st;      // [items][4]
+};
+
+struct Common {
+    const Instr *prog;       // device program, evaluation order
+    const double *fac;       // factor table
+    const Mask4 *fin;        // [G+1] bits final once e gates are applied
+    const uint64_t *inputs;  // [S][W]
+    const uint64_t *outputs; // [M][W]
+    uint32_t S, M, W, n;
+    uint32_t G, L, A;
+    uint32_t c1, c2;         // effective cuts, L <= c1 <= c2 <= G
+    uint32_t Ap, Ar, As;
+    double thr;
+};
+
+// Launchers (kernels.hip).  NW and pruning are dispatched inside.
+hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
+                           uint32_t n_zero, hipStream_t s);
+hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32_t p0, uint32_t B,
+                         hipStream_t s);
+// ss: log2 of the number of lanes that share one (entry, h_r) root task, each
+// walking a contiguous 2^(As-ss) slice of the suffix assignments.
+hipError_t launch_consume(const Common &c, int NW, Table tab, Partials part, uint32_t p0,
+                          uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter,
+                          uint32_t grid, hipStream_t s);
+hipError_t launch_plain(const Common &c, int NW, PreBufs pre, Partials part, uint32_t P,
+                        uint32_t blocks_per_pair, hipStream_t s);
+hipError_t launch_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
+                              uint32_t items_per_pair, uint32_t A, hipStream_t s);
+hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32_t M,
+                           double *amps, uint64_t *stats, hipStream_t s);
+
+// Workgroup size of the persistent consumer and the plain kernel.
+constexpr int kConsumeThreads = 256;
+constexpr int kPlainThreads = 256;
+constexpr int kMaxChunk = 256;   // prefix entries per work item
+
+// Occupancy-derived persistent grid for the consumer.
+int consume_blocks_per_cu(int NW, bool prune);
+
+}  // namespace fhs

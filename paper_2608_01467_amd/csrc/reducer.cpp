@@ -1,0 +1,514 @@
+// reducer.cpp -- host-side reduction of a circuit to a history program.
+//
+// Paper, Section II-A (gate roles), Section IV-A (natural sources, backward
+// artificial-source placement), Section IV-C (Eq. (8) and the autotuned
+// partition).  Host code only; runs without a GPU.
+//
+// Moduli min(1,|U|) feed the threshold-pruning decision, which must be
+// bit-reproducible: they are computed here once, as sqrt(re*re + im*im)
+// with contraction into FMA disabled, and the device only multiplies them.
+#pragma STDC FP_CONTRACT OFF
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cctype>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fhs.h"
+#include "program.hpp"
+
+struct fhs_program {
+    fhs::HostProgram p;
+};
+
+namespace fhs {
+namespace {
+
+using cd = std::complex<double>;
+
+struct Gate {
+    std::string name;
+    std::vector<int> q;        // listed qubits (MCX: q[0] is the target)
+    std::vector<uint8_t> neg;  // polarity per listed qubit (MCX/MCZ)
+    double angle = 0.0;
+    bool has_angle = false;
+    int k = 0;                 // dense matrix size 2^k (k <= 3), 0 for MCX/MCZ
+    cd m[8][8];                // U[out][in], local bit j <-> q[j]
+};
+
+bool all_digits(const std::string &s) {
+    if (s.empty()) return false;
+    for (char c : s)
+        if (!std::isdigit(static_cast<unsigned char>(c))) return false;
+    return true;
+}
+
+// Gate matrix U[out][in] on the listed qubits (local bit j = j-th listed qubit).
+fhs_status build_matrix(Gate &g) {
+    const std::string &nm = g.name;
+    const double h = std::sqrt(0.5);
+    auto need = [&](size_t nq, bool ang) {
+        return g.q.size() == nq && g.has_angle == ang;
+    };
+    for (auto ng : g.neg)
+        if (ng && nm != "MCX" && nm != "MCZ") return FHS_EPARSE;
+    if (nm == "MCX" || nm == "MCZ") {
+        if (g.q.empty() || g.has_angle) return FHS_EPARSE;
+        if (nm == "MCX" && g.neg[0]) return FHS_EPARSE;
+        g.k = 0;
+        return FHS_OK;
+    }
+    int k;
+    if (nm == "H" || nm == "X" || nm == "Y" || nm == "Z" || nm == "S" || nm == "SDG" ||
+        nm == "T" || nm == "TDG") {
+        if (!need(1, false)) return FHS_EPARSE;
+        k = 1;
+    } else if (nm == "P" || nm == "RX" || nm == "RY" || nm == "RZ") {
+        if (!need(1, true)) return FHS_EPARSE;
+        k = 1;
+    } else if (nm == "CX" || nm == "CZ" || nm == "SWAP") {
+        if (!need(2, false)) return FHS_EPARSE;
+        k = 2;
+    } else if (nm == "CP" || nm == "RZZ") {
+        if (!need(2, true)) return FHS_EPARSE;
+        k = 2;
+    } else if (nm == "CCX" || nm == "CSWAP") {
+        if (!need(3, false)) return FHS_EPARSE;
+        k = 3;
+    } else {
+        return FHS_EUNSUPPORTED;
+    }
+    g.k = k;
+    for (auto &row : g.m)
+        for (auto &x : row) x = 0.0;
+    const double a = g.angle;
+    auto bit = [](int x, int j) { return (x >> j) & 1; };
+    if (nm == "H") {
+        g.m[0][0] = h; g.m[0][1] = h; g.m[1][0] = h; g.m[1][1] = -h;
+    } else if (nm == "X") {
+        g.m[0][1] = 1.0; g.m[1][0] = 1.0;
+    } else if (nm == "Y") {
+        g.m[0][1] = cd(0, -1); g.m[1][0] = cd(0, 1);
+    } else if (nm == "Z") {
+        g.m[0][0] = 1.0; g.m[1][1] = -1.0;
+    } else if (nm == "S") {
+        g.m[0][0] = 1.0; g.m[1][1] = cd(0, 1);
+    } else if (nm == "SDG") {
+        g.m[0][0] = 1.0; g.m[1][1] = cd(0, -1);
+    } else if (nm == "T") {
+        g.m[0][0] = 1.0; g.m[1][1] = cd(h, h);
+    } else if (nm == "TDG") {
+        g.m[0][0] = 1.0; g.m[1][1] = cd(h, -h);
+    } else if (nm == "P") {
+        g.m[0][0] = 1.0; g.m[1][1] = cd(std::cos(a), std::sin(a));
+    } else if (nm == "RX" || nm == "RY" || nm == "RZ") {
+        const double c = std::cos(0.5 * a), s = std::sin(0.5 * a);
+        if (nm == "RX") {
+            g.m[0][0] = c; g.m[1][1] = c; g.m[0][1] = cd(0, -s); g.m[1][0] = cd(0, -s);
+        } else if (nm == "RY") {
+            g.m[0][0] = c; g.m[1][1] = c; g.m[0][1] = -s; g.m[1][0] = s;
+        } else {
+            g.m[0][0] = cd(c, -s); g.m[1][1] = cd(c, s);
+        }
+    } else if (nm == "CZ") {
+        for (int x = 0; x < 4; ++x) g.m[x][x] = (x == 3) ? -1.0 : 1.0;
+    } else if (nm == "CP") {
+        for (int x = 0; x < 3; ++x) g.m[x][x] = 1.0;
+        g.m[3][3] = cd(std::cos(a), std::sin(a));
+    } else if (nm == "RZZ") {
+        const double c = std::cos(0.5 * a), s = std::sin(0.5 * a);
+        for (int x = 0; x < 4; ++x) g.m[x][x] = (bit(x, 0) ^ bit(x, 1)) ? cd(c, s) : cd(c, -s);
+    } else {
+        for (int x = 0; x < (1 << k); ++x) {
+            int y = x;
+            if (nm == "CX" && bit(x, 0)) y = x ^ 2;
+            if (nm == "SWAP") y = (bit(x, 0) << 1) | bit(x, 1);
+            if (nm == "CCX" && bit(x, 0) && bit(x, 1)) y = x ^ 4;
+            if (nm == "CSWAP" && bit(x, 0)) y = 1 | (bit(x, 2) << 1) | (bit(x, 1) << 2);
+            g.m[y][x] = 1.0;
+        }
+    }
+    return FHS_OK;
+}
+
+fhs_status parse(const char *text, size_t len, int &n, std::vector<Gate> &gates) {
+    n = -1;
+    size_t pos = 0;
+    while (pos < len) {
+        size_t end = pos;
+        while (end < len && text[end] != '\n') ++end;
+        std::string line(text + pos, end - pos);
+        pos = end + 1;
+        size_t hash = line.find('#');
+        if (hash != std::string::npos) line.resize(hash);
+        std::vector<std::string> tok;
+        size_t i = 0;
+        while (i < line.size()) {
+            while (i < line.size() && std::isspace(static_cast<unsigned char>(line[i]))) ++i;
+            size_t j = i;
+            while (j < line.size() && !std::isspace(static_cast<unsigned char>(line[j]))) ++j;
+            if (j > i) tok.emplace_back(line.substr(i, j - i));
+            i = j;
+        }
+        if (tok.empty()) continue;
+        if (tok[0] == "qubits") {
+            if (tok.size() != 2 || n >= 0 || !all_digits(tok[1])) return FHS_EPARSE;
+            long v = std::strtol(tok[1].c_str(), nullptr, 10);
+            if (v < 1 || v > kMaxQubits) return FHS_ERANGE;
+            n = static_cast<int>(v);
+            continue;
+        }
+        if (n < 0) return FHS_EPARSE;
+        Gate g;
+        g.name = tok[0];
+        for (size_t t = 1; t < tok.size(); ++t) {
+            std::string s = tok[t];
+            bool ng = false;
+            if (!s.empty() && s[0] == '~') {
+                ng = true;
+                s = s.substr(1);
+            }
+            if (all_digits(s)) {
+                long q = std::strtol(s.c_str(), nullptr, 10);
+                if (q < 0 || q >= n) return FHS_ERANGE;
+                for (int prev : g.q)
+                    if (prev == q) return FHS_EPARSE;
+                g.q.push_back(static_cast<int>(q));
+                g.neg.push_back(ng ? 1 : 0);
+            } else {
+                if (ng || t != tok.size() - 1) return FHS_EPARSE;
+                char *e = nullptr;
+                double v = std::strtod(s.c_str(), &e);
+                if (e == s.c_str() || *e != 0 || !std::isfinite(v)) return FHS_EPARSE;
+                g.angle = v;
+                g.has_angle = true;
+            }
+        }
+        fhs_status st = build_matrix(g);
+        if (st != FHS_OK) return st;
+        gates.push_back(std::move(g));
+        if (gates.size() >= (1u << 24)) return FHS_ERANGE;
+    }
+    if (n < 0) return FHS_EPARSE;
+    return FHS_OK;
+}
+
+inline bool is_zero(const cd &z) { return z.real() == 0.0 && z.imag() == 0.0; }
+
+// Role from the matrix (Section II-A): no off-diagonal nonzero -> wire-
+// preserving, exactly one nonzero per column -> deterministic, else branching.
+enum Role { R_PRESERVE = 0, R_DET = 1, R_BRANCH = 2 };
+
+Role role_of(const Gate &g) {
+    if (g.k == 0) return g.name == "MCX" ? R_DET : R_PRESERVE;
+    const int dim = 1 << g.k;
+    bool off = false, multi = false;
+    for (int x = 0; x < dim; ++x) {
+        int nz = 0;
+        for (int y = 0; y < dim; ++y) {
+            if (is_zero(g.m[y][x])) continue;
+            ++nz;
+            if (y != x) off = true;
+        }
+        if (nz > 1) multi = true;
+    }
+    if (!off) return R_PRESERVE;
+    return multi ? R_BRANCH : R_DET;
+}
+
+// Local wire j keeps its value across the gate iff every nonzero transition
+// has the same bit j on both sides (diagonal gates, control roles).
+bool preserves(const Gate &g, int j) {
+    if (g.k == 0) return g.name == "MCZ" || j != 0;
+    const int dim = 1 << g.k;
+    for (int x = 0; x < dim; ++x)
+        for (int y = 0; y < dim; ++y)
+            if (!is_zero(g.m[y][x]) && (((x ^ y) >> j) & 1)) return false;
+    return true;
+}
+
+inline void set_bit(uint32_t *w, int q) { w[q >> 5] |= 1u << (q & 31); }
+
+double modulus1(const cd &z) {
+    const double re = z.real(), im = z.imag();
+    const double m = std::sqrt(re * re + im * im);
+    return m > 1.0 ? 1.0 : m;
+}
+
+// Algorithmic FP64 flops of multiplying the running amplitude by one factor
+// of this table: 0 if every entry is 0, +-1 or +-i, 2 if every entry is purely
+// real or purely imaginary, 6 for a general complex multiply.
+int flops_of(const std::vector<cd> &tab) {
+    bool trivial = true, axis = true;
+    for (const cd &z : tab) {
+        const double re = z.real(), im = z.imag();
+        const bool unit = (re == 0.0 && (im == 0.0 || im == 1.0 || im == -1.0)) ||
+                          (im == 0.0 && (re == 1.0 || re == -1.0));
+        if (!unit) trivial = false;
+        if (re != 0.0 && im != 0.0) axis = false;
+    }
+    return trivial ? 0 : (axis ? 2 : 6);
+}
+
+fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
+    const int G = static_cast<int>(gates.size());
+    P.n = n;
+    P.G = G;
+    P.W = (n + 63) / 64;
+    P.NW = n <= 32 ? 1 : (n <= 64 ? 2 : 4);
+    // first non-preserving gate on each wire, time order (-1: none)
+    std::vector<int> first_np(n, -1);
+    std::vector<Role> role(G);
+    for (int t = 0; t < G; ++t) {
+        const Gate &g = gates[t];
+        role[t] = role_of(g);
+        for (size_t j = 0; j < g.q.size(); ++j)
+            if (!preserves(g, static_cast<int>(j)) && first_np[g.q[j]] < 0) first_np[g.q[j]] = t;
+    }
+    P.ins.assign(G, Instr{});
+    P.role.assign(G, 0);
+    P.fp_cost.assign(G, 0);
+    P.fac.clear();
+    P.src_eval.clear();
+    P.final_before.assign(G + 1, Mask4{{0, 0, 0, 0}});
+    Mask4 fin{{0, 0, 0, 0}};
+    for (int q = 0; q < n; ++q)
+        if (first_np[q] < 0) set_bit(fin.w, q);   // wire never changes: b_out[q] must equal b_in[q]
+    P.final_before[0] = fin;
+    P.n_branch = 0;
+    int A = 0;
+    for (int e = 0; e < G; ++e) {
+        const int t = G - 1 - e;
+        const Gate &g = gates[t];
+        Instr I{};
+        P.role[e] = static_cast<uint8_t>(role[t]);
+        auto push_tab = [&](const std::vector<cd> &tab) {
+            I.fac = static_cast<uint32_t>(P.fac.size());
+            for (const cd &z : tab) {
+                P.fac.push_back(z.real());
+                P.fac.push_back(z.imag());
+            }
+            P.fp_cost[e] = static_cast<uint16_t>(flops_of(tab));
+        };
+        const std::string &nm = g.name;
+        if (g.k == 0) {
+            // MCX / MCZ: control masks with polarity
+            const size_t c0 = (nm == "MCX") ? 1 : 0;
+            for (size_t j = c0; j < g.q.size(); ++j) {
+                set_bit(I.cm, g.q[j]);
+                if (!g.neg[j]) set_bit(I.cv, g.q[j]);
+            }
+            if (nm == "MCX") {
+                I.op = OP_PERM;
+                I.a = static_cast<uint8_t>(g.q[0]);
+            } else {
+                I.op = OP_MCPHASE;
+            }
+        } else if (role[t] == R_BRANCH) {
+            if (g.k != 1) return FHS_EUNSUPPORTED;   // only single-qubit branching gates
+            const int q = g.q[0];
+            ++P.n_branch;
+            std::vector<cd> tab;
+            for (int o = 0; o < 2; ++o)
+                for (int i = 0; i < 2; ++i) tab.push_back(g.m[o][i]);
+            push_tab(tab);
+            for (int o = 0; o < 2; ++o)
+                for (int i = 0; i < 2; ++i) {
+                    P.fac.push_back(modulus1(g.m[o][i]));
+                    if (is_zero(g.m[o][i])) I.zmask |= 1u << (2 * o + i);
+                }
+            I.a = static_cast<uint8_t>(q);
+            if (first_np[q] == t) {
+                I.op = OP_BRANCH_NAT;          // input segment is natural: value from b_in
+            } else {
+                I.op = OP_BRANCH_SRC;          // artificial source k, numbered in sweep order
+                I.k = static_cast<uint32_t>(A++);
+                P.src_eval.push_back(static_cast<uint32_t>(e));
+            }
+        } else if (role[t] == R_PRESERVE) {
+            if (g.k == 1) {
+                I.op = OP_DIAG1;
+                I.a = static_cast<uint8_t>(g.q[0]);
+                push_tab({g.m[0][0], g.m[1][1]});
+            } else if (g.k == 2) {
+                I.op = OP_DIAG2;
+                I.a = static_cast<uint8_t>(g.q[0]);
+                I.b = static_cast<uint8_t>(g.q[1]);
+                push_tab({g.m[0][0], g.m[1][1], g.m[2][2], g.m[3][3]});
+            } else {
+                return FHS_EUNSUPPORTED;
+            }
+        } else {  // deterministic dense gate
+            if (g.k == 1) {
+                // anti-diagonal: out bit o comes from in bit 1-o with factor U[o][1-o]
+                const bool plain = g.m[0][1] == cd(1.0, 0.0) && g.m[1][0] == cd(1.0, 0.0);
+                I.a = static_cast<uint8_t>(g.q[0]);
+                if (plain) {
+                    I.op = OP_PERM;
+                } else {
+                    I.op = OP_DET1;
+                    push_tab({g.m[0][1], g.m[1][0]});
+                }
+            } else if (nm == "CX" || nm == "CCX") {
+                I.op = OP_PERM;
+                for (int j = 0; j < g.k - 1; ++j) {
+                    set_bit(I.cm, g.q[j]);
+                    set_bit(I.cv, g.q[j]);
+                }
+                I.a = static_cast<uint8_t>(g.q[g.k - 1]);
+            } else if (nm == "SWAP" || nm == "CSWAP") {
+                I.op = OP_SWAP;
+                if (nm == "CSWAP") {
+                    set_bit(I.cm, g.q[0]);
+                    set_bit(I.cv, g.q[0]);
+                }
+                I.a = static_cast<uint8_t>(g.q[g.k - 2]);
+                I.b = static_cast<uint8_t>(g.q[g.k - 1]);
+            } else {
+                return FHS_EUNSUPPORTED;
+            }
+        }
+        I.op = op_code(static_cast<Op>(I.op), I.a, I.b);
+        P.ins[e] = I;
+        // bits whose natural input segment starts right below this gate
+        for (size_t j = 0; j < g.q.size(); ++j)
+            if (first_np[g.q[j]] == t) set_bit(fin.w, g.q[j]);
+        P.final_before[e + 1] = fin;
+    }
+    P.A = A;
+    P.L = A > 0 ? static_cast<int>(P.src_eval[0]) : G;
+    return FHS_OK;
+}
+
+void region_sources(const HostProgram &P, uint32_t c1, uint32_t c2, uint32_t out[3]) {
+    out[0] = out[1] = out[2] = 0;
+    for (uint32_t e : P.src_eval) out[e < c1 ? 0 : (e < c2 ? 1 : 2)]++;
+}
+
+unsigned __int128 eq8(uint32_t Ap, uint32_t Ar, uint32_t As, uint64_t Gp, uint64_t Gr,
+                      uint64_t Gs) {
+    using u128 = unsigned __int128;
+    const u128 inner = static_cast<u128>(Gr) + (static_cast<u128>(1) << As) * Gs;
+    return (static_cast<u128>(1) << Ap) * (static_cast<u128>(Gp) + (static_cast<u128>(1) << Ar) * inner);
+}
+
+}  // namespace
+}  // namespace fhs
+
+using namespace fhs;
+
+extern "C" const char *fhs_status_string(fhs_status s) {
+    switch (s) {
+        case FHS_OK: return "ok";
+        case FHS_EINVAL: return "invalid argument";
+        case FHS_EUNSUPPORTED: return "unsupported";
+        case FHS_ERANGE: return "out of range";
+        case FHS_ENOMEM: return "out of memory";
+        case FHS_EHIP: return "HIP error";
+        case FHS_ESTATE: return "wrong call order";
+        case FHS_EPARSE: return "parse error";
+    }
+    return "unknown status";
+}
+
+extern "C" fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out) {
+    if (!text || !out) return FHS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    std::vector<Gate> gates;
+    fhs_status st = parse(text, len, n, gates);
+    if (st != FHS_OK) return st;
+    fhs_program *p = new (std::nothrow) fhs_program;
+    if (!p) return FHS_ENOMEM;
+    st = emit(n, gates, p->p);
+    if (st != FHS_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FHS_OK;
+}
+
+extern "C" void fhs_program_free(fhs_program *prog) { delete prog; }
+
+extern "C" fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info) {
+    if (!prog || !info) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    info->n_qubits = static_cast<uint32_t>(P.n);
+    info->n_gates = static_cast<uint32_t>(P.G);
+    info->n_sources = static_cast<uint32_t>(P.A);
+    info->n_words = static_cast<uint32_t>(P.W);
+    info->n_leading = static_cast<uint32_t>(P.L);
+    info->n_branch = static_cast<uint32_t>(P.n_branch);
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_program_sources(const fhs_program *prog, uint32_t *eval_pos, uint32_t cap) {
+    if (!prog || (!eval_pos && cap)) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    for (uint32_t k = 0; k < cap && k < P.src_eval.size(); ++k) eval_pos[k] = P.src_eval[k];
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
+                                         uint64_t cost[2], uint32_t *regions) {
+    if (!prog || !cost) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    if (c1 > c2 || c2 > static_cast<uint32_t>(P.G)) return FHS_EINVAL;
+    if (P.A > 100) return FHS_ERANGE;
+    uint32_t a3[3];
+    region_sources(P, c1, c2, a3);
+    const unsigned __int128 v = eq8(a3[0], a3[1], a3[2], c1, c2 - c1, P.G - c2);
+    cost[0] = static_cast<uint64_t>(v);
+    cost[1] = static_cast<uint64_t>(v >> 64);
+    if (regions) {
+        regions[0] = c1; regions[1] = c2 - c1; regions[2] = P.G - c2;
+        regions[3] = a3[0]; regions[4] = a3[1]; regions[5] = a3[2];
+    }
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_choose_partition(const fhs_program *prog, int mode, uint32_t *c1,
+                                           uint32_t *c2) {
+    if (!prog || !c1 || !c2) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    const uint32_t G = static_cast<uint32_t>(P.G);
+    if (mode == FHS_PART_NONE) {
+        *c1 = 0; *c2 = 0;
+        return FHS_OK;
+    }
+    if (mode == FHS_PART_THIRDS) {
+        *c1 = G / 3; *c2 = (2 * G) / 3;
+        return FHS_OK;
+    }
+    if (mode != FHS_PART_EQ8) return mode == FHS_PART_MODEL ? FHS_ESTATE : FHS_EINVAL;
+    if (P.A > 100) return FHS_ERANGE;
+    // sources strictly before evaluation position e
+    std::vector<uint32_t> before(G + 1, 0);
+    for (uint32_t e : P.src_eval) before[e + 1]++;
+    for (uint32_t e = 1; e <= G; ++e) before[e] += before[e - 1];
+    unsigned __int128 best = 0;
+    bool have = false;
+    uint32_t b1 = 0, b2 = 0;
+    const uint32_t A = static_cast<uint32_t>(P.A);
+    for (uint32_t x = 0; x <= G; ++x)
+        for (uint32_t y = x; y <= G; ++y) {
+            const uint32_t ap = before[x], ar = before[y] - before[x], as = A - before[y];
+            const unsigned __int128 v = eq8(ap, ar, as, x, y - x, G - y);
+            if (!have || v < best) {
+                best = v; b1 = x; b2 = y; have = true;
+            }
+        }
+    *c1 = b1; *c2 = b2;
+    return FHS_OK;
+}
+
+// Internal accessor for the device side.
+const fhs::HostProgram &fhs_program_host(const fhs_program *p) { return p->p; }

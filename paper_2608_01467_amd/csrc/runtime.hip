@@ -1,0 +1,474 @@
+// runtime.hip -- device context, workspace plan, launch sequences and the
+// HIP-graph cache behind the C ABI (include/fhs.h).
+//
+// The paper's execution model (Section IV-D) decomposes the work over output
+// bitstrings and balances it dynamically with a server that hands batches of
+// outputs to idle workers.  On one GPU the server becomes a device atomic
+// counter: the persistent consumer pops (pair, prefix-chunk) work items until
+// the counter passes the item count.  The launch sequence of one evaluation
+// is captured once into a HIP graph and replayed while its arguments repeat.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fhs.h"
+#include "kernels.hpp"
+#include "program.hpp"
+
+const fhs::HostProgram &fhs_program_host(const fhs_program *p);
+
+namespace fhs {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct GraphKey {
+    const void *inputs, *coeffs, *outputs, *amps, *stats, *ws;
+    uint32_t S, M, c1, c2;
+    uint64_t thr_bits, ws_bytes, generation;
+    bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+// Byte layout of one evaluation's workspace.
+struct Plan {
+    uint32_t P = 0;          // pairs = M * S
+    uint32_t c1 = 0, c2 = 0; // effective cuts (>= L)
+    uint32_t Ap = 0, Ar = 0, As = 0;
+    uint32_t B = 0;          // pairs per batch
+    uint32_t n_batches = 0;
+    uint32_t chunk = 1;      // prefix entries per work item
+    uint32_t nchunks = 1;    // work items per pair
+    uint32_t ss = 0;         // log2 lanes per root task
+    uint32_t bpp = 1;        // plain: blocks per pair
+    uint64_t entries = 0;    // table entries per batch
+    size_t off_pre_st = 0, off_pre_amp = 0, off_pre_M = 0, off_pre_ok = 0;
+    size_t off_res_amp = 0, off_res_st = 0;
+    size_t off_counters = 0;
+    size_t off_tab_st = 0, off_tab_beta = 0, off_tab_M = 0, off_tab_ok = 0;
+    size_t off_part_amp = 0, off_part_st = 0;   // batched mode
+    size_t off_plain_amp = 0, off_plain_st = 0; // plain mode
+    size_t bytes = 0;
+};
+
+}  // namespace
+}  // namespace fhs
+
+using namespace fhs;
+
+struct fhs_ctx {
+    int device = 0;
+    int num_cu = 0;
+    std::string err;
+    bool loaded = false;
+    HostProgram prog;
+    Instr *d_prog = nullptr;
+    double *d_fac = nullptr;
+    Mask4 *d_fin = nullptr;
+    uint32_t c1 = 0, c2 = 0;
+    size_t table_budget = size_t(1) << 30;
+    uint64_t generation = 0;
+    hipStream_t cap_stream = nullptr;
+    bool have_graph = false;
+    GraphKey key{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int consume_bpc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+};
+
+namespace {
+
+fhs_status fail(fhs_ctx *c, fhs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return st;
+}
+
+fhs_status hip_fail(fhs_ctx *c, hipError_t e, const char *what) {
+    return fail(c, FHS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FHS_HIP(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+void free_program(fhs_ctx *c) {
+    if (c->d_prog) hipFree(c->d_prog);
+    if (c->d_fac) hipFree(c->d_fac);
+    if (c->d_fin) hipFree(c->d_fin);
+    c->d_prog = nullptr;
+    c->d_fac = nullptr;
+    c->d_fin = nullptr;
+    c->loaded = false;
+}
+
+void drop_graph(fhs_ctx *c) {
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+    c->have_graph = false;
+}
+
+int nw_of(const HostProgram &P) { return P.NW; }
+
+// Work layout for M outputs x S inputs under the context's program and cuts.
+fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
+    const HostProgram &P = c->prog;
+    const uint64_t pairs = static_cast<uint64_t>(M) * S;
+    if (pairs > 0xffffffffull / 4) return FHS_ERANGE;
+    pl = Plan{};
+    pl.P = static_cast<uint32_t>(pairs);
+    const uint32_t L = static_cast<uint32_t>(P.L);
+    pl.c1 = std::max(c->c1, L);
+    pl.c2 = std::max(c->c2, L);
+    for (uint32_t e : P.src_eval) {
+        if (e < pl.c1) ++pl.Ap;
+        else if (e < pl.c2) ++pl.Ar;
+        else ++pl.As;
+    }
+    const int NW = nw_of(P);
+    const uint32_t n_pairs = std::max<uint32_t>(pl.P, 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    pl.off_pre_st = take(sizeof(uint32_t) * NW * n_pairs);
+    pl.off_pre_amp = take(sizeof(double2) * n_pairs);
+    pl.off_pre_M = take(sizeof(double) * n_pairs);
+    pl.off_pre_ok = take(sizeof(uint32_t) * n_pairs);
+    pl.off_res_amp = take(sizeof(double2) * n_pairs);
+    pl.off_res_st = take(sizeof(uint64_t) * 4 * n_pairs);
+    const size_t common_end = off;
+
+    // batched mode
+    if (P.A > 0) {
+        if (pl.Ap > 30 || pl.Ar > 30) return FHS_ERANGE;
+        const uint64_t per_pair = 1ull << pl.Ap;
+        const size_t entry_bytes = sizeof(uint32_t) * NW + sizeof(double2) + sizeof(double) + sizeof(uint32_t);
+        if (per_pair * entry_bytes > c->table_budget) return FHS_ERANGE;   // one pair's table must fit
+        uint64_t B = c->table_budget / (per_pair * entry_bytes);
+        B = std::max<uint64_t>(1, std::min<uint64_t>(B, n_pairs));
+        pl.B = static_cast<uint32_t>(B);
+        pl.n_batches = (n_pairs + pl.B - 1) / pl.B;
+        pl.chunk = static_cast<uint32_t>(std::min<uint64_t>(per_pair, kMaxChunk));
+        pl.nchunks = static_cast<uint32_t>((per_pair + pl.chunk - 1) / pl.chunk);
+        pl.entries = B * per_pair;
+        // lanes sharing one root task: enough root tasks to fill the device
+        const uint64_t root_tasks = static_cast<uint64_t>(n_pairs) * per_pair << pl.Ar;
+        const uint64_t want = static_cast<uint64_t>(std::max(c->num_cu, 1)) * 2048;
+        while (pl.ss < pl.As && (root_tasks << pl.ss) < want) ++pl.ss;
+        pl.off_counters = take(sizeof(uint32_t) * pl.n_batches);
+        pl.off_tab_st = take(sizeof(uint32_t) * NW * pl.entries);
+        pl.off_tab_beta = take(sizeof(double2) * pl.entries);
+        pl.off_tab_M = take(sizeof(double) * pl.entries);
+        pl.off_tab_ok = take(sizeof(uint32_t) * pl.entries);
+        const uint64_t items = static_cast<uint64_t>(pl.B) * pl.nchunks;
+        if (items > 0xffffffffull) return FHS_ERANGE;
+        pl.off_part_amp = take(sizeof(double2) * items);
+        pl.off_part_st = take(sizeof(uint64_t) * 4 * items);
+    }
+    const size_t batched_end = off;
+
+    // plain mode reuses the space after the common part
+    off = common_end;
+    if (P.A > 0) {
+        const uint64_t NH = 1ull << std::min<uint32_t>(static_cast<uint32_t>(P.A), 62u);
+        const uint64_t max_bpp = std::max<uint64_t>(1, (NH + kPlainThreads - 1) / kPlainThreads);
+        const uint64_t target = static_cast<uint64_t>(std::max(c->num_cu, 1)) * 32;
+        uint64_t bpp = (target + n_pairs - 1) / n_pairs;
+        bpp = std::max<uint64_t>(1, std::min<uint64_t>(bpp, std::min<uint64_t>(max_bpp, 1u << 16)));
+        pl.bpp = static_cast<uint32_t>(bpp);
+        const uint64_t blocks = static_cast<uint64_t>(n_pairs) * pl.bpp;
+        if (blocks > 0x7fffffffull) return FHS_ERANGE;
+        pl.off_plain_amp = take(sizeof(double2) * blocks);
+        pl.off_plain_st = take(sizeof(uint64_t) * 4 * blocks);
+    }
+    pl.bytes = std::max(batched_end, off);
+    return FHS_OK;
+}
+
+fhs_status check_eval_args(fhs_ctx *c, const uint64_t *in, const double *cf, uint32_t S,
+                           const uint64_t *out, uint32_t M, double thr, double *amps,
+                           uint64_t *stats, void *ws, size_t ws_bytes, Plan &pl) {
+    if (!c) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->loaded) return fail(c, FHS_ESTATE, "no program loaded");
+    if (!(thr >= 0.0) || !std::isfinite(thr)) return fail(c, FHS_EINVAL, "threshold must be finite and >= 0");
+    if (c->prog.A > kMaxSources) return fail(c, FHS_ERANGE, "A = %d exceeds %d", c->prog.A, kMaxSources);
+    if (M == 0) return FHS_OK;
+    if (S == 0) return fail(c, FHS_EINVAL, "S must be >= 1");
+    if (!in || !cf || !out || !amps || !stats) return fail(c, FHS_EINVAL, "NULL buffer");
+    fhs_status st = make_plan(c, M, S, pl);
+    if (st != FHS_OK)
+        return fail(c, st, "work layout out of range (prefix table of 2^Ap entries exceeds the table budget, or too many pairs)");
+    if (!ws || ws_bytes < pl.bytes)
+        return fail(c, FHS_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, pl.bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(c, FHS_EINVAL, "workspace not 256-byte aligned");
+    return FHS_OK;
+}
+
+template <class T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_t S,
+                   const uint64_t *out, uint32_t M, double thr) {
+    const HostProgram &P = c->prog;
+    Common cm{};
+    cm.prog = c->d_prog;
+    cm.fac = c->d_fac;
+    cm.fin = c->d_fin;
+    cm.inputs = in;
+    cm.outputs = out;
+    cm.S = S;
+    cm.M = M;
+    cm.W = static_cast<uint32_t>(P.W);
+    cm.n = static_cast<uint32_t>(P.n);
+    cm.G = static_cast<uint32_t>(P.G);
+    cm.L = static_cast<uint32_t>(P.L);
+    cm.A = static_cast<uint32_t>(P.A);
+    cm.c1 = pl.c1;
+    cm.c2 = pl.c2;
+    cm.Ap = pl.Ap;
+    cm.Ar = pl.Ar;
+    cm.As = pl.As;
+    cm.thr = thr;
+    return cm;
+}
+
+PreBufs pre_bufs(void *ws, const Plan &pl) {
+    return PreBufs{at<uint32_t>(ws, pl.off_pre_st), at<double2>(ws, pl.off_pre_amp),
+                   at<double>(ws, pl.off_pre_M), at<uint32_t>(ws, pl.off_pre_ok)};
+}
+
+PairRes pair_res(void *ws, const Plan &pl) {
+    return PairRes{at<double2>(ws, pl.off_res_amp), at<uint64_t>(ws, pl.off_res_st)};
+}
+
+// The batched launch sequence (Algorithm 2): precheck, then per batch the
+// prefix-table build, the persistent consumer and the per-pair reduction,
+// then Eq. (2).
+hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const double *coeffs,
+                           double *amps, uint64_t *stats, void *ws, hipStream_t s) {
+    const HostProgram &P = c->prog;
+    const int NW = nw_of(P);
+    PreBufs pre = pre_bufs(ws, pl);
+    PairRes res = pair_res(ws, pl);
+    uint32_t *counters = P.A > 0 ? at<uint32_t>(ws, pl.off_counters) : nullptr;
+    hipError_t e = launch_precheck(cm, NW, pre, pl.P, counters, P.A > 0 ? pl.n_batches : 0, s);
+    if (e != hipSuccess) return e;
+    if (P.A == 0) {
+        e = launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s);
+        if (e != hipSuccess) return e;
+        return launch_finalize(res, coeffs, cm.S, cm.M, amps, stats, s);
+    }
+    Table tab{at<uint32_t>(ws, pl.off_tab_st), at<double2>(ws, pl.off_tab_beta),
+              at<double>(ws, pl.off_tab_M), at<uint32_t>(ws, pl.off_tab_ok)};
+    Partials part{at<double2>(ws, pl.off_part_amp), at<uint64_t>(ws, pl.off_part_st)};
+    const bool prune = cm.thr > 0.0;
+    const int bpc = std::max(1, c->consume_bpc[NW == 1 ? 0 : (NW == 2 ? 1 : 2)][prune ? 1 : 0]);
+    for (uint32_t b = 0; b < pl.n_batches; ++b) {
+        const uint32_t p0 = b * pl.B;
+        const uint32_t B = std::min(pl.B, pl.P - p0);
+        const uint64_t items = static_cast<uint64_t>(B) * pl.nchunks;
+        uint32_t grid = static_cast<uint32_t>(std::max(c->num_cu, 1)) * static_cast<uint32_t>(bpc);
+        if (items < grid) grid = static_cast<uint32_t>(items);
+        e = launch_prefix(cm, NW, pre, tab, p0, B, s);
+        if (e != hipSuccess) return e;
+        e = launch_consume(cm, NW, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
+        if (e != hipSuccess) return e;
+        e = launch_pair_reduce(pre, part, res, p0, B, pl.nchunks, cm.A, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_finalize(res, coeffs, cm.S, cm.M, amps, stats, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" fhs_status fhs_ctx_create(int device, fhs_ctx **out) {
+    if (!out) return FHS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FHS_EHIP;
+    fhs_ctx *c = new (std::nothrow) fhs_ctx;
+    if (!c) return FHS_ENOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return FHS_EHIP;
+    }
+    *out = c;
+    return FHS_OK;
+}
+
+extern "C" void fhs_ctx_destroy(fhs_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    drop_graph(c);
+    free_program(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+extern "C" const char *fhs_last_error(const fhs_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
+    if (!c || !p) return FHS_EINVAL;
+    c->err.clear();
+    FHS_HIP(c, hipSetDevice(c->device));
+    drop_graph(c);
+    free_program(c);
+    const HostProgram &P = fhs_program_host(p);
+    c->prog = P;
+    const size_t ni = std::max<size_t>(P.ins.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fin), sizeof(Mask4) * P.final_before.size()));
+    if (!P.ins.empty())
+        FHS_HIP(c, hipMemcpy(c->d_prog, P.ins.data(), sizeof(Instr) * P.ins.size(), hipMemcpyHostToDevice));
+    if (!P.fac.empty())
+        FHS_HIP(c, hipMemcpy(c->d_fac, P.fac.data(), sizeof(double) * P.fac.size(), hipMemcpyHostToDevice));
+    FHS_HIP(c, hipMemcpy(c->d_fin, P.final_before.data(), sizeof(Mask4) * P.final_before.size(),
+                         hipMemcpyHostToDevice));
+    c->c1 = c->c2 = 0;
+    c->loaded = true;
+    ++c->generation;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_set_partition(fhs_ctx *c, uint32_t c1, uint32_t c2) {
+    if (!c) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->loaded) return fail(c, FHS_ESTATE, "no program loaded");
+    if (c1 > c2 || c2 > static_cast<uint32_t>(c->prog.G))
+        return fail(c, FHS_EINVAL, "need c1 <= c2 <= G (%u, %u, %d)", c1, c2, c->prog.G);
+    c->c1 = c1;
+    c->c2 = c2;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_get_partition(const fhs_ctx *c, uint32_t *c1, uint32_t *c2) {
+    if (!c || !c1 || !c2) return FHS_EINVAL;
+    if (!c->loaded) return FHS_ESTATE;
+    *c1 = c->c1;
+    *c2 = c->c2;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_set_table_budget(fhs_ctx *c, size_t bytes) {
+    if (!c || bytes < (size_t(1) << 20)) return FHS_EINVAL;
+    c->table_budget = bytes;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_workspace_size(const fhs_ctx *c, uint32_t M, uint32_t S, size_t *bytes) {
+    if (!c || !bytes) return FHS_EINVAL;
+    if (!c->loaded) return FHS_ESTATE;
+    if (c->prog.A > kMaxSources) return FHS_ERANGE;
+    Plan pl;
+    fhs_status st = make_plan(c, M, std::max<uint32_t>(S, 1), pl);
+    if (st != FHS_OK) return st;
+    *bytes = pl.bytes;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const double *d_cf, uint32_t S,
+                                   const uint64_t *d_out, uint32_t M, double thr, double *d_amps,
+                                   uint64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream) {
+    Plan pl;
+    fhs_status st = check_eval_args(c, d_in, d_cf, S, d_out, M, thr, d_amps, d_stats, d_ws, ws_bytes, pl);
+    if (st != FHS_OK || M == 0) return st;
+    FHS_HIP(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GraphKey key{};
+    key.inputs = d_in;
+    key.coeffs = d_cf;
+    key.outputs = d_out;
+    key.amps = d_amps;
+    key.stats = d_stats;
+    key.ws = d_ws;
+    key.S = S;
+    key.M = M;
+    key.c1 = c->c1;
+    key.c2 = c->c2;
+    std::memcpy(&key.thr_bits, &thr, sizeof(thr));
+    key.ws_bytes = ws_bytes;
+    key.generation = c->generation;
+    if (!(c->have_graph && c->key == key)) {
+        drop_graph(c);
+        const int NW = nw_of(c->prog);
+        int &bpc = c->consume_bpc[NW == 1 ? 0 : (NW == 2 ? 1 : 2)][thr > 0.0 ? 1 : 0];
+        if (bpc == 0) bpc = consume_blocks_per_cu(NW, thr > 0.0);
+        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+        FHS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(c, e, "kernel launch during capture");
+        }
+        if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+        c->graph = g;
+        FHS_HIP(c, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+        c->key = key;
+        c->have_graph = true;
+    }
+    FHS_HIP(c, hipGraphLaunch(c->exec, s));
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const double *d_cf,
+                                         uint32_t S, const uint64_t *d_out, uint32_t M, double thr,
+                                         double *d_amps, uint64_t *d_stats, void *d_ws,
+                                         size_t ws_bytes, void *stream) {
+    Plan pl;
+    fhs_status st = check_eval_args(c, d_in, d_cf, S, d_out, M, thr, d_amps, d_stats, d_ws, ws_bytes, pl);
+    if (st != FHS_OK || M == 0) return st;
+    FHS_HIP(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const HostProgram &P = c->prog;
+    const int NW = nw_of(P);
+    // Algorithm 1 has no checkpoint: every source lives in one region.
+    Plan plain = pl;
+    plain.c1 = plain.c2 = static_cast<uint32_t>(P.L);
+    plain.Ap = plain.Ar = 0;
+    plain.As = static_cast<uint32_t>(P.A);
+    const Common cm = make_common(c, plain, d_in, S, d_out, M, thr);
+    PreBufs pre = pre_bufs(d_ws, pl);
+    PairRes res = pair_res(d_ws, pl);
+    FHS_HIP(c, launch_precheck(cm, NW, pre, pl.P, nullptr, 0, s));
+    if (P.A == 0) {
+        FHS_HIP(c, launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s));
+    } else {
+        Partials part{at<double2>(d_ws, pl.off_plain_amp), at<uint64_t>(d_ws, pl.off_plain_st)};
+        FHS_HIP(c, launch_plain(cm, NW, pre, part, pl.P, pl.bpp, s));
+        FHS_HIP(c, launch_pair_reduce(pre, part, res, 0, pl.P, pl.bpp, cm.A, s));
+    }
+    FHS_HIP(c, launch_finalize(res, d_cf, S, M, d_amps, d_stats, s));
+    return FHS_OK;
+}

@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bar: valid-history count, index sum and index hash bit-exact; amplitudes
+within |delta| <= 1e-12 (absolute, per output).  Every case runs both GPU
+forms (plain Algorithm 1 and the batched, checkpointed Algorithm 2) on the
+same seeded inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from oracle import closed_forms as cf
+from oracle import statevector as sv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_01467_amd as fhs  # noqa: E402
+
+TOL = 1e-12
+THREADS = min(16, len(os.sched_getaffinity(0)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return fhs.Context(0)
+
+
+def gpu_eval(ctx, text, inputs, coeffs, outputs, thr=0.0, partition=(0, 0), plain=False,
+             prog=None):
+    prog = prog or fhs.Program(text)
+    ctx.load(prog)
+    ctx.set_partition(*partition)
+    amps, stats = ctx.evaluate(inputs, coeffs, outputs, threshold=thr, plain=plain)
+    torch.cuda.synchronize()
+    a = amps.cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1], stats.cpu().numpy().view(np.uint64)
+
+
+def compare(ctx, text, inputs, coeffs, outputs, thr=0.0, partitions=None, ref=None):
+    """Run plain + batched at each partition; compare with the oracle."""
+    o = oracle.Feynman(text)
+    if ref is None:
+        ref_amps, ref_st = o.evaluate(inputs, coeffs, outputs, threshold=thr, threads=THREADS)
+    else:
+        ref_amps, ref_st = ref
+    prog = fhs.Program(text)
+    if partitions is None:
+        partitions = [(0, 0), prog.choose_partition(fhs.PART_THIRDS),
+                      prog.choose_partition(fhs.PART_EQ8), (prog.G, prog.G), (0, prog.G)]
+    runs = [("plain", (0, 0), True)] + [(f"cut{p}", p, False) for p in partitions]
+    for name, part, plain in runs:
+        amps, st = gpu_eval(ctx, text, inputs, coeffs, outputs, thr, part, plain, prog=prog)
+        err = np.abs(amps - ref_amps).max() if len(outputs) else 0.0
+        assert err <= TOL, (name, err)
+        assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), name
+    return ref_amps, ref_st
+
+
+def test_eq6_and_fig2(ctx):
+    t = "qubits 3\nH 0\nCX 0 1\nS 1\nCX 1 2\n"
+    compare(ctx, t, [0], [1], list(range(8)))
+    fig2 = ("qubits 4\nCX 1 0\nH 1\nSWAP 2 3\nH 3\nP 2 " + math.pi.hex() +
+            "\nCX 0 1\nH 0\nSWAP 1 2\n")
+    for i in range(16):
+        compare(ctx, fig2, [i], [1], list(range(16)), partitions=[(0, 0), (2, 5), (1, 3)])
+
+
+def test_clifford_t_config(ctx):
+    cfg = w.CONFIGS["clifford_t_10q_40g"]()
+    t = cfg["circuit"].to_text()
+    coeffs = [complex(*z) for z in cfg["coeffs"]]
+    ref = sv.amplitudes(t, cfg["inputs"], coeffs, cfg["outputs"])
+    amps, _ = compare(ctx, t, cfg["inputs"], coeffs, cfg["outputs"])
+    assert np.abs(amps - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_mixed(ctx, seed):
+    n = [2, 5, 9, 12, 31, 32, 33, 40, 64, 65, 99, 128][seed % 12]
+    c = w.random_mixed(n, 12 + seed % 20, 4000 + seed, max_controls=4)
+    t = c.to_text()
+    rng = np.random.default_rng(seed)
+    o = oracle.Feynman(t)
+    if o.A > 14:
+        pytest.skip("too many sources for the oracle in a quick test")
+    S = 1 + seed % 3
+    inputs = [int(rng.integers(0, 1 << min(n, 62))) for _ in range(S)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in range(S)]
+    outs = [int(rng.integers(0, 1 << min(n, 62))) for _ in range(20)]
+    # sprinkle outputs reachable from the first input (nonzero amplitudes)
+    if n <= 12:
+        psi = sv.evolve(t, inputs[0])
+        outs += [int(x) for x in np.argsort(-np.abs(psi))[:8]]
+    thr = [0.0, 0.0, 1e-3, 0.02][seed % 4]
+    compare(ctx, t, inputs, coeffs, outs, thr=thr)
+
+
+def test_qft20_closed_form(ctx):
+    cfg = w.CONFIGS["qft_20q"]()
+    t = cfg["circuit"].to_text()
+    x = cfg["inputs"][0]
+    ref = np.array([cf.qft_amplitude(20, x, y) for y in cfg["outputs"]])
+    for plain in (False, True):
+        amps, st = gpu_eval(ctx, t, [x], [1], cfg["outputs"], plain=plain)
+        assert np.abs(amps - ref).max() <= TOL
+        assert (st[:, 0] == 1).all()
+
+
+def _all_h_stats(A):
+    h = np.arange(1 << A, dtype=np.uint64)
+    s = int(h.sum(dtype=np.uint64))
+    z = h.copy()
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    z = z ^ (z >> np.uint64(31))
+    return s, int(np.bitwise_xor.reduce(z))
+
+
+def test_aa_k4_closed_form(ctx):
+    cfg = w.CONFIGS["aa_k4_s3"]()
+    c, marked = cfg["circuit"], cfg["marked"]
+    t = c.to_text()
+    prog = fhs.Program(t)
+    assert prog.A == 24
+    outs = cfg["outputs"]
+    ref = np.array([cf.aa_amplitude(4, 3, marked, y) for y in outs])
+    s_all, x_all = _all_h_stats(24)
+    for part, plain in [((0, 0), True), (prog.choose_partition(fhs.PART_EQ8), False),
+                        (prog.choose_partition(fhs.PART_THIRDS), False)]:
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
+        assert np.abs(amps - ref).max() <= TOL
+        for y, row in zip(outs, st):
+            if y >> 4:           # an ancilla bit set: no valid history
+                assert row[0] == 0
+            else:
+                assert (int(row[0]), int(row[1]), int(row[2])) == (1 << 24, s_all, x_all)
+
+
+def test_qaoa12_statevector_and_counts(ctx):
+    cfg = w.CONFIGS["qaoa_12v_p2"]()
+    t = cfg["circuit"].to_text()
+    prog = fhs.Program(t)
+    assert prog.A == 24
+    outs = cfg["outputs"]
+    ref = sv.amplitudes(t, [0], [1], outs)
+    amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=prog.choose_partition(fhs.PART_EQ8),
+                        prog=prog)
+    assert np.abs(amps - ref).max() <= TOL
+    assert abs(np.sum(np.abs(amps) ** 2) - 1.0) <= 1e-10
+    s_all, x_all = _all_h_stats(24)
+    assert (st[:, 0] == (1 << 24)).all()
+    assert (st[:, 1] == s_all).all() and (st[:, 2] == x_all).all()
+
+
+@pytest.mark.parametrize("thr", [1e-5, 3e-5, 1e-3])
+def test_qaoa_pruning_sampled(ctx, thr):
+    cfg = w.CONFIGS["qaoa_12v_p2"]()
+    t = cfg["circuit"].to_text()
+    prog = fhs.Program(t)
+    rng = np.random.default_rng(7)
+    outs = [int(x) for x in rng.choice(4096, size=2, replace=False)]
+    part = prog.choose_partition(fhs.PART_EQ8)
+    o = oracle.Feynman(t)
+    ref = o.evaluate([0], [1], outs, threshold=thr, partition=part, threads=THREADS)
+    for p, plain in [(part, False), ((0, 0), True)]:
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, thr=thr, partition=p, plain=plain, prog=prog)
+        assert np.abs(amps - ref[0]).max() <= TOL
+        assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64))
+
+
+def test_qaoa8_pruning_all_partitions(ctx):
+    t = w.qaoa_maxcut(8, 2, 411, 412)[0].to_text()
+    for thr in (0.0, 1e-4, 3e-3):
+        compare(ctx, t, [0], [1], list(range(0, 256, 5)), thr=thr)
+
+
+@pytest.mark.parametrize("n_pos,steps", [(6, 5), (99, 7)])
+def test_walk_small(ctx, n_pos, steps):
+    t = w.quantum_walk(n_pos, steps).to_text()
+    outs = w.walk_outputs(n_pos, steps, 40, seed=5)
+    dp = cf.walk_amplitudes(steps)
+    amps, st = compare(ctx, t, [0], [1], outs)
+    for y, a in zip(outs, amps):
+        x = (y >> 1)
+        x = x - (1 << n_pos) if x >= (1 << (n_pos - 1)) else x
+        assert abs(a - dp.get((x, y & 1), 0)) <= TOL
+
+
+def test_walk_config_full(ctx):
+    """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
+    against the position-space closed form and the closed-form valid sets
+    (count, index sum, index hash); the padding outputs exactly zero."""
+    cfg = w.CONFIGS["walk_99p_20s"]()
+    t = cfg["circuit"].to_text()
+    prog = fhs.Program(t)
+    outs = cfg["outputs"]
+    dp = cf.walk_amplitudes(20)
+    for part, plain in [(prog.choose_partition(fhs.PART_EQ8), False), ((0, 0), True)]:
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
+        for y, a, row in zip(outs[:42], amps[:42], st[:42]):
+            x = y >> 1
+            x = x - (1 << 99) if x >= (1 << 98) else x
+            assert abs(a - dp.get((x, y & 1), 0)) <= TOL
+            assert tuple(int(v) for v in row[:3]) == cf.walk_valid_stats(20, x, y & 1)
+        assert abs(np.sum(np.abs(amps[:42]) ** 2) - 1.0) <= 1e-10
+        assert (amps[42:] == 0).all() and (st[42:, 0] == 0).all()
+
+
+def test_multi_input_and_edge_cases(ctx):
+    t = w.random_mixed(7, 30, 77).to_text()
+    inputs = [3, 17, 100]
+    coeffs = [0.5 + 0.1j, -0.3j, 0.7]
+    outs = list(range(128)) + [5, 5]          # duplicates allowed
+    compare(ctx, t, inputs, coeffs, outs)
+    # no outputs: nothing to do
+    prog = fhs.Program(t)
+    ctx.load(prog)
+    amps, st = ctx.evaluate([0], [1], [], threshold=0.0)
+    assert amps.shape[0] == 0
+    # a circuit without gates: amplitude 1 iff output == input
+    amps, st = gpu_eval(ctx, "qubits 3\n", [5], [1], list(range(8)))
+    assert np.array_equal(amps, np.where(np.arange(8) == 5, 1.0, 0.0))
+
+
+def test_bits_above_n_are_flagged(ctx):
+    t = "qubits 3\nH 0\nCX 0 1\n"
+    prog = fhs.Program(t)
+    ctx.load(prog)
+    bad = torch.tensor([[0], [8], [3]], dtype=torch.int64, device="cuda:0")
+    for plain in (False, True):
+        amps, st = ctx.evaluate([0], [1], bad, plain=plain)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy().view(np.uint64)
+        assert st[1, 3] == np.uint64(0xFFFFFFFFFFFFFFFF)
+        assert amps[1].abs().sum().item() == 0.0
+        assert st[0, 3] != np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def test_deterministic_and_graph_replay(ctx):
+    cfg = w.CONFIGS["qaoa_12v_p2"]()
+    t = cfg["circuit"].to_text()
+    prog = fhs.Program(t)
+    ctx.load(prog)
+    ctx.set_partition(*prog.choose_partition(fhs.PART_EQ8))
+    outs = cfg["outputs"][:512]
+    d_in = ctx.device_bits([0])
+    d_out = ctx.device_bits(outs)
+    d_cf = ctx.device_coeffs([1])
+    amps = torch.empty((512, 2), dtype=torch.float64, device="cuda:0")
+    stats = torch.empty((512, 4), dtype=torch.int64, device="cuda:0")
+    first = None
+    for rep in range(4):
+        amps.fill_(float("nan"))
+        stats.fill_(-1)
+        ctx.evaluate(d_in, d_cf, d_out, threshold=0.0, out=(amps, stats))
+        torch.cuda.synchronize()
+        cur = (amps.cpu().numpy().copy(), stats.cpu().numpy().copy())
+        if first is None:
+            first = cur
+        assert np.array_equal(cur[0], first[0]) and np.array_equal(cur[1], first[1])
+    # a different threshold re-captures and still matches the oracle on a sample
+    ctx.evaluate(d_in, d_cf, d_out, threshold=1e-4, out=(amps, stats))
+    torch.cuda.synchronize()
+    ref = oracle.Feynman(t).evaluate([0], [1], outs[:4], threshold=1e-4,
+                                     partition=ctx.partition, threads=THREADS)
+    a = amps.cpu().numpy()[:4]
+    assert np.abs(a[:, 0] + 1j * a[:, 1] - ref[0]).max() <= TOL
+
+
+def test_errors(ctx):
+    t = w.amplitude_amplification(16, 3, 4, 301)[0].to_text()
+    prog = fhs.Program(t)
+    ctx.load(prog)
+    with pytest.raises(fhs.FhsError) as ei:
+        ctx.evaluate([0], [1], [0])
+    assert ei.value.status == 3          # A = 96 > 62
+    ctx.load(fhs.Program("qubits 2\nH 0\n"))
+    with pytest.raises(fhs.FhsError) as ei:
+        ctx.set_partition(1, 0)
+    assert ei.value.status == 1
+    with pytest.raises(fhs.FhsError) as ei:
+        ctx.evaluate([0], [1], [0], threshold=float("nan"))
+    assert ei.value.status == 1
+    with pytest.raises(fhs.FhsError) as ei:
+        ctx.evaluate([0], [1], [0], threshold=-1.0)
+    assert ei.value.status == 1
+    fresh = fhs.Context(0)
+    with pytest.raises(fhs.FhsError) as ei:
+        fresh.set_partition(0, 0)
+    assert ei.value.status == 6

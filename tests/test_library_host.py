@@ -1,0 +1,114 @@
+"""Host-side checks of the native library (no GPU needed).
+
+  * libfhs.so loads and exports every function include/fhs.h declares;
+  * the host reducer's placement (A, source positions, leading gates) and
+    Eq. (8) agree with the independent C oracle;
+  * argument and range errors come back as status codes.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_01467_amd as fhs
+import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fhs.h")).read()
+    return sorted(set(re.findall(r"\b(fhs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = fhs.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(fhs.EXPORTS)
+
+
+def _circuits():
+    yield "eq6", "qubits 3\nH 0\nCX 0 1\nS 1\nCX 1 2\n"
+    for seed in range(80):
+        n = [1, 3, 6, 12, 33, 64, 65, 100, 128][seed % 9]
+        yield f"mixed{seed}", w.random_mixed(n, 10 + seed % 30, 900 + seed, max_controls=5).to_text()
+    yield "qft12", w.qft(12).to_text()
+    yield "aa4", w.amplitude_amplification(4, 3, 4, 301)[0].to_text()
+    yield "aa16", w.amplitude_amplification(16, 3, 4, 301)[0].to_text()
+    yield "qaoa12", w.qaoa_maxcut(12, 2)[0].to_text()
+    yield "qaoa24", w.qaoa_maxcut(24, 2)[0].to_text()
+    yield "walk", w.quantum_walk(99, 20).to_text()
+
+
+@pytest.mark.parametrize("name,text", list(_circuits()), ids=[c[0] for c in _circuits()])
+def test_reducer_matches_oracle_placement(name, text):
+    p = fhs.Program(text)
+    o = oracle.Feynman(text)
+    assert (p.n, p.G, p.A) == (o.n, o.G, o.A)
+    assert p.source_eval_positions == o.source_eval_positions
+    assert p.L == (o.source_eval_positions[0] if o.A else o.G)
+    rng = np.random.default_rng(len(text))
+    for _ in range(20):
+        c1, c2 = sorted(int(x) for x in rng.integers(0, p.G + 1, size=2))
+        cost, reg = p.partition_cost(c1, c2)
+        assert cost == o.eq8(c1, c2)
+        assert reg[:3] == (c1, c2 - c1, p.G - c2)
+        assert reg[3:] == o.region_sources(c1, c2)
+    if p.G <= 1500:
+        c1, c2, cost = o.eq8_argmin()
+        assert p.choose_partition(fhs.PART_EQ8) == (c1, c2)
+        assert p.partition_cost(c1, c2)[0] == cost
+    assert p.choose_partition(fhs.PART_THIRDS) == (p.G // 3, 2 * p.G // 3)
+    assert p.choose_partition(fhs.PART_NONE) == (0, 0)
+
+
+def test_walk_eq8_argmin_matches_oracle():
+    t = w.quantum_walk(99, 20).to_text()
+    p, o = fhs.Program(t), oracle.Feynman(t)
+    c1, c2, cost = o.eq8_argmin()
+    assert p.choose_partition(fhs.PART_EQ8) == (c1, c2)
+    assert p.partition_cost(c1, c2)[0] == cost
+    assert cost < p.partition_cost(0, 0)[0] // 6
+
+
+@pytest.mark.parametrize("text,status", [
+    ("", 7),
+    ("H 0\n", 7),
+    ("qubits 0\n", 3),
+    ("qubits 129\n", 3),
+    ("qubits 2\nH 2\n", 3),
+    ("qubits 2\nFOO 0\n", 2),
+    ("qubits 2\nRX 0\n", 7),
+    ("qubits 2\nH 0 0x1p+0\n", 7),
+    ("qubits 2\nCX 0 0\n", 7),
+    ("qubits 2\nCX ~0 1\n", 7),
+    ("qubits 2\nMCX ~0 1\n", 7),
+    ("qubits 2\nRX 0 nan\n", 7),
+    ("qubits 2\nqubits 2\n", 7),
+])
+def test_reduce_errors(text, status):
+    with pytest.raises(fhs.FhsError) as ei:
+        fhs.Program(text)
+    assert ei.value.status == status
+
+
+def test_partition_cost_errors_and_large_A():
+    p = fhs.Program(w.amplitude_amplification(16, 3, 4, 301)[0].to_text())
+    assert p.A == 96
+    assert p.partition_cost(0, 0)[0] == (2 ** 96) * p.G      # needs 128 bits
+    with pytest.raises(fhs.FhsError) as ei:
+        p.partition_cost(5, 4)
+    assert ei.value.status == 1
+    with pytest.raises(fhs.FhsError):
+        p.partition_cost(0, p.G + 1)
+
+
+def test_empty_circuit():
+    p = fhs.Program("qubits 5\n")
+    assert (p.G, p.A, p.L) == (0, 0, 0)
+    assert p.partition_cost(0, 0)[0] == 0

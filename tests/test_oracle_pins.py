@@ -244,6 +244,7 @@ def test_walk_closed_form_oracle(n_pos, steps):
         for (x, c), a, s in zip(keys, amps, st):
             assert abs(a - dp.get((x, c), 0)) <= 1e-12
             assert int(s[0]) == cf.walk_n_valid(steps, x, c)
+            assert tuple(int(v) for v in s[:3]) == cf.walk_valid_stats(steps, x, c)
             norm += abs(a) ** 2
         assert abs(norm - 1.0) <= 1e-12
 
