@@ -124,6 +124,27 @@ fhs_status fhs_get_partition(const fhs_ctx *ctx, uint32_t *c1, uint32_t *c2);
  * fit.  Minimum 1 MiB. */
 fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
 
+/* Launch shape of the hot kernels (the tile/chunk autotuner's search space;
+ * the paper's execution model, Section IV-D, leaves it to the platform).
+ * Zero fields mean "default".
+ *   histories_per_lane  1 or 2: independent histories each lane walks in
+ *                       lockstep through one decoded instruction stream
+ *                       (default 2);
+ *   chunk               prefix entries per work item of the persistent
+ *                       consumer, a power of two in [1, 256] (default 256);
+ *   blocks_per_cu       persistent workgroups per compute unit, at most the
+ *                       occupancy limit (default: the occupancy limit).
+ * Affects speed and the grouping of the amplitude sums (so their last bits),
+ * never the history counts.  FHS_EINVAL for values out of range. */
+typedef struct {
+    uint32_t histories_per_lane;
+    uint32_t chunk;
+    uint32_t blocks_per_cu;
+} fhs_launch_config;
+
+fhs_status fhs_set_launch_config(fhs_ctx *ctx, const fhs_launch_config *cfg);
+fhs_status fhs_get_launch_config(const fhs_ctx *ctx, fhs_launch_config *cfg);
+
 /* Bytes of device workspace fhs_evaluate / fhs_evaluate_plain need for M
  * outputs and S inputs under the current program and partition. */
 fhs_status fhs_workspace_size(const fhs_ctx *ctx, uint32_t M, uint32_t S, size_t *bytes);

@@ -33,7 +33,7 @@ EXPORTS = [
     "fhs_program_sources", "fhs_partition_cost", "fhs_choose_partition", "fhs_ctx_create",
     "fhs_ctx_destroy", "fhs_last_error", "fhs_load_program", "fhs_set_partition",
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
-    "fhs_evaluate_plain",
+    "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
 ]
 
 
@@ -47,6 +47,11 @@ class ProgramInfo(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("n_gates", ctypes.c_uint32),
                 ("n_sources", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
                 ("n_leading", ctypes.c_uint32), ("n_branch", ctypes.c_uint32)]
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("histories_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32)]
 
 
 _lib = None
@@ -81,6 +86,8 @@ def lib() -> ctypes.CDLL:
         L.fhs_get_partition.argtypes = [P, pU32, pU32]
         L.fhs_set_table_budget.argtypes = [P, ctypes.c_size_t]
         L.fhs_workspace_size.argtypes = [P, U32, U32, ctypes.POINTER(ctypes.c_size_t)]
+        L.fhs_set_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
+        L.fhs_get_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         ev = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P, ctypes.c_size_t, P]
         L.fhs_evaluate.argtypes = ev
         L.fhs_evaluate_plain.argtypes = ev
@@ -183,6 +190,17 @@ class Context:
         c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
         _check(lib().fhs_get_partition(self._h, ctypes.byref(c1), ctypes.byref(c2)), self)
         return c1.value, c2.value
+
+    def set_launch_config(self, histories_per_lane: int = 0, chunk: int = 0,
+                          blocks_per_cu: int = 0) -> None:
+        cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu)
+        _check(lib().fhs_set_launch_config(self._h, ctypes.byref(cfg)), self)
+
+    @property
+    def launch_config(self) -> Tuple[int, int, int]:
+        cfg = LaunchConfig()
+        _check(lib().fhs_get_launch_config(self._h, ctypes.byref(cfg)), self)
+        return cfg.histories_per_lane, cfg.chunk, cfg.blocks_per_cu
 
     def set_table_budget(self, nbytes: int) -> None:
         _check(lib().fhs_set_table_budget(self._h, nbytes), self)

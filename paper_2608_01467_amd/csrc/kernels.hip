@@ -22,10 +22,32 @@
 //   k_pair_reduce / k_finalize: fixed-order sums, then Eq. (2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace fhs {
 namespace {
+
+// The program is read through the constant address space: it is never
+// written while a kernel runs, which lets every instruction field arrive by
+// scalar load even in kernels that store to global memory.
+// (The host compilation pass only parses device code; it gets the plain type.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using Const = const __attribute__((address_space(4))) T;
+#else
+template <class T>
+using Const = const T;
+#endif
+using ConstInstr = Const<Instr>;
+
+// Read-only kernel inputs (masks, bitstrings) through the constant address
+// space, so uniform reads become scalar loads.
+template <class T>
+__device__ __forceinline__ T ld_const(const T *p, size_t i) {
+    return ((Const<T> *)p)[i];
+}
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     // SplitMix64 finaliser (Steele, Lea, Flood 2014)
@@ -36,26 +58,53 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 // State words are only ever indexed with compile-time constants (the word
 // holding a gate's bit is part of its opcode), so the state stays in VGPRs.
+// H independent histories per lane share every decoded instruction.
 template <int W, int NW>
 __device__ __forceinline__ constexpr int wsel() {
     return W < NW ? W : 0;
 }
 
-template <int NW>
-__device__ __forceinline__ bool matches(const uint32_t (&s)[NW], const Instr &I) {
-    uint32_t acc = (s[0] ^ I.cv[0]) & I.cm[0];
-#pragma unroll
-    for (int j = 1; j < NW; ++j)
-        if (I.cm[j] != 0u) acc |= (s[j] ^ I.cv[j]) & I.cm[j];
-    return acc == 0u;
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// f(IC<0>), ..., f(IC<N-1>): compile-time unrolling, so that register arrays
+// are never indexed with a runtime value.
+template <class F, int... I>
+__device__ __forceinline__ void unroll_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(IC<I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F &&f) {
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Call f(IC<w>) for the uniform word index w < NW.
+template <int NW, class F>
+__device__ __forceinline__ void with_word(uint32_t w, F &&f) {
+    if constexpr (NW == 1) {
+        f(IC<0>{});
+    } else if constexpr (NW == 2) {
+        if (w == 0u) f(IC<0>{});
+        else f(IC<1>{});
+    } else {
+        if (w < 2u) {
+            if (w == 0u) f(IC<0>{});
+            else f(IC<1>{});
+        } else {
+            if (w == 2u) f(IC<2>{});
+            else f(IC<3>{});
+        }
+    }
 }
 
 template <int NW>
 __device__ __forceinline__ bool check_final(const uint32_t (&s)[NW], const uint32_t (&bin)[NW],
                                             const Mask4 &m) {
     uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) acc |= (s[j] ^ bin[j]) & m.w[j];
+    unroll<NW>([&](auto jj) {
+        constexpr int j = jj.value;
+        acc |= (s[j] ^ bin[j]) & m.w[j];
+    });
     return acc == 0;
 }
 
@@ -72,8 +121,8 @@ template <int NW>
 __device__ __forceinline__ bool load_bits(const uint64_t *src, uint32_t W, uint32_t n,
                                           uint32_t (&s)[NW]) {
     bool bad = false;
-    uint64_t w0 = src[0];
-    uint64_t w1 = W > 1 ? src[1] : 0;
+    uint64_t w0 = ld_const(src, 0);
+    uint64_t w1 = W > 1 ? ld_const(src, 1) : 0;
     if (n < 64) bad = (w0 >> n) != 0;
     else if (n < 128 && W > 1) bad = (w1 >> (n - 64)) != 0;
     s[0] = static_cast<uint32_t>(w0);
@@ -85,157 +134,234 @@ __device__ __forceinline__ bool load_bits(const uint64_t *src, uint32_t W, uint3
     return bad;
 }
 
-// 4-way select of a complex table entry fac[2x], fac[2x+1].
-__device__ __forceinline__ void pick4(const double *f, uint32_t x, double &fr, double &fi) {
-    const double a0 = f[0], a1 = f[1], b0 = f[2], b1 = f[3];
-    const double c0 = f[4], c1 = f[5], d0 = f[6], d1 = f[7];
-    fr = (x & 2u) ? ((x & 1u) ? d0 : c0) : ((x & 1u) ? b0 : a0);
-    fi = (x & 2u) ? ((x & 1u) ? d1 : c1) : ((x & 1u) ? b1 : a1);
-}
+// Per-history registers of H histories.
+template <int NW, int H>
+struct Lanes {
+    uint32_t s[H][NW];
+    double re[H], im[H], M[H];
+    bool ok[H];
+    uint64_t hb[H];     // this region's source bits, per history
+};
 
-template <int NW, int WA>
-__device__ __forceinline__ void op_perm(uint32_t (&s)[NW], const Instr &I) {
-    constexpr int A = wsel<WA, NW>();
-    const bool m = matches<NW>(s, I);
-    const uint32_t bm = 1u << (I.a & 31u);
-    s[A] ^= m ? bm : 0u;
-}
-
-template <int NW, int WA, int WB>
-__device__ __forceinline__ void op_swap(uint32_t (&s)[NW], const Instr &I) {
-    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
-    const bool m = matches<NW>(s, I);
-    const uint32_t sa = I.a & 31u, sb = I.b & 31u;
-    const uint32_t d = (((s[A] >> sa) ^ (s[B] >> sb)) & 1u) & (m ? 1u : 0u);
-    s[A] ^= d << sa;
-    s[B] ^= d << sb;
-}
-
-template <int NW, int WA>
-__device__ __forceinline__ void op_det1(uint32_t (&s)[NW], const Instr &I, const double *fac,
-                                        double &re, double &im) {
-    constexpr int A = wsel<WA, NW>();
-    const uint32_t o = (s[A] >> (I.a & 31u)) & 1u;
-    const double *f = fac + I.fac;
-    const double f0r = f[0], f0i = f[1], f1r = f[2], f1i = f[3];
-    cmul(re, im, o ? f1r : f0r, o ? f1i : f0i);
-    s[A] ^= 1u << (I.a & 31u);
-}
-
-template <int NW, int WA>
-__device__ __forceinline__ void op_diag1(const uint32_t (&s)[NW], const Instr &I, const double *fac,
-                                         double &re, double &im) {
-    constexpr int A = wsel<WA, NW>();
-    const uint32_t o = (s[A] >> (I.a & 31u)) & 1u;
-    const double *f = fac + I.fac;
-    const double f0r = f[0], f0i = f[1], f1r = f[2], f1i = f[3];
-    cmul(re, im, o ? f1r : f0r, o ? f1i : f0i);
-}
-
-template <int NW, int WA, int WB>
-__device__ __forceinline__ void op_diag2(const uint32_t (&s)[NW], const Instr &I, const double *fac,
-                                         double &re, double &im) {
-    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
-    const uint32_t x = ((s[A] >> (I.a & 31u)) & 1u) | (((s[B] >> (I.b & 31u)) & 1u) << 1);
-    double fr, fi;
-    pick4(fac + I.fac, x, fr, fi);
-    cmul(re, im, fr, fi);
-}
-
-template <int NW, bool PRUNE, int WA, bool SRC>
-__device__ __forceinline__ void op_branch(uint32_t (&s)[NW], const Instr &I, const double *fac,
-                                          double &re, double &im, double &M, bool &ok,
-                                          uint64_t hb, uint32_t kbase, const uint32_t (&bin)[NW],
-                                          double thr) {
-    constexpr int A = wsel<WA, NW>();
-    const uint32_t sh = I.a & 31u;
-    const uint32_t o = (s[A] >> sh) & 1u;
-    const uint32_t i = SRC ? static_cast<uint32_t>((hb >> (I.k - kbase)) & 1u)
-                           : (bin[A] >> sh) & 1u;
-    const uint32_t x = 2u * o + i;
-    const double *f = fac + I.fac;
-    double fr, fi;
-    pick4(f, x, fr, fi);
-    cmul(re, im, fr, fi);
-    if (PRUNE) {
-        const double m0 = f[8], m1 = f[9], m2 = f[10], m3 = f[11];
-        const double md = (x & 2u) ? ((x & 1u) ? m3 : m2) : ((x & 1u) ? m1 : m0);
-        M = M * md;
-        ok = ok && !(M < thr);
+// Factor tables: `fac` points at the slice [lo, ...) of the global table,
+// staged in LDS by the hot kernels; entries are read per lane.
+struct FacRef {
+    const double *p;
+    uint32_t lo;
+    __device__ __forceinline__ double2 c(uint32_t off) const {
+        return *reinterpret_cast<const double2 *>(p + (off - lo));
     }
-    ok = ok && !((I.zmask >> x) & 1u);
-    s[A] ^= (o ^ i) << sh;
+    __device__ __forceinline__ double d(uint32_t off) const { return p[off - lo]; }
+};
+
+__device__ __forceinline__ uint32_t hdr_a(const Instr &I) { return (I.hdr >> 8) & 0xffu; }
+__device__ __forceinline__ uint32_t hdr_b(const Instr &I) { return (I.hdr >> 16) & 0xffu; }
+__device__ __forceinline__ uint32_t hdr_z(const Instr &I) { return I.hdr >> 24; }
+
+template <int NW, int H, int TW, int LW>
+__device__ __forceinline__ void op_perm(Lanes<NW, H> &L, const Instr &I) {
+    constexpr int T = wsel<TW, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        L.s[h][T] ^= (acc == 0u) ? I.k : 0u;
+    });
 }
 
-// Walk evaluation positions [e0, e1) of the history program backward from
-// the state s.  hb holds this region's source bits: source k reads bit
-// (k - kbase).  bin is the input bitstring.
-template <int NW, bool PRUNE>
-__device__ __forceinline__ void run_region(const Common &c, uint32_t e0, uint32_t e1,
-                                           uint32_t (&s)[NW], double &re, double &im, double &M,
-                                           bool &ok, uint64_t hb, uint32_t kbase,
-                                           const uint32_t (&bin)[NW]) {
-    const Instr *__restrict__ prog = c.prog;
-    const double *__restrict__ fac = c.fac;
-    const double thr = c.thr;
-    for (uint32_t e = e0; e < e1; ++e) {
-        const Instr I = prog[e];
-        switch (I.op) {
-#define FHS_A_CASES(WA)                                                                      \
-    case OP_PERM | ((WA) << 4): op_perm<NW, WA>(s, I); break;                                \
-    case OP_DET1 | ((WA) << 4): op_det1<NW, WA>(s, I, fac, re, im); break;                   \
-    case OP_DIAG1 | ((WA) << 4): op_diag1<NW, WA>(s, I, fac, re, im); break;                 \
-    case OP_BRANCH_SRC | ((WA) << 4):                                                        \
-        op_branch<NW, PRUNE, WA, true>(s, I, fac, re, im, M, ok, hb, kbase, bin, thr); break; \
-    case OP_BRANCH_NAT | ((WA) << 4):                                                        \
-        op_branch<NW, PRUNE, WA, false>(s, I, fac, re, im, M, ok, hb, kbase, bin, thr); break;
-#define FHS_AB_CASES(WA, WB)                                                                 \
-    case OP_SWAP | ((WA) << 4) | ((WB) << 6): op_swap<NW, WA, WB>(s, I); break;              \
-    case OP_DIAG2 | ((WA) << 4) | ((WB) << 6): op_diag2<NW, WA, WB>(s, I, fac, re, im); break;
-            FHS_A_CASES(0)
-            FHS_AB_CASES(0, 0)
+template <int NW, int H, int LW>
+__device__ __forceinline__ void op_mcphase(Lanes<NW, H> &L, const Instr &I) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const bool m = acc == 0u;
+        L.re[h] = m ? -L.re[h] : L.re[h];
+        L.im[h] = m ? -L.im[h] : L.im[h];
+    });
+}
+
+template <int NW, int H, int WA, int WB>
+__device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = 0;
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const uint32_t d = (((L.s[h][A] >> sa) ^ (L.s[h][B] >> sb)) & 1u) & (acc == 0u ? 1u : 0u);
+        L.s[h][A] ^= d << sa;
+        L.s[h][B] ^= d << sb;
+    });
+}
+
+template <int NW, int H, int WA>
+__device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const double2 f = F.c(I.fac + 2u * o);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+        L.s[h][A] ^= 1u << sh;
+    });
+}
+
+template <int NW, int H, int WA>
+__device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const double2 f = F.c(I.fac + 2u * o);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+    });
+}
+
+template <int NW, int H, int WA, int WB>
+__device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t x = ((L.s[h][A] >> sa) & 1u) | (((L.s[h][B] >> sb) & 1u) << 1);
+        const double2 f = F.c(I.fac + 2u * x);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+    });
+}
+
+template <int NW, int H, bool PRUNE, int WA, bool SRC>
+__device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const FacRef &F,
+                                          uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    const uint32_t ks = I.k - kbase;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const uint32_t i = SRC ? static_cast<uint32_t>((L.hb[h] >> ks) & 1u) : (bin[A] >> sh) & 1u;
+        const uint32_t x = 2u * o + i;
+        const double2 f = F.c(I.fac + 2u * x);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+        if (PRUNE) {
+            L.M[h] = L.M[h] * F.d(I.fac + 8u + x);
+            L.ok[h] = L.ok[h] && !(L.M[h] < thr);
+        }
+        L.ok[h] = L.ok[h] && !((hdr_z(I) >> x) & 1u);
+        L.s[h][A] ^= (o ^ i) << sh;
+    });
+}
+
+// Walk evaluation positions [e0, e1) of the history program backward for H
+// histories at once.  Source k of history h reads bit (k - kbase) of hb[h];
+// bin is the input bitstring (the same for every history of a lane).  The
+// opcode is dispatched once per run of identical opcodes; the case loops
+// over the run.
+template <int NW, int H, bool PRUNE>
+__device__ __forceinline__ void run_region(const Instr *prog_generic, const FacRef &F,
+                                           uint32_t e0, uint32_t e1, Lanes<NW, H> &L,
+                                           uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
+    ConstInstr *prog = (ConstInstr *)prog_generic;
+    uint32_t e = e0;
+    while (e < e1) {
+        const uint32_t op = prog[e].hdr & 0xffu;
+        const uint32_t n = min(prog[e].run, e1 - e);
+        const uint32_t end = e + n;
+        const uint32_t w1 = (op >> 4) & 3u, w2 = (op >> 6) & 3u;
+        switch (op & 15u) {
+            case OP_PERM:
+                with_word<NW>(w1, [&](auto TW) {
+                    with_word<NW>(w2, [&](auto LW) {
+                        for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                            op_perm<NW, H, TW.value, LW.value>(L, I);
+                        }
+                    });
+                });
+                break;
+            case OP_BRANCH_SRC:
+                with_word<NW>(w1, [&](auto WA) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_branch<NW, H, PRUNE, WA.value, true>(L, I, F, kbase, bin, thr);
+                    }
+                });
+                break;
+            case OP_BRANCH_NAT:
+                with_word<NW>(w1, [&](auto WA) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_branch<NW, H, PRUNE, WA.value, false>(L, I, F, kbase, bin, thr);
+                    }
+                });
+                break;
+            case OP_DIAG2:
+                with_word<NW>(w1, [&](auto WA) {
+                    with_word<NW>(w2, [&](auto WB) {
+                        for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                            op_diag2<NW, H, WA.value, WB.value>(L, I, F);
+                        }
+                    });
+                });
+                break;
+            case OP_DIAG1:
+                with_word<NW>(w1, [&](auto WA) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_diag1<NW, H, WA.value>(L, I, F);
+                    }
+                });
+                break;
             case OP_MCPHASE:
-                if (matches<NW>(s, I)) {
-                    re = -re;
-                    im = -im;
-                }
+                with_word<NW>(w1, [&](auto LW) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_mcphase<NW, H, LW.value>(L, I);
+                    }
+                });
+                break;
+            case OP_SWAP:
+                with_word<NW>(w1, [&](auto WA) {
+                    with_word<NW>(w2, [&](auto WB) {
+                        for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                            op_swap<NW, H, WA.value, WB.value>(L, I);
+                        }
+                    });
+                });
+                break;
+            case OP_DET1:
+                with_word<NW>(w1, [&](auto WA) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_det1<NW, H, WA.value>(L, I, F);
+                    }
+                });
                 break;
             default:
-                if constexpr (NW >= 2) {
-                    switch (I.op) {
-                        FHS_A_CASES(1)
-                        FHS_AB_CASES(0, 1)
-                        FHS_AB_CASES(1, 0)
-                        FHS_AB_CASES(1, 1)
-                        default:
-                            if constexpr (NW == 4) {
-                                switch (I.op) {
-                                    FHS_A_CASES(2)
-                                    FHS_A_CASES(3)
-                                    FHS_AB_CASES(0, 2)
-                                    FHS_AB_CASES(0, 3)
-                                    FHS_AB_CASES(1, 2)
-                                    FHS_AB_CASES(1, 3)
-                                    FHS_AB_CASES(2, 0)
-                                    FHS_AB_CASES(2, 1)
-                                    FHS_AB_CASES(2, 2)
-                                    FHS_AB_CASES(2, 3)
-                                    FHS_AB_CASES(3, 0)
-                                    FHS_AB_CASES(3, 1)
-                                    FHS_AB_CASES(3, 2)
-                                    FHS_AB_CASES(3, 3)
-                                    default:
-                                        break;
-                                }
-                            }
-                            break;
-                    }
-                }
                 break;
-#undef FHS_A_CASES
-#undef FHS_AB_CASES
         }
+        e = end;
     }
+}
+
+// Copy the factor slice [lo, hi) of the global table into LDS.
+__device__ __forceinline__ void stage_factors(double *lds, const double *fac, uint32_t lo,
+                                              uint32_t hi) {
+    for (uint32_t i = threadIdx.x; i < hi - lo; i += blockDim.x) lds[i] = fac[lo + i];
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -296,54 +422,73 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     if (p < n_zero) zero_words[p] = 0u;
     if (p >= P) return;
     const uint32_t j = p / c.S, i = p % c.S;
-    uint32_t s[NW], bin[NW];
-    const bool bad_o = load_bits<NW>(c.outputs + static_cast<size_t>(j) * c.W, c.W, c.n, s);
+    Lanes<NW, 1> L;
+    uint32_t bin[NW];
+    const bool bad_o = load_bits<NW>(c.outputs + static_cast<size_t>(j) * c.W, c.W, c.n, L.s[0]);
     const bool bad_i = load_bits<NW>(c.inputs + static_cast<size_t>(i) * c.W, c.W, c.n, bin);
-    double re = 1.0, im = 0.0, M = 1.0;
-    bool ok = !(bad_o || bad_i);
-    run_region<NW, PRUNE>(c, 0, c.L, s, re, im, M, ok, 0, 0, bin);
-    ok = ok && check_final<NW>(s, bin, c.fin[c.L]);
+    L.re[0] = 1.0;
+    L.im[0] = 0.0;
+    L.M[0] = 1.0;
+    L.ok[0] = !(bad_o || bad_i);
+    L.hb[0] = 0;
+    const FacRef F{c.fac, 0u};
+    run_region<NW, 1, PRUNE>(c.prog, F, 0, c.L, L, 0, bin, c.thr);
+    const bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
 #pragma unroll
-    for (int w = 0; w < NW; ++w) pre.st[static_cast<size_t>(w) * P + p] = s[w];
-    pre.amp[p] = make_double2(re, im);
-    pre.M[p] = M;
+    for (int w = 0; w < NW; ++w) pre.st[static_cast<size_t>(w) * P + p] = L.s[0][w];
+    pre.amp[p] = make_double2(L.re[0], L.im[0]);
+    pre.M[p] = L.M[0];
     pre.ok[p] = (ok ? 1u : 0u) | ((bad_o || bad_i) ? 2u : 0u);
 }
 
-template <int NW, bool PRUNE>
+template <int NW, bool PRUNE, bool FLDS>
 __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab, uint32_t p0,
                                                 uint32_t B, uint32_t P) {
+    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
+    FacRef F{c.fac, 0u};
+    if constexpr (FLDS) {
+        stage_factors(l_fac, c.fac, c.f_L, c.f_c1);
+        F = FacRef{l_fac, c.f_L};
+    }
     const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
     const uint64_t hmask = (1ull << c.Ap) - 1ull;
-    for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < E;
-         e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const Mask4 fin_c1 = ld_const(c.fin, c.c1);
+    for (uint64_t eb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; eb < E;
+         eb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t e_raw = eb + threadIdx.x;
+        const bool live = e_raw < E;
+        const uint64_t e = live ? e_raw : E - 1;   // clamp so every lane reads in bounds
         const uint32_t p = p0 + static_cast<uint32_t>(e >> c.Ap);
-        const uint64_t hp = e & hmask;
-        uint32_t s[NW], bin[NW];
+        Lanes<NW, 1> L;
+        uint32_t bin[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) s[w] = pre.st[static_cast<size_t>(w) * P + p];
+        for (int w = 0; w < NW; ++w) L.s[0][w] = pre.st[static_cast<size_t>(w) * P + p];
         load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
         const double2 a = pre.amp[p];
-        double re = a.x, im = a.y, M = pre.M[p];
-        bool ok = pre.ok[p] == 1u;
-        if (ok) {
-            run_region<NW, PRUNE>(c, c.L, c.c1, s, re, im, M, ok, hp, 0, bin);
-            ok = ok && check_final<NW>(s, bin, c.fin[c.c1]);
-        }
+        L.re[0] = a.x;
+        L.im[0] = a.y;
+        L.M[0] = pre.M[p];
+        L.ok[0] = pre.ok[p] == 1u;
+        L.hb[0] = e & hmask;
+        run_region<NW, 1, PRUNE>(c.prog, F, c.L, c.c1, L, 0, bin, c.thr);
+        L.ok[0] = L.ok[0] && check_final<NW>(L.s[0], bin, fin_c1);
+        if (live) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = s[w];
-        tab.beta[e] = make_double2(re, im);
-        if (PRUNE) tab.M[e] = M;
-        tab.ok[e] = ok ? 1u : 0u;
+            for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = L.s[0][w];
+            tab.beta[e] = make_double2(L.re[0], L.im[0]);
+            if (PRUNE) tab.M[e] = L.M[0];
+            tab.ok[e] = L.ok[0] ? 1u : 0u;
+        }
     }
 }
 
-template <int NW, bool PRUNE>
+template <int NW, int H, bool PRUNE, bool FLDS>
 __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab, Partials part,
                                                              uint32_t p0, uint32_t B,
                                                              uint32_t chunk, uint32_t ss,
                                                              uint32_t *counter) {
     constexpr int NT = kConsumeThreads;
+    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
     __shared__ uint32_t s_item;
     __shared__ uint32_t l_st[NW][kMaxChunk];
     __shared__ double2 l_beta[kMaxChunk];
@@ -352,6 +497,11 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
     __shared__ uint32_t l_wcount[NT / 64];
     __shared__ Acc l_red[NT / 64];
 
+    FacRef F{c.fac, 0u};
+    if constexpr (FLDS) {
+        stage_factors(l_fac, c.fac, c.f_c1, c.f_G);
+        F = FacRef{l_fac, c.f_c1};
+    }
     const uint32_t per_pair = 1u << c.Ap;
     const uint32_t nchunks = (per_pair + chunk - 1) / chunk;
     const uint32_t n_items = B * nchunks;
@@ -360,6 +510,8 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
     const uint32_t rmask = (1u << c.Ar) - 1u;
     const uint32_t smask = (1u << ss) - 1u;
     const uint64_t n_suffix = 1ull << (c.As - ss);   // suffix assignments per task
+    const uint32_t sshift = c.Ap + c.Ar;
+    const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
 
     for (;;) {
         if (t == 0) s_item = atomicAdd(counter, 1u);
@@ -409,51 +561,70 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
         load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
         Acc acc{0.0, 0.0, 0, 0, 0, 0};
         const uint64_t ntask = static_cast<uint64_t>(nv) << (c.Ar + ss);
-        for (uint64_t task = t; task < ntask; task += NT) {
-            const uint32_t jx = static_cast<uint32_t>(task >> (c.Ar + ss));
-            const uint32_t hr = static_cast<uint32_t>(task >> ss) & rmask;
-            const uint64_t hs0 = static_cast<uint64_t>(task & smask) * n_suffix;
-            uint32_t s[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) s[w] = l_st[w][jx];
-            const double2 b = l_beta[jx];
-            double re = b.x, im = b.y, M = l_M[jx];
-            bool ok = true;
-            run_region<NW, PRUNE>(c, c.c1, c.c2, s, re, im, M, ok, hr, c.Ap, bin);
-            ok = ok && check_final<NW>(s, bin, c.fin[c.c2]);
-            if (ok) {
-                const uint64_t hbase = static_cast<uint64_t>(l_hp[jx]) |
-                                       (static_cast<uint64_t>(hr) << c.Ap);
-                for (uint64_t hs = hs0; hs < hs0 + n_suffix; ++hs) {
-                    uint32_t s2[NW];
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) s2[w] = s[w];
-                    double re2 = re, im2 = im, M2 = M;
-                    bool ok2 = true;
-                    run_region<NW, PRUNE>(c, c.c2, c.G, s2, re2, im2, M2, ok2, hs, c.Ap + c.Ar, bin);
-                    ok2 = ok2 && check_final<NW>(s2, bin, c.fin[c.G]);
-                    acc.leaves += 1;
+        // uniform loop bounds: the program counter inside stays wave-uniform
+        for (uint64_t tb = 0; tb < ntask; tb += static_cast<uint64_t>(H) * NT) {
+            Lanes<NW, H> R;
+            uint64_t hbase[H], hs0[H];
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                const uint64_t task = tb + t + static_cast<uint64_t>(j) * NT;
+                const bool valid = task < ntask;
+                const uint32_t jx = valid ? static_cast<uint32_t>(task >> (c.Ar + ss)) : 0u;
+                const uint32_t hr = static_cast<uint32_t>(task >> ss) & rmask;
+                hs0[j] = static_cast<uint64_t>(task & smask) * n_suffix;
+                unroll<NW>([&](auto ww) { R.s[j][ww.value] = l_st[ww.value][jx]; });
+                const double2 b = l_beta[jx];
+                R.re[j] = b.x;
+                R.im[j] = b.y;
+                R.M[j] = l_M[jx];
+                R.ok[j] = valid;
+                R.hb[j] = hr;
+                hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
+            });
+            run_region<NW, H, PRUNE>(c.prog, F, c.c1, c.c2, R, c.Ap, bin, c.thr);
+            bool any = false;
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                R.ok[j] = R.ok[j] && check_final<NW>(R.s[j], bin, fin_c2);
+                any = any || R.ok[j];
+            });
+            if (!__any(any)) continue;   // wave-uniform skip
+            for (uint64_t q = 0; q < n_suffix; ++q) {
+                Lanes<NW, H> S2 = R;
+                unroll<H>([&](auto jj) { S2.hb[jj.value] = hs0[jj.value] + q; });
+                run_region<NW, H, PRUNE>(c.prog, F, c.c2, c.G, S2, sshift, bin, c.thr);
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
+                    acc.leaves += R.ok[j] ? 1u : 0u;
                     if (ok2) {
-                        const uint64_t h = hbase | (hs << (c.Ap + c.Ar));
-                        acc.re += re2;
-                        acc.im += im2;
+                        const uint64_t h = hbase[j] | ((hs0[j] + q) << sshift);
+                        acc.re += S2.re[j];
+                        acc.im += S2.im[j];
                         acc.nval += 1;
                         acc.sumh += h;
                         acc.xorh ^= mix64(h);
                     }
-                }
+                });
             }
         }
         block_reduce_store<NT>(acc, l_red, part, item);
     }
 }
 
-template <int NW, bool PRUNE>
+template <int NW, int H, bool PRUNE, bool FLDS>
 __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, Partials part,
                                                          uint32_t P, uint32_t bpp) {
     constexpr int NT = kPlainThreads;
+    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
     __shared__ Acc l_red[NT / 64];
+    FacRef F{c.fac, 0u};
+    if constexpr (FLDS) {
+        stage_factors(l_fac, c.fac, c.f_L, c.f_G);
+        F = FacRef{l_fac, c.f_L};
+    }
     const uint32_t p = blockIdx.x / bpp, b = blockIdx.x - p * bpp;
+    const Mask4 fin_G = ld_const(c.fin, c.G);
     Acc acc{0.0, 0.0, 0, 0, 0, 0};
     if (pre.ok[p] == 1u) {
         uint32_t s0[NW], bin[NW];
@@ -463,23 +634,33 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
         const double2 a = pre.amp[p];
         const double M0 = pre.M[p];
         const uint64_t NH = 1ull << c.A;
-        for (uint64_t h = static_cast<uint64_t>(b) * NT + threadIdx.x; h < NH;
-             h += static_cast<uint64_t>(bpp) * NT) {
-            uint32_t s[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) s[w] = s0[w];
-            double re = a.x, im = a.y, M = M0;
-            bool ok = true;
-            run_region<NW, PRUNE>(c, c.L, c.G, s, re, im, M, ok, h, 0, bin);
-            ok = ok && check_final<NW>(s, bin, c.fin[c.G]);
-            acc.leaves += 1;
-            if (ok) {
-                acc.re += re;
-                acc.im += im;
-                acc.nval += 1;
-                acc.sumh += h;
-                acc.xorh ^= mix64(h);
-            }
+        const uint64_t stride = static_cast<uint64_t>(bpp) * NT;
+        for (uint64_t hb0 = static_cast<uint64_t>(b) * NT; hb0 < NH; hb0 += H * stride) {
+            const uint64_t h0 = hb0 + threadIdx.x;
+            Lanes<NW, H> L;
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                unroll<NW>([&](auto ww) { L.s[j][ww.value] = s0[ww.value]; });
+                L.re[j] = a.x;
+                L.im[j] = a.y;
+                L.M[j] = M0;
+                L.hb[j] = h0 + j * stride;
+                L.ok[j] = L.hb[j] < NH;
+            });
+            run_region<NW, H, PRUNE>(c.prog, F, c.L, c.G, L, 0, bin, c.thr);
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                const bool inrange = L.hb[j] < NH;
+                const bool ok = L.ok[j] && check_final<NW>(L.s[j], bin, fin_G);
+                acc.leaves += inrange ? 1u : 0u;
+                if (ok) {
+                    acc.re += L.re[j];
+                    acc.im += L.im[j];
+                    acc.nval += 1;
+                    acc.sumh += L.hb[j];
+                    acc.xorh ^= mix64(L.hb[j]);
+                }
+            });
         }
     }
     block_reduce_store<NT>(acc, l_red, part, blockIdx.x);
@@ -558,27 +739,39 @@ __global__ void k_finalize(PairRes res, const double *coeffs, uint32_t S, uint32
 // launchers
 // ---------------------------------------------------------------------------
 
-#define FHS_DISPATCH(NWV, PR, ...)                                              \
-    do {                                                                        \
-        if ((NWV) == 1) {                                                       \
-            if (PR) { constexpr int NW_ = 1; constexpr bool PR_ = true; __VA_ARGS__; }  \
-            else { constexpr int NW_ = 1; constexpr bool PR_ = false; __VA_ARGS__; }    \
-        } else if ((NWV) == 2) {                                                \
-            if (PR) { constexpr int NW_ = 2; constexpr bool PR_ = true; __VA_ARGS__; }  \
-            else { constexpr int NW_ = 2; constexpr bool PR_ = false; __VA_ARGS__; }    \
-        } else {                                                                \
-            if (PR) { constexpr int NW_ = 4; constexpr bool PR_ = true; __VA_ARGS__; }  \
-            else { constexpr int NW_ = 4; constexpr bool PR_ = false; __VA_ARGS__; }    \
-        }                                                                       \
-    } while (0)
+template <class F>
+void dispatch_nw(int NW, F &&f) {
+    if (NW == 1) f(IC<1>{});
+    else if (NW == 2) f(IC<2>{});
+    else f(IC<4>{});
+}
+
+template <class F>
+void dispatch_bool(bool b, F &&f) {
+    if (b) f(std::true_type{});
+    else f(std::false_type{});
+}
+
+template <class F>
+void dispatch_h(int H, F &&f) {
+    if (H <= 1) f(IC<1>{});
+    else f(IC<2>{});
+}
+
+size_t lds_bytes(uint32_t lo, uint32_t hi) { return static_cast<size_t>(hi - lo) * sizeof(double); }
+
+bool fits_lds(uint32_t lo, uint32_t hi) { return hi - lo <= kMaxLdsFactors; }
 
 hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
                            uint32_t n_zero, hipStream_t s) {
     const uint32_t n = P > n_zero ? P : n_zero;
     const uint32_t blocks = (n + 255) / 256;
     if (blocks == 0) return hipSuccess;
-    const bool pr = c.thr > 0.0;
-    FHS_DISPATCH(NW, pr, k_precheck<NW_, PR_><<<blocks, 256, 0, s>>>(c, pre, P, zero_words, n_zero));
+    dispatch_nw(NW, [&](auto nw) {
+        dispatch_bool(c.thr > 0.0, [&](auto pr) {
+            k_precheck<nw.value, pr.value><<<blocks, 256, 0, s>>>(c, pre, P, zero_words, n_zero);
+        });
+    });
     return hipGetLastError();
 }
 
@@ -588,27 +781,55 @@ hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32
     if (E == 0) return hipSuccess;
     uint64_t blocks = (E + 255) / 256;
     if (blocks > (1u << 20)) blocks = 1u << 20;
-    const bool pr = c.thr > 0.0;
     const uint32_t P = c.M * c.S;
-    FHS_DISPATCH(NW, pr, k_prefix<NW_, PR_><<<static_cast<uint32_t>(blocks), 256, 0, s>>>(c, pre, tab, p0, B, P));
+    const bool flds = fits_lds(c.f_L, c.f_c1);
+    const size_t shm = flds ? lds_bytes(c.f_L, c.f_c1) : 0;
+    dispatch_nw(NW, [&](auto nw) {
+        dispatch_bool(c.thr > 0.0, [&](auto pr) {
+            dispatch_bool(flds, [&](auto fl) {
+                k_prefix<nw.value, pr.value, fl.value>
+                    <<<static_cast<uint32_t>(blocks), 256, shm, s>>>(c, pre, tab, p0, B, P);
+            });
+        });
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_consume(const Common &c, int NW, Table tab, Partials part, uint32_t p0,
+hipError_t launch_consume(const Common &c, int NW, int H, Table tab, Partials part, uint32_t p0,
                           uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter,
                           uint32_t grid, hipStream_t s) {
     if (B == 0 || grid == 0) return hipSuccess;
-    const bool pr = c.thr > 0.0;
-    FHS_DISPATCH(NW, pr, k_consume<NW_, PR_><<<grid, kConsumeThreads, 0, s>>>(c, tab, part, p0, B, chunk, ss, counter));
+    const bool flds = fits_lds(c.f_c1, c.f_G);
+    const size_t shm = flds ? lds_bytes(c.f_c1, c.f_G) : 0;
+    dispatch_nw(NW, [&](auto nw) {
+        dispatch_h(H, [&](auto hh) {
+            dispatch_bool(c.thr > 0.0, [&](auto pr) {
+                dispatch_bool(flds, [&](auto fl) {
+                    k_consume<nw.value, hh.value, pr.value, fl.value>
+                        <<<grid, kConsumeThreads, shm, s>>>(c, tab, part, p0, B, chunk, ss, counter);
+                });
+            });
+        });
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_plain(const Common &c, int NW, PreBufs pre, Partials part, uint32_t P,
+hipError_t launch_plain(const Common &c, int NW, int H, PreBufs pre, Partials part, uint32_t P,
                         uint32_t bpp, hipStream_t s) {
     const uint64_t blocks = static_cast<uint64_t>(P) * bpp;
     if (blocks == 0) return hipSuccess;
-    const bool pr = c.thr > 0.0;
-    FHS_DISPATCH(NW, pr, k_plain<NW_, PR_><<<static_cast<uint32_t>(blocks), kPlainThreads, 0, s>>>(c, pre, part, P, bpp));
+    const bool flds = fits_lds(c.f_L, c.f_G);
+    const size_t shm = flds ? lds_bytes(c.f_L, c.f_G) : 0;
+    dispatch_nw(NW, [&](auto nw) {
+        dispatch_h(H, [&](auto hh) {
+            dispatch_bool(c.thr > 0.0, [&](auto pr) {
+                dispatch_bool(flds, [&](auto fl) {
+                    k_plain<nw.value, hh.value, pr.value, fl.value>
+                        <<<static_cast<uint32_t>(blocks), kPlainThreads, shm, s>>>(c, pre, part, P, bpp);
+                });
+            });
+        });
+    });
     return hipGetLastError();
 }
 
@@ -626,12 +847,22 @@ hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32
     return hipGetLastError();
 }
 
-int consume_blocks_per_cu(int NW, bool prune) {
+int consume_blocks_per_cu(const Common &c, int NW, int H) {
     int nb = 0;
     hipError_t e = hipSuccess;
-    FHS_DISPATCH(NW, prune, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                &nb, reinterpret_cast<const void *>(k_consume<NW_, PR_>),
-                                kConsumeThreads, 0));
+    const bool flds = fits_lds(c.f_c1, c.f_G);
+    const size_t shm = flds ? lds_bytes(c.f_c1, c.f_G) : 0;
+    dispatch_nw(NW, [&](auto nw) {
+        dispatch_h(H, [&](auto hh) {
+            dispatch_bool(c.thr > 0.0, [&](auto pr) {
+                dispatch_bool(flds, [&](auto fl) {
+                    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, reinterpret_cast<const void *>(k_consume<nw.value, hh.value, pr.value, fl.value>),
+                        kConsumeThreads, shm);
+                });
+            });
+        });
+    });
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

@@ -47,6 +47,7 @@ struct Common {
     uint32_t G, L, A;
     uint32_t c1, c2;         // effective cuts, L <= c1 <= c2 <= G
     uint32_t Ap, Ar, As;
+    uint32_t f_L, f_c1, f_c2, f_G;   // factor-table offsets of evaluation positions L, c1, c2, G
     double thr;
 };
 
@@ -57,10 +58,11 @@ hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32
                          hipStream_t s);
 // ss: log2 of the number of lanes that share one (entry, h_r) root task, each
 // walking a contiguous 2^(As-ss) slice of the suffix assignments.
-hipError_t launch_consume(const Common &c, int NW, Table tab, Partials part, uint32_t p0,
+// H: histories per lane (1 or 2).
+hipError_t launch_consume(const Common &c, int NW, int H, Table tab, Partials part, uint32_t p0,
                           uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter,
                           uint32_t grid, hipStream_t s);
-hipError_t launch_plain(const Common &c, int NW, PreBufs pre, Partials part, uint32_t P,
+hipError_t launch_plain(const Common &c, int NW, int H, PreBufs pre, Partials part, uint32_t P,
                         uint32_t blocks_per_pair, hipStream_t s);
 hipError_t launch_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
                               uint32_t items_per_pair, uint32_t A, hipStream_t s);
@@ -71,8 +73,10 @@ hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32
 constexpr int kConsumeThreads = 256;
 constexpr int kPlainThreads = 256;
 constexpr int kMaxChunk = 256;   // prefix entries per work item
+// Factor slices up to this many doubles are staged in LDS by the hot kernels.
+constexpr uint32_t kMaxLdsFactors = 4096;
 
 // Occupancy-derived persistent grid for the consumer.
-int consume_blocks_per_cu(int NW, bool prune);
+int consume_blocks_per_cu(const Common &c, int NW, int H);
 
 }  // namespace fhs

@@ -38,27 +38,41 @@ enum Op : uint8_t {
     OP_BRANCH_NAT = 8,  // o = bit a, i = input bit a:  factor U[o][i], bit a := i
 };
 
-// The opcode byte carries the base op in its low 4 bits and the 32-bit
-// state word holding bit a (bits 4-5) and bit b (bits 6-7), so the device
-// indexes its state registers with compile-time constants only.
-constexpr uint8_t op_code(Op base, int a, int b) {
-    return static_cast<uint8_t>(base | ((a >> 5) << 4) | ((b >> 5) << 6));
+// The opcode byte carries the base op in its low 4 bits; bits 4-5 and 6-7
+// carry 32-bit state-word indices, so the device touches its state registers
+// with compile-time indices only:
+//   PERM     bits 4-5: word of the target bit, 6-7: highest nonzero control word
+//   MCPHASE  bits 4-5: highest nonzero control word
+//   SWAP, DIAG2  bits 4-5: word of bit a, 6-7: word of bit b
+//   DET1, DIAG1, BRANCH_*  bits 4-5: word of bit a
+constexpr uint8_t op_code(Op base, int w1, int w2) {
+    return static_cast<uint8_t>(base | (w1 << 4) | (w2 << 6));
 }
 constexpr int op_base(uint8_t code) { return code & 15; }
 
 // One instruction, 48 bytes, read wave-uniformly.  Masks are four 32-bit
-// words (state bits 0..127).  For branching gates fac points at
-// U[o][i] as (re,im) at fac + 2*(2o+i), followed by the four moduli
-// min(1,|U[o][i]|) at fac + 8 + (2o+i).
+// words (state bits 0..127).  fac is even (16-byte aligned entries): a
+// factor table of complex (re,im) pairs selected by the gate's bits; for
+// branching gates U[o][i] sits at fac + 2*(2o+i), followed by the four
+// moduli min(1,|U[o][i]|) at fac + 8 + (2o+i).  Factor tables are laid out
+// in evaluation order, so a range of gates owns a contiguous slice.
 struct alignas(16) Instr {
-    uint8_t op, a, b, pad0;   // op: op_code(); a, b: qubit (state bit) indices
-    uint32_t k;        // global source index (OP_BRANCH_SRC)
+    // hdr = op | a << 8 | b << 16 | zmask << 24 (one dword, so the device
+    // reads it with a scalar load): op = op_code(); a, b = qubit (state bit)
+    // indices; zmask (branching gates) has bit (2o+i) set when U[o][i] is
+    // exactly zero.
+    uint32_t hdr;
+    uint32_t k;        // OP_BRANCH_SRC: global source index; OP_PERM: target bit mask
     uint32_t fac;      // offset into the factor table, in doubles
-    uint32_t zmask;    // branching: bit (2o+i) set when U[o][i] is exactly zero
+    uint32_t run;      // instructions from here to the end of this run of identical opcodes
     uint32_t cm[4];    // control mask
     uint32_t cv[4];    // control values (subset of cm)
 };
 static_assert(sizeof(Instr) == 48, "instruction layout");
+
+constexpr uint32_t pack_hdr(uint32_t op, uint32_t a, uint32_t b, uint32_t zmask) {
+    return op | (a << 8) | (b << 16) | (zmask << 24);
+}
 
 struct Mask4 {
     uint32_t w[4];
@@ -78,6 +92,7 @@ struct HostProgram {
     std::vector<Mask4> final_before;   // [G+1]: bits final once e gates are applied
     std::vector<uint8_t> role;         // per evaluation position: 0 preserve, 1 det, 2 branch
     std::vector<uint16_t> fp_cost;     // per evaluation position: algorithmic FP64 flops
+    std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };
 
 }  // namespace fhs

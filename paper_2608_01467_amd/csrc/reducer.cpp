@@ -278,6 +278,7 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
     P.fac.clear();
     P.src_eval.clear();
     P.final_before.assign(G + 1, Mask4{{0, 0, 0, 0}});
+    P.fac_begin.assign(G + 1, 0);
     Mask4 fin{{0, 0, 0, 0}};
     for (int q = 0; q < n; ++q)
         if (first_np[q] < 0) set_bit(fin.w, q);   // wire never changes: b_out[q] must equal b_in[q]
@@ -288,6 +289,8 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
         const int t = G - 1 - e;
         const Gate &g = gates[t];
         Instr I{};
+        uint32_t op = 0, qa = 0, qb = 0, zmask = 0;
+        P.fac_begin[e] = static_cast<uint32_t>(P.fac.size());
         P.role[e] = static_cast<uint8_t>(role[t]);
         auto push_tab = [&](const std::vector<cd> &tab) {
             I.fac = static_cast<uint32_t>(P.fac.size());
@@ -306,10 +309,10 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
                 if (!g.neg[j]) set_bit(I.cv, g.q[j]);
             }
             if (nm == "MCX") {
-                I.op = OP_PERM;
-                I.a = static_cast<uint8_t>(g.q[0]);
+                op = OP_PERM;
+                qa = static_cast<uint32_t>(g.q[0]);
             } else {
-                I.op = OP_MCPHASE;
+                op = OP_MCPHASE;
             }
         } else if (role[t] == R_BRANCH) {
             if (g.k != 1) return FHS_EUNSUPPORTED;   // only single-qubit branching gates
@@ -322,25 +325,25 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
             for (int o = 0; o < 2; ++o)
                 for (int i = 0; i < 2; ++i) {
                     P.fac.push_back(modulus1(g.m[o][i]));
-                    if (is_zero(g.m[o][i])) I.zmask |= 1u << (2 * o + i);
+                    if (is_zero(g.m[o][i])) zmask |= 1u << (2 * o + i);
                 }
-            I.a = static_cast<uint8_t>(q);
+            qa = static_cast<uint32_t>(q);
             if (first_np[q] == t) {
-                I.op = OP_BRANCH_NAT;          // input segment is natural: value from b_in
+                op = OP_BRANCH_NAT;          // input segment is natural: value from b_in
             } else {
-                I.op = OP_BRANCH_SRC;          // artificial source k, numbered in sweep order
+                op = OP_BRANCH_SRC;          // artificial source k, numbered in sweep order
                 I.k = static_cast<uint32_t>(A++);
                 P.src_eval.push_back(static_cast<uint32_t>(e));
             }
         } else if (role[t] == R_PRESERVE) {
             if (g.k == 1) {
-                I.op = OP_DIAG1;
-                I.a = static_cast<uint8_t>(g.q[0]);
+                op = OP_DIAG1;
+                qa = static_cast<uint32_t>(g.q[0]);
                 push_tab({g.m[0][0], g.m[1][1]});
             } else if (g.k == 2) {
-                I.op = OP_DIAG2;
-                I.a = static_cast<uint8_t>(g.q[0]);
-                I.b = static_cast<uint8_t>(g.q[1]);
+                op = OP_DIAG2;
+                qa = static_cast<uint32_t>(g.q[0]);
+                qb = static_cast<uint32_t>(g.q[1]);
                 push_tab({g.m[0][0], g.m[1][1], g.m[2][2], g.m[3][3]});
             } else {
                 return FHS_EUNSUPPORTED;
@@ -349,39 +352,64 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
             if (g.k == 1) {
                 // anti-diagonal: out bit o comes from in bit 1-o with factor U[o][1-o]
                 const bool plain = g.m[0][1] == cd(1.0, 0.0) && g.m[1][0] == cd(1.0, 0.0);
-                I.a = static_cast<uint8_t>(g.q[0]);
+                qa = static_cast<uint32_t>(g.q[0]);
                 if (plain) {
-                    I.op = OP_PERM;
+                    op = OP_PERM;
                 } else {
-                    I.op = OP_DET1;
+                    op = OP_DET1;
                     push_tab({g.m[0][1], g.m[1][0]});
                 }
             } else if (nm == "CX" || nm == "CCX") {
-                I.op = OP_PERM;
+                op = OP_PERM;
                 for (int j = 0; j < g.k - 1; ++j) {
                     set_bit(I.cm, g.q[j]);
                     set_bit(I.cv, g.q[j]);
                 }
-                I.a = static_cast<uint8_t>(g.q[g.k - 1]);
+                qa = static_cast<uint32_t>(g.q[g.k - 1]);
             } else if (nm == "SWAP" || nm == "CSWAP") {
-                I.op = OP_SWAP;
+                op = OP_SWAP;
                 if (nm == "CSWAP") {
                     set_bit(I.cm, g.q[0]);
                     set_bit(I.cv, g.q[0]);
                 }
-                I.a = static_cast<uint8_t>(g.q[g.k - 2]);
-                I.b = static_cast<uint8_t>(g.q[g.k - 1]);
+                qa = static_cast<uint32_t>(g.q[g.k - 2]);
+                qb = static_cast<uint32_t>(g.q[g.k - 1]);
             } else {
                 return FHS_EUNSUPPORTED;
             }
         }
-        I.op = op_code(static_cast<Op>(I.op), I.a, I.b);
+        {
+            // state-word indices carried by the opcode
+            auto hiword = [](const uint32_t *m) {
+                int w = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (m[j]) w = j;
+                return w;
+            };
+            const Op base = static_cast<Op>(op);
+            int w1 = static_cast<int>(qa >> 5), w2 = static_cast<int>(qb >> 5);
+            if (base == OP_PERM) {
+                w2 = hiword(I.cm);
+                I.k = 1u << (qa & 31);
+            } else if (base == OP_MCPHASE) {
+                w1 = hiword(I.cm);
+                w2 = 0;
+            } else if (base != OP_SWAP && base != OP_DIAG2) {
+                w2 = 0;
+            }
+            I.hdr = pack_hdr(op_code(base, w1, w2), qa, qb, zmask);
+        }
         P.ins[e] = I;
         // bits whose natural input segment starts right below this gate
         for (size_t j = 0; j < g.q.size(); ++j)
             if (first_np[g.q[j]] == t) set_bit(fin.w, g.q[j]);
         P.final_before[e + 1] = fin;
     }
+    P.fac_begin[G] = static_cast<uint32_t>(P.fac.size());
+    // runs of identical opcodes: the device dispatches once per run
+    for (int e = G - 1; e >= 0; --e)
+        P.ins[e].run = (e + 1 < G && (P.ins[e + 1].hdr & 0xffu) == (P.ins[e].hdr & 0xffu))
+                           ? P.ins[e + 1].run + 1 : 1;
     P.A = A;
     P.L = A > 0 ? static_cast<int>(P.src_eval[0]) : G;
     return FHS_OK;

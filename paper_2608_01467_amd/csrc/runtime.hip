@@ -81,7 +81,9 @@ struct fhs_ctx {
     GraphKey key{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int consume_bpc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int ilp = 2;             // histories per lane in the hot kernels
+    uint32_t chunk_max = kMaxChunk;
+    uint32_t blocks_per_cu = 0;   // 0: occupancy limit
 };
 
 namespace {
@@ -167,7 +169,7 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
         B = std::max<uint64_t>(1, std::min<uint64_t>(B, n_pairs));
         pl.B = static_cast<uint32_t>(B);
         pl.n_batches = (n_pairs + pl.B - 1) / pl.B;
-        pl.chunk = static_cast<uint32_t>(std::min<uint64_t>(per_pair, kMaxChunk));
+        pl.chunk = static_cast<uint32_t>(std::min<uint64_t>(per_pair, c->chunk_max));
         pl.nchunks = static_cast<uint32_t>((per_pair + pl.chunk - 1) / pl.chunk);
         pl.entries = B * per_pair;
         // lanes sharing one root task: enough root tasks to fill the device
@@ -250,6 +252,10 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.Ap = pl.Ap;
     cm.Ar = pl.Ar;
     cm.As = pl.As;
+    cm.f_L = P.fac_begin[P.L];
+    cm.f_c1 = P.fac_begin[pl.c1];
+    cm.f_c2 = P.fac_begin[pl.c2];
+    cm.f_G = P.fac_begin[P.G];
     cm.thr = thr;
     return cm;
 }
@@ -267,7 +273,7 @@ PairRes pair_res(void *ws, const Plan &pl) {
 // prefix-table build, the persistent consumer and the per-pair reduction,
 // then Eq. (2).
 hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const double *coeffs,
-                           double *amps, uint64_t *stats, void *ws, hipStream_t s) {
+                           double *amps, uint64_t *stats, void *ws, int bpc, hipStream_t s) {
     const HostProgram &P = c->prog;
     const int NW = nw_of(P);
     PreBufs pre = pre_bufs(ws, pl);
@@ -283,8 +289,6 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
     Table tab{at<uint32_t>(ws, pl.off_tab_st), at<double2>(ws, pl.off_tab_beta),
               at<double>(ws, pl.off_tab_M), at<uint32_t>(ws, pl.off_tab_ok)};
     Partials part{at<double2>(ws, pl.off_part_amp), at<uint64_t>(ws, pl.off_part_st)};
-    const bool prune = cm.thr > 0.0;
-    const int bpc = std::max(1, c->consume_bpc[NW == 1 ? 0 : (NW == 2 ? 1 : 2)][prune ? 1 : 0]);
     for (uint32_t b = 0; b < pl.n_batches; ++b) {
         const uint32_t p0 = b * pl.B;
         const uint32_t B = std::min(pl.B, pl.P - p0);
@@ -293,7 +297,7 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         if (items < grid) grid = static_cast<uint32_t>(items);
         e = launch_prefix(cm, NW, pre, tab, p0, B, s);
         if (e != hipSuccess) return e;
-        e = launch_consume(cm, NW, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
+        e = launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
         e = launch_pair_reduce(pre, part, res, p0, B, pl.nchunks, cm.A, s);
         if (e != hipSuccess) return e;
@@ -385,6 +389,27 @@ extern "C" fhs_status fhs_set_table_budget(fhs_ctx *c, size_t bytes) {
     return FHS_OK;
 }
 
+extern "C" fhs_status fhs_set_launch_config(fhs_ctx *c, const fhs_launch_config *cfg) {
+    if (!c || !cfg) return FHS_EINVAL;
+    const uint32_t h = cfg->histories_per_lane ? cfg->histories_per_lane : 2;
+    const uint32_t ch = cfg->chunk ? cfg->chunk : kMaxChunk;
+    if (h > 2 || ch > static_cast<uint32_t>(kMaxChunk) || (ch & (ch - 1)) || cfg->blocks_per_cu > 64)
+        return fail(c, FHS_EINVAL, "launch config out of range");
+    c->ilp = static_cast<int>(h);
+    c->chunk_max = ch;
+    c->blocks_per_cu = cfg->blocks_per_cu;
+    drop_graph(c);
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_get_launch_config(const fhs_ctx *c, fhs_launch_config *cfg) {
+    if (!c || !cfg) return FHS_EINVAL;
+    cfg->histories_per_lane = static_cast<uint32_t>(c->ilp);
+    cfg->chunk = c->chunk_max;
+    cfg->blocks_per_cu = c->blocks_per_cu;
+    return FHS_OK;
+}
+
 extern "C" fhs_status fhs_workspace_size(const fhs_ctx *c, uint32_t M, uint32_t S, size_t *bytes) {
     if (!c || !bytes) return FHS_EINVAL;
     if (!c->loaded) return FHS_ESTATE;
@@ -420,12 +445,11 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
     key.generation = c->generation;
     if (!(c->have_graph && c->key == key)) {
         drop_graph(c);
-        const int NW = nw_of(c->prog);
-        int &bpc = c->consume_bpc[NW == 1 ? 0 : (NW == 2 ? 1 : 2)][thr > 0.0 ? 1 : 0];
-        if (bpc == 0) bpc = consume_blocks_per_cu(NW, thr > 0.0);
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+        int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
+        if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         FHS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, c->cap_stream);
+        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, c->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) {
@@ -466,7 +490,7 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
         FHS_HIP(c, launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s));
     } else {
         Partials part{at<double2>(d_ws, pl.off_plain_amp), at<uint64_t>(d_ws, pl.off_plain_st)};
-        FHS_HIP(c, launch_plain(cm, NW, pre, part, pl.P, pl.bpp, s));
+        FHS_HIP(c, launch_plain(cm, NW, c->ilp, pre, part, pl.P, pl.bpp, s));
         FHS_HIP(c, launch_pair_reduce(pre, part, res, 0, pl.P, pl.bpp, cm.A, s));
     }
     FHS_HIP(c, launch_finalize(res, d_cf, S, M, d_amps, d_stats, s));
