@@ -94,6 +94,25 @@ fhs_status fhs_program_sources(const fhs_program *prog, uint32_t *eval_pos, uint
 fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
                               uint64_t cost[2], uint32_t *regions);
 
+/* Algorithmic work of evaluation positions [e0, e1) for one history, by a
+ * fixed per-gate model (a history's backward step through one gate):
+ *   int_ops:    32-bit integer operations: controlled permutation or phase
+ *               3w+1 (w = state words spanned by its controls, at least 1),
+ *               swap 3w+4, one-qubit diagonal 1, two-qubit diagonal 3,
+ *               anti-diagonal 2, branching 4;
+ *   fp64_flops: complex multiply of the running amplitude: 6 for a general
+ *               factor table, 2 if every entry is purely real or imaginary,
+ *               0 if every entry is 0, +-1 or +-i; a negation counts 0;
+ *   branch:     branching gates (one modulus multiply each when pruning). */
+typedef struct {
+    uint64_t gates;
+    uint64_t int_ops;
+    uint64_t fp64_flops;
+    uint64_t branch;
+} fhs_work;
+
+fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1, fhs_work *out);
+
 /* Section IV-C: choose cuts.  FHS_PART_NONE, FHS_PART_THIRDS and
  * FHS_PART_EQ8 need no context; FHS_PART_MODEL needs fhs_choose_partition_ctx. */
 fhs_status fhs_choose_partition(const fhs_program *prog, int mode, uint32_t *c1, uint32_t *c2);
@@ -144,6 +163,35 @@ typedef struct {
 
 fhs_status fhs_set_launch_config(fhs_ctx *ctx, const fhs_launch_config *cfg);
 fhs_status fhs_get_launch_config(const fhs_ctx *ctx, fhs_launch_config *cfg);
+
+/* Kernel timing.  When enabled, every later evaluation records HIP events
+ * around each launch of its hot kernel (the persistent consumer of
+ * fhs_evaluate, the plain kernel of fhs_evaluate_plain); fhs_evaluate then
+ * enqueues its launch sequence directly on the stream instead of replaying
+ * its graph, since events recorded inside a graph carry no timestamps.  After the stream has synchronized, fhs_kernel_times
+ * writes the durations in milliseconds of the most recent call's launches to
+ * ms[0..min(count,cap)-1] and their number to *count.  FHS_ESTATE if timing
+ * is off or nothing was timed; FHS_EHIP if the events have not completed. */
+fhs_status fhs_set_kernel_timing(fhs_ctx *ctx, int enable);
+fhs_status fhs_kernel_times(fhs_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
+
+/* Work layout fhs_evaluate would use for M outputs and S inputs.  The cuts
+ * are the effective ones: the source-free gates nearest the output run once
+ * per pair in the precheck, so a cut below n_leading moves up to it (the
+ * source counts per region are unchanged). */
+typedef struct {
+    uint32_t c1, c2;               /* effective cuts, evaluation order */
+    uint32_t Ap, Ar, As;           /* sources per region */
+    uint32_t n_batches;            /* launches of the prefix build and the consumer */
+    uint32_t pairs_per_batch;      /* (input, output) pairs per batch (last may be fewer) */
+    uint32_t chunk;                /* prefix entries per work item */
+    uint32_t items_per_pair;       /* work items per pair */
+    uint32_t lanes_per_root_task;  /* lanes that share one (entry, h_r) root task */
+    uint32_t plain_blocks_per_pair;
+    uint64_t table_bytes;          /* prefix-table bytes per batch */
+} fhs_plan;
+
+fhs_status fhs_get_plan(const fhs_ctx *ctx, uint32_t M, uint32_t S, fhs_plan *plan);
 
 /* Bytes of device workspace fhs_evaluate / fhs_evaluate_plain need for M
  * outputs and S inputs under the current program and partition. */

@@ -62,6 +62,8 @@ def _load():
         lib.orc_pair.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P]
         lib.orc_evaluate.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int]
+        lib.orc_sample.argtypes = [P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, P, P, ctypes.c_int]
         lib.orc_eq8.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         lib.orc_eq8_argmin.argtypes = [P, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int), P]
@@ -153,6 +155,20 @@ class Feynman:
                                     bo.ctypes.data, len(outputs), float(threshold), int(c1),
                                     int(c2), amps.ctypes.data, st.ctypes.data, int(threads)),
                "orc_evaluate")
+        return amps[:, 0] + 1j * amps[:, 1], st
+
+    def sample(self, b_in: int, outputs: Sequence[int], partition: Tuple[int, int],
+               hp_range: Tuple[int, int], threshold: float = 0.0, threads: int = 1):
+        """Algorithm 2 restricted to prefix assignments h_p in hp_range, for
+        timing a bounded share of a workload.  Returns (amps, stats)."""
+        bi = _words([b_in], self.n)
+        bo = _words(outputs, self.n)
+        amps = np.zeros((len(outputs), 2), dtype=np.float64)
+        st = np.zeros((len(outputs), 4), dtype=np.uint64)
+        _check(_load().orc_sample(self._h, bi.ctypes.data, bo.ctypes.data, len(outputs),
+                                  float(threshold), int(partition[0]), int(partition[1]),
+                                  int(hp_range[0]), int(hp_range[1]), amps.ctypes.data,
+                                  st.ctypes.data, int(threads)), "orc_sample")
         return amps[:, 0] + 1j * amps[:, 1], st
 
     def eq8(self, c1: int, c2: int) -> int:

@@ -573,7 +573,7 @@ static int advance(const orc_circuit *c, const signed char *src, signed char *ds
 }
 
 static void alg2(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
-                 double thr, int c1, int c2, acc_t *a) {
+                 double thr, int c1, int c2, uint64_t hp_lo, uint64_t hp_hi, acc_t *a) {
     /* eval cuts -> time ranges: prefix = [G-c1, G), root = [G-c2, G-c1), suffix = [0, G-c2) */
     int G = c->G;
     int Ap = 0, Ar = 0, As = 0;
@@ -585,7 +585,8 @@ static void alg2(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout
     signed char *s0 = (signed char *)malloc(ns), *sp = (signed char *)malloc(ns);
     signed char *sr = (signed char *)malloc(ns), *ss = (signed char *)malloc(ns);
     if (set_boundary(c, s0, bin, bout) == 0 && propagate(c, s0, 0, G) == 0) {
-        for (uint64_t hp = 0; hp < (1ULL << Ap); ++hp) {
+        if (hp_hi > (1ULL << Ap)) hp_hi = 1ULL << Ap;
+        for (uint64_t hp = hp_lo; hp < hp_hi; ++hp) {
             partial pp = {{1.0, 0.0}, 1.0};
             if (advance(c, s0, sp, G - c1, G, 0, Ap, hp, thr, &pp, &a->gate_evals)) continue;
             for (uint64_t hr = 0; hr < (1ULL << Ar); ++hr) {
@@ -613,7 +614,7 @@ int orc_pair(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
     acc_t a;
     memset(&a, 0, sizeof(a));
     if (c1 < 0) alg1(c, bin, bout, thr, &a);
-    else alg2(c, bin, bout, thr, c1, c2, &a);
+    else alg2(c, bin, bout, thr, c1, c2, 0, ~0ULL, &a);
     amp[0] = a.re.s + a.re.c;
     amp[1] = a.im.s + a.im.c;
     stats[0] = a.n_valid; stats[1] = a.sum_h; stats[2] = a.xor_h; stats[3] = a.gate_evals;
@@ -654,6 +655,34 @@ int orc_evaluate(const orc_circuit *c, const uint64_t *inputs, const double *coe
         for (int k = 0; k < 4; ++k) stats[4 * (size_t)j + k] = st[k];
     }
     return rc;
+}
+
+/* A bounded sample of Algorithm 2 for timing: prefix assignments
+ * h_p in [hp_lo, hp_hi) only, for each of the M outputs (one input b_in),
+ * OpenMP over outputs.  amps/stats as orc_evaluate (partial sums). */
+int orc_sample(const orc_circuit *c, const uint64_t *bin, const uint64_t *outputs, int M,
+               double thr, int c1, int c2, uint64_t hp_lo, uint64_t hp_hi,
+               double *amps, uint64_t *stats, int nthreads) {
+    if (!(thr >= 0.0) || !isfinite(thr) || M < 0) return ORC_EINVAL;
+    if (c->A > 62) return ORC_ERANGE;
+    if (c1 < 0 || c1 > c2 || c2 > c->G) return ORC_EINVAL;
+    int W = (c->n + 63) / 64;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int j = 0; j < M; ++j) {
+        acc_t a;
+        memset(&a, 0, sizeof(a));
+        alg2(c, bin, outputs + (size_t)j * W, thr, c1, c2, hp_lo, hp_hi, &a);
+        amps[2 * j] = a.re.s + a.re.c;
+        amps[2 * j + 1] = a.im.s + a.im.c;
+        stats[4 * (size_t)j] = a.n_valid;
+        stats[4 * (size_t)j + 1] = a.sum_h;
+        stats[4 * (size_t)j + 2] = a.xor_h;
+        stats[4 * (size_t)j + 3] = a.gate_evals;
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */

@@ -34,6 +34,7 @@ EXPORTS = [
     "fhs_ctx_destroy", "fhs_last_error", "fhs_load_program", "fhs_set_partition",
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
     "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
+    "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_get_plan",
 ]
 
 
@@ -47,6 +48,17 @@ class ProgramInfo(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("n_gates", ctypes.c_uint32),
                 ("n_sources", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
                 ("n_leading", ctypes.c_uint32), ("n_branch", ctypes.c_uint32)]
+
+
+class Work(ctypes.Structure):
+    _fields_ = [("gates", ctypes.c_uint64), ("int_ops", ctypes.c_uint64),
+                ("fp64_flops", ctypes.c_uint64), ("branch", ctypes.c_uint64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in (
+        "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
+        "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -86,6 +98,10 @@ def lib() -> ctypes.CDLL:
         L.fhs_get_partition.argtypes = [P, pU32, pU32]
         L.fhs_set_table_budget.argtypes = [P, ctypes.c_size_t]
         L.fhs_workspace_size.argtypes = [P, U32, U32, ctypes.POINTER(ctypes.c_size_t)]
+        L.fhs_program_work.argtypes = [P, U32, U32, ctypes.POINTER(Work)]
+        L.fhs_set_kernel_timing.argtypes = [P, I32]
+        L.fhs_get_plan.argtypes = [P, U32, U32, ctypes.POINTER(Plan)]
+        L.fhs_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), U32, ctypes.POINTER(U32)]
         L.fhs_set_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         L.fhs_get_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         ev = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P, ctypes.c_size_t, P]
@@ -136,6 +152,12 @@ class Program:
         reg = (ctypes.c_uint32 * 6)()
         _check(lib().fhs_partition_cost(self._h, c1, c2, cost, reg))
         return int(cost[0]) | (int(cost[1]) << 64), tuple(reg)
+
+    def work(self, e0: int, e1: int) -> dict:
+        """Algorithmic work of evaluation positions [e0, e1) per history."""
+        w = Work()
+        _check(lib().fhs_program_work(self._h, e0, e1, ctypes.byref(w)))
+        return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch)
 
     def choose_partition(self, mode: int = PART_EQ8) -> Tuple[int, int]:
         c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
@@ -201,6 +223,21 @@ class Context:
         cfg = LaunchConfig()
         _check(lib().fhs_get_launch_config(self._h, ctypes.byref(cfg)), self)
         return cfg.histories_per_lane, cfg.chunk, cfg.blocks_per_cu
+
+    def plan(self, M: int, S: int) -> dict:
+        p = Plan()
+        _check(lib().fhs_get_plan(self._h, M, S, ctypes.byref(p)), self)
+        return {k: getattr(p, k) for k, _ in Plan._fields_}
+
+    def set_kernel_timing(self, enable: bool) -> None:
+        _check(lib().fhs_set_kernel_timing(self._h, 1 if enable else 0), self)
+
+    def kernel_times(self) -> list:
+        """Durations (ms) of the hot-kernel launches of the last evaluation."""
+        n = ctypes.c_uint32()
+        buf = (ctypes.c_float * 4096)()
+        _check(lib().fhs_kernel_times(self._h, buf, 4096, ctypes.byref(n)), self)
+        return [float(buf[i]) for i in range(min(n.value, 4096))]
 
     def set_table_budget(self, nbytes: int) -> None:
         _check(lib().fhs_set_table_budget(self._h, nbytes), self)

@@ -92,6 +92,7 @@ struct HostProgram {
     std::vector<Mask4> final_before;   // [G+1]: bits final once e gates are applied
     std::vector<uint8_t> role;         // per evaluation position: 0 preserve, 1 det, 2 branch
     std::vector<uint16_t> fp_cost;     // per evaluation position: algorithmic FP64 flops
+    std::vector<uint16_t> int_cost;    // per evaluation position: algorithmic int32 ops
     std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };
 

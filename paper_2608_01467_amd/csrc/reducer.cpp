@@ -275,6 +275,7 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
     P.ins.assign(G, Instr{});
     P.role.assign(G, 0);
     P.fp_cost.assign(G, 0);
+    P.int_cost.assign(G, 0);
     P.fac.clear();
     P.src_eval.clear();
     P.final_before.assign(G + 1, Mask4{{0, 0, 0, 0}});
@@ -398,6 +399,19 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
                 w2 = 0;
             }
             I.hdr = pack_hdr(op_code(base, w1, w2), qa, qb, zmask);
+            // algorithmic int32 ops of one backward step (fhs_program_work)
+            const int wspan = hiword(I.cm) + 1;
+            int ops = 0;
+            switch (base) {
+                case OP_PERM: ops = (I.cm[0] | I.cm[1] | I.cm[2] | I.cm[3]) ? 3 * wspan + 1 : 1; break;
+                case OP_MCPHASE: ops = 3 * wspan + 1; break;
+                case OP_SWAP: ops = (I.cm[0] | I.cm[1] | I.cm[2] | I.cm[3]) ? 3 * wspan + 4 : 4; break;
+                case OP_DIAG1: ops = 1; break;
+                case OP_DIAG2: ops = 3; break;
+                case OP_DET1: ops = 2; break;
+                default: ops = 4; break;   // branching
+            }
+            P.int_cost[e] = static_cast<uint16_t>(ops);
         }
         P.ins[e] = I;
         // bits whose natural input segment starts right below this gate
@@ -500,6 +514,22 @@ extern "C" fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, u
         regions[0] = c1; regions[1] = c2 - c1; regions[2] = P.G - c2;
         regions[3] = a3[0]; regions[4] = a3[1]; regions[5] = a3[2];
     }
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1,
+                                       fhs_work *out) {
+    if (!prog || !out) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    if (e0 > e1 || e1 > static_cast<uint32_t>(P.G)) return FHS_EINVAL;
+    fhs_work w{0, 0, 0, 0};
+    for (uint32_t e = e0; e < e1; ++e) {
+        w.gates += 1;
+        w.int_ops += P.int_cost[e];
+        w.fp64_flops += P.fp_cost[e];
+        w.branch += P.role[e] == 2 ? 1 : 0;
+    }
+    *out = w;
     return FHS_OK;
 }
 

@@ -33,7 +33,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct GraphKey {
     const void *inputs, *coeffs, *outputs, *amps, *stats, *ws;
-    uint32_t S, M, c1, c2;
+    uint32_t S, M, c1, c2, timing;
     uint64_t thr_bits, ws_bytes, generation;
     bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -84,6 +84,9 @@ struct fhs_ctx {
     int ilp = 2;             // histories per lane in the hot kernels
     uint32_t chunk_max = kMaxChunk;
     uint32_t blocks_per_cu = 0;   // 0: occupancy limit
+    bool timing = false;            // record events around hot-kernel launches
+    std::vector<hipEvent_t> events; // [2 * launches]: start, end
+    uint32_t n_timed = 0;
 };
 
 namespace {
@@ -116,6 +119,17 @@ void free_program(fhs_ctx *c) {
     c->d_fac = nullptr;
     c->d_fin = nullptr;
     c->loaded = false;
+}
+
+// Make sure 2*n timing events exist (created outside any capture).
+hipError_t ensure_events(fhs_ctx *c, uint32_t n) {
+    while (c->events.size() < 2 * static_cast<size_t>(n)) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->events.push_back(e);
+    }
+    return hipSuccess;
 }
 
 void drop_graph(fhs_ctx *c) {
@@ -273,7 +287,8 @@ PairRes pair_res(void *ws, const Plan &pl) {
 // prefix-table build, the persistent consumer and the per-pair reduction,
 // then Eq. (2).
 hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const double *coeffs,
-                           double *amps, uint64_t *stats, void *ws, int bpc, hipStream_t s) {
+                           double *amps, uint64_t *stats, void *ws, int bpc, bool timed,
+                           hipStream_t s) {
     const HostProgram &P = c->prog;
     const int NW = nw_of(P);
     PreBufs pre = pre_bufs(ws, pl);
@@ -297,8 +312,10 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         if (items < grid) grid = static_cast<uint32_t>(items);
         e = launch_prefix(cm, NW, pre, tab, p0, B, s);
         if (e != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(c->events[2 * b], s)) != hipSuccess) return e;
         e = launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(c->events[2 * b + 1], s)) != hipSuccess) return e;
         e = launch_pair_reduce(pre, part, res, p0, B, pl.nchunks, cm.A, s);
         if (e != hipSuccess) return e;
     }
@@ -334,6 +351,7 @@ extern "C" void fhs_ctx_destroy(fhs_ctx *c) {
     hipSetDevice(c->device);
     drop_graph(c);
     free_program(c);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
 }
@@ -410,6 +428,48 @@ extern "C" fhs_status fhs_get_launch_config(const fhs_ctx *c, fhs_launch_config 
     return FHS_OK;
 }
 
+extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs_plan *out) {
+    if (!c || !out) return FHS_EINVAL;
+    if (!c->loaded) return FHS_ESTATE;
+    if (c->prog.A > kMaxSources) return FHS_ERANGE;
+    Plan pl;
+    fhs_status st = make_plan(c, M, std::max<uint32_t>(S, 1), pl);
+    if (st != FHS_OK) return st;
+    out->c1 = pl.c1;
+    out->c2 = pl.c2;
+    out->Ap = pl.Ap;
+    out->Ar = pl.Ar;
+    out->As = pl.As;
+    out->n_batches = pl.n_batches;
+    out->pairs_per_batch = pl.B;
+    out->chunk = pl.chunk;
+    out->items_per_pair = pl.nchunks;
+    out->lanes_per_root_task = 1u << pl.ss;
+    out->plain_blocks_per_pair = pl.bpp;
+    out->table_bytes = pl.entries * (sizeof(uint32_t) * nw_of(c->prog) + sizeof(double2) +
+                                     sizeof(double) + sizeof(uint32_t));
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_set_kernel_timing(fhs_ctx *c, int enable) {
+    if (!c) return FHS_EINVAL;
+    c->timing = enable != 0;
+    c->n_timed = 0;
+    drop_graph(c);
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_kernel_times(fhs_ctx *c, float *ms, uint32_t cap, uint32_t *count) {
+    if (!c || !count || (!ms && cap)) return FHS_EINVAL;
+    if (!c->timing || c->n_timed == 0) return fail(c, FHS_ESTATE, "no timed launch");
+    *count = c->n_timed;
+    for (uint32_t i = 0; i < c->n_timed && i < cap; ++i) {
+        hipError_t e = hipEventElapsedTime(&ms[i], c->events[2 * i], c->events[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    }
+    return FHS_OK;
+}
+
 extern "C" fhs_status fhs_workspace_size(const fhs_ctx *c, uint32_t M, uint32_t S, size_t *bytes) {
     if (!c || !bytes) return FHS_EINVAL;
     if (!c->loaded) return FHS_ESTATE;
@@ -443,13 +503,27 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
     std::memcpy(&key.thr_bits, &thr, sizeof(thr));
     key.ws_bytes = ws_bytes;
     key.generation = c->generation;
+    key.timing = 0;
+    const bool timed = c->timing && c->prog.A > 0;
+    if (c->timing) {
+        // Timing mode: the same launch sequence, enqueued directly on the
+        // caller's stream with events around every consumer launch (events
+        // recorded inside a captured graph carry no usable timestamps).
+        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+        int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
+        if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
+        if (timed) FHS_HIP(c, ensure_events(c, pl.n_batches));
+        FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s));
+        c->n_timed = timed ? pl.n_batches : 0;
+        return FHS_OK;
+    }
     if (!(c->have_graph && c->key == key)) {
         drop_graph(c);
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
         int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         FHS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, c->cap_stream);
+        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, false, c->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) {
@@ -490,7 +564,13 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
         FHS_HIP(c, launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s));
     } else {
         Partials part{at<double2>(d_ws, pl.off_plain_amp), at<uint64_t>(d_ws, pl.off_plain_st)};
+        if (c->timing) {
+            FHS_HIP(c, ensure_events(c, 1));
+            FHS_HIP(c, hipEventRecord(c->events[0], s));
+        }
         FHS_HIP(c, launch_plain(cm, NW, c->ilp, pre, part, pl.P, pl.bpp, s));
+        if (c->timing) FHS_HIP(c, hipEventRecord(c->events[1], s));
+        c->n_timed = c->timing ? 1 : 0;
         FHS_HIP(c, launch_pair_reduce(pre, part, res, 0, pl.P, pl.bpp, cm.A, s));
     }
     FHS_HIP(c, launch_finalize(res, d_cf, S, M, d_amps, d_stats, s));
