@@ -114,7 +114,8 @@ typedef struct {
 fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1, fhs_work *out);
 
 /* Section IV-C: choose cuts.  FHS_PART_NONE, FHS_PART_THIRDS and
- * FHS_PART_EQ8 need no context; FHS_PART_MODEL needs fhs_choose_partition_ctx. */
+ * FHS_PART_EQ8 need no context; FHS_PART_MODEL needs fhs_choose_partition_ctx
+ * (FHS_ESTATE here). */
 fhs_status fhs_choose_partition(const fhs_program *prog, int mode, uint32_t *c1, uint32_t *c2);
 
 /* ---------------------------------------------------------------------
@@ -228,6 +229,79 @@ fhs_status fhs_evaluate_plain(fhs_ctx *ctx,
                               const uint64_t *d_outputs, uint32_t M, double threshold,
                               double *d_amps, uint64_t *d_stats,
                               void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Learned split (cost model).  The paper picks the checkpoint partition by
+ * minimising Eq. (8) (Section IV-C); here a small network, trained on the
+ * autotuner's measured times, predicts the log run time of each candidate
+ * split from split features, and the argmin is used.  Exhaustive timing
+ * remains the fallback and the judge of its regret.
+ * ------------------------------------------------------------------- */
+
+/* Features of the split (c1, c2) for M outputs and S inputs, FHS_N_FEATURES
+ * doubles: A_p, A_r, A_s; log2(1 + work) of the prefix, root and suffix
+ * evaluations per pair (int32 ops and FP64 flops each, counts as in Eq. (8):
+ * 2^A_p prefixes, 2^(A_p+A_r) roots, 2^A suffixes, work per fhs_program_work,
+ * effective cuts); log2 of the prefix-table bytes per pair; log2(M S);
+ * 32-bit state words; log2(1 + Eq. (8)); log2 of the root tasks
+ * (M S 2^(A_p+A_r)). */
+#define FHS_N_FEATURES 14
+fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, uint32_t c2, uint32_t M,
+                              uint32_t S, double *out);
+
+/* The candidate splits the cost model and the exhaustive autotuner search:
+ * both cuts taken from {evaluation positions of the source gates} U {G}
+ * (moving a cut inside a source-free stretch only moves gates between
+ * regions with the same source counts), c1 <= c2: (A+1)(A+2)/2 pairs.
+ * Writes min(count, cap) pairs. */
+fhs_status fhs_candidate_splits(const fhs_program *prog, uint32_t *c1, uint32_t *c2, uint32_t cap,
+                                uint32_t *count);
+
+/* Load a trained cost model into ctx: blob = [n_in, h1, h2, mu[n_in],
+ * sd[n_in], params...] (doubles; n_in = FHS_N_FEATURES; features are
+ * standardised as (f - mu) / sd).  The prediction is log(seconds). */
+fhs_status fhs_load_cost_model(fhs_ctx *ctx, const double *blob, size_t n);
+
+/* fhs_choose_partition with access to the device: FHS_PART_MODEL scores
+ * every candidate split for M outputs and S inputs with the loaded model
+ * (one fhs_mlp_forward on the device) and returns the argmin (smallest
+ * (c1, c2) on ties); other modes behave as fhs_choose_partition.
+ * FHS_ESTATE without a loaded program or model. */
+fhs_status fhs_choose_partition_ctx(fhs_ctx *ctx, int mode, uint32_t M, uint32_t S, uint32_t *c1,
+                                    uint32_t *c2);
+
+/* Network x -> tanh(W1 x + b1) -> tanh(W2 a1 + b2) -> w3.a2 + b3 in FP64,
+ * n_in, h1, h2 in [1, 64].  Flat parameters, in order: W1 [h1][n_in]
+ * row-major, b1 [h1], W2 [h2][h1], b2 [h2], w3 [h2], b3. */
+typedef struct {
+    uint32_t n_in, h1, h2;
+} fhs_mlp_shape;
+
+fhs_status fhs_mlp_param_count(const fhs_mlp_shape *shape, size_t *n);
+
+/* Device workspace fhs_mlp_backward needs for a batch of B rows. */
+fhs_status fhs_mlp_workspace_size(const fhs_mlp_shape *shape, uint32_t B, size_t *bytes);
+
+/* y[b] = network(x[b]) for b < B; x is B x n_in row-major.  act (may be
+ * NULL) receives the hidden activations, B x (h1 + h2).  Device pointers,
+ * asynchronous on `stream`. */
+fhs_status fhs_mlp_forward(const fhs_mlp_shape *shape, const double *d_params, const double *d_x,
+                           uint32_t B, double *d_y, double *d_act, void *stream);
+
+/* Gradient of the mean squared error (1/B) sum_b (network(x[b]) - t[b])^2
+ * with respect to every parameter (d_grad, same layout as the parameters),
+ * and the loss itself (d_loss, may be NULL).  Per-tile partial sums are
+ * reduced in a fixed order: deterministic. */
+fhs_status fhs_mlp_backward(const fhs_mlp_shape *shape, const double *d_params, const double *d_x,
+                            const double *d_t, uint32_t B, double *d_grad, double *d_loss,
+                            void *d_ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba 2015), iteration `step` >= 1, with bias
+ * correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+fhs_status fhs_mlp_adam(size_t n, double *d_params, const double *d_grad, double *d_m, double *d_v,
+                        uint32_t step, double lr, double beta1, double beta2, double eps,
+                        void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,12 @@ EXPORTS = [
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
     "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
     "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_get_plan",
+    "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
+    "fhs_choose_partition_ctx", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
+    "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam",
 ]
+
+N_FEATURES = 14
 
 
 class FhsError(RuntimeError):
@@ -59,6 +64,10 @@ class Plan(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
         "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)]
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_uint32), ("h1", ctypes.c_uint32), ("h2", ctypes.c_uint32)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -103,6 +112,18 @@ def lib() -> ctypes.CDLL:
         L.fhs_get_plan.argtypes = [P, U32, U32, ctypes.POINTER(Plan)]
         L.fhs_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), U32, ctypes.POINTER(U32)]
         L.fhs_set_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
+        pD = ctypes.POINTER(ctypes.c_double)
+        L.fhs_split_features.argtypes = [P, U32, U32, U32, U32, pD]
+        L.fhs_candidate_splits.argtypes = [P, pU32, pU32, U32, pU32]
+        L.fhs_load_cost_model.argtypes = [P, pD, ctypes.c_size_t]
+        L.fhs_choose_partition_ctx.argtypes = [P, I32, U32, U32, pU32, pU32]
+        pS = ctypes.POINTER(MlpShape)
+        L.fhs_mlp_param_count.argtypes = [pS, ctypes.POINTER(ctypes.c_size_t)]
+        L.fhs_mlp_workspace_size.argtypes = [pS, U32, ctypes.POINTER(ctypes.c_size_t)]
+        L.fhs_mlp_forward.argtypes = [pS, P, P, U32, P, P, P]
+        L.fhs_mlp_backward.argtypes = [pS, P, P, P, U32, P, P, P, ctypes.c_size_t, P]
+        L.fhs_mlp_adam.argtypes = [ctypes.c_size_t, P, P, P, P, U32, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         L.fhs_get_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         ev = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P, ctypes.c_size_t, P]
         L.fhs_evaluate.argtypes = ev
@@ -158,6 +179,19 @@ class Program:
         w = Work()
         _check(lib().fhs_program_work(self._h, e0, e1, ctypes.byref(w)))
         return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch)
+
+    def split_features(self, c1: int, c2: int, M: int, S: int) -> np.ndarray:
+        out = (ctypes.c_double * N_FEATURES)()
+        _check(lib().fhs_split_features(self._h, c1, c2, M, S, out))
+        return np.array(out[:], dtype=np.float64)
+
+    def candidate_splits(self) -> list:
+        n = ctypes.c_uint32()
+        _check(lib().fhs_candidate_splits(self._h, None, None, 0, ctypes.byref(n)))
+        a = (ctypes.c_uint32 * max(1, n.value))()
+        b = (ctypes.c_uint32 * max(1, n.value))()
+        _check(lib().fhs_candidate_splits(self._h, a, b, n.value, ctypes.byref(n)))
+        return list(zip(a[: n.value], b[: n.value]))
 
     def choose_partition(self, mode: int = PART_EQ8) -> Tuple[int, int]:
         c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
@@ -229,6 +263,17 @@ class Context:
         _check(lib().fhs_get_plan(self._h, M, S, ctypes.byref(p)), self)
         return {k: getattr(p, k) for k, _ in Plan._fields_}
 
+    def load_cost_model(self, blob) -> None:
+        arr = np.ascontiguousarray(np.asarray(blob, dtype=np.float64))
+        _check(lib().fhs_load_cost_model(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         arr.size), self)
+
+    def choose_partition(self, mode: int, M: int, S: int = 1) -> Tuple[int, int]:
+        c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().fhs_choose_partition_ctx(self._h, mode, M, S, ctypes.byref(c1),
+                                              ctypes.byref(c2)), self)
+        return c1.value, c2.value
+
     def set_kernel_timing(self, enable: bool) -> None:
         _check(lib().fhs_set_kernel_timing(self._h, 1 if enable else 0), self)
 
@@ -295,3 +340,45 @@ class Context:
                   float(threshold), amps.data_ptr(), stats.data_ptr(), ws.data_ptr(),
                   ws.numel(), ctypes.c_void_p(stream)), self)
         return amps, stats
+
+
+# ---------------------------------------------------------------------------
+# Cost-model network on the device (fhs_mlp_*): thin wrappers over torch tensors
+# ---------------------------------------------------------------------------
+
+def mlp_param_count(n_in: int, h1: int, h2: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().fhs_mlp_param_count(ctypes.byref(MlpShape(n_in, h1, h2)), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_forward(shape, params, x, y, act=None) -> None:
+    """y[b] = network(x[b]) (device tensors, float64)."""
+    sh = MlpShape(*shape)
+    _check(lib().fhs_mlp_forward(ctypes.byref(sh), params.data_ptr(), x.data_ptr(), x.shape[0],
+                                 y.data_ptr(), act.data_ptr() if act is not None else None,
+                                 _stream_ptr(x)))
+
+
+def mlp_backward(shape, params, x, t, grad, loss, ws) -> None:
+    sh = MlpShape(*shape)
+    _check(lib().fhs_mlp_backward(ctypes.byref(sh), params.data_ptr(), x.data_ptr(), t.data_ptr(),
+                                  x.shape[0], grad.data_ptr(),
+                                  loss.data_ptr() if loss is not None else None,
+                                  ws.data_ptr(), ws.numel(), _stream_ptr(x)))
+
+
+def mlp_workspace_size(shape, B: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().fhs_mlp_workspace_size(ctypes.byref(MlpShape(*shape)), B, ctypes.byref(n)))
+    return n.value
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+    _check(lib().fhs_mlp_adam(params.numel(), params.data_ptr(), grad.data_ptr(), m.data_ptr(),
+                              v.data_ptr(), step, lr, beta1, beta2, eps, _stream_ptr(params)))

@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(tmp, "reducer.o")
         _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "reducer.cpp"), "-o", o])
         objs.append(o)
-        for src in ("kernels.hip", "runtime.hip"):
+        for src in ("kernels.hip", "runtime.hip", "mlp.hip"):
             o = os.path.join(tmp, src.replace(".hip", ".o"))
             _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)

@@ -533,6 +533,70 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     return FHS_OK;
 }
 
+extern "C" fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, uint32_t c2,
+                                         uint32_t M, uint32_t S, double *f) {
+    if (!prog || !f) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    const uint32_t G = static_cast<uint32_t>(P.G);
+    if (c1 > c2 || c2 > G) return FHS_EINVAL;
+    if (P.A > 100) return FHS_ERANGE;
+    const uint32_t L = static_cast<uint32_t>(P.L);
+    const uint32_t e1 = std::max(c1, L), e2 = std::max(c2, L);
+    uint32_t a3[3];
+    region_sources(P, c1, c2, a3);
+    auto work = [&](uint32_t lo, uint32_t hi, double &iops, double &flops) {
+        iops = flops = 0.0;
+        for (uint32_t e = lo; e < hi; ++e) {
+            iops += P.int_cost[e];
+            flops += P.fp_cost[e];
+        }
+    };
+    double ip, fp, ir, fr, is, fs;
+    work(L, e1, ip, fp);
+    work(e1, e2, ir, fr);
+    work(e2, G, is, fs);
+    const double np = std::ldexp(1.0, static_cast<int>(a3[0]));
+    const double nr = std::ldexp(1.0, static_cast<int>(a3[0] + a3[1]));
+    const double ns = std::ldexp(1.0, P.A);
+    const double pairs = std::max(1.0, static_cast<double>(M) * static_cast<double>(S));
+    const double entry = 4.0 * P.NW + 16.0 + 8.0 + 4.0;
+    const unsigned __int128 e8 = eq8(a3[0], a3[1], a3[2], c1, c2 - c1, G - c2);
+    f[0] = a3[0];
+    f[1] = a3[1];
+    f[2] = a3[2];
+    f[3] = std::log2(1.0 + np * ip);
+    f[4] = std::log2(1.0 + np * fp);
+    f[5] = std::log2(1.0 + nr * ir);
+    f[6] = std::log2(1.0 + nr * fr);
+    f[7] = std::log2(1.0 + ns * is);
+    f[8] = std::log2(1.0 + ns * fs);
+    f[9] = a3[0] + std::log2(entry);
+    f[10] = std::log2(pairs);
+    f[11] = P.NW;
+    f[12] = std::log2(1.0 + static_cast<double>(e8));
+    f[13] = std::log2(pairs) + a3[0] + a3[1];
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_candidate_splits(const fhs_program *prog, uint32_t *c1, uint32_t *c2,
+                                           uint32_t cap, uint32_t *count) {
+    if (!prog || !count || ((!c1 || !c2) && cap)) return FHS_EINVAL;
+    const HostProgram &P = prog->p;
+    std::vector<uint32_t> cuts(P.src_eval.begin(), P.src_eval.end());
+    cuts.push_back(static_cast<uint32_t>(P.G));
+    uint32_t k = 0;
+    for (size_t i = 0; i < cuts.size(); ++i)
+        for (size_t j = i; j < cuts.size(); ++j) {
+            if (k < cap) {
+                c1[k] = cuts[i];
+                c2[k] = cuts[j];
+            }
+            ++k;
+        }
+    *count = k;
+    return FHS_OK;
+}
+
 extern "C" fhs_status fhs_choose_partition(const fhs_program *prog, int mode, uint32_t *c1,
                                            uint32_t *c2) {
     if (!prog || !c1 || !c2) return FHS_EINVAL;
@@ -568,5 +632,6 @@ extern "C" fhs_status fhs_choose_partition(const fhs_program *prog, int mode, ui
     return FHS_OK;
 }
 
-// Internal accessor for the device side.
+// Internal accessors for the device side.
 const fhs::HostProgram &fhs_program_host(const fhs_program *p) { return p->p; }
+fhs_program *fhs_program_clone(const fhs_program *p) { return new (std::nothrow) fhs_program(*p); }

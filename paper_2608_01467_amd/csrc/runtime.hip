@@ -23,6 +23,12 @@
 #include "program.hpp"
 
 const fhs::HostProgram &fhs_program_host(const fhs_program *p);
+fhs_program *fhs_program_clone(const fhs_program *p);
+
+namespace fhs {
+hipError_t mlp_forward(const fhs_mlp_shape *s, const double *p, const double *x, uint32_t B,
+                       double *y, double *act, hipStream_t st);
+}
 
 namespace fhs {
 namespace {
@@ -84,6 +90,12 @@ struct fhs_ctx {
     int ilp = 2;             // histories per lane in the hot kernels
     uint32_t chunk_max = kMaxChunk;
     uint32_t blocks_per_cu = 0;   // 0: occupancy limit
+    const fhs_program *host_prog = nullptr;   // for features (not owned)
+    fhs_program *prog_copy = nullptr;         // owned copy used by the cost model
+    bool have_model = false;
+    fhs_mlp_shape model_shape{0, 0, 0};
+    std::vector<double> model_mu, model_sd;
+    double *d_model = nullptr;
     bool timing = false;            // record events around hot-kernel launches
     std::vector<hipEvent_t> events; // [2 * launches]: start, end
     uint32_t n_timed = 0;
@@ -351,6 +363,8 @@ extern "C" void fhs_ctx_destroy(fhs_ctx *c) {
     hipSetDevice(c->device);
     drop_graph(c);
     free_program(c);
+    fhs_program_free(c->prog_copy);
+    if (c->d_model) hipFree(c->d_model);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
@@ -366,6 +380,8 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     free_program(c);
     const HostProgram &P = fhs_program_host(p);
     c->prog = P;
+    fhs_program_free(c->prog_copy);
+    c->prog_copy = fhs_program_clone(p);
     const size_t ni = std::max<size_t>(P.ins.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
@@ -379,6 +395,71 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     c->c1 = c->c2 = 0;
     c->loaded = true;
     ++c->generation;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_load_cost_model(fhs_ctx *c, const double *blob, size_t n) {
+    if (!c || !blob || n < 3) return FHS_EINVAL;
+    c->err.clear();
+    fhs_mlp_shape sh{static_cast<uint32_t>(blob[0]), static_cast<uint32_t>(blob[1]),
+                     static_cast<uint32_t>(blob[2])};
+    size_t np = 0;
+    if (sh.n_in != FHS_N_FEATURES || fhs_mlp_param_count(&sh, &np) != FHS_OK)
+        return fail(c, FHS_EINVAL, "cost model shape");
+    if (n != 3 + 2 * static_cast<size_t>(sh.n_in) + np) return fail(c, FHS_EINVAL, "cost model size");
+    for (uint32_t i = 0; i < sh.n_in; ++i)
+        if (!(blob[3 + sh.n_in + i] > 0.0)) return fail(c, FHS_EINVAL, "cost model scale must be > 0");
+    FHS_HIP(c, hipSetDevice(c->device));
+    if (c->d_model) hipFree(c->d_model);
+    c->d_model = nullptr;
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_model), sizeof(double) * np));
+    FHS_HIP(c, hipMemcpy(c->d_model, blob + 3 + 2 * sh.n_in, sizeof(double) * np, hipMemcpyHostToDevice));
+    c->model_shape = sh;
+    c->model_mu.assign(blob + 3, blob + 3 + sh.n_in);
+    c->model_sd.assign(blob + 3 + sh.n_in, blob + 3 + 2 * sh.n_in);
+    c->have_model = true;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_choose_partition_ctx(fhs_ctx *c, int mode, uint32_t M, uint32_t S,
+                                               uint32_t *c1, uint32_t *c2) {
+    if (!c || !c1 || !c2) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->loaded || !c->prog_copy) return fail(c, FHS_ESTATE, "no program loaded");
+    if (mode != FHS_PART_MODEL) return fhs_choose_partition(c->prog_copy, mode, c1, c2);
+    if (!c->have_model) return fail(c, FHS_ESTATE, "no cost model loaded");
+    uint32_t n = 0;
+    fhs_candidate_splits(c->prog_copy, nullptr, nullptr, 0, &n);
+    std::vector<uint32_t> a(n), b(n);
+    fhs_candidate_splits(c->prog_copy, a.data(), b.data(), n, &n);
+    const uint32_t F = c->model_shape.n_in;
+    std::vector<double> X(static_cast<size_t>(n) * F), Y(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        fhs_status st = fhs_split_features(c->prog_copy, a[i], b[i], M, S, &X[static_cast<size_t>(i) * F]);
+        if (st != FHS_OK) return fail(c, st, "features");
+        for (uint32_t k = 0; k < F; ++k) {
+            double &v = X[static_cast<size_t>(i) * F + k];
+            v = (v - c->model_mu[k]) / c->model_sd[k];
+        }
+    }
+    FHS_HIP(c, hipSetDevice(c->device));
+    double *dx = nullptr, *dy = nullptr;
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&dx), sizeof(double) * X.size()));
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&dy), sizeof(double) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, c->cap_stream);
+    if (e == hipSuccess) e = mlp_forward(&c->model_shape, c->d_model, dx, n, dy, nullptr, c->cap_stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Y.data(), dy, sizeof(double) * n, hipMemcpyDeviceToHost, c->cap_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->cap_stream);
+    hipFree(dx);
+    if (dy) hipFree(dy);
+    if (e != hipSuccess) return hip_fail(c, e, "cost model inference");
+    uint32_t best = 0;
+    for (uint32_t i = 1; i < n; ++i) {
+        if (Y[i] < Y[best] || (Y[i] == Y[best] && (a[i] < a[best] || (a[i] == a[best] && b[i] < b[best]))))
+            best = i;
+    }
+    *c1 = a[best];
+    *c2 = b[best];
     return FHS_OK;
 }
 

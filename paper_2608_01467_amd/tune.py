@@ -1,0 +1,219 @@
+"""Autotuner and learned split model.
+
+The paper chooses the checkpoint split by minimising its gate-operation
+estimate, Eq. (8) (Section IV-C).  On the GPU the run time also depends on
+what Eq. (8) does not see: the prefix table's size and traffic, how many
+root tasks there are to fill 256 compute units, and the mix of integer and
+FP64 work per region.  This module
+
+  * times evaluations on the device (`time_split`), sweeps the launch shape
+    (`autotune_launch`) and searches every candidate split exhaustively
+    (`exhaustive`): the ground truth;
+  * turns (split features, measured time) pairs into a training set
+    (`collect`), the features coming from the library (fhs_split_features);
+  * trains the cost-model network on the device with the library's own
+    forward/backward/Adam kernels (`train`), and packs it as the blob
+    fhs_load_cost_model expects;
+  * evaluates the trained model's regret against exhaustive search and
+    Eq. (8) (`regret`).
+
+Everything here drives the C ABI; no computation of the method happens in
+Python.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import (N_FEATURES, PART_EQ8, PART_MODEL, Context, Program, mlp_adam, mlp_backward,
+               mlp_forward, mlp_param_count, mlp_workspace_size)
+
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_model.json")
+SHAPE = (N_FEATURES, 32, 32)
+
+
+class Workload:
+    """A circuit plus resident device inputs for timing."""
+
+    def __init__(self, ctx: Context, text: str, inputs, coeffs, outputs, threshold=0.0):
+        import torch
+        self.ctx = ctx
+        self.prog = Program(text)
+        ctx.load(self.prog)
+        self.d_in = ctx.device_bits(inputs)
+        self.d_cf = ctx.device_coeffs(coeffs)
+        self.d_out = ctx.device_bits(outputs)
+        self.M, self.S = len(outputs), len(inputs)
+        self.thr = threshold
+        self.amps = torch.empty((self.M, 2), dtype=torch.float64, device=self.d_out.device)
+        self.stats = torch.empty((self.M, 4), dtype=torch.int64, device=self.d_out.device)
+
+    def run(self, partition: Tuple[int, int], plain: bool = False) -> None:
+        if self.ctx.program is not self.prog:
+            self.ctx.load(self.prog)
+        self.ctx.set_partition(*partition)
+        self.ctx.evaluate(self.d_in, self.d_cf, self.d_out, threshold=self.thr, plain=plain,
+                          out=(self.amps, self.stats))
+
+    def table_bytes(self, partition) -> int:
+        if self.ctx.program is not self.prog:
+            self.ctx.load(self.prog)
+        self.ctx.set_partition(*partition)
+        return self.ctx.plan(self.M, self.S)["table_bytes"]
+
+
+def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False) -> float:
+    """Best-of-`reps` wall time of one evaluation (graph replay), seconds."""
+    import torch
+    wl.run(partition, plain)
+    torch.cuda.synchronize()
+    best = math.inf
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        wl.run(partition, plain)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int], List]:
+    """Sweep histories per lane x chunk x blocks per CU; keep the fastest."""
+    log = []
+    best, best_t = None, math.inf
+    for h in (1, 2):
+        for chunk in (64, 128, 256):
+            for bpc in (0, 2, 4):
+                wl.ctx.set_launch_config(h, chunk, bpc)
+                t = time_split(wl, partition, reps)
+                log.append(((h, chunk, bpc), t))
+                if t < best_t:
+                    best, best_t = (h, chunk, bpc), t
+    wl.ctx.set_launch_config(*best)
+    return best, log
+
+
+def candidates(wl: Workload, max_cost_ratio: float = 64.0, extra: int = 8,
+               max_table_bytes: int = 8 << 30, seed: int = 0) -> List[Tuple[int, int]]:
+    """Candidate splits worth timing: every one within max_cost_ratio of the
+    Eq. (8) optimum, plus a few random others, all with a table that fits."""
+    cand = wl.prog.candidate_splits()
+    costs = {c: wl.prog.partition_cost(*c)[0] for c in cand}
+    best = min(costs.values())
+    near = [c for c in cand if costs[c] <= max_cost_ratio * best]
+    far = [c for c in cand if costs[c] > max_cost_ratio * best]
+    rng = np.random.default_rng(seed)
+    if far and extra:
+        idx = rng.choice(len(far), size=min(extra, len(far)), replace=False)
+        near += [far[i] for i in idx]
+    keep = []
+    for c in near:
+        try:
+            if wl.table_bytes(c) <= max_table_bytes:
+                keep.append(c)
+        except Exception:
+            pass
+    return keep
+
+
+def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2):
+    """Time every split; returns [(split, seconds)] and the fastest split."""
+    rows = [(c, time_split(wl, c, reps)) for c in splits]
+    best = min(rows, key=lambda r: (r[1], r[0]))[0]
+    return rows, best
+
+
+def collect(wl: Workload, splits, reps: int = 2):
+    """Feature rows and log-times for the given splits."""
+    rows, _ = exhaustive(wl, splits, reps)
+    X = np.array([wl.prog.split_features(c[0], c[1], wl.M, wl.S) for c, _ in rows])
+    y = np.log(np.array([t for _, t in rows]))
+    return X, y, rows
+
+
+def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, seed: int = 0,
+          device: str = "cuda:0", log_every: int = 0):
+    """Fit the network on the device (fhs_mlp_forward/backward/adam); returns
+    (blob, final training loss).  Features are standardised here and the
+    scaling travels in the blob."""
+    import torch
+    n_in, h1, h2 = SHAPE
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd[sd < 1e-9] = 1.0
+    Xs = (X - mu) / sd
+    rng = np.random.default_rng(seed)
+    # Glorot-uniform initialisation
+    parts = []
+    for fo, fi in ((h1, n_in), (h2, h1)):
+        lim = math.sqrt(6.0 / (fi + fo))
+        parts += [rng.uniform(-lim, lim, fo * fi), np.zeros(fo)]
+    parts += [rng.uniform(-math.sqrt(6.0 / (h2 + 1)), math.sqrt(6.0 / (h2 + 1)), h2),
+              np.array([y.mean()])]
+    p0 = np.concatenate(parts)
+    assert p0.size == mlp_param_count(n_in, h1, h2)
+    P = torch.tensor(p0, dtype=torch.float64, device=device)
+    G = torch.zeros_like(P)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    dX = torch.tensor(Xs, dtype=torch.float64, device=device).contiguous()
+    dT = torch.tensor(y, dtype=torch.float64, device=device).contiguous()
+    B = dX.shape[0]
+    ws = torch.empty(mlp_workspace_size(SHAPE, B), dtype=torch.uint8, device=device)
+    loss = torch.zeros(1, dtype=torch.float64, device=device)
+    for k in range(1, epochs + 1):
+        mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
+        mlp_adam(P, G, m, v, k, lr)
+        if log_every and k % log_every == 0:
+            torch.cuda.synchronize()
+            print(f"epoch {k} loss {loss.item():.5f}", flush=True)
+    mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
+    torch.cuda.synchronize()
+    blob = np.concatenate([[n_in, h1, h2], mu, sd, P.cpu().numpy()])
+    return blob, float(loss.item())
+
+
+def predict(blob: np.ndarray, X: np.ndarray, device: str = "cuda:0") -> np.ndarray:
+    """Model output for raw feature rows, through fhs_mlp_forward."""
+    import torch
+    n_in, h1, h2 = (int(v) for v in blob[:3])
+    mu = blob[3:3 + n_in]
+    sd = blob[3 + n_in:3 + 2 * n_in]
+    P = torch.tensor(blob[3 + 2 * n_in:], dtype=torch.float64, device=device)
+    dX = torch.tensor((X - mu) / sd, dtype=torch.float64, device=device).contiguous()
+    dY = torch.empty(X.shape[0], dtype=torch.float64, device=device)
+    mlp_forward((n_in, h1, h2), P, dX, dY)
+    torch.cuda.synchronize()
+    return dY.cpu().numpy()
+
+
+def save_model(blob: np.ndarray, meta: Dict, path: str = MODEL_PATH) -> None:
+    with open(path, "w") as f:
+        json.dump({"shape": list(SHAPE), "blob": [float(x).hex() for x in blob], "meta": meta},
+                  f, indent=1)
+
+
+def load_model(path: str = MODEL_PATH) -> Optional[np.ndarray]:
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return np.array([float.fromhex(x) for x in d["blob"]], dtype=np.float64)
+
+
+def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2) -> Dict:
+    """Time the model's choice, Eq. (8)'s choice and the exhaustive best."""
+    wl.ctx.load_cost_model(blob)
+    rows, best = exhaustive(wl, splits, reps)
+    t_best = min(t for _, t in rows)
+    c_model = wl.ctx.choose_partition(PART_MODEL, wl.M, wl.S)
+    c_eq8 = wl.prog.choose_partition(PART_EQ8)
+    t_model = time_split(wl, c_model, reps)
+    t_eq8 = time_split(wl, c_eq8, reps)
+    return {"best": best, "t_best": t_best, "model": c_model, "t_model": t_model,
+            "eq8": c_eq8, "t_eq8": t_eq8, "model_regret": t_model / t_best - 1.0,
+            "eq8_regret": t_eq8 / t_best - 1.0, "gain_over_eq8": t_eq8 / t_model}

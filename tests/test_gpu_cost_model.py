@@ -1,0 +1,101 @@
+"""GPU: the cost-model network's kernels against the FP64 reference MLP, and
+the model-driven split choice."""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+import workloads as w
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_01467_amd as fhs  # noqa: E402
+from paper_2608_01467_amd import tune  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def _case(shape, B, seed):
+    n_in, h1, h2 = shape
+    rng = np.random.default_rng(seed)
+    p = ref.init(n_in, h1, h2, seed) + 0.2 * rng.normal(size=ref.param_count(n_in, h1, h2))
+    X = rng.normal(size=(B, n_in))
+    t = rng.normal(size=B)
+    return p, X, t
+
+
+@pytest.mark.parametrize("shape,B", [((14, 32, 32), 1000), ((3, 5, 7), 17), ((64, 64, 64), 33),
+                                     ((1, 1, 1), 1)])
+def test_forward_backward_match_reference(dev, shape, B):
+    p, X, t = _case(shape, B, B)
+    dP = torch.tensor(p, device=dev)
+    dX = torch.tensor(X, device=dev)
+    dT = torch.tensor(t, device=dev)
+    y = torch.empty(B, dtype=torch.float64, device=dev)
+    fhs.mlp_forward(shape, dP, dX, y)
+    G = torch.empty_like(dP)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(fhs.mlp_workspace_size(shape, B), dtype=torch.uint8, device=dev)
+    fhs.mlp_backward(shape, dP, dX, dT, G, loss, ws)
+    torch.cuda.synchronize()
+    y_ref, _, _ = ref.forward(p, X, *shape)
+    g_ref = ref.grad(p, X, t, *shape)
+    assert np.abs(y.cpu().numpy() - y_ref).max() <= 1e-12 * max(1.0, np.abs(y_ref).max())
+    assert np.abs(G.cpu().numpy() - g_ref).max() <= 1e-12 * max(1.0, np.abs(g_ref).max())
+    assert abs(loss.item() - ref.loss(p, X, t, *shape)) <= 1e-12 * max(1.0, loss.item())
+    # deterministic reduction: a second pass is bit-identical
+    G2 = torch.empty_like(dP)
+    fhs.mlp_backward(shape, dP, dX, dT, G2, None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(G, G2)
+
+
+def test_adam_matches_reference(dev):
+    rng = np.random.default_rng(4)
+    n = 1505
+    p, g = rng.normal(size=n), rng.normal(size=n)
+    m, v = rng.normal(size=n) * 0.1, np.abs(rng.normal(size=n)) * 0.1
+    dP, dG, dM, dV = (torch.tensor(a, device=dev) for a in (p, g, m, v))
+    fhs.mlp_adam(dP, dG, dM, dV, 7, 3e-3)
+    torch.cuda.synchronize()
+    p2, m2, v2 = ref.adam_step(p, g, m, v, 7, 3e-3)
+    assert np.abs(dP.cpu().numpy() - p2).max() <= 1e-14
+    assert np.abs(dM.cpu().numpy() - m2).max() <= 1e-15
+    assert np.abs(dV.cpu().numpy() - v2).max() <= 1e-15
+
+
+def test_gpu_training_fits(dev):
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(256, fhs.N_FEATURES))
+    y = np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.1 * X[:, 12]
+    blob, loss = tune.train(X, y, epochs=1500, lr=3e-3)
+    assert loss < 0.05 * np.var(y)
+    pred = tune.predict(blob, X)
+    assert np.mean((pred - y) ** 2) == pytest.approx(loss, rel=1e-9)
+
+
+def test_model_choice_uses_the_network(dev):
+    """A network that is monotone in feature 12, log2(1 + Eq. (8)), must pick
+    an Eq. (8)-optimal split; one that is monotone in -feature 12 the worst."""
+    text = w.quantum_walk(30, 12).to_text()
+    prog = fhs.Program(text)
+    ctx = fhs.Context(0)
+    ctx.load(prog)
+    n_in, h1, h2 = fhs.N_FEATURES, 1, 1
+    for sign in (1.0, -1.0):
+        params = np.zeros(ref.param_count(n_in, h1, h2))
+        W1, b1, W2, b2, w3, b3 = ref.unpack(params, n_in, h1, h2)
+        W1[0, 12] = 0.01 * sign
+        W2[0, 0] = 1.0
+        w3[0] = 1.0
+        blob = np.concatenate([[n_in, h1, h2], np.zeros(n_in), np.ones(n_in), params])
+        ctx.load_cost_model(blob)
+        c = ctx.choose_partition(fhs.PART_MODEL, 64, 1)
+        costs = [prog.partition_cost(*x)[0] for x in prog.candidate_splits()]
+        want = min(costs) if sign > 0 else max(costs)
+        assert prog.partition_cost(*c)[0] == want
