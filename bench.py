@@ -45,15 +45,16 @@ def kernels_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str):
+def traffic_from_profile(workload: str, partition):
     """HBM bytes per launch of the consumer, from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current kernels."""
+    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current kernels
+    with the same split."""
     path = os.path.join(ROOT, "profiles", f"consume_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernels_hash") != kernels_hash():
+    if d.get("kernels_hash") != kernels_hash() or d.get("partition") != list(partition):
         return None
     return d.get("bytes_per_launch")
 
@@ -96,7 +97,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="walk_99p_20s")
-    ap.add_argument("--partition", default="eq8", choices=["eq8", "thirds", "none"])
+    ap.add_argument("--partition", default="model", choices=["model", "eq8", "thirds", "none"],
+                    help="model: the learned cost model's split (Eq. (8) if the workload lies "
+                         "outside its training range)")
+    ap.add_argument("--cost-model", default=None, help="cost model file (default: the package's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -128,11 +132,27 @@ def main() -> int:
     prog = fhs.Program(text)
     ctx = fhs.Context(0)
     ctx.load(prog)
-    mode = {"eq8": fhs.PART_EQ8, "thirds": fhs.PART_THIRDS, "none": fhs.PART_NONE}[args.partition]
-    part = prog.choose_partition(mode)
+    M, S = len(cfg["outputs"]), len(cfg["inputs"])
+    part_eq8 = prog.choose_partition(fhs.PART_EQ8)
+    how = args.partition
+    if args.partition == "model":
+        from paper_2608_01467_amd import tune
+        blob = tune.load_model(args.cost_model) if args.cost_model else tune.load_model()
+        part = None
+        if blob is not None:
+            ctx.load_cost_model(blob)
+            try:
+                part = ctx.choose_partition(fhs.PART_MODEL, M, S)
+            except fhs.FhsError as e:
+                if e.status != 3:
+                    raise
+        if part is None:
+            part, how = part_eq8, "eq8 (no cost model for this range)"
+    else:
+        mode = {"eq8": fhs.PART_EQ8, "thirds": fhs.PART_THIRDS, "none": fhs.PART_NONE}
+        part = prog.choose_partition(mode[args.partition])
     ctx.set_partition(*part)
     ctx.set_table_budget(32 << 30)          # one batch: the whole workload in HBM
-    M, S = len(cfg["outputs"]), len(cfg["inputs"])
     thr = cfg["threshold"]
     d_in = ctx.device_bits(cfg["inputs"])
     d_out = ctx.device_bits(cfg["outputs"])
@@ -184,7 +204,7 @@ def main() -> int:
     else:
         roof = {"bound": "alu", "achieved": fp_rate / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": fp_rate / PEAK_FP64, "operand": "FP64 flops"}
-    tb = traffic_from_profile(args.workload)
+    tb = traffic_from_profile(args.workload, part)
     roof["traffic"] = tb
     roof["kernel"] = "k_consume"
     roof["avg_launch_ms"] = avg_launch * 1e3
@@ -210,7 +230,7 @@ def main() -> int:
             "workload": args.workload,
             "qubits": prog.n, "gates": prog.G, "sources": prog.A,
             "outputs": M, "inputs": S, "threshold": thr,
-            "partition": list(part), "partition_mode": args.partition,
+            "partition": list(part), "partition_mode": how,
             "regions": [plan["Ap"], plan["Ar"], plan["As"]],
         },
         "amplitudes_per_s": M * S / T,
@@ -219,6 +239,19 @@ def main() -> int:
         "gate_ops_per_s": M * S * prog.partition_cost(*part)[0] / T,
         "roofline": roof,
     }
+    if tuple(part) != tuple(part_eq8):
+        # the paper's own choice, Eq. (8), on the same inputs
+        ctx.set_partition(*part_eq8)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, min(args.steps, 3))):
+            step()
+        torch.cuda.synchronize()
+        Te = (time.perf_counter() - t0) / max(1, min(args.steps, 3))
+        ctx.set_partition(*part)
+        out["eq8_split"] = {"partition": list(part_eq8), "ms_per_step": Te * 1e3,
+                            "histories_per_s": cand / Te, "learned_speedup": Te / T}
     if not args.no_plain:
         step(plain=True)
         torch.cuda.synchronize()

@@ -37,7 +37,7 @@ typedef enum {
     FHS_OK = 0,
     FHS_EINVAL = 1,        /* bad argument (NULL pointer, c1 > c2, NaN/negative threshold, bits >= n) */
     FHS_EUNSUPPORTED = 2,  /* gate or feature outside the supported set */
-    FHS_ERANGE = 3,        /* n > 128, A > 62, or a size that overflows */
+    FHS_ERANGE = 3,        /* n > 128, A > 62, a size that overflows, or a cost model used outside its training range */
     FHS_ENOMEM = 4,        /* workspace too small, or a host/device allocation failed */
     FHS_EHIP = 5,          /* a HIP runtime call failed (message in fhs_last_error) */
     FHS_ESTATE = 6,        /* call order violated (e.g. evaluate before load) */
@@ -258,15 +258,22 @@ fhs_status fhs_candidate_splits(const fhs_program *prog, uint32_t *c1, uint32_t 
                                 uint32_t *count);
 
 /* Load a trained cost model into ctx: blob = [n_in, h1, h2, mu[n_in],
- * sd[n_in], params...] (doubles; n_in = FHS_N_FEATURES; features are
- * standardised as (f - mu) / sd).  The prediction is log(seconds). */
+ * sd[n_in], lo[n_in], hi[n_in], params...] (doubles; n_in =
+ * FHS_N_FEATURES; features are standardised as (f - mu) / sd; [lo, hi] is
+ * the per-feature range of the training rows).  The prediction is
+ * log(seconds).  FHS_EINVAL on a wrong shape or size, sd <= 0 or lo > hi;
+ * the blob is copied (the caller keeps ownership). */
 fhs_status fhs_load_cost_model(fhs_ctx *ctx, const double *blob, size_t n);
 
 /* fhs_choose_partition with access to the device: FHS_PART_MODEL scores
- * every candidate split for M outputs and S inputs with the loaded model
- * (one fhs_mlp_forward on the device) and returns the argmin (smallest
- * (c1, c2) on ties); other modes behave as fhs_choose_partition.
- * FHS_ESTATE without a loaded program or model. */
+ * the candidate splits for M outputs and S inputs whose features all lie in
+ * the model's training range (each [lo, hi] widened by 5% of its width)
+ * with the loaded model (one fhs_mlp_forward on the device) and returns the
+ * argmin (smallest (c1, c2) on ties).  FHS_ERANGE, cuts untouched, when
+ * no candidate of minimal Eq. (8) cost lies in that range: the model is not
+ * trusted there and the caller falls back to timing the candidates.  Other
+ * modes behave as fhs_choose_partition.  FHS_ESTATE without a loaded
+ * program or model. */
 fhs_status fhs_choose_partition_ctx(fhs_ctx *ctx, int mode, uint32_t M, uint32_t S, uint32_t *c1,
                                     uint32_t *c2);
 

@@ -94,7 +94,7 @@ struct fhs_ctx {
     fhs_program *prog_copy = nullptr;         // owned copy used by the cost model
     bool have_model = false;
     fhs_mlp_shape model_shape{0, 0, 0};
-    std::vector<double> model_mu, model_sd;
+    std::vector<double> model_mu, model_sd, model_lo, model_hi;
     double *d_model = nullptr;
     bool timing = false;            // record events around hot-kernel launches
     std::vector<hipEvent_t> events; // [2 * launches]: start, end
@@ -406,17 +406,23 @@ extern "C" fhs_status fhs_load_cost_model(fhs_ctx *c, const double *blob, size_t
     size_t np = 0;
     if (sh.n_in != FHS_N_FEATURES || fhs_mlp_param_count(&sh, &np) != FHS_OK)
         return fail(c, FHS_EINVAL, "cost model shape");
-    if (n != 3 + 2 * static_cast<size_t>(sh.n_in) + np) return fail(c, FHS_EINVAL, "cost model size");
-    for (uint32_t i = 0; i < sh.n_in; ++i)
-        if (!(blob[3 + sh.n_in + i] > 0.0)) return fail(c, FHS_EINVAL, "cost model scale must be > 0");
+    const size_t F = sh.n_in;
+    if (n != 3 + 4 * F + np) return fail(c, FHS_EINVAL, "cost model size");
+    for (size_t i = 0; i < F; ++i) {
+        if (!(blob[3 + F + i] > 0.0)) return fail(c, FHS_EINVAL, "cost model scale must be > 0");
+        if (!(blob[3 + 2 * F + i] <= blob[3 + 3 * F + i]))
+            return fail(c, FHS_EINVAL, "cost model range: lo > hi for feature %zu", i);
+    }
     FHS_HIP(c, hipSetDevice(c->device));
     if (c->d_model) hipFree(c->d_model);
     c->d_model = nullptr;
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_model), sizeof(double) * np));
-    FHS_HIP(c, hipMemcpy(c->d_model, blob + 3 + 2 * sh.n_in, sizeof(double) * np, hipMemcpyHostToDevice));
+    FHS_HIP(c, hipMemcpy(c->d_model, blob + 3 + 4 * F, sizeof(double) * np, hipMemcpyHostToDevice));
     c->model_shape = sh;
-    c->model_mu.assign(blob + 3, blob + 3 + sh.n_in);
-    c->model_sd.assign(blob + 3 + sh.n_in, blob + 3 + 2 * sh.n_in);
+    c->model_mu.assign(blob + 3, blob + 3 + F);
+    c->model_sd.assign(blob + 3 + F, blob + 3 + 2 * F);
+    c->model_lo.assign(blob + 3 + 2 * F, blob + 3 + 3 * F);
+    c->model_hi.assign(blob + 3 + 3 * F, blob + 3 + 4 * F);
     c->have_model = true;
     return FHS_OK;
 }
@@ -433,15 +439,41 @@ extern "C" fhs_status fhs_choose_partition_ctx(fhs_ctx *c, int mode, uint32_t M,
     std::vector<uint32_t> a(n), b(n);
     fhs_candidate_splits(c->prog_copy, a.data(), b.data(), n, &n);
     const uint32_t F = c->model_shape.n_in;
-    std::vector<double> X(static_cast<size_t>(n) * F), Y(n);
+    // Only splits whose features lie inside the training box (per-feature
+    // [lo, hi] widened by 5% of its width) are scored; if no split of
+    // minimal Eq. (8) cost is among them the model is not trusted for this
+    // program.
+    uint32_t e1 = 0, e2 = 0;
+    uint64_t emin[2] = {0, 0}, cost[2] = {0, 0};
+    fhs_status st = fhs_choose_partition(c->prog_copy, FHS_PART_EQ8, &e1, &e2);
+    if (st == FHS_OK) st = fhs_partition_cost(c->prog_copy, e1, e2, emin, nullptr);
+    if (st != FHS_OK) return fail(c, st, "Eq. (8) split");
+    std::vector<double> X;
+    std::vector<uint32_t> ka, kb;
+    std::vector<double> f(F);
+    bool eq8_in = false;
     for (uint32_t i = 0; i < n; ++i) {
-        fhs_status st = fhs_split_features(c->prog_copy, a[i], b[i], M, S, &X[static_cast<size_t>(i) * F]);
+        st = fhs_split_features(c->prog_copy, a[i], b[i], M, S, f.data());
         if (st != FHS_OK) return fail(c, st, "features");
-        for (uint32_t k = 0; k < F; ++k) {
-            double &v = X[static_cast<size_t>(i) * F + k];
-            v = (v - c->model_mu[k]) / c->model_sd[k];
+        bool in = true;
+        for (uint32_t k = 0; k < F && in; ++k) {
+            const double pad = 0.05 * (c->model_hi[k] - c->model_lo[k]);
+            in = f[k] >= c->model_lo[k] - pad && f[k] <= c->model_hi[k] + pad;
         }
+        if (!in) continue;
+        st = fhs_partition_cost(c->prog_copy, a[i], b[i], cost, nullptr);
+        if (st != FHS_OK) return fail(c, st, "Eq. (8) cost");
+        if (cost[0] == emin[0] && cost[1] == emin[1]) eq8_in = true;
+        ka.push_back(a[i]);
+        kb.push_back(b[i]);
+        for (uint32_t k = 0; k < F; ++k) X.push_back((f[k] - c->model_mu[k]) / c->model_sd[k]);
     }
+    if (!eq8_in)
+        return fail(c, FHS_ERANGE, "split features outside the cost model's training range");
+    n = static_cast<uint32_t>(ka.size());
+    a.swap(ka);
+    b.swap(kb);
+    std::vector<double> Y(n);
     FHS_HIP(c, hipSetDevice(c->device));
     double *dx = nullptr, *dy = nullptr;
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&dx), sizeof(double) * X.size()));

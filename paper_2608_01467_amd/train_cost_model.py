@@ -64,57 +64,105 @@ TRAIN = [
     ("qaoa", dict(nv=10, p=2, gseed=7, aseed=8)),
     ("aa", dict(k=3, s=3)), ("aa", dict(k=4, s=2)), ("aa", dict(k=5, s=2)),
     ("clifford_t", dict(n=16, g=80, seed=5)), ("clifford_t", dict(n=24, g=120, seed=6)),
+    ("walk", dict(n_pos=99, steps=18)), ("walk", dict(n_pos=50, steps=20)),
+    ("qaoa", dict(nv=14, p=1)), ("qaoa", dict(nv=8, p=3)), ("qaoa", dict(nv=6, p=3)),
+    ("aa", dict(k=6, s=2)), ("clifford_t", dict(n=20, g=100, seed=7)),
+    ("clifford_t", dict(n=12, g=60, seed=9)),
 ]
 HELD_OUT = [
     ("walk", dict(n_pos=99, steps=20)), ("qaoa", dict(nv=12, p=2)), ("aa", dict(k=4, s=3)),
-    ("walk", dict(n_pos=70, steps=19)),
+    ("walk", dict(n_pos=70, steps=19)), ("walk", dict(n_pos=40, steps=15)),
+    ("qaoa", dict(nv=10, p=1, gseed=21, aseed=22)), ("aa", dict(k=3, s=4)),
+    ("aa", dict(k=5, s=1)), ("clifford_t", dict(n=18, g=90, seed=11)),
+    ("clifford_t", dict(n=16, g=80, seed=13)), ("clifford_t", dict(n=20, g=100, seed=14)),
 ]
+
+
+def in_sample(blob, X, y, case, report) -> None:
+    """Per training case: the measured time of the model's pick among the
+    timed splits, against the best timed split and Eq. (8)'s split."""
+    pred = tune.predict(blob, X)
+    for k, entry in enumerate(report["train"]):
+        idx = np.where(case == k)[0]
+        t_best = float(np.exp(y[idx].min()))
+        t_model = float(np.exp(y[idx[np.argmin(pred[idx])]]))
+        entry["t_model"] = t_model
+        entry["model_regret"] = t_model / t_best - 1.0
+        if entry.get("t_eq8") is not None:
+            entry["eq8_regret"] = entry["t_eq8"] / t_best - 1.0
+
+
+def held_out(ctx, blob, args, report) -> None:
+    for name, kw in HELD_OUT:
+        text, ins, outs = build(name, kw, 1.0)
+        wl = tune.Workload(ctx, text, ins, [1.0], outs)
+        splits = tune.candidates(wl, max_cost_ratio=args.ratio, extra=0)
+        r = tune.regret(wl, blob, splits, reps=3, log=lambda m: print(m, flush=True))
+        r["case"] = [name, kw]
+        r["M"] = wl.M
+        r["A"] = wl.prog.A
+        report["held_out"].append(r)
+        print(f"held-out {name} {kw}: best {r['best']} {r['t_best']*1e3:.2f} ms, model "
+              f"({r['how']}) {r['model']} {r['t_model']*1e3:.2f} ms, eq8 {r['eq8']} "
+              f"{r['t_eq8']*1e3:.2f} ms", flush=True)
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "cost_model"))
     ap.add_argument("--epochs", type=int, default=4000)
+    ap.add_argument("--ratio", type=float, default=16.0,
+                    help="time every split whose Eq. (8) cost is within this factor of the best")
+    ap.add_argument("--cases", type=int, default=len(TRAIN), help="use the first N training cases")
+    ap.add_argument("--case-budget", type=float, default=30.0,
+                    help="seconds of split timing per training case")
+    ap.add_argument("--model-out", default=tune.MODEL_PATH)
+    ap.add_argument("--evaluate", default=None,
+                    help="skip training: measure the held-out regret of this saved model")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     ctx = Context(0)
-    Xs, ys, report = [], [], {"train": [], "held_out": []}
+    report = {"train": [], "held_out": []}
+    if args.evaluate:
+        blob = tune.load_model(args.evaluate)
+        held_out(ctx, blob, args, report)
+        with open(os.path.join(args.out, "report_held_out.json"), "w") as f:
+            json.dump(report, f, indent=1, default=str)
+        return 0
+    Xs, ys, cid = [], [], []
     t0 = time.time()
-    for name, kw in TRAIN:
+    for name, kw in TRAIN[: args.cases]:
         for scale in (1.0, 4.0):
             text, ins, outs = build(name, kw, scale)
             wl = tune.Workload(ctx, text, ins, [1.0], outs)
-            splits = tune.candidates(wl, max_cost_ratio=64.0 if scale == 1.0 else 8.0,
-                                     extra=8 if scale == 1.0 else 0)
-            X, y, rows = tune.collect(wl, splits)
+            splits = tune.candidates(wl, max_cost_ratio=args.ratio, extra=6 if scale == 1.0 else 0,
+                                     limit=None if scale == 1.0 else 48)
+            print(f"[{time.time()-t0:6.1f}s] {name} {kw} x{scale}: timing {len(splits)} splits",
+                  flush=True)
+            X, y, rows = tune.collect(wl, splits, log=lambda m: print(m, flush=True),
+                                      budget=args.case_budget)
             Xs.append(X)
             ys.append(y)
+            cid.append(np.full(len(y), len(report["train"])))
             best = min(rows, key=lambda r: r[1])
             eq8 = wl.prog.choose_partition(PART_EQ8)
+            t_eq8 = dict(rows).get(eq8)
             report["train"].append({"case": [name, kw, scale], "M": wl.M, "A": wl.prog.A,
                                     "splits": len(rows), "best": best[0], "t_best": best[1],
-                                    "eq8": eq8})
+                                    "eq8": eq8, "t_eq8": t_eq8})
             print(f"[{time.time()-t0:6.1f}s] {name} {kw} x{scale}: M={wl.M} A={wl.prog.A} "
                   f"{len(rows)} splits, best {best[0]} {best[1]*1e3:.2f} ms", flush=True)
     X = np.concatenate(Xs)
     y = np.concatenate(ys)
-    np.save(os.path.join(args.out, "features.npy"), X)
-    np.save(os.path.join(args.out, "log_seconds.npy"), y)
+    case = np.concatenate(cid)
+    np.savez(os.path.join(args.out, "dataset.npz"), features=X, log_seconds=y, case=case)
     blob, loss = tune.train(X, y, epochs=args.epochs, lr=3e-3)
     print(f"trained on {len(y)} rows, loss {loss:.4f}", flush=True)
     tune.save_model(blob, {"rows": int(len(y)), "loss": loss, "epochs": args.epochs,
-                           "train": [[n, kw] for n, kw in TRAIN]})
-    for name, kw in HELD_OUT:
-        text, ins, outs = build(name, kw, 1.0)
-        wl = tune.Workload(ctx, text, ins, [1.0], outs)
-        splits = tune.candidates(wl, max_cost_ratio=64.0, extra=0)
-        r = tune.regret(wl, blob, splits)
-        r["case"] = [name, kw]
-        r["M"] = wl.M
-        report["held_out"].append(r)
-        print(f"held-out {name} {kw}: best {r['best']} {r['t_best']*1e3:.2f} ms, model "
-              f"{r['model']} {r['t_model']*1e3:.2f} ms, eq8 {r['eq8']} {r['t_eq8']*1e3:.2f} ms",
-              flush=True)
+                           "train": [[n, kw] for n, kw in TRAIN[: args.cases]]},
+                    path=args.model_out)
+    in_sample(blob, X, y, case, report)
+    held_out(ctx, blob, args, report)
     with open(os.path.join(args.out, "report.json"), "w") as f:
         json.dump(report, f, indent=1, default=str)
     return 0

@@ -30,8 +30,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import (N_FEATURES, PART_EQ8, PART_MODEL, Context, Program, mlp_adam, mlp_backward,
-               mlp_forward, mlp_param_count, mlp_workspace_size)
+from . import (N_FEATURES, PART_EQ8, PART_MODEL, Context, FhsError, Program, mlp_adam,
+               mlp_backward, mlp_forward, mlp_param_count, mlp_workspace_size)
 
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_model.json")
 SHAPE = (N_FEATURES, 32, 32)
@@ -67,11 +67,19 @@ class Workload:
         return self.ctx.plan(self.M, self.S)["table_bytes"]
 
 
-def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False) -> float:
-    """Best-of-`reps` wall time of one evaluation (graph replay), seconds."""
+def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False,
+               cutoff: Optional[float] = None) -> float:
+    """Best-of-`reps` wall time of one evaluation (graph replay), seconds.
+    The first, untimed-for-the-record run captures the graph; if it already
+    took longer than `cutoff` seconds its time is returned as is (a split
+    that slow is measured once, well enough to rank it last)."""
     import torch
+    t0 = time.perf_counter()
     wl.run(partition, plain)
     torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    if cutoff is not None and first > cutoff:
+        return first
     best = math.inf
     for _ in range(reps):
         t0 = time.perf_counter()
@@ -98,14 +106,17 @@ def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, 
 
 
 def candidates(wl: Workload, max_cost_ratio: float = 64.0, extra: int = 8,
-               max_table_bytes: int = 8 << 30, seed: int = 0) -> List[Tuple[int, int]]:
+               max_table_bytes: int = 8 << 30, seed: int = 0,
+               limit: Optional[int] = None) -> List[Tuple[int, int]]:
     """Candidate splits worth timing: every one within max_cost_ratio of the
-    Eq. (8) optimum, plus a few random others, all with a table that fits."""
+    Eq. (8) optimum (at most `limit`, cheapest first), plus a few random
+    others, all with a table that fits."""
     cand = wl.prog.candidate_splits()
     costs = {c: wl.prog.partition_cost(*c)[0] for c in cand}
     best = min(costs.values())
-    near = [c for c in cand if costs[c] <= max_cost_ratio * best]
-    far = [c for c in cand if costs[c] > max_cost_ratio * best]
+    ranked = sorted(cand, key=lambda c: (costs[c], c))
+    near = [c for c in ranked if costs[c] <= max_cost_ratio * best][:limit]
+    far = [c for c in ranked if c not in near]
     rng = np.random.default_rng(seed)
     if far and extra:
         idx = rng.choice(len(far), size=min(extra, len(far)), replace=False)
@@ -120,16 +131,33 @@ def candidates(wl: Workload, max_cost_ratio: float = 64.0, extra: int = 8,
     return keep
 
 
-def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2):
-    """Time every split; returns [(split, seconds)] and the fastest split."""
-    rows = [(c, time_split(wl, c, reps)) for c in splits]
+def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2, log=None,
+               slow_factor: float = 8.0, budget: Optional[float] = None):
+    """Time every split (in the given order, best guesses first); returns
+    [(split, seconds)] and the fastest split.  A split whose first run is
+    slower than `slow_factor` x the best so far is timed once; after
+    `budget` seconds the remaining splits are skipped.  `log`, if given, is
+    called with a progress string every few splits."""
+    rows = []
+    t0 = time.perf_counter()
+    best = math.inf
+    for i, c in enumerate(splits):
+        if budget is not None and rows and time.perf_counter() - t0 > budget:
+            if log is not None:
+                log(f"  budget reached: {len(rows)}/{len(splits)} splits timed")
+            break
+        t = time_split(wl, c, reps, cutoff=slow_factor * best if best < math.inf else None)
+        rows.append((c, t))
+        best = min(best, t)
+        if log is not None and (i + 1) % 16 == 0:
+            log(f"  {i + 1}/{len(splits)} splits timed, {time.perf_counter() - t0:.1f} s")
     best = min(rows, key=lambda r: (r[1], r[0]))[0]
     return rows, best
 
 
-def collect(wl: Workload, splits, reps: int = 2):
+def collect(wl: Workload, splits, reps: int = 2, log=None, budget: Optional[float] = None):
     """Feature rows and log-times for the given splits."""
-    rows, _ = exhaustive(wl, splits, reps)
+    rows, _ = exhaustive(wl, splits, reps, log, budget=budget)
     X = np.array([wl.prog.split_features(c[0], c[1], wl.M, wl.S) for c, _ in rows])
     y = np.log(np.array([t for _, t in rows]))
     return X, y, rows
@@ -138,8 +166,8 @@ def collect(wl: Workload, splits, reps: int = 2):
 def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, seed: int = 0,
           device: str = "cuda:0", log_every: int = 0):
     """Fit the network on the device (fhs_mlp_forward/backward/adam); returns
-    (blob, final training loss).  Features are standardised here and the
-    scaling travels in the blob."""
+    (blob, final training loss).  Features are standardised here; the
+    scaling and the per-feature training range travel in the blob."""
     import torch
     n_in, h1, h2 = SHAPE
     mu = X.mean(axis=0)
@@ -165,6 +193,7 @@ def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, se
     B = dX.shape[0]
     ws = torch.empty(mlp_workspace_size(SHAPE, B), dtype=torch.uint8, device=device)
     loss = torch.zeros(1, dtype=torch.float64, device=device)
+    lo, hi = X.min(axis=0), X.max(axis=0)
     for k in range(1, epochs + 1):
         mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
         mlp_adam(P, G, m, v, k, lr)
@@ -173,7 +202,7 @@ def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, se
             print(f"epoch {k} loss {loss.item():.5f}", flush=True)
     mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
     torch.cuda.synchronize()
-    blob = np.concatenate([[n_in, h1, h2], mu, sd, P.cpu().numpy()])
+    blob = np.concatenate([[n_in, h1, h2], mu, sd, lo, hi, P.cpu().numpy()])
     return blob, float(loss.item())
 
 
@@ -183,7 +212,7 @@ def predict(blob: np.ndarray, X: np.ndarray, device: str = "cuda:0") -> np.ndarr
     n_in, h1, h2 = (int(v) for v in blob[:3])
     mu = blob[3:3 + n_in]
     sd = blob[3 + n_in:3 + 2 * n_in]
-    P = torch.tensor(blob[3 + 2 * n_in:], dtype=torch.float64, device=device)
+    P = torch.tensor(blob[3 + 4 * n_in:], dtype=torch.float64, device=device)
     dX = torch.tensor((X - mu) / sd, dtype=torch.float64, device=device).contiguous()
     dY = torch.empty(X.shape[0], dtype=torch.float64, device=device)
     mlp_forward((n_in, h1, h2), P, dX, dY)
@@ -205,15 +234,37 @@ def load_model(path: str = MODEL_PATH) -> Optional[np.ndarray]:
     return np.array([float.fromhex(x) for x in d["blob"]], dtype=np.float64)
 
 
-def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2) -> Dict:
-    """Time the model's choice, Eq. (8)'s choice and the exhaustive best."""
-    wl.ctx.load_cost_model(blob)
-    rows, best = exhaustive(wl, splits, reps)
-    t_best = min(t for _, t in rows)
-    c_model = wl.ctx.choose_partition(PART_MODEL, wl.M, wl.S)
+def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
+           budget: Optional[float] = None) -> Tuple[Tuple[int, int], str]:
+    """The split to run: the cost model's argmin when the program lies in the
+    model's training range, else (or with no model) the fastest candidate by
+    exhaustive timing.  Returns (split, "model" | "timed")."""
+    if blob is not None:
+        wl.ctx.load_cost_model(blob)
+        try:
+            return wl.ctx.choose_partition(PART_MODEL, wl.M, wl.S), "model"
+        except FhsError as e:
+            if e.status != 3:      # FHS_ERANGE: outside the training range
+                raise
+    _, best = exhaustive(wl, candidates(wl, extra=0), reps, log, budget=budget)
+    return best, "timed"
+
+
+def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2, log=None) -> Dict:
+    """Time the model's choice, Eq. (8)'s choice and the exhaustive best.
+    The best time is the minimum over every timing taken, the two choices'
+    re-timings included, so that a regret is never negative."""
+    rows, best = exhaustive(wl, splits, reps, log)
+    c_model, how = choose(wl, blob, reps)
     c_eq8 = wl.prog.choose_partition(PART_EQ8)
     t_model = time_split(wl, c_model, reps)
     t_eq8 = time_split(wl, c_eq8, reps)
-    return {"best": best, "t_best": t_best, "model": c_model, "t_model": t_model,
+    t_best = min([t for _, t in rows] + [t_model, t_eq8])
+    if t_model == t_best:
+        best = c_model
+    elif t_eq8 == t_best and t_eq8 < min(t for _, t in rows):
+        best = c_eq8
+    return {"best": best, "t_best": t_best, "model": c_model, "how": how, "t_model": t_model,
             "eq8": c_eq8, "t_eq8": t_eq8, "model_regret": t_model / t_best - 1.0,
-            "eq8_regret": t_eq8 / t_best - 1.0, "gain_over_eq8": t_eq8 / t_model}
+            "eq8_regret": t_eq8 / t_best - 1.0, "gain_over_eq8": t_eq8 / t_model,
+            "splits_timed": len(rows)}

@@ -93,9 +93,45 @@ def test_model_choice_uses_the_network(dev):
         W1[0, 12] = 0.01 * sign
         W2[0, 0] = 1.0
         w3[0] = 1.0
-        blob = np.concatenate([[n_in, h1, h2], np.zeros(n_in), np.ones(n_in), params])
+        blob = np.concatenate([[n_in, h1, h2], np.zeros(n_in), np.ones(n_in),
+                               np.full(n_in, -1e9), np.full(n_in, 1e9), params])
         ctx.load_cost_model(blob)
         c = ctx.choose_partition(fhs.PART_MODEL, 64, 1)
         costs = [prog.partition_cost(*x)[0] for x in prog.candidate_splits()]
         want = min(costs) if sign > 0 else max(costs)
         assert prog.partition_cost(*c)[0] == want
+
+
+def _unit_blob(lo, hi):
+    n_in, h1, h2 = fhs.N_FEATURES, 1, 1
+    params = np.zeros(ref.param_count(n_in, h1, h2))
+    return np.concatenate([[n_in, h1, h2], np.zeros(n_in), np.ones(n_in), lo, hi, params])
+
+
+def test_model_outside_training_range(dev):
+    """Features outside the model's training box: FHS_ERANGE, and the tuner
+    falls back to timing the candidates; malformed blobs are refused."""
+    text = w.quantum_walk(12, 6).to_text()
+    prog = fhs.Program(text)
+    ctx = fhs.Context(0)
+    ctx.load(prog)
+    feats = np.array([prog.split_features(*c, 8, 1) for c in prog.candidate_splits()])
+    lo, hi = feats.min(axis=0), feats.max(axis=0)
+    ctx.load_cost_model(_unit_blob(lo, hi))
+    ctx.choose_partition(fhs.PART_MODEL, 8, 1)            # inside: fine
+    lo2 = lo.copy()
+    lo2[9] = hi[9] + 10.0 * (hi[9] - lo[9] + 1.0)         # log2(M S) far above every row
+    hi2 = hi.copy()
+    hi2[9] = lo2[9]
+    ctx.load_cost_model(_unit_blob(lo2, hi2))
+    with pytest.raises(fhs.FhsError) as e:
+        ctx.choose_partition(fhs.PART_MODEL, 8, 1)
+    assert e.value.status == 3
+    wl = tune.Workload(ctx, text, [0], [1.0], w.walk_outputs(12, 6, 8, seed=5))
+    split, how = tune.choose(wl, _unit_blob(lo2, hi2), reps=1)
+    assert how == "timed" and split in prog.candidate_splits()
+    bad = _unit_blob(hi, lo - 1.0)                         # lo > hi
+    with pytest.raises(fhs.FhsError):
+        ctx.load_cost_model(bad)
+    with pytest.raises(fhs.FhsError):
+        ctx.load_cost_model(bad[:-1])
