@@ -129,34 +129,29 @@ def main() -> int:
         del src, dst
     cfg = w.CONFIGS[args.workload]()
     text = cfg["circuit"].to_text()
-    prog = fhs.Program(text)
     ctx = fhs.Context(0)
-    ctx.load(prog)
     M, S = len(cfg["outputs"]), len(cfg["inputs"])
+    thr = cfg["threshold"]
+    ctx.set_table_budget(32 << 30)          # one batch: the whole workload in HBM
+    from paper_2608_01467_amd import tune
+    wl = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
+                       cfg["outputs"], thr)
+    prog = wl.prog              # loaded into ctx
     part_eq8 = prog.choose_partition(fhs.PART_EQ8)
     how = args.partition
+    t_setup = time.perf_counter()
     if args.partition == "model":
-        from paper_2608_01467_amd import tune
         blob = tune.load_model(args.cost_model) if args.cost_model else tune.load_model()
-        part = None
-        if blob is not None:
-            ctx.load_cost_model(blob)
-            try:
-                part = ctx.choose_partition(fhs.PART_MODEL, M, S)
-            except fhs.FhsError as e:
-                if e.status != 3:
-                    raise
-        if part is None:
-            part, how = part_eq8, "eq8 (no cost model for this range)"
+        # the model's three best predictions and the Eq. (8) optimum, timed
+        # once each on this workload (or every candidate without a model)
+        part, how = tune.choose(wl, blob, reps=1, shortlist=3) if blob is not None else \
+            (part_eq8, "eq8 (no cost model)")
     else:
         mode = {"eq8": fhs.PART_EQ8, "thirds": fhs.PART_THIRDS, "none": fhs.PART_NONE}
         part = prog.choose_partition(mode[args.partition])
+    t_setup = time.perf_counter() - t_setup
     ctx.set_partition(*part)
-    ctx.set_table_budget(32 << 30)          # one batch: the whole workload in HBM
-    thr = cfg["threshold"]
-    d_in = ctx.device_bits(cfg["inputs"])
-    d_out = ctx.device_bits(cfg["outputs"])
-    d_cf = ctx.device_coeffs([complex(*z) for z in cfg["coeffs"]])
+    d_in, d_out, d_cf = wl.d_in, wl.d_out, wl.d_cf
     amps = torch.empty((M, 2), dtype=torch.float64, device="cuda:0")
     stats = torch.empty((M, 4), dtype=torch.int64, device="cuda:0")
     def step(plain=False):
@@ -181,20 +176,26 @@ def main() -> int:
         torch.cuda.synchronize()
         kt += ctx.kernel_times()
     T_timed = (time.perf_counter() - t0) / max(args.steps, 1)
+    n_entries, n_valid_entries = ctx.kernel_counts()
     ctx.set_kernel_timing(False)
+
     leaves = int(st[:, 3].sum())
     valid = int(st[:, 0].sum())
     cand = M * S * (1 << prog.A)
-
     plan = ctx.plan(M, S)
-    # algorithmic work of one consumer launch (Eq. (8) counts of its regions)
+    # Algorithmic work of the consumer per step, summed over the gates that
+    # must be evaluated: the root region once for each of the 2^Ar root
+    # assignments of every prefix entry still consistent after the prefix
+    # region, the suffix region once per leaf walked (2^As per consistent
+    # root).  Redundant evaluations the kernel makes for parallelism (root
+    # re-runs by the lanes that share a root task, lanes that idle inside a
+    # wave) do not count.
     root = prog.work(plan["c1"], plan["c2"])
     suffix = prog.work(plan["c2"], prog.G)
-    pairs = plan["pairs_per_batch"]
-    n_root = pairs << (plan["Ap"] + plan["Ar"])
-    n_leaf = pairs << prog.A
-    int_ops = n_root * root["int_ops"] + n_leaf * suffix["int_ops"]
-    flops = n_root * root["fp64_flops"] + n_leaf * suffix["fp64_flops"]
+    launches = max(1, len(kt) // max(args.steps, 1))
+    n_root = n_valid_entries << plan["Ar"]
+    int_ops = (n_root * root["int_ops"] + leaves * suffix["int_ops"]) / launches
+    flops = (n_root * root["fp64_flops"] + leaves * suffix["fp64_flops"]) / launches
     avg_launch = sum(kt) / len(kt) / 1e3
     int_rate = int_ops / avg_launch
     fp_rate = flops / avg_launch
@@ -208,7 +209,12 @@ def main() -> int:
     roof["traffic"] = tb
     roof["kernel"] = "k_consume"
     roof["avg_launch_ms"] = avg_launch * 1e3
-    roof["launches_per_step"] = len(kt) // max(args.steps, 1)
+    roof["launches_per_step"] = launches
+    roof["work"] = {"prefix_entries": n_entries, "prefix_entries_consistent": n_valid_entries,
+                    "root_evaluations": n_root, "leaves": leaves,
+                    "root_int_ops": root["int_ops"], "suffix_int_ops": suffix["int_ops"],
+                    "root_fp64_flops": root["fp64_flops"],
+                    "suffix_fp64_flops": suffix["fp64_flops"]}
     roof["ms_per_step_timed"] = T_timed * 1e3
     roof["fp64_tflops"] = fp_rate / 1e12
     roof["int32_tops"] = int_rate / 1e12
@@ -230,7 +236,7 @@ def main() -> int:
             "workload": args.workload,
             "qubits": prog.n, "gates": prog.G, "sources": prog.A,
             "outputs": M, "inputs": S, "threshold": thr,
-            "partition": list(part), "partition_mode": how,
+            "partition": list(part), "partition_mode": how, "partition_setup_s": t_setup,
             "regions": [plan["Ap"], plan["Ar"], plan["As"]],
         },
         "amplitudes_per_s": M * S / T,

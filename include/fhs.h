@@ -176,6 +176,14 @@ fhs_status fhs_get_launch_config(const fhs_ctx *ctx, fhs_launch_config *cfg);
 fhs_status fhs_set_kernel_timing(fhs_ctx *ctx, int enable);
 fhs_status fhs_kernel_times(fhs_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
 
+/* Work counts of the most recent fhs_evaluate run in timing mode (Section
+ * IV-C, Algorithm 2): prefix-table entries built (M S 2^Ap) and those still
+ * consistent after the prefix region, i.e. the entries whose 2^Ar root
+ * assignments the consumer evaluates.  Counted by a separate kernel after
+ * each table build, outside the timed interval.  Blocks until that count
+ * is available.  FHS_ESTATE if timing is off or nothing was timed. */
+fhs_status fhs_kernel_counts(fhs_ctx *ctx, uint64_t *prefix_entries, uint64_t *prefix_valid);
+
 /* Work layout fhs_evaluate would use for M outputs and S inputs.  The cuts
  * are the effective ones: the source-free gates nearest the output run once
  * per pair in the precheck, so a cut below n_leading moves up to it (the
@@ -260,9 +268,11 @@ fhs_status fhs_candidate_splits(const fhs_program *prog, uint32_t *c1, uint32_t 
 /* Load a trained cost model into ctx: blob = [n_in, h1, h2, mu[n_in],
  * sd[n_in], lo[n_in], hi[n_in], params...] (doubles; n_in =
  * FHS_N_FEATURES; features are standardised as (f - mu) / sd; [lo, hi] is
- * the per-feature range of the training rows).  The prediction is
- * log(seconds).  FHS_EINVAL on a wrong shape or size, sd <= 0 or lo > hi;
- * the blob is copied (the caller keeps ownership). */
+ * the per-feature range of the training rows).  params holds K >= 1
+ * networks of that shape back to back (K <= 64, from the blob's length);
+ * their outputs are averaged into the predicted log(seconds).
+ * FHS_EINVAL on a wrong shape or size, sd <= 0 or lo > hi; the blob is
+ * copied (the caller keeps ownership). */
 fhs_status fhs_load_cost_model(fhs_ctx *ctx, const double *blob, size_t n);
 
 /* fhs_choose_partition with access to the device: FHS_PART_MODEL scores
@@ -276,6 +286,14 @@ fhs_status fhs_load_cost_model(fhs_ctx *ctx, const double *blob, size_t n);
  * program or model. */
 fhs_status fhs_choose_partition_ctx(fhs_ctx *ctx, int mode, uint32_t M, uint32_t S, uint32_t *c1,
                                     uint32_t *c2);
+
+/* The loaded model's predicted log(seconds) of the n splits (c1[i], c2[i])
+ * for M outputs and S inputs (host arrays), NaN for a split whose features
+ * fall outside the training range.  Lets a tuner shortlist splits by
+ * prediction and time only the shortlist.  FHS_EINVAL on a split with
+ * c1 > c2 or c2 > G, or M or S = 0; FHS_ESTATE without a program or model. */
+fhs_status fhs_predict_splits(fhs_ctx *ctx, uint32_t M, uint32_t S, const uint32_t *c1,
+                              const uint32_t *c2, uint32_t n, double *log_seconds);
 
 /* Network x -> tanh(W1 x + b1) -> tanh(W2 a1 + b2) -> w3.a2 + b3 in FP64,
  * n_in, h1, h2 in [1, 64].  Flat parameters, in order: W1 [h1][n_in]

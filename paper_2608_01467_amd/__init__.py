@@ -34,9 +34,9 @@ EXPORTS = [
     "fhs_ctx_destroy", "fhs_last_error", "fhs_load_program", "fhs_set_partition",
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
     "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
-    "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_get_plan",
+    "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_kernel_counts", "fhs_get_plan",
     "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
-    "fhs_choose_partition_ctx", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
+    "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
     "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam",
 ]
 
@@ -111,12 +111,14 @@ def lib() -> ctypes.CDLL:
         L.fhs_set_kernel_timing.argtypes = [P, I32]
         L.fhs_get_plan.argtypes = [P, U32, U32, ctypes.POINTER(Plan)]
         L.fhs_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), U32, ctypes.POINTER(U32)]
+        L.fhs_kernel_counts.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.fhs_set_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         pD = ctypes.POINTER(ctypes.c_double)
         L.fhs_split_features.argtypes = [P, U32, U32, U32, U32, pD]
         L.fhs_candidate_splits.argtypes = [P, pU32, pU32, U32, pU32]
         L.fhs_load_cost_model.argtypes = [P, pD, ctypes.c_size_t]
         L.fhs_choose_partition_ctx.argtypes = [P, I32, U32, U32, pU32, pU32]
+        L.fhs_predict_splits.argtypes = [P, U32, U32, pU32, pU32, U32, pD]
         pS = ctypes.POINTER(MlpShape)
         L.fhs_mlp_param_count.argtypes = [pS, ctypes.POINTER(ctypes.c_size_t)]
         L.fhs_mlp_workspace_size.argtypes = [pS, U32, ctypes.POINTER(ctypes.c_size_t)]
@@ -274,8 +276,24 @@ class Context:
                                               ctypes.byref(c2)), self)
         return c1.value, c2.value
 
+    def predict_splits(self, splits, M: int, S: int = 1) -> np.ndarray:
+        """Predicted log(seconds) per split (NaN outside the training range)."""
+        n = len(splits)
+        a = (ctypes.c_uint32 * max(1, n))(*[c[0] for c in splits])
+        b = (ctypes.c_uint32 * max(1, n))(*[c[1] for c in splits])
+        out = (ctypes.c_double * max(1, n))()
+        _check(lib().fhs_predict_splits(self._h, M, S, a, b, n, out), self)
+        return np.array(out[:n], dtype=np.float64)
+
     def set_kernel_timing(self, enable: bool) -> None:
         _check(lib().fhs_set_kernel_timing(self._h, 1 if enable else 0), self)
+
+    def kernel_counts(self) -> Tuple[int, int]:
+        """(prefix entries built, prefix entries still consistent) of the last
+        evaluation in timing mode."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().fhs_kernel_counts(self._h, ctypes.byref(a), ctypes.byref(b)), self)
+        return a.value, b.value
 
     def kernel_times(self) -> list:
         """Durations (ms) of the hot-kernel launches of the last evaluation."""

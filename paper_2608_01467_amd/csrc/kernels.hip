@@ -22,6 +22,7 @@
 //   k_pair_reduce / k_finalize: fixed-order sums, then Eq. (2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -666,6 +667,21 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
     block_reduce_store<NT>(acc, l_red, part, blockIdx.x);
 }
 
+// Number of nonzero flags in ok[0..n): one ballot per wave, one global
+// (vector) atomic add per wave.  Used only when kernel timing is on, to
+// report how many prefix-table entries the consumer expands.
+__global__ __launch_bounds__(256) void k_count_valid(const uint32_t *ok, uint64_t n,
+                                                     unsigned long long *out) {
+    uint64_t cnt = 0;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * blockDim.x; base < n; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        const bool v = i < n && ok[i] != 0u;
+        cnt += static_cast<uint64_t>(__popcll(__ballot(v)));
+    }
+    if ((threadIdx.x & 63u) == 0u && cnt) atomicAdd(out, static_cast<unsigned long long>(cnt));
+}
+
 __global__ void k_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
                               uint32_t ipp, uint32_t A) {
     const uint32_t pl = blockIdx.x * blockDim.x + threadIdx.x;
@@ -837,6 +853,14 @@ hipError_t launch_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t 
                               uint32_t ipp, uint32_t A, hipStream_t s) {
     if (B == 0) return hipSuccess;
     k_pair_reduce<<<(B + 255) / 256, 256, 0, s>>>(pre, part, res, p0, B, ipp, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_valid(const uint32_t *ok, uint64_t n, unsigned long long *out,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+    k_count_valid<<<static_cast<uint32_t>(blocks), 256, 0, s>>>(ok, n, out);
     return hipGetLastError();
 }
 

@@ -66,6 +66,9 @@ hipError_t launch_plain(const Common &c, int NW, int H, PreBufs pre, Partials pa
                         uint32_t blocks_per_pair, hipStream_t s);
 hipError_t launch_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
                               uint32_t items_per_pair, uint32_t A, hipStream_t s);
+// Adds the number of nonzero ok[0..n) flags to *out.
+hipError_t launch_count_valid(const uint32_t *ok, uint64_t n, unsigned long long *out,
+                              hipStream_t s);
 hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32_t M,
                            double *amps, uint64_t *stats, hipStream_t s);
 

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -95,10 +96,14 @@ struct fhs_ctx {
     bool have_model = false;
     fhs_mlp_shape model_shape{0, 0, 0};
     std::vector<double> model_mu, model_sd, model_lo, model_hi;
-    double *d_model = nullptr;
+    double *d_model = nullptr;      // model_k networks, model_np parameters each
+    uint32_t model_k = 0;
+    size_t model_np = 0;
     bool timing = false;            // record events around hot-kernel launches
     std::vector<hipEvent_t> events; // [2 * launches]: start, end
     uint32_t n_timed = 0;
+    unsigned long long *d_valid = nullptr;  // timing mode: consistent prefix entries
+    uint64_t n_entries = 0;                 // timing mode: prefix entries built
 };
 
 namespace {
@@ -324,6 +329,12 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         if (items < grid) grid = static_cast<uint32_t>(items);
         e = launch_prefix(cm, NW, pre, tab, p0, B, s);
         if (e != hipSuccess) return e;
+        if (timed) {
+            // outside the timed interval: how many entries the consumer expands
+            e = launch_count_valid(tab.ok, static_cast<uint64_t>(B) << pl.Ap, c->d_valid, s);
+            if (e != hipSuccess) return e;
+            c->n_entries += static_cast<uint64_t>(B) << pl.Ap;
+        }
         if (timed && (e = hipEventRecord(c->events[2 * b], s)) != hipSuccess) return e;
         e = launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
@@ -365,6 +376,7 @@ extern "C" void fhs_ctx_destroy(fhs_ctx *c) {
     free_program(c);
     fhs_program_free(c->prog_copy);
     if (c->d_model) hipFree(c->d_model);
+    if (c->d_valid) hipFree(c->d_valid);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
@@ -398,6 +410,8 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     return FHS_OK;
 }
 
+constexpr uint32_t kMaxEnsemble = 64;   // networks in one cost model
+
 extern "C" fhs_status fhs_load_cost_model(fhs_ctx *c, const double *blob, size_t n) {
     if (!c || !blob || n < 3) return FHS_EINVAL;
     c->err.clear();
@@ -407,24 +421,96 @@ extern "C" fhs_status fhs_load_cost_model(fhs_ctx *c, const double *blob, size_t
     if (sh.n_in != FHS_N_FEATURES || fhs_mlp_param_count(&sh, &np) != FHS_OK)
         return fail(c, FHS_EINVAL, "cost model shape");
     const size_t F = sh.n_in;
-    if (n != 3 + 4 * F + np) return fail(c, FHS_EINVAL, "cost model size");
+    // an ensemble of K networks of one shape, predictions averaged
+    if (n <= 3 + 4 * F || (n - 3 - 4 * F) % np != 0) return fail(c, FHS_EINVAL, "cost model size");
+    const size_t K = (n - 3 - 4 * F) / np;
+    if (K > kMaxEnsemble) return fail(c, FHS_EINVAL, "cost model ensemble of %zu > %u networks", K, kMaxEnsemble);
     for (size_t i = 0; i < F; ++i) {
         if (!(blob[3 + F + i] > 0.0)) return fail(c, FHS_EINVAL, "cost model scale must be > 0");
         if (!(blob[3 + 2 * F + i] <= blob[3 + 3 * F + i]))
             return fail(c, FHS_EINVAL, "cost model range: lo > hi for feature %zu", i);
     }
     FHS_HIP(c, hipSetDevice(c->device));
+    c->have_model = false;
     if (c->d_model) hipFree(c->d_model);
     c->d_model = nullptr;
-    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_model), sizeof(double) * np));
-    FHS_HIP(c, hipMemcpy(c->d_model, blob + 3 + 4 * F, sizeof(double) * np, hipMemcpyHostToDevice));
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_model), sizeof(double) * K * np));
+    FHS_HIP(c, hipMemcpy(c->d_model, blob + 3 + 4 * F, sizeof(double) * K * np, hipMemcpyHostToDevice));
     c->model_shape = sh;
+    c->model_k = static_cast<uint32_t>(K);
+    c->model_np = np;
     c->model_mu.assign(blob + 3, blob + 3 + F);
     c->model_sd.assign(blob + 3 + F, blob + 3 + 2 * F);
     c->model_lo.assign(blob + 3 + 2 * F, blob + 3 + 3 * F);
     c->model_hi.assign(blob + 3 + 3 * F, blob + 3 + 4 * F);
     c->have_model = true;
     return FHS_OK;
+}
+
+namespace {
+
+// Predicted log(seconds) of the splits (a[i], b[i]) for M outputs and S
+// inputs; NaN where a split's features fall outside the model's training
+// box (per-feature [lo, hi] widened by 5% of its width).  One forward pass
+// of the network on the device for all in-range splits.
+fhs_status predict_splits(fhs_ctx *c, uint32_t M, uint32_t S, const uint32_t *a,
+                          const uint32_t *b, uint32_t n, double *out) {
+    const uint32_t F = c->model_shape.n_in;
+    std::vector<double> X;
+    std::vector<uint32_t> idx;
+    std::vector<double> f(F);
+    for (uint32_t i = 0; i < n; ++i) {
+        out[i] = std::numeric_limits<double>::quiet_NaN();
+        fhs_status st = fhs_split_features(c->prog_copy, a[i], b[i], M, S, f.data());
+        if (st != FHS_OK) return fail(c, st, "features of split (%u, %u)", a[i], b[i]);
+        bool in = true;
+        for (uint32_t k = 0; k < F && in; ++k) {
+            const double pad = 0.05 * (c->model_hi[k] - c->model_lo[k]);
+            in = f[k] >= c->model_lo[k] - pad && f[k] <= c->model_hi[k] + pad;
+        }
+        if (!in) continue;
+        idx.push_back(i);
+        for (uint32_t k = 0; k < F; ++k) X.push_back((f[k] - c->model_mu[k]) / c->model_sd[k]);
+    }
+    const uint32_t m = static_cast<uint32_t>(idx.size());
+    if (m == 0) return FHS_OK;
+    const uint32_t K = c->model_k;
+    std::vector<double> Y(static_cast<size_t>(K) * m);
+    FHS_HIP(c, hipSetDevice(c->device));
+    double *dx = nullptr, *dy = nullptr;
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&dx), sizeof(double) * X.size()));
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&dy), sizeof(double) * Y.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, c->cap_stream);
+    for (uint32_t k = 0; k < K && e == hipSuccess; ++k)
+        e = mlp_forward(&c->model_shape, c->d_model + k * c->model_np, dx, m, dy + static_cast<size_t>(k) * m,
+                        nullptr, c->cap_stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Y.data(), dy, sizeof(double) * Y.size(), hipMemcpyDeviceToHost, c->cap_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->cap_stream);
+    hipFree(dx);
+    if (dy) hipFree(dy);
+    if (e != hipSuccess) return hip_fail(c, e, "cost model inference");
+    // mean over the ensemble, in network order
+    for (uint32_t j = 0; j < m; ++j) {
+        double y = 0.0;
+        for (uint32_t k = 0; k < K; ++k) y += Y[static_cast<size_t>(k) * m + j];
+        out[idx[j]] = y / K;
+    }
+    return FHS_OK;
+}
+
+}  // namespace
+
+extern "C" fhs_status fhs_predict_splits(fhs_ctx *c, uint32_t M, uint32_t S, const uint32_t *c1,
+                                         const uint32_t *c2, uint32_t n, double *log_seconds) {
+    if (!c || (n && (!c1 || !c2 || !log_seconds))) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->loaded || !c->prog_copy) return fail(c, FHS_ESTATE, "no program loaded");
+    if (!c->have_model) return fail(c, FHS_ESTATE, "no cost model loaded");
+    if (M == 0 || S == 0) return fail(c, FHS_EINVAL, "M and S must be >= 1");
+    for (uint32_t i = 0; i < n; ++i)
+        if (c1[i] > c2[i] || c2[i] > static_cast<uint32_t>(c->prog.G))
+            return fail(c, FHS_EINVAL, "split %u: need c1 <= c2 <= G (%u, %u)", i, c1[i], c2[i]);
+    return predict_splits(c, M, S, c1, c2, n, log_seconds);
 }
 
 extern "C" fhs_status fhs_choose_partition_ctx(fhs_ctx *c, int mode, uint32_t M, uint32_t S,
@@ -434,62 +520,34 @@ extern "C" fhs_status fhs_choose_partition_ctx(fhs_ctx *c, int mode, uint32_t M,
     if (!c->loaded || !c->prog_copy) return fail(c, FHS_ESTATE, "no program loaded");
     if (mode != FHS_PART_MODEL) return fhs_choose_partition(c->prog_copy, mode, c1, c2);
     if (!c->have_model) return fail(c, FHS_ESTATE, "no cost model loaded");
+    if (M == 0 || S == 0) return fail(c, FHS_EINVAL, "M and S must be >= 1");
     uint32_t n = 0;
     fhs_candidate_splits(c->prog_copy, nullptr, nullptr, 0, &n);
     std::vector<uint32_t> a(n), b(n);
     fhs_candidate_splits(c->prog_copy, a.data(), b.data(), n, &n);
-    const uint32_t F = c->model_shape.n_in;
-    // Only splits whose features lie inside the training box (per-feature
-    // [lo, hi] widened by 5% of its width) are scored; if no split of
-    // minimal Eq. (8) cost is among them the model is not trusted for this
-    // program.
+    std::vector<double> Y(n);
+    fhs_status st = predict_splits(c, M, S, a.data(), b.data(), n, Y.data());
+    if (st != FHS_OK) return st;
+    // The model is trusted for this program only if some split of minimal
+    // Eq. (8) cost lies in its training range.
     uint32_t e1 = 0, e2 = 0;
     uint64_t emin[2] = {0, 0}, cost[2] = {0, 0};
-    fhs_status st = fhs_choose_partition(c->prog_copy, FHS_PART_EQ8, &e1, &e2);
+    st = fhs_choose_partition(c->prog_copy, FHS_PART_EQ8, &e1, &e2);
     if (st == FHS_OK) st = fhs_partition_cost(c->prog_copy, e1, e2, emin, nullptr);
     if (st != FHS_OK) return fail(c, st, "Eq. (8) split");
-    std::vector<double> X;
-    std::vector<uint32_t> ka, kb;
-    std::vector<double> f(F);
     bool eq8_in = false;
+    int best = -1;
     for (uint32_t i = 0; i < n; ++i) {
-        st = fhs_split_features(c->prog_copy, a[i], b[i], M, S, f.data());
-        if (st != FHS_OK) return fail(c, st, "features");
-        bool in = true;
-        for (uint32_t k = 0; k < F && in; ++k) {
-            const double pad = 0.05 * (c->model_hi[k] - c->model_lo[k]);
-            in = f[k] >= c->model_lo[k] - pad && f[k] <= c->model_hi[k] + pad;
-        }
-        if (!in) continue;
+        if (std::isnan(Y[i])) continue;
         st = fhs_partition_cost(c->prog_copy, a[i], b[i], cost, nullptr);
         if (st != FHS_OK) return fail(c, st, "Eq. (8) cost");
         if (cost[0] == emin[0] && cost[1] == emin[1]) eq8_in = true;
-        ka.push_back(a[i]);
-        kb.push_back(b[i]);
-        for (uint32_t k = 0; k < F; ++k) X.push_back((f[k] - c->model_mu[k]) / c->model_sd[k]);
+        if (best < 0 || Y[i] < Y[best] ||
+            (Y[i] == Y[best] && (a[i] < a[best] || (a[i] == a[best] && b[i] < b[best]))))
+            best = static_cast<int>(i);
     }
-    if (!eq8_in)
+    if (!eq8_in || best < 0)
         return fail(c, FHS_ERANGE, "split features outside the cost model's training range");
-    n = static_cast<uint32_t>(ka.size());
-    a.swap(ka);
-    b.swap(kb);
-    std::vector<double> Y(n);
-    FHS_HIP(c, hipSetDevice(c->device));
-    double *dx = nullptr, *dy = nullptr;
-    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&dx), sizeof(double) * X.size()));
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&dy), sizeof(double) * n);
-    if (e == hipSuccess) e = hipMemcpyAsync(dx, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, c->cap_stream);
-    if (e == hipSuccess) e = mlp_forward(&c->model_shape, c->d_model, dx, n, dy, nullptr, c->cap_stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(Y.data(), dy, sizeof(double) * n, hipMemcpyDeviceToHost, c->cap_stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->cap_stream);
-    hipFree(dx);
-    if (dy) hipFree(dy);
-    if (e != hipSuccess) return hip_fail(c, e, "cost model inference");
-    uint32_t best = 0;
-    for (uint32_t i = 1; i < n; ++i) {
-        if (Y[i] < Y[best] || (Y[i] == Y[best] && (a[i] < a[best] || (a[i] == a[best] && b[i] < b[best]))))
-            best = i;
-    }
     *c1 = a[best];
     *c2 = b[best];
     return FHS_OK;
@@ -566,9 +624,27 @@ extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs
 
 extern "C" fhs_status fhs_set_kernel_timing(fhs_ctx *c, int enable) {
     if (!c) return FHS_EINVAL;
+    c->err.clear();
+    if (enable && !c->d_valid) {
+        FHS_HIP(c, hipSetDevice(c->device));
+        FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_valid), sizeof(unsigned long long)));
+    }
     c->timing = enable != 0;
     c->n_timed = 0;
+    c->n_entries = 0;
     drop_graph(c);
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_kernel_counts(fhs_ctx *c, uint64_t *prefix_entries, uint64_t *prefix_valid) {
+    if (!c || !prefix_entries || !prefix_valid) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->timing || c->n_timed == 0) return fail(c, FHS_ESTATE, "no timed launch");
+    unsigned long long v = 0;
+    FHS_HIP(c, hipSetDevice(c->device));
+    FHS_HIP(c, hipMemcpy(&v, c->d_valid, sizeof(v), hipMemcpyDeviceToHost));
+    *prefix_entries = c->n_entries;
+    *prefix_valid = v;
     return FHS_OK;
 }
 
@@ -625,7 +701,12 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
         int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
-        if (timed) FHS_HIP(c, ensure_events(c, pl.n_batches));
+        if (timed) {
+            FHS_HIP(c, ensure_events(c, pl.n_batches));
+            // not captured: a plain memset is fine here
+            FHS_HIP(c, hipMemsetAsync(c->d_valid, 0, sizeof(unsigned long long), s));
+            c->n_entries = 0;
+        }
         FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s));
         c->n_timed = timed ? pl.n_batches : 0;
         return FHS_OK;

@@ -163,61 +163,73 @@ def collect(wl: Workload, splits, reps: int = 2, log=None, budget: Optional[floa
     return X, y, rows
 
 
-def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, seed: int = 0,
-          device: str = "cuda:0", log_every: int = 0):
-    """Fit the network on the device (fhs_mlp_forward/backward/adam); returns
-    (blob, final training loss).  Features are standardised here; the
-    scaling and the per-feature training range travel in the blob."""
+def train(X: np.ndarray, y: np.ndarray, epochs: int = 3000, lr: float = 3e-3, ensemble: int = 5,
+          seed: int = 0, device: str = "cuda:0", log_every: int = 0):
+    """Fit `ensemble` networks (different initialisations) on the device with
+    fhs_mlp_backward / fhs_mlp_adam to the log times `y`; returns (blob,
+    training loss of the averaged prediction).  Features are standardised
+    here; the scaling and the per-feature training range travel in the
+    blob."""
     import torch
     n_in, h1, h2 = SHAPE
     mu = X.mean(axis=0)
     sd = X.std(axis=0)
     sd[sd < 1e-9] = 1.0
+    lo, hi = X.min(axis=0), X.max(axis=0)
     Xs = (X - mu) / sd
-    rng = np.random.default_rng(seed)
-    # Glorot-uniform initialisation
-    parts = []
-    for fo, fi in ((h1, n_in), (h2, h1)):
-        lim = math.sqrt(6.0 / (fi + fo))
-        parts += [rng.uniform(-lim, lim, fo * fi), np.zeros(fo)]
-    parts += [rng.uniform(-math.sqrt(6.0 / (h2 + 1)), math.sqrt(6.0 / (h2 + 1)), h2),
-              np.array([y.mean()])]
-    p0 = np.concatenate(parts)
-    assert p0.size == mlp_param_count(n_in, h1, h2)
-    P = torch.tensor(p0, dtype=torch.float64, device=device)
-    G = torch.zeros_like(P)
-    m = torch.zeros_like(P)
-    v = torch.zeros_like(P)
     dX = torch.tensor(Xs, dtype=torch.float64, device=device).contiguous()
     dT = torch.tensor(y, dtype=torch.float64, device=device).contiguous()
     B = dX.shape[0]
     ws = torch.empty(mlp_workspace_size(SHAPE, B), dtype=torch.uint8, device=device)
     loss = torch.zeros(1, dtype=torch.float64, device=device)
-    lo, hi = X.min(axis=0), X.max(axis=0)
-    for k in range(1, epochs + 1):
-        mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
-        mlp_adam(P, G, m, v, k, lr)
-        if log_every and k % log_every == 0:
-            torch.cuda.synchronize()
-            print(f"epoch {k} loss {loss.item():.5f}", flush=True)
-    mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
-    torch.cuda.synchronize()
-    blob = np.concatenate([[n_in, h1, h2], mu, sd, lo, hi, P.cpu().numpy()])
-    return blob, float(loss.item())
+    nets = []
+    for k in range(ensemble):
+        rng = np.random.default_rng(seed + k)
+        parts = []
+        for fo, fi in ((h1, n_in), (h2, h1)):          # Glorot-uniform weights
+            lim = math.sqrt(6.0 / (fi + fo))
+            parts += [rng.uniform(-lim, lim, fo * fi), np.zeros(fo)]
+        lim = math.sqrt(6.0 / (h2 + 1))
+        parts += [rng.uniform(-lim, lim, h2), np.array([y.mean()])]
+        p0 = np.concatenate(parts)
+        assert p0.size == mlp_param_count(n_in, h1, h2)
+        P = torch.tensor(p0, dtype=torch.float64, device=device)
+        G = torch.zeros_like(P)
+        m = torch.zeros_like(P)
+        v = torch.zeros_like(P)
+        for it in range(1, epochs + 1):
+            mlp_backward(SHAPE, P, dX, dT, G, loss, ws)
+            mlp_adam(P, G, m, v, it, lr)
+            if log_every and it % log_every == 0:
+                torch.cuda.synchronize()
+                print(f"network {k} epoch {it} loss {loss.item():.5f}", flush=True)
+        torch.cuda.synchronize()
+        nets.append(P.cpu().numpy())
+    blob = np.concatenate([[n_in, h1, h2], mu, sd, lo, hi] + nets)
+    pred = predict(blob, X, device)
+    return blob, float(np.mean((pred - y) ** 2))
 
 
 def predict(blob: np.ndarray, X: np.ndarray, device: str = "cuda:0") -> np.ndarray:
-    """Model output for raw feature rows, through fhs_mlp_forward."""
+    """Predicted log(seconds) for raw feature rows: fhs_mlp_forward per
+    network of the blob, averaged."""
     import torch
     n_in, h1, h2 = (int(v) for v in blob[:3])
     mu = blob[3:3 + n_in]
     sd = blob[3 + n_in:3 + 2 * n_in]
-    P = torch.tensor(blob[3 + 4 * n_in:], dtype=torch.float64, device=device)
+    params = blob[3 + 4 * n_in:]
+    npar = mlp_param_count(n_in, h1, h2)
+    assert params.size % npar == 0
     dX = torch.tensor((X - mu) / sd, dtype=torch.float64, device=device).contiguous()
     dY = torch.empty(X.shape[0], dtype=torch.float64, device=device)
-    mlp_forward((n_in, h1, h2), P, dX, dY)
-    torch.cuda.synchronize()
-    return dY.cpu().numpy()
+    out = np.zeros(X.shape[0])
+    K = params.size // npar
+    for k in range(K):
+        P = torch.tensor(params[k * npar:(k + 1) * npar], dtype=torch.float64, device=device)
+        mlp_forward((n_in, h1, h2), P, dX, dY)
+        torch.cuda.synchronize()
+        out += dY.cpu().numpy()
+    return out / K
 
 
 def save_model(blob: np.ndarray, meta: Dict, path: str = MODEL_PATH) -> None:
@@ -235,36 +247,55 @@ def load_model(path: str = MODEL_PATH) -> Optional[np.ndarray]:
 
 
 def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
-           budget: Optional[float] = None) -> Tuple[Tuple[int, int], str]:
-    """The split to run: the cost model's argmin when the program lies in the
-    model's training range, else (or with no model) the fastest candidate by
-    exhaustive timing.  Returns (split, "model" | "timed")."""
+           budget: Optional[float] = None, shortlist: int = 0) -> Tuple[Tuple[int, int], str]:
+    """The split to run.  With a model whose training range covers the
+    program: its argmin (shortlist = 0), or, with shortlist = k > 0, the
+    fastest by measurement among the model's k best predictions and the
+    Eq. (8) optimum.  Otherwise, or with no model, the fastest candidate by
+    exhaustive timing.  Returns (split, "model" | "model+timed" | "timed")."""
     if blob is not None:
         wl.ctx.load_cost_model(blob)
         try:
-            return wl.ctx.choose_partition(PART_MODEL, wl.M, wl.S), "model"
+            pick = wl.ctx.choose_partition(PART_MODEL, wl.M, wl.S)
         except FhsError as e:
             if e.status != 3:      # FHS_ERANGE: outside the training range
                 raise
+            pick = None
+        if pick is not None and shortlist <= 0:
+            return pick, "model"
+        if pick is not None:
+            cand = wl.prog.candidate_splits()
+            pred = wl.ctx.predict_splits(cand, wl.M, wl.S)
+            order = [cand[i] for i in np.argsort(np.where(np.isnan(pred), np.inf, pred), kind="stable")
+                     if not np.isnan(pred[i])]
+            short = list(dict.fromkeys(order[:shortlist] + [wl.prog.choose_partition(PART_EQ8)]))
+            _, best = exhaustive(wl, short, reps, log)
+            return best, "model+timed"
     _, best = exhaustive(wl, candidates(wl, extra=0), reps, log, budget=budget)
     return best, "timed"
 
 
-def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2, log=None) -> Dict:
-    """Time the model's choice, Eq. (8)'s choice and the exhaustive best.
-    The best time is the minimum over every timing taken, the two choices'
-    re-timings included, so that a regret is never negative."""
+def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2, log=None,
+           shortlist: int = 3) -> Dict:
+    """Time the model's choice, the model's shortlist verified by timing,
+    Eq. (8)'s choice and the exhaustive best.  The best time is the minimum
+    over every timing taken, so that a regret is never negative."""
     rows, best = exhaustive(wl, splits, reps, log)
     c_model, how = choose(wl, blob, reps)
+    c_short, how_s = choose(wl, blob, reps, shortlist=shortlist)
     c_eq8 = wl.prog.choose_partition(PART_EQ8)
     t_model = time_split(wl, c_model, reps)
+    t_short = time_split(wl, c_short, reps)
     t_eq8 = time_split(wl, c_eq8, reps)
-    t_best = min([t for _, t in rows] + [t_model, t_eq8])
-    if t_model == t_best:
-        best = c_model
-    elif t_eq8 == t_best and t_eq8 < min(t for _, t in rows):
-        best = c_eq8
+    timed = dict(rows)
+    for c, t in ((c_model, t_model), (c_short, t_short), (c_eq8, t_eq8)):
+        if t < timed.get(c, math.inf):
+            timed[c] = t
+    best = min(timed, key=lambda c: (timed[c], c))
+    t_best = timed[best]
     return {"best": best, "t_best": t_best, "model": c_model, "how": how, "t_model": t_model,
+            "shortlist": c_short, "how_shortlist": how_s, "t_shortlist": t_short,
             "eq8": c_eq8, "t_eq8": t_eq8, "model_regret": t_model / t_best - 1.0,
+            "shortlist_regret": t_short / t_best - 1.0,
             "eq8_regret": t_eq8 / t_best - 1.0, "gain_over_eq8": t_eq8 / t_model,
             "splits_timed": len(rows)}

@@ -73,33 +73,53 @@ def test_gpu_training_fits(dev):
     rng = np.random.default_rng(3)
     X = rng.normal(size=(256, fhs.N_FEATURES))
     y = np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.1 * X[:, 12]
-    blob, loss = tune.train(X, y, epochs=1500, lr=3e-3)
+    blob, loss = tune.train(X, y, epochs=1500, lr=3e-3, ensemble=2)
     assert loss < 0.05 * np.var(y)
     pred = tune.predict(blob, X)
-    assert np.mean((pred - y) ** 2) == pytest.approx(loss, rel=1e-9)
+    assert np.mean((pred - y) ** 2) == pytest.approx(loss, rel=1e-12)
+    # the library's choice scores splits with the same averaged ensemble
+    n_in, h1, h2 = tune.SHAPE
+    assert blob.size == 3 + 4 * n_in + 2 * ref.param_count(n_in, h1, h2)
+
+
+def _slope_net(n_in, slope):
+    """A 1-1 network whose output is ~ slope * feature 12 (tanh(tanh(z)) ~ z
+    for the tiny z used here)."""
+    params = np.zeros(ref.param_count(n_in, 1, 1))
+    W1, b1, W2, b2, w3, b3 = ref.unpack(params, n_in, 1, 1)
+    W1[0, 12] = 1e-3
+    W2[0, 0] = 1.0
+    w3[0] = 1e3 * slope
+    return params
 
 
 def test_model_choice_uses_the_network(dev):
-    """A network that is monotone in feature 12, log2(1 + Eq. (8)), must pick
-    an Eq. (8)-optimal split; one that is monotone in -feature 12 the worst."""
+    """A network increasing in feature 12, log2(1 + Eq. (8)), must pick an
+    Eq. (8)-optimal split; an ensemble whose mean decreases in it the worst.
+    fhs_predict_splits returns the ensemble mean of the reference network."""
     text = w.quantum_walk(30, 12).to_text()
     prog = fhs.Program(text)
     ctx = fhs.Context(0)
     ctx.load(prog)
-    n_in, h1, h2 = fhs.N_FEATURES, 1, 1
-    for sign in (1.0, -1.0):
-        params = np.zeros(ref.param_count(n_in, h1, h2))
-        W1, b1, W2, b2, w3, b3 = ref.unpack(params, n_in, h1, h2)
-        W1[0, 12] = 0.01 * sign
-        W2[0, 0] = 1.0
-        w3[0] = 1.0
-        blob = np.concatenate([[n_in, h1, h2], np.zeros(n_in), np.ones(n_in),
-                               np.full(n_in, -1e9), np.full(n_in, 1e9), params])
-        ctx.load_cost_model(blob)
+    n_in = fhs.N_FEATURES
+    cand = prog.candidate_splits()
+    costs = [prog.partition_cost(*x)[0] for x in cand]
+    rng = np.random.default_rng(8)
+    mu, sd = rng.normal(size=n_in), rng.uniform(0.5, 2.0, size=n_in)
+    for nets, want in (([_slope_net(n_in, 1.0)], min(costs)),
+                       ([_slope_net(n_in, -2.0), _slope_net(n_in, 1.0)], max(costs))):
+        head = np.concatenate([[n_in, 1, 1], np.zeros(n_in), np.ones(n_in),
+                               np.full(n_in, -1e9), np.full(n_in, 1e9)])
+        ctx.load_cost_model(np.concatenate([head] + nets))
         c = ctx.choose_partition(fhs.PART_MODEL, 64, 1)
-        costs = [prog.partition_cost(*x)[0] for x in prog.candidate_splits()]
-        want = min(costs) if sign > 0 else max(costs)
         assert prog.partition_cost(*c)[0] == want
+        # standardisation and averaging against the reference network
+        head[3:3 + n_in], head[3 + n_in:3 + 2 * n_in] = mu, sd
+        ctx.load_cost_model(np.concatenate([head] + nets))
+        F = np.array([prog.split_features(*x, 64, 1) for x in cand])
+        ref_y = np.mean([ref.forward(p, (F - mu) / sd, n_in, 1, 1)[0] for p in nets], axis=0)
+        got = ctx.predict_splits(cand, 64, 1)
+        assert np.abs(got - ref_y).max() <= 1e-12 * max(1.0, np.abs(ref_y).max())
 
 
 def _unit_blob(lo, hi):
@@ -120,9 +140,9 @@ def test_model_outside_training_range(dev):
     ctx.load_cost_model(_unit_blob(lo, hi))
     ctx.choose_partition(fhs.PART_MODEL, 8, 1)            # inside: fine
     lo2 = lo.copy()
-    lo2[9] = hi[9] + 10.0 * (hi[9] - lo[9] + 1.0)         # log2(M S) far above every row
+    lo2[10] = hi[10] + 10.0 * (hi[10] - lo[10] + 1.0)     # log2(M S) far above every row
     hi2 = hi.copy()
-    hi2[9] = lo2[9]
+    hi2[10] = lo2[10]
     ctx.load_cost_model(_unit_blob(lo2, hi2))
     with pytest.raises(fhs.FhsError) as e:
         ctx.choose_partition(fhs.PART_MODEL, 8, 1)
