@@ -102,6 +102,10 @@ def main() -> int:
                          "outside its training range)")
     ap.add_argument("--cost-model", default=None, help="cost model file (default: the package's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape instead of sweeping it")
+    ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC",
+                    help="fix the launch shape (histories per lane, chunk, blocks per CU)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM-counter calibration)")
@@ -149,6 +153,17 @@ def main() -> int:
     else:
         mode = {"eq8": fhs.PART_EQ8, "thirds": fhs.PART_THIRDS, "none": fhs.PART_NONE}
         part = prog.choose_partition(mode[args.partition])
+    launch = None
+    if args.launch:
+        ctx.set_launch_config(*(int(v) for v in args.launch.split(",")))
+    elif not args.no_autotune and prog.A > 0:
+        # launch shape (histories per lane, chunk, blocks per CU) swept on a
+        # 1024-output subsample with the chosen split; kept for the full run
+        sub = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
+                            cfg["outputs"][:1024], thr)
+        launch, _ = tune.autotune_launch(sub, part, reps=2)
+        ctx.load(prog)
+        del sub
     t_setup = time.perf_counter() - t_setup
     ctx.set_partition(*part)
     d_in, d_out, d_cf = wl.d_in, wl.d_out, wl.d_cf
@@ -237,6 +252,7 @@ def main() -> int:
             "qubits": prog.n, "gates": prog.G, "sources": prog.A,
             "outputs": M, "inputs": S, "threshold": thr,
             "partition": list(part), "partition_mode": how, "partition_setup_s": t_setup,
+            "launch_config": list(ctx.launch_config), "launch_autotuned": launch is not None,
             "regions": [plan["Ap"], plan["Ar"], plan["As"]],
         },
         "amplitudes_per_s": M * S / T,

@@ -1,0 +1,147 @@
+"""GPU: the runtime around the kernels -- launch shapes, table batching,
+timing mode and its work counts, the launch-shape autotuner -- each checked
+against the CPU oracle (same bar as the parity tests)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_01467_amd as fhs  # noqa: E402
+from paper_2608_01467_amd import tune  # noqa: E402
+
+TOL = 1e-12
+THREADS = min(16, len(os.sched_getaffinity(0)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fhs.Context(0)
+    yield c
+    c.set_launch_config(0, 0, 0)
+
+
+def _cases():
+    walk = w.quantum_walk(99, 7).to_text()
+    qaoa = w.qaoa_maxcut(8, 2, 11, 12)[0].to_text()
+    return [("walk", walk, w.walk_outputs(99, 7, 40, seed=5), 0.0),
+            ("qaoa", qaoa, list(range(0, 256, 3)), 1e-4)]
+
+
+def _run(ctx, prog, outs, thr, part):
+    ctx.load(prog)
+    ctx.set_partition(*part)
+    amps, st = ctx.evaluate([0], [1], outs, threshold=thr)
+    torch.cuda.synchronize()
+    a = amps.cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1], st.cpu().numpy().view(np.uint64)
+
+
+def _check(name, amps, st, ref):
+    assert np.abs(amps - ref[0]).max() <= TOL, name
+    assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), name
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_launch_shapes(ctx, case):
+    """Every histories-per-lane x chunk x blocks-per-CU shape gives the
+    oracle's amplitudes and bit-identical valid-set statistics."""
+    name, text, outs, thr = _cases()[case]
+    prog = fhs.Program(text)
+    part = prog.choose_partition(fhs.PART_EQ8)
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    for h in (1, 2):
+        for chunk in (1, 64, 256):
+            for bpc in (0, 1, 3):
+                ctx.set_launch_config(h, chunk, bpc)
+                assert ctx.launch_config == (h, chunk, bpc)
+                amps, st = _run(ctx, prog, outs, thr, part)
+                _check((name, h, chunk, bpc), amps, st, ref)
+    ctx.set_launch_config(0, 0, 0)
+    with pytest.raises(fhs.FhsError):
+        ctx.set_launch_config(3, 0, 0)
+    with pytest.raises(fhs.FhsError):
+        ctx.set_launch_config(1, 96, 0)       # not a power of two
+
+
+def test_table_batches_and_timing(ctx):
+    """A table budget of a few pairs splits the work into many batches (one
+    prefix build + consumer launch each); results are unchanged, timing
+    mode reports one duration per batch, and the work counts are exact."""
+    name, text, outs, thr = _cases()[0]
+    prog = fhs.Program(text)
+    part = prog.choose_partition(fhs.PART_EQ8)
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    ctx.load(prog)
+    ctx.set_partition(*part)
+    plan1 = ctx.plan(len(outs), 1)
+    assert plan1["n_batches"] == 1
+    assert plan1["Ap"] + plan1["Ar"] + plan1["As"] == prog.A
+    per_pair = plan1["table_bytes"] // plan1["pairs_per_batch"]
+    ctx.set_table_budget(3 * per_pair)
+    plan = ctx.plan(len(outs), 1)
+    assert plan["pairs_per_batch"] == 3
+    assert plan["n_batches"] == (len(outs) + 2) // 3
+    amps, st = _run(ctx, prog, outs, thr, part)
+    _check("batched", amps, st, ref)
+    ctx.set_kernel_timing(True)
+    amps, st = _run(ctx, prog, outs, thr, part)
+    _check("timed", amps, st, ref)
+    times = ctx.kernel_times()
+    assert len(times) == plan["n_batches"] and all(t > 0 for t in times)
+    entries, valid = ctx.kernel_counts()
+    assert entries == len(outs) << plan["Ap"]
+    assert 0 < valid <= entries
+    ctx.set_kernel_timing(False)
+    ctx.set_table_budget(1 << 30)
+    # all sources in the prefix: a consistent prefix entry is a valid history
+    ctx.set_kernel_timing(True)
+    amps, st = _run(ctx, prog, outs, thr, (prog.G, prog.G))
+    entries, valid = ctx.kernel_counts()
+    assert entries == len(outs) << prog.A
+    assert valid == int(ref[1][:, 0].sum())
+    ctx.set_kernel_timing(False)
+
+
+def test_autotune_launch(ctx):
+    name, text, outs, thr = _cases()[1]
+    wl = tune.Workload(ctx, text, [0], [1.0], outs, thr)
+    part = wl.prog.choose_partition(fhs.PART_EQ8)
+    best, log = tune.autotune_launch(wl, part, reps=1)
+    assert len(log) == 18 and best in [c for c, _ in log]
+    assert ctx.launch_config == best
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    wl.run(part)
+    torch.cuda.synchronize()
+    a = wl.amps.cpu().numpy()
+    _check("autotuned", a[:, 0] + 1j * a[:, 1], wl.stats.cpu().numpy().view(np.uint64), ref)
+    ctx.set_launch_config(0, 0, 0)
+
+
+def test_literal_aa16_split_choice(ctx):
+    """Amplitude amplification with 16 + 14 qubits (A = 96): only the split
+    choice runs -- features, Eq. (8), the model's predictions (outside its
+    training range: NaN, and FHS_ERANGE for the model's choice)."""
+    text = w.amplitude_amplification(16, 3, 4, 301)[0].to_text()
+    prog = fhs.Program(text)
+    assert prog.A == 96
+    cand = prog.candidate_splits()
+    assert len(cand) == 97 * 98 // 2
+    f = prog.split_features(*prog.choose_partition(fhs.PART_EQ8), 64, 1)
+    assert np.isfinite(f).all() and f[12] > 64     # Eq. (8) cost beyond 2^64, in 128 bits
+    ctx.load(prog)
+    blob = tune.load_model()
+    if blob is None:
+        pytest.skip("no trained cost model in the package")
+    ctx.load_cost_model(blob)
+    assert np.isnan(ctx.predict_splits(cand[:50], 64, 1)).all()
+    with pytest.raises(fhs.FhsError) as e:
+        ctx.choose_partition(fhs.PART_MODEL, 64, 1)
+    assert e.value.status == 3
