@@ -75,39 +75,40 @@ def test_table_batches_and_timing(ctx):
     """A table budget of a few pairs splits the work into many batches (one
     prefix build + consumer launch each); results are unchanged, timing
     mode reports one duration per batch, and the work counts are exact."""
-    name, text, outs, thr = _cases()[0]
+    text = w.quantum_walk(99, 14).to_text()        # A = 13: 2^13 entries per pair
+    outs = w.walk_outputs(99, 14, 12, seed=5)
     prog = fhs.Program(text)
-    part = prog.choose_partition(fhs.PART_EQ8)
-    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threads=THREADS,
+                                        partition=prog.choose_partition(fhs.PART_EQ8))
     ctx.load(prog)
-    ctx.set_partition(*part)
-    plan1 = ctx.plan(len(outs), 1)
-    assert plan1["n_batches"] == 1
-    assert plan1["Ap"] + plan1["Ar"] + plan1["As"] == prog.A
-    per_pair = plan1["table_bytes"] // plan1["pairs_per_batch"]
-    ctx.set_table_budget(3 * per_pair)
-    plan = ctx.plan(len(outs), 1)
-    assert plan["pairs_per_batch"] == 3
-    assert plan["n_batches"] == (len(outs) + 2) // 3
-    amps, st = _run(ctx, prog, outs, thr, part)
-    _check("batched", amps, st, ref)
-    ctx.set_kernel_timing(True)
-    amps, st = _run(ctx, prog, outs, thr, part)
-    _check("timed", amps, st, ref)
-    times = ctx.kernel_times()
-    assert len(times) == plan["n_batches"] and all(t > 0 for t in times)
-    entries, valid = ctx.kernel_counts()
-    assert entries == len(outs) << plan["Ap"]
-    assert 0 < valid <= entries
-    ctx.set_kernel_timing(False)
-    ctx.set_table_budget(1 << 30)
-    # all sources in the prefix: a consistent prefix entry is a valid history
-    ctx.set_kernel_timing(True)
-    amps, st = _run(ctx, prog, outs, thr, (prog.G, prog.G))
-    entries, valid = ctx.kernel_counts()
-    assert entries == len(outs) << prog.A
-    assert valid == int(ref[1][:, 0].sum())
-    ctx.set_kernel_timing(False)
+    for part in ((prog.G, prog.G), prog.choose_partition(fhs.PART_EQ8)):
+        ctx.set_partition(*part)
+        plan1 = ctx.plan(len(outs), 1)
+        assert plan1["n_batches"] == 1
+        assert plan1["Ap"] + plan1["Ar"] + plan1["As"] == prog.A
+        per_pair = plan1["table_bytes"] // plan1["pairs_per_batch"]
+        budget = max(1 << 20, 3 * per_pair)
+        ctx.set_table_budget(budget)
+        plan = ctx.plan(len(outs), 1)
+        B = min(len(outs), budget // per_pair)
+        assert plan["pairs_per_batch"] == B
+        assert plan["n_batches"] == (len(outs) + B - 1) // B
+        amps, st = _run(ctx, prog, outs, 0.0, part)
+        _check(("batched", part), amps, st, ref)
+        ctx.set_kernel_timing(True)
+        amps, st = _run(ctx, prog, outs, 0.0, part)
+        _check(("timed", part), amps, st, ref)
+        times = ctx.kernel_times()
+        assert len(times) == plan["n_batches"] and all(t > 0 for t in times)
+        entries, valid = ctx.kernel_counts()
+        assert entries == len(outs) << plan["Ap"]
+        assert 0 < valid <= entries
+        if part == (prog.G, prog.G):
+            # all sources in the prefix: a consistent entry is a valid history
+            assert plan["Ap"] == prog.A
+            assert valid == int(ref[1][:, 0].sum())
+        ctx.set_kernel_timing(False)
+        ctx.set_table_budget(1 << 30)
 
 
 def test_autotune_launch(ctx):
