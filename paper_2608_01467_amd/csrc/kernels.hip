@@ -358,6 +358,68 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
     }
 }
 
+// Copy every per-history register of src into dst except the source bits.
+template <int NW, int H>
+__device__ __forceinline__ void copy_core(Lanes<NW, H> &dst, const Lanes<NW, H> &src) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        unroll<NW>([&](auto ww) { dst.s[h][ww.value] = src.s[h][ww.value]; });
+        dst.re[h] = src.re[h];
+        dst.im[h] = src.im[h];
+        dst.M[h] = src.M[h];
+        dst.ok[h] = src.ok[h];
+    });
+}
+
+// Depth-first enumeration of the D <= DMAX consecutive sources k0 ..
+// k0+D-1 (evaluation order) of a region that ends at e_end.  On entry L
+// holds each history's state just before source k0's gate; its hb carries
+// the region's other source bits.  For every one of the 2^D assignments
+// (source k0 varying slowest) the histories are carried to e_end and
+// leaf(C) is called with C.hb holding the assignment.  The gates between
+// source k0+l and the next enumerated source run 2^(l+1) times rather than
+// 2^D: the state before each enumerated source is kept in registers and
+// reused by every assignment that agrees on the earlier sources (the
+// checkpoint idea of Algorithm 2 applied at every source).  Control flow is
+// wave-uniform throughout.
+template <int NW, int H, bool PRUNE, int DMAX, class Leaf>
+__device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, const uint32_t *src,
+                                           uint32_t k0, uint32_t D, uint32_t e_end,
+                                           const Lanes<NW, H> &L, uint32_t kbase,
+                                           const uint32_t (&bin)[NW], double thr, Leaf &&leaf) {
+    Lanes<NW, H> C = L;
+    Lanes<NW, H> S[DMAX];      // S[l]: state before level l's source (l >= 1)
+    const uint32_t nt = 1u << D;
+    for (uint32_t t = 0; t < nt; ++t) {
+        uint32_t l0 = 0;
+        if (t != 0u) {
+            // the levels whose bit changed since t - 1 are l0 .. D-1
+            l0 = D - 1u - static_cast<uint32_t>(__builtin_ctz(t));
+            unroll<DMAX>([&](auto LV) {
+                if (static_cast<uint32_t>(LV.value) == l0) {
+                    if constexpr (LV.value == 0) copy_core(C, L);
+                    else copy_core(C, S[LV.value]);
+                }
+            });
+        }
+        for (uint32_t l = l0; l < D; ++l) {
+            const uint32_t kb = k0 + l - kbase;
+            const uint64_t bit = static_cast<uint64_t>((t >> (D - 1u - l)) & 1u) << kb;
+            unroll<H>([&](auto hh) { C.hb[hh.value] = (C.hb[hh.value] & ~(1ull << kb)) | bit; });
+            const uint32_t a = ld_const(src, k0 + l);
+            const uint32_t b = (l + 1u < D) ? ld_const(src, k0 + l + 1u) : e_end;
+            run_region<NW, H, PRUNE>(prog, F, a, b, C, kbase, bin, thr);
+            if (l + 1u < D) {
+                unroll<DMAX>([&](auto LV) {
+                    if constexpr (LV.value > 0)
+                        if (static_cast<uint32_t>(LV.value) == l + 1u) copy_core(S[LV.value], C);
+                });
+            }
+        }
+        leaf(C);
+    }
+}
+
 // Copy the factor slice [lo, hi) of the global table into LDS.
 __device__ __forceinline__ void stage_factors(double *lds, const double *fac, uint32_t lo,
                                               uint32_t hi) {
@@ -444,22 +506,27 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
 
 template <int NW, bool PRUNE, bool FLDS>
 __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab, uint32_t p0,
-                                                uint32_t B, uint32_t P) {
+                                                uint32_t B, uint32_t P, uint32_t Dp) {
     extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
     FacRef F{c.fac, 0u};
     if constexpr (FLDS) {
         stage_factors(l_fac, c.fac, c.f_L, c.f_c1);
         F = FacRef{l_fac, c.f_L};
     }
-    const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
-    const uint64_t hmask = (1ull << c.Ap) - 1ull;
+    // One lane per subtree: the lane's index fixes the first Ap - Dp prefix
+    // sources, the last Dp are enumerated depth-first; 2^Dp entries per lane.
+    const uint32_t lo_bits = c.Ap - Dp;
+    const uint64_t NL = static_cast<uint64_t>(B) << lo_bits;
+    const uint64_t lomask = (1ull << lo_bits) - 1ull;
+    const uint32_t e_split = Dp ? ld_const(c.src, lo_bits) : c.c1;
     const Mask4 fin_c1 = ld_const(c.fin, c.c1);
-    for (uint64_t eb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; eb < E;
-         eb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint64_t e_raw = eb + threadIdx.x;
-        const bool live = e_raw < E;
-        const uint64_t e = live ? e_raw : E - 1;   // clamp so every lane reads in bounds
-        const uint32_t p = p0 + static_cast<uint32_t>(e >> c.Ap);
+    for (uint64_t lb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; lb < NL;
+         lb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t l_raw = lb + threadIdx.x;
+        const bool live = l_raw < NL;
+        const uint64_t li = live ? l_raw : NL - 1;   // clamp so every lane reads in bounds
+        const uint64_t pl = li >> lo_bits;
+        const uint32_t p = p0 + static_cast<uint32_t>(pl);
         Lanes<NW, 1> L;
         uint32_t bin[NW];
 #pragma unroll
@@ -470,16 +537,22 @@ __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab
         L.im[0] = a.y;
         L.M[0] = pre.M[p];
         L.ok[0] = pre.ok[p] == 1u;
-        L.hb[0] = e & hmask;
-        run_region<NW, 1, PRUNE>(c.prog, F, c.L, c.c1, L, 0, bin, c.thr);
-        L.ok[0] = L.ok[0] && check_final<NW>(L.s[0], bin, fin_c1);
-        if (live) {
+        L.hb[0] = li & lomask;
+        run_region<NW, 1, PRUNE>(c.prog, F, c.L, e_split, L, 0, bin, c.thr);
+        const uint64_t ebase = pl << c.Ap;
+        const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
+        dfs_region<NW, 1, PRUNE, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.c1, L, 0u, bin, c.thr,
+                                        [&](Lanes<NW, 1> &C) {
+            const bool ok = C.ok[0] && check_final<NW>(C.s[0], bin, fin_c1);
+            if (live) {
+                const uint64_t e = ebase | C.hb[0];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = L.s[0][w];
-            tab.beta[e] = make_double2(L.re[0], L.im[0]);
-            if (PRUNE) tab.M[e] = L.M[0];
-            tab.ok[e] = L.ok[0] ? 1u : 0u;
-        }
+                for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = C.s[0][w];
+                tab.beta[e] = make_double2(C.re[0], C.im[0]);
+                if (PRUNE) tab.M[e] = C.M[0];
+                tab.ok[e] = ok ? 1u : 0u;
+            }
+        });
     }
 }
 
@@ -792,10 +865,11 @@ hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uin
 }
 
 hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32_t p0, uint32_t B,
-                         hipStream_t s) {
-    const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
-    if (E == 0) return hipSuccess;
-    uint64_t blocks = (E + 255) / 256;
+                         uint32_t Dp, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    if (Dp > c.Ap || Dp > static_cast<uint32_t>(kDfsMax)) return hipErrorInvalidValue;
+    const uint64_t NL = static_cast<uint64_t>(B) << (c.Ap - Dp);
+    uint64_t blocks = (NL + 255) / 256;
     if (blocks > (1u << 20)) blocks = 1u << 20;
     const uint32_t P = c.M * c.S;
     const bool flds = fits_lds(c.f_L, c.f_c1);
@@ -804,7 +878,7 @@ hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32
         dispatch_bool(c.thr > 0.0, [&](auto pr) {
             dispatch_bool(flds, [&](auto fl) {
                 k_prefix<nw.value, pr.value, fl.value>
-                    <<<static_cast<uint32_t>(blocks), 256, shm, s>>>(c, pre, tab, p0, B, P);
+                    <<<static_cast<uint32_t>(blocks), 256, shm, s>>>(c, pre, tab, p0, B, P, Dp);
             });
         });
     });

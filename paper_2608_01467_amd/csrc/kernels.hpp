@@ -41,6 +41,7 @@ struct Common {
     const Instr *prog;       // device program, evaluation order
     const double *fac;       // factor table
     const Mask4 *fin;        // [G+1] bits final once e gates are applied
+    const uint32_t *src;     // [A] evaluation position of source k's gate (ascending)
     const uint64_t *inputs;  // [S][W]
     const uint64_t *outputs; // [M][W]
     uint32_t S, M, W, n;
@@ -54,8 +55,10 @@ struct Common {
 // Launchers (kernels.hip).  NW and pruning are dispatched inside.
 hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
                            uint32_t n_zero, hipStream_t s);
+// Dp: the last Dp prefix sources are enumerated depth-first inside a lane
+// (Dp <= min(Ap, kDfsMax)); B << (Ap - Dp) lanes.
 hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32_t p0, uint32_t B,
-                         hipStream_t s);
+                         uint32_t Dp, hipStream_t s);
 // ss: log2 of the number of lanes that share one (entry, h_r) root task, each
 // walking a contiguous 2^(As-ss) slice of the suffix assignments.
 // H: histories per lane (1 or 2).
@@ -76,6 +79,7 @@ hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32
 constexpr int kConsumeThreads = 256;
 constexpr int kPlainThreads = 256;
 constexpr int kMaxChunk = 256;   // prefix entries per work item
+constexpr int kDfsMax = 4;       // prefix sources enumerated depth-first inside one lane
 // Factor slices up to this many doubles are staged in LDS by the hot kernels.
 constexpr uint32_t kMaxLdsFactors = 4096;
 

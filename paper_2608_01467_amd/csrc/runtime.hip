@@ -55,6 +55,7 @@ struct Plan {
     uint32_t chunk = 1;      // prefix entries per work item
     uint32_t nchunks = 1;    // work items per pair
     uint32_t ss = 0;         // log2 lanes per root task
+    uint32_t Dp = 0;         // prefix sources enumerated depth-first inside a lane
     uint32_t bpp = 1;        // plain: blocks per pair
     uint64_t entries = 0;    // table entries per batch
     size_t off_pre_st = 0, off_pre_amp = 0, off_pre_M = 0, off_pre_ok = 0;
@@ -80,6 +81,7 @@ struct fhs_ctx {
     Instr *d_prog = nullptr;
     double *d_fac = nullptr;
     Mask4 *d_fin = nullptr;
+    uint32_t *d_src = nullptr;   // [max(A,1)] evaluation position of each source
     uint32_t c1 = 0, c2 = 0;
     size_t table_budget = size_t(1) << 30;
     uint64_t generation = 0;
@@ -132,9 +134,11 @@ void free_program(fhs_ctx *c) {
     if (c->d_prog) hipFree(c->d_prog);
     if (c->d_fac) hipFree(c->d_fac);
     if (c->d_fin) hipFree(c->d_fin);
+    if (c->d_src) hipFree(c->d_src);
     c->d_prog = nullptr;
     c->d_fac = nullptr;
     c->d_fin = nullptr;
+    c->d_src = nullptr;
     c->loaded = false;
 }
 
@@ -207,6 +211,9 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
         const uint64_t root_tasks = static_cast<uint64_t>(n_pairs) * per_pair << pl.Ar;
         const uint64_t want = static_cast<uint64_t>(std::max(c->num_cu, 1)) * 2048;
         while (pl.ss < pl.As && (root_tasks << pl.ss) < want) ++pl.ss;
+        // prefix sources enumerated depth-first per lane, keeping enough lanes
+        pl.Dp = std::min<uint32_t>(pl.Ap, static_cast<uint32_t>(kDfsMax));
+        while (pl.Dp > 0 && (static_cast<uint64_t>(pl.B) << (pl.Ap - pl.Dp)) < want) --pl.Dp;
         pl.off_counters = take(sizeof(uint32_t) * pl.n_batches);
         pl.off_tab_st = take(sizeof(uint32_t) * NW * pl.entries);
         pl.off_tab_beta = take(sizeof(double2) * pl.entries);
@@ -269,6 +276,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.prog = c->d_prog;
     cm.fac = c->d_fac;
     cm.fin = c->d_fin;
+    cm.src = c->d_src;
     cm.inputs = in;
     cm.outputs = out;
     cm.S = S;
@@ -327,7 +335,7 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         const uint64_t items = static_cast<uint64_t>(B) * pl.nchunks;
         uint32_t grid = static_cast<uint32_t>(std::max(c->num_cu, 1)) * static_cast<uint32_t>(bpc);
         if (items < grid) grid = static_cast<uint32_t>(items);
-        e = launch_prefix(cm, NW, pre, tab, p0, B, s);
+        e = launch_prefix(cm, NW, pre, tab, p0, B, pl.Dp, s);
         if (e != hipSuccess) return e;
         if (timed) {
             // outside the timed interval: how many entries the consumer expands
@@ -404,6 +412,11 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
         FHS_HIP(c, hipMemcpy(c->d_fac, P.fac.data(), sizeof(double) * P.fac.size(), hipMemcpyHostToDevice));
     FHS_HIP(c, hipMemcpy(c->d_fin, P.final_before.data(), sizeof(Mask4) * P.final_before.size(),
                          hipMemcpyHostToDevice));
+    FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_src),
+                         sizeof(uint32_t) * std::max<size_t>(P.src_eval.size(), 1)));
+    if (!P.src_eval.empty())
+        FHS_HIP(c, hipMemcpy(c->d_src, P.src_eval.data(), sizeof(uint32_t) * P.src_eval.size(),
+                             hipMemcpyHostToDevice));
     c->c1 = c->c2 = 0;
     c->loaded = true;
     ++c->generation;
