@@ -104,6 +104,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape instead of sweeping it")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="keep one instruction per gate (no add/subtract ladder folding)")
     ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC",
                     help="fix the launch shape (histories per lane, chunk, blocks per CU)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
@@ -139,7 +141,7 @@ def main() -> int:
     ctx.set_table_budget(32 << 30)          # one batch: the whole workload in HBM
     from paper_2608_01467_amd import tune
     wl = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
-                       cfg["outputs"], thr)
+                       cfg["outputs"], thr, fuse=not args.no_fuse)
     prog = wl.prog              # loaded into ctx
     part_eq8 = prog.choose_partition(fhs.PART_EQ8)
     how = args.partition
@@ -160,7 +162,7 @@ def main() -> int:
         # launch shape (histories per lane, chunk, blocks per CU) swept on a
         # 1024-output subsample with the chosen split; kept for the full run
         sub = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
-                            cfg["outputs"][:1024], thr)
+                            cfg["outputs"][:1024], thr, fuse=not args.no_fuse)
         launch, _ = tune.autotune_launch(sub, part, reps=2)
         ctx.load(prog)
         del sub
@@ -251,6 +253,7 @@ def main() -> int:
             "workload": args.workload,
             "qubits": prog.n, "gates": prog.G, "sources": prog.A,
             "outputs": M, "inputs": S, "threshold": thr,
+            "fused_ladders": not args.no_fuse,
             "partition": list(part), "partition_mode": how, "partition_setup_s": t_setup,
             "launch_config": list(ctx.launch_config), "launch_autotuned": launch is not None,
             "regions": [plan["Ap"], plan["Ar"], plan["As"]],

@@ -24,12 +24,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfhs.so")
 
 PART_NONE, PART_THIRDS, PART_EQ8, PART_MODEL = 0, 1, 2, 3
+REDUCE_FUSE = 1
 
 STATUS = {0: "FHS_OK", 1: "FHS_EINVAL", 2: "FHS_EUNSUPPORTED", 3: "FHS_ERANGE",
           4: "FHS_ENOMEM", 5: "FHS_EHIP", 6: "FHS_ESTATE", 7: "FHS_EPARSE"}
 
 EXPORTS = [
-    "fhs_status_string", "fhs_reduce", "fhs_program_free", "fhs_program_get_info",
+    "fhs_status_string", "fhs_reduce", "fhs_reduce_ex", "fhs_program_free", "fhs_program_get_info",
     "fhs_program_sources", "fhs_partition_cost", "fhs_choose_partition", "fhs_ctx_create",
     "fhs_ctx_destroy", "fhs_last_error", "fhs_load_program", "fhs_set_partition",
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         L.fhs_status_string.restype = ctypes.c_char_p
         L.fhs_status_string.argtypes = [I32]
         L.fhs_reduce.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(P)]
+        L.fhs_reduce_ex.argtypes = [ctypes.c_char_p, ctypes.c_size_t, U32, ctypes.POINTER(P)]
         L.fhs_program_free.argtypes = [P]
         L.fhs_program_free.restype = None
         L.fhs_program_get_info.argtypes = [P, ctypes.POINTER(ProgramInfo)]
@@ -145,10 +147,10 @@ def _check(st: int, ctx=None) -> None:
 class Program:
     """Host-side reduced-history program (fhs_reduce)."""
 
-    def __init__(self, circuit_text: str):
+    def __init__(self, circuit_text: str, fuse: bool = True):
         b = circuit_text.encode()
         h = ctypes.c_void_p()
-        _check(lib().fhs_reduce(b, len(b), ctypes.byref(h)))
+        _check(lib().fhs_reduce_ex(b, len(b), REDUCE_FUSE if fuse else 0, ctypes.byref(h)))
         self._h = h
         info = ProgramInfo()
         _check(lib().fhs_program_get_info(h, ctypes.byref(info)))

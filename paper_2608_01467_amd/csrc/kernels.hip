@@ -188,6 +188,61 @@ __device__ __forceinline__ void op_mcphase(Lanes<NW, H> &L, const Instr &I) {
     });
 }
 
+// Fused ladder (OP_ADD): when the controls match, add or subtract one on
+// the bit field [lo, lo+m) of the state, mod 2^m.  The field is masked out of
+// the state words, the +-2^lo is propagated through them with carries, and
+// the result is merged back under the field mask.
+template <int NW, int H, int LW>
+__device__ __forceinline__ void op_add(Lanes<NW, H> &L, const Instr &I) {
+    const uint32_t lo = hdr_a(I), m = hdr_b(I);
+    const bool sub = (hdr_z(I) & 1u) != 0u;
+    uint32_t fm[NW];   // field mask per 32-bit word (wave-uniform)
+    unroll<NW>([&](auto ww) {
+        constexpr int w = ww.value;
+        const int a = min(32, max(0, static_cast<int>(lo) - 32 * w));
+        const int b = min(32, max(0, static_cast<int>(lo + m) - 32 * w));
+        const uint32_t below_b = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+        const uint32_t below_a = a >= 32 ? 0xffffffffu : ((1u << a) - 1u);
+        fm[w] = below_b & ~below_a;
+    });
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const uint64_t one = acc == 0u ? 1ull : 0ull;
+        if constexpr (NW == 1) {
+            const uint32_t x = L.s[h][0] & fm[0];
+            const uint32_t d = static_cast<uint32_t>(one) << lo;
+            const uint32_t r = sub ? x - d : x + d;
+            L.s[h][0] = (L.s[h][0] & ~fm[0]) | (r & fm[0]);
+        } else {
+            const uint64_t f0 = (static_cast<uint64_t>(fm[1]) << 32) | fm[0];
+            const uint64_t s0 = (static_cast<uint64_t>(L.s[h][1]) << 32) | L.s[h][0];
+            const uint64_t x0 = s0 & f0;
+            const uint64_t d0 = lo < 64u ? one << lo : 0ull;
+            const uint64_t r0 = sub ? x0 - d0 : x0 + d0;
+            const uint64_t n0 = (s0 & ~f0) | (r0 & f0);
+            L.s[h][0] = static_cast<uint32_t>(n0);
+            L.s[h][1] = static_cast<uint32_t>(n0 >> 32);
+            if constexpr (NW == 4) {
+                const uint64_t f1 = (static_cast<uint64_t>(fm[3]) << 32) | fm[2];
+                const uint64_t s1 = (static_cast<uint64_t>(L.s[h][3]) << 32) | L.s[h][2];
+                const uint64_t x1 = s1 & f1;
+                const uint64_t d1 = lo >= 64u ? one << (lo - 64u) : 0ull;
+                // carry (borrow) out of the low 64 bits
+                const uint64_t c = sub ? (x0 < d0 ? 1ull : 0ull) : (r0 < x0 ? 1ull : 0ull);
+                const uint64_t r1 = sub ? x1 - d1 - c : x1 + d1 + c;
+                const uint64_t n1 = (s1 & ~f1) | (r1 & f1);
+                L.s[h][2] = static_cast<uint32_t>(n1);
+                L.s[h][3] = static_cast<uint32_t>(n1 >> 32);
+            }
+        }
+    });
+}
+
 template <int NW, int H, int WA, int WB>
 __device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
     constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
@@ -351,7 +406,15 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
                     }
                 });
                 break;
-            default:
+            case OP_ADD:
+                with_word<NW>(w1, [&](auto LW) {
+                    for (uint32_t x = e; x < end; ++x) {
+                        const Instr I = prog[x];
+                        op_add<NW, H, LW.value>(L, I);
+                    }
+                });
+                break;
+            default:   // OP_NOP: gates folded into the preceding OP_ADD
                 break;
         }
         e = end;

@@ -36,13 +36,16 @@ enum Op : uint8_t {
     OP_MCPHASE = 6,     // if ((s ^ cv) & cm) == 0: amplitude *= -1       (MCZ)
     OP_BRANCH_SRC = 7,  // o = bit a, i = source bit k: factor U[o][i], bit a := i
     OP_BRANCH_NAT = 8,  // o = bit a, i = input bit a:  factor U[o][i], bit a := i
+    OP_ADD = 9,         // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) -= 1 (zmask bit 0) or += 1,
+                        // mod 2^b: a fused ladder of controlled X gates (see the reducer)
+    OP_NOP = 10,        // a gate folded into the OP_ADD before it
 };
 
 // The opcode byte carries the base op in its low 4 bits; bits 4-5 and 6-7
 // carry 32-bit state-word indices, so the device touches its state registers
 // with compile-time indices only:
 //   PERM     bits 4-5: word of the target bit, 6-7: highest nonzero control word
-//   MCPHASE  bits 4-5: highest nonzero control word
+//   MCPHASE, ADD  bits 4-5: highest nonzero control word
 //   SWAP, DIAG2  bits 4-5: word of bit a, 6-7: word of bit b
 //   DET1, DIAG1, BRANCH_*  bits 4-5: word of bit a
 constexpr uint8_t op_code(Op base, int w1, int w2) {
@@ -86,7 +89,8 @@ struct HostProgram {
     int NW = 1;                // 32-bit words per device state (1, 2 or 4)
     int L = 0;                 // leading source-free gates (evaluation order)
     int n_branch = 0;
-    std::vector<Instr> ins;            // evaluation order, size G
+    std::vector<Instr> ins;            // evaluation order, size G (fused gates become OP_NOP)
+    int n_fused = 0;                   // ladders folded into OP_ADD
     std::vector<double> fac;           // factor table
     std::vector<uint32_t> src_eval;    // evaluation position of source k's gate
     std::vector<Mask4> final_before;   // [G+1]: bits final once e gates are applied

@@ -420,13 +420,95 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
         P.final_before[e + 1] = fin;
     }
     P.fac_begin[G] = static_cast<uint32_t>(P.fac.size());
-    // runs of identical opcodes: the device dispatches once per run
-    for (int e = G - 1; e >= 0; --e)
-        P.ins[e].run = (e + 1 < G && (P.ins[e + 1].hdr & 0xffu) == (P.ins[e].hdr & 0xffu))
-                           ? P.ins[e + 1].run + 1 : 1;
     P.A = A;
     P.L = A > 0 ? static_cast<int>(P.src_eval[0]) : G;
     return FHS_OK;
+}
+
+inline bool test_bit(const uint32_t *w, uint32_t q) { return (w[q >> 5] >> (q & 31)) & 1u; }
+
+// Fold ladders of controlled X gates that add or subtract one on a block of
+// consecutive qubits into one OP_ADD.  In evaluation order the ladder reads
+// (j = 0 .. m-1): X on bit lo+j under the common controls K and the
+// controls bits lo .. lo+j-1, all of one polarity v.  Walking backward,
+// bit lo+j flips iff K holds and bits lo .. lo+j-1 all equal v after their
+// own flips, i.e. iff they all equalled 1-v before: the ladder subtracts one
+// from the m-bit field when v = 1 and adds one when v = 0, mod 2^m (an
+// incrementer built this way is a standard reversible-arithmetic circuit).
+// The folded gates stay in place as OP_NOP, so every evaluation position,
+// cut, source index, final-bit mask and Eq. (8) count is unchanged; only the
+// work per history drops.
+void fuse_ladders(HostProgram &P) {
+    const int G = P.G;
+    P.n_fused = 0;
+    for (int e = 0; e < G;) {
+        const Instr &I0 = P.ins[e];
+        if (static_cast<Op>(op_base(I0.hdr & 0xffu)) != OP_PERM) {
+            ++e;
+            continue;
+        }
+        const uint32_t lo = (I0.hdr >> 8) & 0xffu;
+        int m = 1;
+        int v = -1;
+        while (e + m < G && lo + m < static_cast<uint32_t>(P.n)) {
+            const Instr &J = P.ins[e + m];
+            if (static_cast<Op>(op_base(J.hdr & 0xffu)) != OP_PERM) break;
+            if (((J.hdr >> 8) & 0xffu) != lo + m) break;
+            const uint32_t prev = lo + m - 1;      // the new control, bit lo+m-1
+            if (!test_bit(J.cm, prev)) break;
+            const int pol = test_bit(J.cv, prev) ? 1 : 0;
+            if (v >= 0 && pol != v) break;
+            // J's controls = I0's controls + bits lo .. lo+m-1 of polarity pol
+            bool same = true;
+            for (int w = 0; w < 4 && same; ++w) {
+                uint32_t field = 0;
+                for (uint32_t b = lo; b < lo + static_cast<uint32_t>(m); ++b)
+                    if ((b >> 5) == static_cast<uint32_t>(w)) field |= 1u << (b & 31);
+                same = J.cm[w] == (I0.cm[w] | field) &&
+                       J.cv[w] == (I0.cv[w] | (pol ? field : 0u)) && (I0.cm[w] & field) == 0u;
+            }
+            if (!same) break;
+            v = pol;
+            ++m;
+        }
+        if (m < 2) {
+            ++e;
+            continue;
+        }
+        // common controls must not touch the field
+        bool clean = true;
+        for (uint32_t b = lo; b < lo + static_cast<uint32_t>(m); ++b)
+            if (test_bit(I0.cm, b)) clean = false;
+        if (!clean) {
+            ++e;
+            continue;
+        }
+        Instr A = I0;
+        int wspan = 0;
+        for (int w = 0; w < 4; ++w)
+            if (A.cm[w]) wspan = w;
+        A.k = 0;
+        A.hdr = pack_hdr(op_code(OP_ADD, wspan, 0), lo, static_cast<uint32_t>(m), v == 1 ? 1u : 0u);
+        P.ins[e] = A;
+        const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
+        P.int_cost[e] = static_cast<uint16_t>(3 * (wspan + 1) + 1 + 3 * wfield);
+        for (int j = 1; j < m; ++j) {
+            Instr N{};
+            N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
+            P.ins[e + j] = N;
+            P.int_cost[e + j] = 0;
+        }
+        ++P.n_fused;
+        e += m;
+    }
+}
+
+// Runs of identical opcodes: the device dispatches once per run.
+void set_runs(HostProgram &P) {
+    const int G = P.G;
+    for (int e = G - 1; e >= 0; --e)
+        P.ins[e].run = (e + 1 < G && (P.ins[e + 1].hdr & 0xffu) == (P.ins[e].hdr & 0xffu))
+                           ? P.ins[e + 1].run + 1 : 1;
 }
 
 void region_sources(const HostProgram &P, uint32_t c1, uint32_t c2, uint32_t out[3]) {
@@ -460,8 +542,9 @@ extern "C" const char *fhs_status_string(fhs_status s) {
     return "unknown status";
 }
 
-extern "C" fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out) {
-    if (!text || !out) return FHS_EINVAL;
+extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags,
+                                    fhs_program **out) {
+    if (!text || !out || (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE))) return FHS_EINVAL;
     *out = nullptr;
     int n = 0;
     std::vector<Gate> gates;
@@ -474,8 +557,14 @@ extern "C" fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out
         delete p;
         return st;
     }
+    if (flags & FHS_REDUCE_FUSE) fuse_ladders(p->p);
+    set_runs(p->p);
     *out = p;
     return FHS_OK;
+}
+
+extern "C" fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out) {
+    return fhs_reduce_ex(text, len, FHS_REDUCE_FUSE, out);
 }
 
 extern "C" void fhs_program_free(fhs_program *prog) { delete prog; }

@@ -40,10 +40,11 @@ SHAPE = (N_FEATURES, 32, 32)
 class Workload:
     """A circuit plus resident device inputs for timing."""
 
-    def __init__(self, ctx: Context, text: str, inputs, coeffs, outputs, threshold=0.0):
+    def __init__(self, ctx: Context, text: str, inputs, coeffs, outputs, threshold=0.0,
+                 fuse: bool = True):
         import torch
         self.ctx = ctx
-        self.prog = Program(text)
+        self.prog = Program(text, fuse=fuse)
         ctx.load(self.prog)
         self.d_in = ctx.device_bits(inputs)
         self.d_cf = ctx.device_coeffs(coeffs)

@@ -1,0 +1,61 @@
+"""Host checks of ladder folding (fhs_reduce_ex with FHS_REDUCE_FUSE): the
+folded program keeps every position, source, final-bit mask and Eq. (8)
+count of the gate-by-gate program and only its work per history drops."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2608_01467_amd as fhs
+import workloads as w
+
+CASES = [w.quantum_walk(99, 20).to_text(), w.quantum_walk(20, 9).to_text(),
+         w.random_ladders(12, 10, 1).to_text(), w.random_ladders(45, 10, 2).to_text(),
+         w.random_ladders(100, 10, 3).to_text(), w.random_mixed(9, 60, 4).to_text(),
+         w.qaoa_maxcut(8, 2, 5, 6)[0].to_text()]
+
+
+@pytest.mark.parametrize("text", CASES)
+def test_fused_program_keeps_positions_and_eq8(text):
+    a, b = fhs.Program(text, fuse=False), fhs.Program(text)
+    assert (a.n, a.G, a.A, a.L, a.W, a.n_branch) == (b.n, b.G, b.A, b.L, b.W, b.n_branch)
+    assert a.source_eval_positions == b.source_eval_positions
+    assert a.candidate_splits() == b.candidate_splits()
+    for c in a.candidate_splits()[::5]:
+        assert a.partition_cost(*c) == b.partition_cost(*c)
+        fa, fb = a.split_features(*c, 64, 1), b.split_features(*c, 64, 1)
+        same = [0, 1, 2, 9, 10, 11, 12, 13]             # everything but the work features
+        assert np.array_equal(fa[same], fb[same])
+        assert (fb[3:9] <= fa[3:9]).all()
+    for k in (PART for PART in (fhs.PART_NONE, fhs.PART_THIRDS, fhs.PART_EQ8)):
+        assert a.choose_partition(k) == b.choose_partition(k)
+    wa, wb = a.work(0, a.G), b.work(0, b.G)
+    assert wa["gates"] == wb["gates"] and wa["fp64_flops"] == wb["fp64_flops"]
+    assert wa["branch"] == wb["branch"] and wb["int_ops"] <= wa["int_ops"]
+
+
+def test_walk_ladders_fold_to_one_instruction_each():
+    n_pos, steps = 99, 20
+    a = fhs.Program(w.quantum_walk(n_pos, steps).to_text(), fuse=False)
+    b = fhs.Program(w.quantum_walk(n_pos, steps).to_text())
+    # unfolded: the X on position bit i has controls up to qubit i (w words): 3w+1;
+    # folded: one add per ladder, 3*1+1 for the coin control + 3 per field word
+    words = lambda hi: hi // 32 + 1
+    unfolded = steps * (4 + 2 * sum(3 * words(i) + 1 for i in range(n_pos)))
+    assert a.work(0, a.G)["int_ops"] == unfolded
+    assert b.work(0, b.G)["int_ops"] == steps * (4 + 2 * (4 + 3 * 4))
+
+
+def test_mixed_circuits_without_ladders_are_unchanged():
+    for seed in range(5):
+        t = w.random_clifford_t(10, 60, seed).to_text()
+        a, b = fhs.Program(t, fuse=False), fhs.Program(t)
+        assert a.work(0, a.G) == b.work(0, b.G)
+
+
+def test_reduce_ex_rejects_unknown_flags():
+    t = b"qubits 2\nH 0\n"
+    h = ctypes.c_void_p()
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 2, ctypes.byref(h)) == 1
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 0, ctypes.byref(h)) == 0
+    fhs.lib().fhs_program_free(h)

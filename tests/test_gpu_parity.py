@@ -213,6 +213,60 @@ def test_walk_config_full(ctx):
         assert (amps[42:] == 0).all() and (st[42:, 0] == 0).all()
 
 
+def _reachable(circuit, count, seed):
+    """Outputs reachable from |0>: follow the circuit forward with a random
+    value at every H (permutations applied, phases ignored)."""
+    rng = np.random.default_rng(seed)
+    outs = set()
+    for _ in range(count * 4):
+        x = 0
+        for g in circuit.gates:
+            q = g.qubits
+            negs = g.negs or (False,) * len(q)
+            if g.name == "H":
+                x = (x & ~(1 << q[0])) | (int(rng.integers(0, 2)) << q[0])
+            elif g.name == "X":
+                x ^= 1 << q[0]
+            elif g.name == "CX":
+                if (x >> q[0]) & 1:
+                    x ^= 1 << q[1]
+            elif g.name == "MCX":
+                if all(((x >> c) & 1) != int(ng) for c, ng in zip(q[1:], negs[1:])):
+                    x ^= 1 << q[0]
+        outs.add(x)
+        if len(outs) >= count:
+            break
+    return sorted(outs)
+
+
+@pytest.mark.parametrize("n,seed", [(12, 1), (40, 2), (64, 3), (100, 4)])
+def test_folded_ladders(ctx, n, seed):
+    """Add/subtract-one ladders folded into one instruction (the default)
+    and left gate by gate: both match the oracle at every cut, plain too."""
+    c = w.random_ladders(n, 12, seed)
+    t = c.to_text()
+    outs = _reachable(c, 24, seed) + w.random_outputs(n, 8, seed + 50)
+    o = oracle.Feynman(t)
+    ref = o.evaluate([0], [1], outs, threads=THREADS)
+    assert np.abs(ref[0]).max() > 0.0          # some amplitudes are nonzero
+    for fuse in (True, False):
+        prog = fhs.Program(t, fuse=fuse)
+        parts = [prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
+                 (0, prog.G), (prog.G, prog.G)]
+        # cuts inside a folded ladder: the next few positions after each source
+        src = prog.source_eval_positions
+        if src:
+            parts += [(src[0] + 1, src[-1] + 2), (src[len(src) // 2] + 3, prog.G)]
+        for part, plain in [((0, 0), True)] + [(p, False) for p in parts]:
+            part = (min(part[0], prog.G), min(part[1], prog.G))
+            amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
+            assert np.abs(amps - ref[0]).max() <= TOL, (fuse, part, plain)
+            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (fuse, part)
+    if n <= 12:
+        sv_ref = sv.amplitudes(t, [0], [1], outs)
+        assert np.abs(ref[0] - sv_ref).max() <= 1e-12
+
+
 def test_multi_input_and_edge_cases(ctx):
     t = w.random_mixed(7, 30, 77).to_text()
     inputs = [3, 17, 100]

@@ -33,7 +33,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "Gate", "Circuit", "random_clifford_t", "random_mixed", "qft", "amplitude_amplification",
+    "Gate", "Circuit", "random_clifford_t", "random_mixed", "random_ladders", "qft", "amplitude_amplification",
     "qaoa_maxcut", "quantum_walk", "random_outputs", "bits_to_words",
     "words_to_bits", "n_words", "three_regular_graph", "CONFIGS",
 ]
@@ -162,6 +162,43 @@ def random_mixed(n: int, n_gates: int, seed: int, max_controls: int = 3) -> Circ
             if k == "MCX":
                 negs[0] = False
             c.add(k, *qs, negs=negs)
+    return c
+
+
+def random_ladders(n: int, n_ladders: int, seed: int, n_extra: int = 4) -> Circuit:
+    """Random circuit built around add/subtract-one ladders (test coverage
+    for ladder folding): each ladder is preceded by an H on a random qubit
+    and a few random one- and two-qubit gates, then adds or subtracts one on
+    a random block of consecutive qubits under 0-2 extra controls of random
+    polarity, written as the walk writes it (MCX from the top bit down).
+    Some ladders are broken on purpose (one gate with a wrong control) so
+    that partial ladders occur too."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    for _ in range(n_ladders):
+        c.add("H", int(rng.integers(0, n)))
+        for _ in range(int(rng.integers(0, n_extra + 1))):
+            k = ["T", "S", "CX", "CZ", "X"][int(rng.integers(0, 5))]
+            if k in ("CX", "CZ"):
+                a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+                c.add(k, a, b)
+            else:
+                c.add(k, int(rng.integers(0, n)))
+        m = int(rng.integers(2, min(n - 1, 40) + 1))
+        lo = int(rng.integers(0, n - m + 1))
+        block = list(range(lo, lo + m))
+        rest = [q for q in range(n) if q < lo or q >= lo + m]
+        n_k = int(rng.integers(0, min(2, len(rest)) + 1))
+        ks = [int(x) for x in rng.choice(rest, size=n_k, replace=False)] if n_k else []
+        kneg = [bool(rng.integers(0, 2)) for _ in ks]
+        neg = bool(rng.integers(0, 2))         # False: add one, True: subtract one
+        broken = int(rng.integers(0, m)) if rng.random() < 0.25 else -1
+        for i in range(m - 1, -1, -1):
+            ctrls = ks + block[:i]
+            negs = [False] + kneg + [neg] * i
+            if i == broken and i > 0:
+                negs[-1] = not neg
+            c.add("MCX", block[i], *ctrls, negs=tuple(negs))
     return c
 
 
