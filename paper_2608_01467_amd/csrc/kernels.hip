@@ -188,23 +188,33 @@ __device__ __forceinline__ void op_mcphase(Lanes<NW, H> &L, const Instr &I) {
     });
 }
 
-// Fused ladder (OP_ADD): when the controls match, add or subtract one on
-// the bit field [lo, lo+m) of the state, mod 2^m.  The field is masked out of
-// the state words, the +-2^lo is propagated through them with carries, and
-// the result is merged back under the field mask.
+// Folded ladder (OP_ADD): when the controls match, add one to (zmask bit
+// 0: subtract one from) the bit field [lo, lo+m) of the state, mod 2^m.  The
+// whole state is added to +-2^lo (two's complement over the state's width)
+// with one carry chain over its 32-bit words: no bit below lo changes, and
+// whatever the carry does above the field is discarded when the field bits
+// of the sum are merged back.
 template <int NW, int H, int LW>
 __device__ __forceinline__ void op_add(Lanes<NW, H> &L, const Instr &I) {
-    const uint32_t lo = hdr_a(I), m = hdr_b(I);
-    const bool sub = (hdr_z(I) & 1u) != 0u;
-    uint32_t fm[NW];   // field mask per 32-bit word (wave-uniform)
-    unroll<NW>([&](auto ww) {
-        constexpr int w = ww.value;
-        const int a = min(32, max(0, static_cast<int>(lo) - 32 * w));
-        const int b = min(32, max(0, static_cast<int>(lo + m) - 32 * w));
-        const uint32_t below_b = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
-        const uint32_t below_a = a >= 32 ? 0xffffffffu : ((1u << a) - 1u);
-        fm[w] = below_b & ~below_a;
-    });
+    const uint32_t lo = hdr_a(I), hi = lo + hdr_b(I);   // field [lo, hi), hi <= 128
+    // 128-bit masks and addend as two 64-bit halves, all wave-uniform
+    auto below = [](uint32_t b, uint64_t &m0, uint64_t &m1) {   // bits [0, b)
+        m0 = b >= 64u ? ~0ull : ((1ull << b) - 1ull);
+        m1 = b >= 128u ? ~0ull : (b > 64u ? ((1ull << (b - 64u)) - 1ull) : 0ull);
+    };
+    uint64_t a0, a1, b0, b1;
+    below(lo, a0, a1);
+    below(hi, b0, b1);
+    const uint64_t f0 = b0 & ~a0, f1 = b1 & ~a1;
+    uint64_t d0 = lo < 64u ? (1ull << lo) : 0ull, d1 = lo >= 64u ? (1ull << (lo - 64u)) : 0ull;
+    if (hdr_z(I) & 1u) {   // -2^lo = ~2^lo + 1 over 128 bits
+        d0 = ~d0 + 1ull;
+        d1 = ~d1 + (d0 == 0ull ? 1ull : 0ull);
+    }
+    const uint32_t fm[4] = {static_cast<uint32_t>(f0), static_cast<uint32_t>(f0 >> 32),
+                            static_cast<uint32_t>(f1), static_cast<uint32_t>(f1 >> 32)};
+    const uint32_t dd[4] = {static_cast<uint32_t>(d0), static_cast<uint32_t>(d0 >> 32),
+                            static_cast<uint32_t>(d1), static_cast<uint32_t>(d1 >> 32)};
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
@@ -212,34 +222,14 @@ __device__ __forceinline__ void op_add(Lanes<NW, H> &L, const Instr &I) {
             constexpr int j = jj.value;
             if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
         });
-        const uint64_t one = acc == 0u ? 1ull : 0ull;
-        if constexpr (NW == 1) {
-            const uint32_t x = L.s[h][0] & fm[0];
-            const uint32_t d = static_cast<uint32_t>(one) << lo;
-            const uint32_t r = sub ? x - d : x + d;
-            L.s[h][0] = (L.s[h][0] & ~fm[0]) | (r & fm[0]);
-        } else {
-            const uint64_t f0 = (static_cast<uint64_t>(fm[1]) << 32) | fm[0];
-            const uint64_t s0 = (static_cast<uint64_t>(L.s[h][1]) << 32) | L.s[h][0];
-            const uint64_t x0 = s0 & f0;
-            const uint64_t d0 = lo < 64u ? one << lo : 0ull;
-            const uint64_t r0 = sub ? x0 - d0 : x0 + d0;
-            const uint64_t n0 = (s0 & ~f0) | (r0 & f0);
-            L.s[h][0] = static_cast<uint32_t>(n0);
-            L.s[h][1] = static_cast<uint32_t>(n0 >> 32);
-            if constexpr (NW == 4) {
-                const uint64_t f1 = (static_cast<uint64_t>(fm[3]) << 32) | fm[2];
-                const uint64_t s1 = (static_cast<uint64_t>(L.s[h][3]) << 32) | L.s[h][2];
-                const uint64_t x1 = s1 & f1;
-                const uint64_t d1 = lo >= 64u ? one << (lo - 64u) : 0ull;
-                // carry (borrow) out of the low 64 bits
-                const uint64_t c = sub ? (x0 < d0 ? 1ull : 0ull) : (r0 < x0 ? 1ull : 0ull);
-                const uint64_t r1 = sub ? x1 - d1 - c : x1 + d1 + c;
-                const uint64_t n1 = (s1 & ~f1) | (r1 & f1);
-                L.s[h][2] = static_cast<uint32_t>(n1);
-                L.s[h][3] = static_cast<uint32_t>(n1 >> 32);
-            }
-        }
+        const bool go = acc == 0u;
+        uint32_t carry = 0;
+        unroll<NW>([&](auto ww) {
+            constexpr int w = ww.value;
+            const uint32_t x = L.s[h][w];
+            const uint32_t r = __builtin_addc(x, dd[w], carry, &carry);
+            L.s[h][w] = go ? ((x & ~fm[w]) | (r & fm[w])) : x;
+        });
     });
 }
 
@@ -414,7 +404,7 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
                     }
                 });
                 break;
-            default:   // OP_NOP: gates folded into the preceding OP_ADD
+            default:
                 break;
         }
         e = end;
@@ -558,7 +548,7 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     L.ok[0] = !(bad_o || bad_i);
     L.hb[0] = 0;
     const FacRef F{c.fac, 0u};
-    run_region<NW, 1, PRUNE>(c.prog, F, 0, c.L, L, 0, bin, c.thr);
+    run_region<NW, 1, PRUNE>(c.prog, F, 0, c.iL, L, 0, bin, c.thr);
     const bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
 #pragma unroll
     for (int w = 0; w < NW; ++w) pre.st[static_cast<size_t>(w) * P + p] = L.s[0][w];
@@ -581,7 +571,7 @@ __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab
     const uint32_t lo_bits = c.Ap - Dp;
     const uint64_t NL = static_cast<uint64_t>(B) << lo_bits;
     const uint64_t lomask = (1ull << lo_bits) - 1ull;
-    const uint32_t e_split = Dp ? ld_const(c.src, lo_bits) : c.c1;
+    const uint32_t e_split = Dp ? ld_const(c.src, lo_bits) : c.i1;
     const Mask4 fin_c1 = ld_const(c.fin, c.c1);
     for (uint64_t lb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; lb < NL;
          lb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -601,10 +591,10 @@ __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab
         L.M[0] = pre.M[p];
         L.ok[0] = pre.ok[p] == 1u;
         L.hb[0] = li & lomask;
-        run_region<NW, 1, PRUNE>(c.prog, F, c.L, e_split, L, 0, bin, c.thr);
+        run_region<NW, 1, PRUNE>(c.prog, F, c.iL, e_split, L, 0, bin, c.thr);
         const uint64_t ebase = pl << c.Ap;
         const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
-        dfs_region<NW, 1, PRUNE, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.c1, L, 0u, bin, c.thr,
+        dfs_region<NW, 1, PRUNE, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.i1, L, 0u, bin, c.thr,
                                         [&](Lanes<NW, 1> &C) {
             const bool ok = C.ok[0] && check_final<NW>(C.s[0], bin, fin_c1);
             if (live) {
@@ -718,7 +708,7 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
                 R.hb[j] = hr;
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
-            run_region<NW, H, PRUNE>(c.prog, F, c.c1, c.c2, R, c.Ap, bin, c.thr);
+            run_region<NW, H, PRUNE>(c.prog, F, c.i1, c.i2, R, c.Ap, bin, c.thr);
             bool any = false;
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
@@ -729,7 +719,7 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
             for (uint64_t q = 0; q < n_suffix; ++q) {
                 Lanes<NW, H> S2 = R;
                 unroll<H>([&](auto jj) { S2.hb[jj.value] = hs0[jj.value] + q; });
-                run_region<NW, H, PRUNE>(c.prog, F, c.c2, c.G, S2, sshift, bin, c.thr);
+                run_region<NW, H, PRUNE>(c.prog, F, c.i2, c.iG, S2, sshift, bin, c.thr);
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
                     const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
@@ -784,7 +774,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
                 L.hb[j] = h0 + j * stride;
                 L.ok[j] = L.hb[j] < NH;
             });
-            run_region<NW, H, PRUNE>(c.prog, F, c.L, c.G, L, 0, bin, c.thr);
+            run_region<NW, H, PRUNE>(c.prog, F, c.iL, c.iG, L, 0, bin, c.thr);
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
                 const bool inrange = L.hb[j] < NH;

@@ -41,12 +41,15 @@ struct Common {
     const Instr *prog;       // device program, evaluation order
     const double *fac;       // factor table
     const Mask4 *fin;        // [G+1] bits final once e gates are applied
-    const uint32_t *src;     // [A] evaluation position of source k's gate (ascending)
+    const uint32_t *src;     // [A] device-program index of source k's gate (ascending)
     const uint64_t *inputs;  // [S][W]
     const uint64_t *outputs; // [M][W]
     uint32_t S, M, W, n;
     uint32_t G, L, A;
-    uint32_t c1, c2;         // effective cuts, L <= c1 <= c2 <= G
+    uint32_t c1, c2;         // effective cuts, L <= c1 <= c2 <= G (evaluation positions)
+    // The device program drops the gates folded into an OP_ADD, so region
+    // bounds are device-program indices: iL, i1, i2, iG of positions L, c1, c2, G.
+    uint32_t iL, i1, i2, iG;
     uint32_t Ap, Ar, As;
     uint32_t f_L, f_c1, f_c2, f_G;   // factor-table offsets of evaluation positions L, c1, c2, G
     double thr;

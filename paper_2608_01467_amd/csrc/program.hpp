@@ -36,9 +36,9 @@ enum Op : uint8_t {
     OP_MCPHASE = 6,     // if ((s ^ cv) & cm) == 0: amplitude *= -1       (MCZ)
     OP_BRANCH_SRC = 7,  // o = bit a, i = source bit k: factor U[o][i], bit a := i
     OP_BRANCH_NAT = 8,  // o = bit a, i = input bit a:  factor U[o][i], bit a := i
-    OP_ADD = 9,         // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) -= 1 (zmask bit 0) or += 1,
-                        // mod 2^b: a fused ladder of controlled X gates (see the reducer)
-    OP_NOP = 10,        // a gate folded into the OP_ADD before it
+    OP_ADD = 9,         // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) += 1 mod 2^b, or -= 1
+                        // when zmask bit 0 is set (a folded ladder of controlled X gates)
+    OP_NOP = 10,        // a gate folded into the OP_ADD before it (dropped from the device copy)
 };
 
 // The opcode byte carries the base op in its low 4 bits; bits 4-5 and 6-7

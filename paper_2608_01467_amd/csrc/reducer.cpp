@@ -428,16 +428,16 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
 inline bool test_bit(const uint32_t *w, uint32_t q) { return (w[q >> 5] >> (q & 31)) & 1u; }
 
 // Fold ladders of controlled X gates that add or subtract one on a block of
-// consecutive qubits into one OP_ADD.  In evaluation order the ladder reads
-// (j = 0 .. m-1): X on bit lo+j under the common controls K and the
-// controls bits lo .. lo+j-1, all of one polarity v.  Walking backward,
+// consecutive qubits into one OP_ADD.  In evaluation order the
+// ladder reads (j = 0 .. m-1): X on bit lo+j under the common controls K and
+// the controls bits lo .. lo+j-1, all of one polarity v.  Walking backward,
 // bit lo+j flips iff K holds and bits lo .. lo+j-1 all equal v after their
 // own flips, i.e. iff they all equalled 1-v before: the ladder subtracts one
-// from the m-bit field when v = 1 and adds one when v = 0, mod 2^m (an
-// incrementer built this way is a standard reversible-arithmetic circuit).
-// The folded gates stay in place as OP_NOP, so every evaluation position,
-// cut, source index, final-bit mask and Eq. (8) count is unchanged; only the
-// work per history drops.
+// from the m-bit field when v = 1 and adds one when v = 0, mod 2^m (one
+// OP_ADD, the sign in zmask bit 0; an incrementer built this way is a standard
+// reversible-arithmetic circuit).  The folded gates stay in place as OP_NOP,
+// so every evaluation position, cut, source index, final-bit mask and Eq. (8)
+// count is unchanged; only the work per history drops.
 void fuse_ladders(HostProgram &P) {
     const int G = P.G;
     P.n_fused = 0;
@@ -491,7 +491,7 @@ void fuse_ladders(HostProgram &P) {
         A.hdr = pack_hdr(op_code(OP_ADD, wspan, 0), lo, static_cast<uint32_t>(m), v == 1 ? 1u : 0u);
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
-        P.int_cost[e] = static_cast<uint16_t>(3 * (wspan + 1) + 1 + 3 * wfield);
+        P.int_cost[e] = static_cast<uint16_t>(3 * (wspan + 1) + 1 + 3 * wfield);   // test, carry, merge
         for (int j = 1; j < m; ++j) {
             Instr N{};
             N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);

@@ -81,7 +81,8 @@ struct fhs_ctx {
     Instr *d_prog = nullptr;
     double *d_fac = nullptr;
     Mask4 *d_fin = nullptr;
-    uint32_t *d_src = nullptr;   // [max(A,1)] evaluation position of each source
+    uint32_t *d_src = nullptr;   // [max(A,1)] device-program index of each source gate
+    std::vector<uint32_t> pos2ins;   // [G+1] evaluation position -> device-program index
     uint32_t c1 = 0, c2 = 0;
     size_t table_budget = size_t(1) << 30;
     uint64_t generation = 0;
@@ -288,6 +289,10 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.A = static_cast<uint32_t>(P.A);
     cm.c1 = pl.c1;
     cm.c2 = pl.c2;
+    cm.iL = c->pos2ins[P.L];
+    cm.i1 = c->pos2ins[pl.c1];
+    cm.i2 = c->pos2ins[pl.c2];
+    cm.iG = c->pos2ins[P.G];
     cm.Ap = pl.Ap;
     cm.Ar = pl.Ar;
     cm.As = pl.As;
@@ -402,20 +407,37 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     c->prog = P;
     fhs_program_free(c->prog_copy);
     c->prog_copy = fhs_program_clone(p);
-    const size_t ni = std::max<size_t>(P.ins.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
+    // Device copy of the program without the gates folded into an OP_ADD;
+    // pos2ins maps evaluation positions to its indices (a position inside a
+    // folded ladder maps to the next kept instruction, so the whole ladder
+    // runs in the region where it starts).  Runs are recounted.
+    std::vector<Instr> dev;
+    dev.reserve(P.ins.size());
+    c->pos2ins.assign(static_cast<size_t>(P.G) + 1, 0);
+    for (int e = 0; e < P.G; ++e) {
+        c->pos2ins[e] = static_cast<uint32_t>(dev.size());
+        if (op_base(P.ins[e].hdr & 0xffu) != OP_NOP) dev.push_back(P.ins[e]);
+    }
+    c->pos2ins[P.G] = static_cast<uint32_t>(dev.size());
+    for (size_t i = dev.size(); i-- > 0;)
+        dev[i].run = (i + 1 < dev.size() && (dev[i + 1].hdr & 0xffu) == (dev[i].hdr & 0xffu))
+                         ? dev[i + 1].run + 1 : 1;
+    std::vector<uint32_t> src_dev(P.src_eval.size());
+    for (size_t k = 0; k < P.src_eval.size(); ++k) src_dev[k] = c->pos2ins[P.src_eval[k]];
+    const size_t ni = std::max<size_t>(dev.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fin), sizeof(Mask4) * P.final_before.size()));
-    if (!P.ins.empty())
-        FHS_HIP(c, hipMemcpy(c->d_prog, P.ins.data(), sizeof(Instr) * P.ins.size(), hipMemcpyHostToDevice));
+    if (!dev.empty())
+        FHS_HIP(c, hipMemcpy(c->d_prog, dev.data(), sizeof(Instr) * dev.size(), hipMemcpyHostToDevice));
     if (!P.fac.empty())
         FHS_HIP(c, hipMemcpy(c->d_fac, P.fac.data(), sizeof(double) * P.fac.size(), hipMemcpyHostToDevice));
     FHS_HIP(c, hipMemcpy(c->d_fin, P.final_before.data(), sizeof(Mask4) * P.final_before.size(),
                          hipMemcpyHostToDevice));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_src),
                          sizeof(uint32_t) * std::max<size_t>(P.src_eval.size(), 1)));
-    if (!P.src_eval.empty())
-        FHS_HIP(c, hipMemcpy(c->d_src, P.src_eval.data(), sizeof(uint32_t) * P.src_eval.size(),
+    if (!src_dev.empty())
+        FHS_HIP(c, hipMemcpy(c->d_src, src_dev.data(), sizeof(uint32_t) * src_dev.size(),
                              hipMemcpyHostToDevice));
     c->c1 = c->c2 = 0;
     c->loaded = true;
