@@ -106,7 +106,7 @@ def main() -> int:
                     help="keep the default launch shape instead of sweeping it")
     ap.add_argument("--no-fuse", action="store_true",
                     help="keep one instruction per gate (no add/subtract ladder folding)")
-    ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC",
+    ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC[,DISPATCH]",
                     help="fix the launch shape (histories per lane, chunk, blocks per CU)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

@@ -166,13 +166,18 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *   chunk               prefix entries per work item of the persistent
  *                       consumer, a power of two in [1, 256] (default 256);
  *   blocks_per_cu       persistent workgroups per compute unit, at most the
- *                       occupancy limit (default: the occupancy limit).
+ *                       occupancy limit (default: the occupancy limit);
+ *   dispatch            how the kernels walk the program: 1 one opcode
+ *                       dispatch per run of identical opcodes, 2 one per
+ *                       instruction, 0 automatic (per run when the program's
+ *                       runs average two or more instructions).
  * Affects speed and the grouping of the amplitude sums (so their last bits),
  * never the history counts.  FHS_EINVAL for values out of range. */
 typedef struct {
     uint32_t histories_per_lane;
     uint32_t chunk;
     uint32_t blocks_per_cu;
+    uint32_t dispatch;
 } fhs_launch_config;
 
 fhs_status fhs_set_launch_config(fhs_ctx *ctx, const fhs_launch_config *cfg);

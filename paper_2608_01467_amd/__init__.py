@@ -73,7 +73,7 @@ class MlpShape(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("histories_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("dispatch", ctypes.c_uint32)]
 
 
 _lib = None
@@ -252,15 +252,15 @@ class Context:
         return c1.value, c2.value
 
     def set_launch_config(self, histories_per_lane: int = 0, chunk: int = 0,
-                          blocks_per_cu: int = 0) -> None:
-        cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu)
+                          blocks_per_cu: int = 0, dispatch: int = 0) -> None:
+        cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu, dispatch)
         _check(lib().fhs_set_launch_config(self._h, ctypes.byref(cfg)), self)
 
     @property
-    def launch_config(self) -> Tuple[int, int, int]:
+    def launch_config(self) -> Tuple[int, int, int, int]:
         cfg = LaunchConfig()
         _check(lib().fhs_get_launch_config(self._h, ctypes.byref(cfg)), self)
-        return cfg.histories_per_lane, cfg.chunk, cfg.blocks_per_cu
+        return cfg.histories_per_lane, cfg.chunk, cfg.blocks_per_cu, cfg.dispatch
 
     def plan(self, M: int, S: int) -> dict:
         p = Plan()

@@ -314,7 +314,7 @@ __device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const
 // bin is the input bitstring (the same for every history of a lane).  The
 // opcode is dispatched once per run of identical opcodes; the case loops
 // over the run.
-template <int NW, int H, bool PRUNE>
+template <int NW, int H, bool PRUNE, bool RUNS>
 __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacRef &F,
                                            uint32_t e0, uint32_t e1, Lanes<NW, H> &L,
                                            uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
@@ -322,86 +322,70 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
     uint32_t e = e0;
     while (e < e1) {
         const uint32_t op = prog[e].hdr & 0xffu;
-        const uint32_t n = min(prog[e].run, e1 - e);
-        const uint32_t end = e + n;
+        const uint32_t end = RUNS ? e + min(prog[e].run, e1 - e) : e + 1u;
         const uint32_t w1 = (op >> 4) & 3u, w2 = (op >> 6) & 3u;
+        // the instructions of this dispatch: the run, or just prog[e]
+        auto each = [&](auto &&f) {
+            if constexpr (RUNS) {
+                for (uint32_t x = e; x < end; ++x) {
+                    const Instr I = prog[x];
+                    f(I);
+                }
+            } else {
+                const Instr I = prog[e];
+                f(I);
+            }
+        };
         switch (op & 15u) {
             case OP_PERM:
                 with_word<NW>(w1, [&](auto TW) {
                     with_word<NW>(w2, [&](auto LW) {
-                        for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                            op_perm<NW, H, TW.value, LW.value>(L, I);
-                        }
+                        each([&](const Instr &I) { op_perm<NW, H, TW.value, LW.value>(L, I); });
                     });
                 });
                 break;
             case OP_BRANCH_SRC:
                 with_word<NW>(w1, [&](auto WA) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_branch<NW, H, PRUNE, WA.value, true>(L, I, F, kbase, bin, thr);
-                    }
+                    each([&](const Instr &I) { op_branch<NW, H, PRUNE, WA.value, true>(L, I, F, kbase, bin, thr); });
                 });
                 break;
             case OP_BRANCH_NAT:
                 with_word<NW>(w1, [&](auto WA) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_branch<NW, H, PRUNE, WA.value, false>(L, I, F, kbase, bin, thr);
-                    }
+                    each([&](const Instr &I) { op_branch<NW, H, PRUNE, WA.value, false>(L, I, F, kbase, bin, thr); });
                 });
                 break;
             case OP_DIAG2:
                 with_word<NW>(w1, [&](auto WA) {
                     with_word<NW>(w2, [&](auto WB) {
-                        for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                            op_diag2<NW, H, WA.value, WB.value>(L, I, F);
-                        }
+                        each([&](const Instr &I) { op_diag2<NW, H, WA.value, WB.value>(L, I, F); });
                     });
                 });
                 break;
             case OP_DIAG1:
                 with_word<NW>(w1, [&](auto WA) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_diag1<NW, H, WA.value>(L, I, F);
-                    }
+                    each([&](const Instr &I) { op_diag1<NW, H, WA.value>(L, I, F); });
                 });
                 break;
             case OP_MCPHASE:
                 with_word<NW>(w1, [&](auto LW) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_mcphase<NW, H, LW.value>(L, I);
-                    }
+                    each([&](const Instr &I) { op_mcphase<NW, H, LW.value>(L, I); });
                 });
                 break;
             case OP_SWAP:
                 with_word<NW>(w1, [&](auto WA) {
                     with_word<NW>(w2, [&](auto WB) {
-                        for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                            op_swap<NW, H, WA.value, WB.value>(L, I);
-                        }
+                        each([&](const Instr &I) { op_swap<NW, H, WA.value, WB.value>(L, I); });
                     });
                 });
                 break;
             case OP_DET1:
                 with_word<NW>(w1, [&](auto WA) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_det1<NW, H, WA.value>(L, I, F);
-                    }
+                    each([&](const Instr &I) { op_det1<NW, H, WA.value>(L, I, F); });
                 });
                 break;
             case OP_ADD:
                 with_word<NW>(w1, [&](auto LW) {
-                    for (uint32_t x = e; x < end; ++x) {
-                        const Instr I = prog[x];
-                        op_add<NW, H, LW.value>(L, I);
-                    }
+                    each([&](const Instr &I) { op_add<NW, H, LW.value>(L, I); });
                 });
                 break;
             default:
@@ -435,7 +419,7 @@ __device__ __forceinline__ void copy_core(Lanes<NW, H> &dst, const Lanes<NW, H> 
 // reused by every assignment that agrees on the earlier sources (the
 // checkpoint idea of Algorithm 2 applied at every source).  Control flow is
 // wave-uniform throughout.
-template <int NW, int H, bool PRUNE, int DMAX, class Leaf>
+template <int NW, int H, bool PRUNE, bool RUNS, int DMAX, class Leaf>
 __device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, const uint32_t *src,
                                            uint32_t k0, uint32_t D, uint32_t e_end,
                                            const Lanes<NW, H> &L, uint32_t kbase,
@@ -461,7 +445,7 @@ __device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, c
             unroll<H>([&](auto hh) { C.hb[hh.value] = (C.hb[hh.value] & ~(1ull << kb)) | bit; });
             const uint32_t a = ld_const(src, k0 + l);
             const uint32_t b = (l + 1u < D) ? ld_const(src, k0 + l + 1u) : e_end;
-            run_region<NW, H, PRUNE>(prog, F, a, b, C, kbase, bin, thr);
+            run_region<NW, H, PRUNE, RUNS>(prog, F, a, b, C, kbase, bin, thr);
             if (l + 1u < D) {
                 unroll<DMAX>([&](auto LV) {
                     if constexpr (LV.value > 0)
@@ -548,7 +532,7 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     L.ok[0] = !(bad_o || bad_i);
     L.hb[0] = 0;
     const FacRef F{c.fac, 0u};
-    run_region<NW, 1, PRUNE>(c.prog, F, 0, c.iL, L, 0, bin, c.thr);
+    run_region<NW, 1, PRUNE, true>(c.prog, F, 0, c.iL, L, 0, bin, c.thr);
     const bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
 #pragma unroll
     for (int w = 0; w < NW; ++w) pre.st[static_cast<size_t>(w) * P + p] = L.s[0][w];
@@ -557,7 +541,7 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     pre.ok[p] = (ok ? 1u : 0u) | ((bad_o || bad_i) ? 2u : 0u);
 }
 
-template <int NW, bool PRUNE, bool FLDS>
+template <int NW, bool PRUNE, bool FLDS, bool RUNS>
 __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab, uint32_t p0,
                                                 uint32_t B, uint32_t P, uint32_t Dp) {
     extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
@@ -591,10 +575,11 @@ __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab
         L.M[0] = pre.M[p];
         L.ok[0] = pre.ok[p] == 1u;
         L.hb[0] = li & lomask;
-        run_region<NW, 1, PRUNE>(c.prog, F, c.iL, e_split, L, 0, bin, c.thr);
+        run_region<NW, 1, PRUNE, RUNS>(c.prog, F, c.iL, e_split, L, 0, bin, c.thr);
         const uint64_t ebase = pl << c.Ap;
         const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
-        dfs_region<NW, 1, PRUNE, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.i1, L, 0u, bin, c.thr,
+        dfs_region<NW, 1, PRUNE, RUNS, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.i1, L, 0u, bin,
+                                                c.thr,
                                         [&](Lanes<NW, 1> &C) {
             const bool ok = C.ok[0] && check_final<NW>(C.s[0], bin, fin_c1);
             if (live) {
@@ -609,7 +594,7 @@ __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab
     }
 }
 
-template <int NW, int H, bool PRUNE, bool FLDS>
+template <int NW, int H, bool PRUNE, bool FLDS, bool RUNS>
 __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab, Partials part,
                                                              uint32_t p0, uint32_t B,
                                                              uint32_t chunk, uint32_t ss,
@@ -708,7 +693,7 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
                 R.hb[j] = hr;
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
-            run_region<NW, H, PRUNE>(c.prog, F, c.i1, c.i2, R, c.Ap, bin, c.thr);
+            run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.i1, c.i2, R, c.Ap, bin, c.thr);
             bool any = false;
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
@@ -719,7 +704,7 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
             for (uint64_t q = 0; q < n_suffix; ++q) {
                 Lanes<NW, H> S2 = R;
                 unroll<H>([&](auto jj) { S2.hb[jj.value] = hs0[jj.value] + q; });
-                run_region<NW, H, PRUNE>(c.prog, F, c.i2, c.iG, S2, sshift, bin, c.thr);
+                run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.i2, c.iG, S2, sshift, bin, c.thr);
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
                     const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
@@ -739,7 +724,7 @@ __global__ __launch_bounds__(kConsumeThreads) void k_consume(Common c, Table tab
     }
 }
 
-template <int NW, int H, bool PRUNE, bool FLDS>
+template <int NW, int H, bool PRUNE, bool FLDS, bool RUNS>
 __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, Partials part,
                                                          uint32_t P, uint32_t bpp) {
     constexpr int NT = kPlainThreads;
@@ -774,7 +759,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
                 L.hb[j] = h0 + j * stride;
                 L.ok[j] = L.hb[j] < NH;
             });
-            run_region<NW, H, PRUNE>(c.prog, F, c.iL, c.iG, L, 0, bin, c.thr);
+            run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.iL, c.iG, L, 0, bin, c.thr);
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
                 const bool inrange = L.hb[j] < NH;
@@ -930,8 +915,10 @@ hipError_t launch_prefix(const Common &c, int NW, PreBufs pre, Table tab, uint32
     dispatch_nw(NW, [&](auto nw) {
         dispatch_bool(c.thr > 0.0, [&](auto pr) {
             dispatch_bool(flds, [&](auto fl) {
-                k_prefix<nw.value, pr.value, fl.value>
-                    <<<static_cast<uint32_t>(blocks), 256, shm, s>>>(c, pre, tab, p0, B, P, Dp);
+                dispatch_bool(c.runs != 0u, [&](auto ru) {
+                    k_prefix<nw.value, pr.value, fl.value, ru.value>
+                        <<<static_cast<uint32_t>(blocks), 256, shm, s>>>(c, pre, tab, p0, B, P, Dp);
+                });
             });
         });
     });
@@ -948,8 +935,10 @@ hipError_t launch_consume(const Common &c, int NW, int H, Table tab, Partials pa
         dispatch_h(H, [&](auto hh) {
             dispatch_bool(c.thr > 0.0, [&](auto pr) {
                 dispatch_bool(flds, [&](auto fl) {
-                    k_consume<nw.value, hh.value, pr.value, fl.value>
-                        <<<grid, kConsumeThreads, shm, s>>>(c, tab, part, p0, B, chunk, ss, counter);
+                    dispatch_bool(c.runs != 0u, [&](auto ru) {
+                        k_consume<nw.value, hh.value, pr.value, fl.value, ru.value>
+                            <<<grid, kConsumeThreads, shm, s>>>(c, tab, part, p0, B, chunk, ss, counter);
+                    });
                 });
             });
         });
@@ -967,8 +956,10 @@ hipError_t launch_plain(const Common &c, int NW, int H, PreBufs pre, Partials pa
         dispatch_h(H, [&](auto hh) {
             dispatch_bool(c.thr > 0.0, [&](auto pr) {
                 dispatch_bool(flds, [&](auto fl) {
-                    k_plain<nw.value, hh.value, pr.value, fl.value>
-                        <<<static_cast<uint32_t>(blocks), kPlainThreads, shm, s>>>(c, pre, part, P, bpp);
+                    dispatch_bool(c.runs != 0u, [&](auto ru) {
+                        k_plain<nw.value, hh.value, pr.value, fl.value, ru.value>
+                            <<<static_cast<uint32_t>(blocks), kPlainThreads, shm, s>>>(c, pre, part, P, bpp);
+                    });
                 });
             });
         });
@@ -1007,9 +998,13 @@ int consume_blocks_per_cu(const Common &c, int NW, int H) {
         dispatch_h(H, [&](auto hh) {
             dispatch_bool(c.thr > 0.0, [&](auto pr) {
                 dispatch_bool(flds, [&](auto fl) {
-                    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &nb, reinterpret_cast<const void *>(k_consume<nw.value, hh.value, pr.value, fl.value>),
-                        kConsumeThreads, shm);
+                    dispatch_bool(c.runs != 0u, [&](auto ru) {
+                        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb,
+                            reinterpret_cast<const void *>(
+                                k_consume<nw.value, hh.value, pr.value, fl.value, ru.value>),
+                            kConsumeThreads, shm);
+                    });
                 });
             });
         });

@@ -50,6 +50,9 @@ struct Common {
     // The device program drops the gates folded into an OP_ADD, so region
     // bounds are device-program indices: iL, i1, i2, iG of positions L, c1, c2, G.
     uint32_t iL, i1, i2, iG;
+    // 1: dispatch once per run of identical opcodes; 0: once per instruction
+    // (better when runs are short, e.g. programs dominated by folded ladders)
+    uint32_t runs;
     uint32_t Ap, Ar, As;
     uint32_t f_L, f_c1, f_c2, f_G;   // factor-table offsets of evaluation positions L, c1, c2, G
     double thr;

@@ -94,6 +94,8 @@ struct fhs_ctx {
     int ilp = 2;             // histories per lane in the hot kernels
     uint32_t chunk_max = kMaxChunk;
     uint32_t blocks_per_cu = 0;   // 0: occupancy limit
+    uint32_t dispatch = 0;        // 0 auto, 1 per run, 2 per instruction
+    bool long_runs = true;        // the device program's runs average >= 2 instructions
     const fhs_program *host_prog = nullptr;   // for features (not owned)
     fhs_program *prog_copy = nullptr;         // owned copy used by the cost model
     bool have_model = false;
@@ -293,6 +295,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.i1 = c->pos2ins[pl.c1];
     cm.i2 = c->pos2ins[pl.c2];
     cm.iG = c->pos2ins[P.G];
+    cm.runs = c->dispatch == 1 ? 1u : (c->dispatch == 2 ? 0u : (c->long_runs ? 1u : 0u));
     cm.Ap = pl.Ap;
     cm.Ar = pl.Ar;
     cm.As = pl.As;
@@ -419,9 +422,13 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
         if (op_base(P.ins[e].hdr & 0xffu) != OP_NOP) dev.push_back(P.ins[e]);
     }
     c->pos2ins[P.G] = static_cast<uint32_t>(dev.size());
-    for (size_t i = dev.size(); i-- > 0;)
-        dev[i].run = (i + 1 < dev.size() && (dev[i + 1].hdr & 0xffu) == (dev[i].hdr & 0xffu))
-                         ? dev[i + 1].run + 1 : 1;
+    size_t n_runs = 0;
+    for (size_t i = dev.size(); i-- > 0;) {
+        const bool cont = i + 1 < dev.size() && (dev[i + 1].hdr & 0xffu) == (dev[i].hdr & 0xffu);
+        dev[i].run = cont ? dev[i + 1].run + 1 : 1;
+        if (!cont) ++n_runs;
+    }
+    c->long_runs = dev.size() >= 2 * n_runs;
     std::vector<uint32_t> src_dev(P.src_eval.size());
     for (size_t k = 0; k < P.src_eval.size(); ++k) src_dev[k] = c->pos2ins[P.src_eval[k]];
     const size_t ni = std::max<size_t>(dev.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
@@ -617,11 +624,13 @@ extern "C" fhs_status fhs_set_launch_config(fhs_ctx *c, const fhs_launch_config 
     if (!c || !cfg) return FHS_EINVAL;
     const uint32_t h = cfg->histories_per_lane ? cfg->histories_per_lane : 2;
     const uint32_t ch = cfg->chunk ? cfg->chunk : kMaxChunk;
-    if (h > 2 || ch > static_cast<uint32_t>(kMaxChunk) || (ch & (ch - 1)) || cfg->blocks_per_cu > 64)
+    if (h > 2 || ch > static_cast<uint32_t>(kMaxChunk) || (ch & (ch - 1)) || cfg->blocks_per_cu > 64 ||
+        cfg->dispatch > 2)
         return fail(c, FHS_EINVAL, "launch config out of range");
     c->ilp = static_cast<int>(h);
     c->chunk_max = ch;
     c->blocks_per_cu = cfg->blocks_per_cu;
+    c->dispatch = cfg->dispatch;
     drop_graph(c);
     return FHS_OK;
 }
@@ -631,6 +640,7 @@ extern "C" fhs_status fhs_get_launch_config(const fhs_ctx *c, fhs_launch_config 
     cfg->histories_per_lane = static_cast<uint32_t>(c->ilp);
     cfg->chunk = c->chunk_max;
     cfg->blocks_per_cu = c->blocks_per_cu;
+    cfg->dispatch = c->dispatch;
     return FHS_OK;
 }
 

@@ -90,18 +90,28 @@ def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False,
     return best
 
 
-def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int], List]:
-    """Sweep histories per lane x chunk x blocks per CU; keep the fastest."""
+def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int, int], List]:
+    """Sweep histories per lane x chunk x blocks per CU (automatic dispatch),
+    then both explicit dispatch granularities at the best shape; keep the
+    fastest."""
     log = []
     best, best_t = None, math.inf
     for h in (1, 2):
         for chunk in (64, 128, 256):
             for bpc in (0, 2, 4):
-                wl.ctx.set_launch_config(h, chunk, bpc)
+                cfg = (h, chunk, bpc, 0)
+                wl.ctx.set_launch_config(*cfg)
                 t = time_split(wl, partition, reps)
-                log.append(((h, chunk, bpc), t))
+                log.append((cfg, t))
                 if t < best_t:
-                    best, best_t = (h, chunk, bpc), t
+                    best, best_t = cfg, t
+    for dispatch in (1, 2):
+        cfg = best[:3] + (dispatch,)
+        wl.ctx.set_launch_config(*cfg)
+        t = time_split(wl, partition, reps)
+        log.append((cfg, t))
+        if t < best_t:
+            best, best_t = cfg, t
     wl.ctx.set_launch_config(*best)
     return best, log
 

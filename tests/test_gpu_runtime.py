@@ -60,15 +60,27 @@ def test_launch_shapes(ctx, case):
     for h in (1, 2):
         for chunk in (1, 64, 256):
             for bpc in (0, 1, 3):
-                ctx.set_launch_config(h, chunk, bpc)
-                assert ctx.launch_config == (h, chunk, bpc)
-                amps, st = _run(ctx, prog, outs, thr, part)
-                _check((name, h, chunk, bpc), amps, st, ref)
+                for dispatch in ((0, 1, 2) if chunk == 64 else (0,)):
+                    ctx.set_launch_config(h, chunk, bpc, dispatch)
+                    assert ctx.launch_config == (h, chunk, bpc, dispatch)
+                    amps, st = _run(ctx, prog, outs, thr, part)
+                    _check((name, h, chunk, bpc, dispatch), amps, st, ref)
+    # the plain form under both dispatch granularities
+    for dispatch in (1, 2):
+        ctx.set_launch_config(2, 0, 0, dispatch)
+        ctx.load(prog)
+        amps, st = ctx.evaluate([0], [1], outs, threshold=thr, plain=True)
+        torch.cuda.synchronize()
+        a = amps.cpu().numpy()
+        _check((name, "plain", dispatch), a[:, 0] + 1j * a[:, 1],
+               st.cpu().numpy().view(np.uint64), ref)
     ctx.set_launch_config(0, 0, 0)
     with pytest.raises(fhs.FhsError):
         ctx.set_launch_config(3, 0, 0)
     with pytest.raises(fhs.FhsError):
         ctx.set_launch_config(1, 96, 0)       # not a power of two
+    with pytest.raises(fhs.FhsError):
+        ctx.set_launch_config(1, 64, 0, 3)    # no such dispatch mode
 
 
 def test_table_batches_and_timing(ctx):
@@ -116,7 +128,7 @@ def test_autotune_launch(ctx):
     wl = tune.Workload(ctx, text, [0], [1.0], outs, thr)
     part = wl.prog.choose_partition(fhs.PART_EQ8)
     best, log = tune.autotune_launch(wl, part, reps=1)
-    assert len(log) == 18 and best in [c for c, _ in log]
+    assert len(log) == 20 and best in [c for c, _ in log]
     assert ctx.launch_config == best
     ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
     wl.run(part)
