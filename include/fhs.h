@@ -270,8 +270,9 @@ fhs_status fhs_evaluate_plain(fhs_ctx *ctx,
  * 2^A_p prefixes, 2^(A_p+A_r) roots, 2^A suffixes, work per fhs_program_work,
  * effective cuts); log2 of the prefix-table bytes per pair; log2(M S);
  * 32-bit state words; log2(1 + Eq. (8)); log2 of the root tasks
- * (M S 2^(A_p+A_r)). */
-#define FHS_N_FEATURES 14
+ * (M S 2^(A_p+A_r)); log2(1 + device instructions) and log2(1 + opcode
+ * runs) walked per pair over the three regions (folded gates excluded). */
+#define FHS_N_FEATURES 16
 fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, uint32_t c2, uint32_t M,
                               uint32_t S, double *out);
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam",
 ]
 
-N_FEATURES = 14
+N_FEATURES = 16
 
 
 class FhsError(RuntimeError):

@@ -640,10 +640,26 @@ extern "C" fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, u
             flops += P.fp_cost[e];
         }
     };
-    double ip, fp, ir, fr, is, fs;
+    // instructions the device walks (folded gates excluded) and opcode runs
+    // among them: the decode work, a first-order cost once ladders are folded
+    auto decode = [&](uint32_t lo, uint32_t hi, double &ins, double &runs) {
+        ins = runs = 0.0;
+        uint32_t prev = 0xffffffffu;
+        for (uint32_t e = lo; e < hi; ++e) {
+            const uint32_t op = P.ins[e].hdr & 0xffu;
+            if (op_base(op) == OP_NOP) continue;
+            ins += 1.0;
+            if (op != prev) runs += 1.0;
+            prev = op;
+        }
+    };
+    double ip, fp, ir, fr, is, fs, dp, rp, dr, rr, ds, rs;
     work(L, e1, ip, fp);
     work(e1, e2, ir, fr);
     work(e2, G, is, fs);
+    decode(L, e1, dp, rp);
+    decode(e1, e2, dr, rr);
+    decode(e2, G, ds, rs);
     const double np = std::ldexp(1.0, static_cast<int>(a3[0]));
     const double nr = std::ldexp(1.0, static_cast<int>(a3[0] + a3[1]));
     const double ns = std::ldexp(1.0, P.A);
@@ -664,6 +680,8 @@ extern "C" fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, u
     f[11] = P.NW;
     f[12] = std::log2(1.0 + static_cast<double>(e8));
     f[13] = std::log2(pairs) + a3[0] + a3[1];
+    f[14] = std::log2(1.0 + np * dp + nr * dr + ns * ds);
+    f[15] = std::log2(1.0 + np * rp + nr * rr + ns * rs);
     return FHS_OK;
 }
 

@@ -3,8 +3,8 @@
     python -m paper_2608_01467_amd.train_cost_model [--out DIR]
 
 Times every candidate split near the Eq. (8) optimum (plus a few far ones)
-on a set of training circuits drawn from the paper's families at sizes that
-take milliseconds per evaluation, trains the network on the device, writes
+on a set of training circuits drawn from the paper's families, with output
+counts sized so that one evaluation is about 2e11 algorithmic int32 ops, trains the network on the device, writes
 paper_2608_01467_amd/cost_model.json and a JSON report of the data and of the
 regret on held-out circuits (exhaustive best vs model vs Eq. (8)).
 """
@@ -27,7 +27,7 @@ import workloads as w  # noqa: E402
 from . import Context, PART_EQ8, Program  # noqa: E402
 from . import tune  # noqa: E402
 
-TARGET_GATE_OPS = 1.5e10   # per timed evaluation at the Eq. (8) optimum
+TARGET_INT_OPS = 2e11      # algorithmic int32 ops per timed evaluation at the Eq. (8) split
 
 
 def build(name: str, kw: dict, m_scale: float = 1.0):
@@ -51,8 +51,12 @@ def build(name: str, kw: dict, m_scale: float = 1.0):
     else:
         raise ValueError(name)
     prog = Program(text)
-    best = min(prog.partition_cost(*x)[0] for x in prog.candidate_splits())
-    m = int(max(4, min(8192, round(m_scale * TARGET_GATE_OPS / max(best, 1)))))
+    # int32 work per pair at the Eq. (8) split: prefix, root and suffix
+    # evaluations (features 3, 5, 7 are their log2(1 + work)), folded
+    # ladders included, so walks and gate-level circuits get similar times
+    f = prog.split_features(*prog.choose_partition(PART_EQ8), 1, 1)
+    per_pair = float(2 ** f[3] + 2 ** f[5] + 2 ** f[7])
+    m = int(max(4, min(8192, round(m_scale * TARGET_INT_OPS / max(per_pair, 1.0)))))
     return text, [0], pool(m)
 
 
@@ -97,7 +101,8 @@ def held_out(ctx, blob, args, report) -> None:
         text, ins, outs = build(name, kw, 1.0)
         wl = tune.Workload(ctx, text, ins, [1.0], outs)
         splits = tune.candidates(wl, max_cost_ratio=args.ratio, extra=0)
-        r = tune.regret(wl, blob, splits, reps=3, log=lambda m: print(m, flush=True))
+        r = tune.regret(wl, blob, splits, reps=3, log=lambda m: print(m, flush=True),
+                        budget=args.heldout_budget)
         r["case"] = [name, kw]
         r["M"] = wl.M
         r["A"] = wl.prog.A
@@ -118,6 +123,8 @@ def main() -> int:
     ap.add_argument("--case-budget", type=float, default=30.0,
                     help="seconds of split timing per training case")
     ap.add_argument("--model-out", default=tune.MODEL_PATH)
+    ap.add_argument("--heldout-budget", type=float, default=40.0,
+                    help="seconds of exhaustive timing per held-out circuit (cheapest Eq. (8) first)")
     ap.add_argument("--evaluate", default=None,
                     help="skip training: measure the held-out regret of this saved model")
     args = ap.parse_args()

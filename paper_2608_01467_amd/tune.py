@@ -250,11 +250,16 @@ def save_model(blob: np.ndarray, meta: Dict, path: str = MODEL_PATH) -> None:
 
 
 def load_model(path: str = MODEL_PATH) -> Optional[np.ndarray]:
+    """The saved blob, or None if there is none or it was trained on another
+    feature set than this library's."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    return np.array([float.fromhex(x) for x in d["blob"]], dtype=np.float64)
+    blob = np.array([float.fromhex(x) for x in d["blob"]], dtype=np.float64)
+    if blob.size < 3 or int(blob[0]) != N_FEATURES:
+        return None
+    return blob
 
 
 def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
@@ -287,11 +292,11 @@ def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
 
 
 def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2, log=None,
-           shortlist: int = 3) -> Dict:
+           shortlist: int = 3, budget: Optional[float] = None) -> Dict:
     """Time the model's choice, the model's shortlist verified by timing,
     Eq. (8)'s choice and the exhaustive best.  The best time is the minimum
     over every timing taken, so that a regret is never negative."""
-    rows, best = exhaustive(wl, splits, reps, log)
+    rows, best = exhaustive(wl, splits, reps, log, budget=budget)
     c_model, how = choose(wl, blob, reps)
     c_short, how_s = choose(wl, blob, reps, shortlist=shortlist)
     c_eq8 = wl.prog.choose_partition(PART_EQ8)

@@ -33,3 +33,4 @@ def test_features_match_regions_and_eq8():
         e2 = max(c2, p.L)
         wk = p.work(e2, p.G)
         assert abs(f[7] - math.log2(1 + 2 ** p.A * wk["int_ops"])) < 1e-9
+        assert f[15] <= f[14] and f[14] > 0

@@ -26,7 +26,7 @@ def test_fused_program_keeps_positions_and_eq8(text):
         fa, fb = a.split_features(*c, 64, 1), b.split_features(*c, 64, 1)
         same = [0, 1, 2, 9, 10, 11, 12, 13]             # everything but the work features
         assert np.array_equal(fa[same], fb[same])
-        assert (fb[3:9] <= fa[3:9]).all()
+        assert (fb[3:9] <= fa[3:9]).all() and fb[14] <= fa[14]   # runs may split
     for k in (PART for PART in (fhs.PART_NONE, fhs.PART_THIRDS, fhs.PART_EQ8)):
         assert a.choose_partition(k) == b.choose_partition(k)
     wa, wb = a.work(0, a.G), b.work(0, b.G)
