@@ -48,15 +48,17 @@ def kernels_hash() -> str:
 def traffic_from_profile(workload: str, partition):
     """HBM bytes per launch of the consumer, from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current kernels
-    with the same split."""
+    with the same split (the summary holds the splits the learned shortlist
+    picks for the workload)."""
     path = os.path.join(ROOT, "profiles", f"consume_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernels_hash") != kernels_hash() or d.get("partition") != list(partition):
+    if d.get("kernels_hash") != kernels_hash():
         return None
-    return d.get("bytes_per_launch")
+    entry = d.get("splits", {}).get(f"{partition[0]},{partition[1]}")
+    return entry.get("bytes_per_launch") if entry else None
 
 
 def cpu_baseline(text, inputs, outputs, partition, threshold, seconds_target=15.0):
@@ -100,6 +102,8 @@ def main() -> int:
     ap.add_argument("--partition", default="model", choices=["model", "eq8", "thirds", "none"],
                     help="model: the learned cost model's split (Eq. (8) if the workload lies "
                          "outside its training range)")
+    ap.add_argument("--cuts", default=None, metavar="C1,C2",
+                    help="fix the split (evaluation positions); overrides --partition")
     ap.add_argument("--cost-model", default=None, help="cost model file (default: the package's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true",
@@ -109,6 +113,8 @@ def main() -> int:
     ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC[,DISPATCH]",
                     help="fix the launch shape (histories per lane, chunk, blocks per CU)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-eq8", action="store_true",
+                    help="skip timing the Eq. (8) split when the chosen split differs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -146,7 +152,10 @@ def main() -> int:
     part_eq8 = prog.choose_partition(fhs.PART_EQ8)
     how = args.partition
     t_setup = time.perf_counter()
-    if args.partition == "model":
+    if args.cuts:
+        part = tuple(int(v) for v in args.cuts.split(","))
+        how = "fixed"
+    elif args.partition == "model":
         blob = tune.load_model(args.cost_model) if args.cost_model else tune.load_model()
         # the model's three best predictions and the Eq. (8) optimum, timed
         # once each on this workload (or every candidate without a model)
@@ -264,7 +273,7 @@ def main() -> int:
         "gate_ops_per_s": M * S * prog.partition_cost(*part)[0] / T,
         "roofline": roof,
     }
-    if tuple(part) != tuple(part_eq8):
+    if tuple(part) != tuple(part_eq8) and not args.no_eq8:
         # the paper's own choice, Eq. (8), on the same inputs
         ctx.set_partition(*part_eq8)
         step()
