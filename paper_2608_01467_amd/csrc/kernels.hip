@@ -392,6 +392,16 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
                 break;
         }
         e = end;
+        // With pruning, histories die at branching gates; once no history of
+        // the wave is alive the rest of the region cannot change any result.
+        if constexpr (PRUNE) {
+            const uint32_t base = op & 15u;
+            if (base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) {
+                bool any = false;
+                unroll<H>([&](auto hh) { any = any || L.ok[hh.value]; });
+                if (!__any(any)) return;
+            }
+        }
     }
 }
 

@@ -155,3 +155,34 @@ def test_model_outside_training_range(dev):
         ctx.load_cost_model(bad)
     with pytest.raises(fhs.FhsError):
         ctx.load_cost_model(bad[:-1])
+
+
+def test_learned_split_gains_over_eq8(dev):
+    """What the trained network gains over the paper's Eq. (8) choice, on a
+    circuit it was not trained on (random Clifford+T, 16 qubits, 80 gates,
+    8192 outputs: many cheap outputs, where Eq. (8) ignores the prefix
+    table's cost): both the network's own choice and the shortlist are
+    clearly faster than the Eq. (8) split, timed on the same inputs."""
+    blob = tune.load_model()
+    if blob is None:
+        pytest.skip("no trained cost model in the package")
+    c = w.random_clifford_t(16, 80, seed=13)
+    outs = w.random_outputs(16, 8192, seed=80)
+    ctx = fhs.Context(0)
+    wl = tune.Workload(ctx, c.to_text(), [0], [1.0], outs)
+    eq8 = wl.prog.choose_partition(fhs.PART_EQ8)
+    model, how = tune.choose(wl, blob, reps=2)
+    short, how_s = tune.choose(wl, blob, reps=2, shortlist=3)
+    assert how == "model" and how_s == "model+timed"
+    t_eq8 = tune.time_split(wl, eq8, reps=7)
+    t_model = tune.time_split(wl, model, reps=7)
+    t_short = tune.time_split(wl, short, reps=7)
+    assert t_model < 0.8 * t_eq8, (model, t_model, eq8, t_eq8)
+    assert t_short < 0.8 * t_eq8, (short, t_short, eq8, t_eq8)
+    # the faster split gives the same amplitudes (Algorithm 2 at any cut)
+    wl.run(model)
+    torch.cuda.synchronize()
+    a_model = wl.amps.cpu().numpy().copy()
+    wl.run(eq8)
+    torch.cuda.synchronize()
+    assert np.abs(a_model - wl.amps.cpu().numpy()).max() <= 1e-12
