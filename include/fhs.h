@@ -170,7 +170,15 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *   dispatch            how the kernels walk the program: 1 one opcode
  *                       dispatch per run of identical opcodes, 2 one per
  *                       instruction, 0 automatic (per run when the program's
- *                       runs average two or more instructions).
+ *                       runs average two or more instructions), 3 compiled:
+ *                       the consumer's root and suffix regions are emitted as
+ *                       straight-line code and compiled for gfx950 at the
+ *                       first evaluation of each program and split (hipRTC,
+ *                       about a second; cached in the context) when they
+ *                       hold at most 1024 device instructions, else as 1.
+ *                       fhs_evaluate returns FHS_EUNSUPPORTED, with the
+ *                       compiler log in fhs_last_error, if that compilation
+ *                       fails.
  * Affects speed and the grouping of the amplitude sums (so their last bits),
  * never the history counts.  FHS_EINVAL for values out of range. */
 typedef struct {

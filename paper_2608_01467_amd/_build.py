@@ -34,6 +34,20 @@ def _run(cmd):
     return out
 
 
+def _write_jit_headers(path: str) -> None:
+    """The device headers as C++ string constants, for the consumer the
+    runtime compiles (jit.hip)."""
+    delim = "FHS_SRC"
+    with open(path, "w") as out:
+        for name, var in (("program.hpp", "kSrcProgramHpp"), ("kernels.hpp", "kSrcKernelsHpp"),
+                          ("device.hpp", "kSrcDeviceHpp")):
+            with open(os.path.join(CSRC, name)) as f:
+                text = f.read()
+            if ")" + delim + '"' in text:
+                raise RuntimeError(f"{name} contains the raw-string delimiter")
+            out.write(f'static const char {var}[] = R"{delim}(' + text + f'){delim}";\n')
+
+
 def build(verbose: bool = False) -> str:
     tmp = tempfile.mkdtemp(prefix="fhs_build_")
     try:
@@ -41,12 +55,13 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(tmp, "reducer.o")
         _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "reducer.cpp"), "-o", o])
         objs.append(o)
-        for src in ("kernels.hip", "runtime.hip", "mlp.hip"):
+        _write_jit_headers(os.path.join(tmp, "jit_headers.inc"))
+        for src in ("kernels.hip", "runtime.hip", "mlp.hip", "jit.hip"):
             o = os.path.join(tmp, src.replace(".hip", ".o"))
-            _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+            _run([HIPCC] + HIP_FLAGS + ["-I" + tmp, "-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)
         out = LIB + f".tmp{os.getpid()}"
-        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs)
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs + ["-lhiprtc"])
         os.replace(out, LIB)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)

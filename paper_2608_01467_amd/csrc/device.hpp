@@ -1,0 +1,677 @@
+// device.hpp -- device-side building blocks of the reduced-history kernels:
+// per-history registers, the per-opcode backward steps, the program
+// interpreter (run_region), the depth-first region walk, deterministic
+// reductions and the persistent consumer's body.  Included by kernels.hip
+// and, as source text, by the consumer the runtime compiles for a program.
+//
+// Each lane owns one history at a time: an n-bit time-slice state held in
+// NW 32-bit VGPRs, an FP64 complex partial amplitude and (with pruning) the
+// running modulus product M.  The history program is read wave-uniformly
+// (scalar loads), so every lane of a wave executes the same gate and only
+// the selected matrix element differs.  Source bits are decoded from the
+// lane's history index in registers.
+#pragma once
+
+#if !defined(__HIPCC_RTC__)
+#include <hip/hip_runtime.h>
+#endif
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#include "kernels.hpp"
+
+namespace fhs {
+namespace {
+
+
+// The program is read through the constant address space: it is never
+// written while a kernel runs, which lets every instruction field arrive by
+// scalar load even in kernels that store to global memory.
+// (The host compilation pass only parses device code; it gets the plain type.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using Const = const __attribute__((address_space(4))) T;
+#else
+template <class T>
+using Const = const T;
+#endif
+using ConstInstr = Const<Instr>;
+
+// Read-only kernel inputs (masks, bitstrings) through the constant address
+// space, so uniform reads become scalar loads.
+template <class T>
+__device__ __forceinline__ T ld_const(const T *p, size_t i) {
+    return ((Const<T> *)p)[i];
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // SplitMix64 finaliser (Steele, Lea, Flood 2014)
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// State words are only ever indexed with compile-time constants (the word
+// holding a gate's bit is part of its opcode), so the state stays in VGPRs.
+// H independent histories per lane share every decoded instruction.
+template <int W, int NW>
+__device__ __forceinline__ constexpr int wsel() {
+    return W < NW ? W : 0;
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// f(IC<0>), ..., f(IC<N-1>): compile-time unrolling, so that register arrays
+// are never indexed with a runtime value.
+template <class F, int... I>
+__device__ __forceinline__ void unroll_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(IC<I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F &&f) {
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Call f(IC<w>) for the uniform word index w < NW.
+template <int NW, class F>
+__device__ __forceinline__ void with_word(uint32_t w, F &&f) {
+    if constexpr (NW == 1) {
+        f(IC<0>{});
+    } else if constexpr (NW == 2) {
+        if (w == 0u) f(IC<0>{});
+        else f(IC<1>{});
+    } else {
+        if (w < 2u) {
+            if (w == 0u) f(IC<0>{});
+            else f(IC<1>{});
+        } else {
+            if (w == 2u) f(IC<2>{});
+            else f(IC<3>{});
+        }
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ bool check_final(const uint32_t (&s)[NW], const uint32_t (&bin)[NW],
+                                            const Mask4 &m) {
+    uint32_t acc = 0;
+    unroll<NW>([&](auto jj) {
+        constexpr int j = jj.value;
+        acc |= (s[j] ^ bin[j]) & m.w[j];
+    });
+    return acc == 0;
+}
+
+__device__ __forceinline__ void cmul(double &re, double &im, double fr, double fi) {
+    const double r = fma(re, fr, -(im * fi));
+    const double i = fma(re, fi, im * fr);
+    re = r;
+    im = i;
+}
+
+// Bitstring words (uint64, little-endian) -> NW 32-bit state words.
+// Returns true when a bit at position >= n is set.
+template <int NW>
+__device__ __forceinline__ bool load_bits(const uint64_t *src, uint32_t W, uint32_t n,
+                                          uint32_t (&s)[NW]) {
+    bool bad = false;
+    uint64_t w0 = ld_const(src, 0);
+    uint64_t w1 = W > 1 ? ld_const(src, 1) : 0;
+    if (n < 64) bad = (w0 >> n) != 0;
+    else if (n < 128 && W > 1) bad = (w1 >> (n - 64)) != 0;
+    s[0] = static_cast<uint32_t>(w0);
+    if constexpr (NW >= 2) s[1] = static_cast<uint32_t>(w0 >> 32);
+    if constexpr (NW == 4) {
+        s[2] = static_cast<uint32_t>(w1);
+        s[3] = static_cast<uint32_t>(w1 >> 32);
+    }
+    return bad;
+}
+
+// Per-history registers of H histories.
+template <int NW, int H>
+struct Lanes {
+    uint32_t s[H][NW];
+    double re[H], im[H], M[H];
+    bool ok[H];
+    uint64_t hb[H];     // this region's source bits, per history
+};
+
+// Factor tables: `fac` points at the slice [lo, ...) of the global table,
+// staged in LDS by the hot kernels; entries are read per lane.
+struct FacRef {
+    const double *p;
+    uint32_t lo;
+    __device__ __forceinline__ double2 c(uint32_t off) const {
+        return *reinterpret_cast<const double2 *>(p + (off - lo));
+    }
+    __device__ __forceinline__ double d(uint32_t off) const { return p[off - lo]; }
+};
+
+__device__ __forceinline__ uint32_t hdr_a(const Instr &I) { return (I.hdr >> 8) & 0xffu; }
+__device__ __forceinline__ uint32_t hdr_b(const Instr &I) { return (I.hdr >> 16) & 0xffu; }
+__device__ __forceinline__ uint32_t hdr_z(const Instr &I) { return I.hdr >> 24; }
+
+template <int NW, int H, int TW, int LW>
+__device__ __forceinline__ void op_perm(Lanes<NW, H> &L, const Instr &I) {
+    constexpr int T = wsel<TW, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        L.s[h][T] ^= (acc == 0u) ? I.k : 0u;
+    });
+}
+
+template <int NW, int H, int LW>
+__device__ __forceinline__ void op_mcphase(Lanes<NW, H> &L, const Instr &I) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const bool m = acc == 0u;
+        L.re[h] = m ? -L.re[h] : L.re[h];
+        L.im[h] = m ? -L.im[h] : L.im[h];
+    });
+}
+
+// Folded ladder (OP_ADD): when the controls match, add one to (zmask bit
+// 0: subtract one from) the bit field [lo, lo+m) of the state, mod 2^m.  The
+// whole state is added to +-2^lo (two's complement over the state's width)
+// with one carry chain over its 32-bit words: no bit below lo changes, and
+// whatever the carry does above the field is discarded when the field bits
+// of the sum are merged back.
+template <int NW, int H, int LW>
+__device__ __forceinline__ void op_add(Lanes<NW, H> &L, const Instr &I) {
+    const uint32_t lo = hdr_a(I), hi = lo + hdr_b(I);   // field [lo, hi), hi <= 128
+    // 128-bit masks and addend as two 64-bit halves, all wave-uniform
+    auto below = [](uint32_t b, uint64_t &m0, uint64_t &m1) {   // bits [0, b)
+        m0 = b >= 64u ? ~0ull : ((1ull << b) - 1ull);
+        m1 = b >= 128u ? ~0ull : (b > 64u ? ((1ull << (b - 64u)) - 1ull) : 0ull);
+    };
+    uint64_t a0, a1, b0, b1;
+    below(lo, a0, a1);
+    below(hi, b0, b1);
+    const uint64_t f0 = b0 & ~a0, f1 = b1 & ~a1;
+    uint64_t d0 = lo < 64u ? (1ull << lo) : 0ull, d1 = lo >= 64u ? (1ull << (lo - 64u)) : 0ull;
+    if (hdr_z(I) & 1u) {   // -2^lo = ~2^lo + 1 over 128 bits
+        d0 = ~d0 + 1ull;
+        d1 = ~d1 + (d0 == 0ull ? 1ull : 0ull);
+    }
+    const uint32_t fm[4] = {static_cast<uint32_t>(f0), static_cast<uint32_t>(f0 >> 32),
+                            static_cast<uint32_t>(f1), static_cast<uint32_t>(f1 >> 32)};
+    const uint32_t dd[4] = {static_cast<uint32_t>(d0), static_cast<uint32_t>(d0 >> 32),
+                            static_cast<uint32_t>(d1), static_cast<uint32_t>(d1 >> 32)};
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const bool go = acc == 0u;
+        uint32_t carry = 0;
+        unroll<NW>([&](auto ww) {
+            constexpr int w = ww.value;
+            const uint32_t x = L.s[h][w];
+            const uint32_t r = __builtin_addc(x, dd[w], carry, &carry);
+            L.s[h][w] = go ? ((x & ~fm[w]) | (r & fm[w])) : x;
+        });
+    });
+}
+
+template <int NW, int H, int WA, int WB>
+__device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t acc = 0;
+        unroll<NW>([&](auto jj) {
+            constexpr int j = jj.value;
+            acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+        });
+        const uint32_t d = (((L.s[h][A] >> sa) ^ (L.s[h][B] >> sb)) & 1u) & (acc == 0u ? 1u : 0u);
+        L.s[h][A] ^= d << sa;
+        L.s[h][B] ^= d << sb;
+    });
+}
+
+template <int NW, int H, int WA>
+__device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const double2 f = F.c(I.fac + 2u * o);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+        L.s[h][A] ^= 1u << sh;
+    });
+}
+
+template <int NW, int H, int WA>
+__device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const double2 f = F.c(I.fac + 2u * o);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+    });
+}
+
+template <int NW, int H, int WA, int WB>
+__device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t x = ((L.s[h][A] >> sa) & 1u) | (((L.s[h][B] >> sb) & 1u) << 1);
+        const double2 f = F.c(I.fac + 2u * x);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+    });
+}
+
+template <int NW, int H, bool PRUNE, int WA, bool SRC>
+__device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const FacRef &F,
+                                          uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    const uint32_t ks = I.k - kbase;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const uint32_t i = SRC ? static_cast<uint32_t>((L.hb[h] >> ks) & 1u) : (bin[A] >> sh) & 1u;
+        const uint32_t x = 2u * o + i;
+        const double2 f = F.c(I.fac + 2u * x);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+        if (PRUNE) {
+            L.M[h] = L.M[h] * F.d(I.fac + 8u + x);
+            L.ok[h] = L.ok[h] && !(L.M[h] < thr);
+        }
+        L.ok[h] = L.ok[h] && !((hdr_z(I) >> x) & 1u);
+        L.s[h][A] ^= (o ^ i) << sh;
+    });
+}
+
+// Walk evaluation positions [e0, e1) of the history program backward for H
+// histories at once.  Source k of history h reads bit (k - kbase) of hb[h];
+// bin is the input bitstring (the same for every history of a lane).  The
+// opcode is dispatched once per run of identical opcodes; the case loops
+// over the run.
+template <int NW, int H, bool PRUNE, bool RUNS>
+__device__ __forceinline__ void run_region(const Instr *prog_generic, const FacRef &F,
+                                           uint32_t e0, uint32_t e1, Lanes<NW, H> &L,
+                                           uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
+    ConstInstr *prog = (ConstInstr *)prog_generic;
+    uint32_t e = e0;
+    while (e < e1) {
+        const uint32_t op = prog[e].hdr & 0xffu;
+        const uint32_t end = RUNS ? e + min(prog[e].run, e1 - e) : e + 1u;
+        const uint32_t w1 = (op >> 4) & 3u, w2 = (op >> 6) & 3u;
+        // the instructions of this dispatch: the run, or just prog[e]
+        auto each = [&](auto &&f) {
+            if constexpr (RUNS) {
+                for (uint32_t x = e; x < end; ++x) {
+                    const Instr I = prog[x];
+                    f(I);
+                }
+            } else {
+                const Instr I = prog[e];
+                f(I);
+            }
+        };
+        switch (op & 15u) {
+            case OP_PERM:
+                with_word<NW>(w1, [&](auto TW) {
+                    with_word<NW>(w2, [&](auto LW) {
+                        each([&](const Instr &I) { op_perm<NW, H, TW.value, LW.value>(L, I); });
+                    });
+                });
+                break;
+            case OP_BRANCH_SRC:
+                with_word<NW>(w1, [&](auto WA) {
+                    each([&](const Instr &I) { op_branch<NW, H, PRUNE, WA.value, true>(L, I, F, kbase, bin, thr); });
+                });
+                break;
+            case OP_BRANCH_NAT:
+                with_word<NW>(w1, [&](auto WA) {
+                    each([&](const Instr &I) { op_branch<NW, H, PRUNE, WA.value, false>(L, I, F, kbase, bin, thr); });
+                });
+                break;
+            case OP_DIAG2:
+                with_word<NW>(w1, [&](auto WA) {
+                    with_word<NW>(w2, [&](auto WB) {
+                        each([&](const Instr &I) { op_diag2<NW, H, WA.value, WB.value>(L, I, F); });
+                    });
+                });
+                break;
+            case OP_DIAG1:
+                with_word<NW>(w1, [&](auto WA) {
+                    each([&](const Instr &I) { op_diag1<NW, H, WA.value>(L, I, F); });
+                });
+                break;
+            case OP_MCPHASE:
+                with_word<NW>(w1, [&](auto LW) {
+                    each([&](const Instr &I) { op_mcphase<NW, H, LW.value>(L, I); });
+                });
+                break;
+            case OP_SWAP:
+                with_word<NW>(w1, [&](auto WA) {
+                    with_word<NW>(w2, [&](auto WB) {
+                        each([&](const Instr &I) { op_swap<NW, H, WA.value, WB.value>(L, I); });
+                    });
+                });
+                break;
+            case OP_DET1:
+                with_word<NW>(w1, [&](auto WA) {
+                    each([&](const Instr &I) { op_det1<NW, H, WA.value>(L, I, F); });
+                });
+                break;
+            case OP_ADD:
+                with_word<NW>(w1, [&](auto LW) {
+                    each([&](const Instr &I) { op_add<NW, H, LW.value>(L, I); });
+                });
+                break;
+            default:
+                break;
+        }
+        e = end;
+        // With pruning, histories die at branching gates; once no history of
+        // the wave is alive the rest of the region cannot change any result.
+        if constexpr (PRUNE) {
+            const uint32_t base = op & 15u;
+            if (base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) {
+                bool any = false;
+                unroll<H>([&](auto hh) { any = any || L.ok[hh.value]; });
+                if (!__any(any)) return;
+            }
+        }
+    }
+}
+
+// Copy every per-history register of src into dst except the source bits.
+template <int NW, int H>
+__device__ __forceinline__ void copy_core(Lanes<NW, H> &dst, const Lanes<NW, H> &src) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        unroll<NW>([&](auto ww) { dst.s[h][ww.value] = src.s[h][ww.value]; });
+        dst.re[h] = src.re[h];
+        dst.im[h] = src.im[h];
+        dst.M[h] = src.M[h];
+        dst.ok[h] = src.ok[h];
+    });
+}
+
+// Depth-first enumeration of the D <= DMAX consecutive sources k0 ..
+// k0+D-1 (evaluation order) of a region that ends at e_end.  On entry L
+// holds each history's state just before source k0's gate; its hb carries
+// the region's other source bits.  For every one of the 2^D assignments
+// (source k0 varying slowest) the histories are carried to e_end and
+// leaf(C) is called with C.hb holding the assignment.  The gates between
+// source k0+l and the next enumerated source run 2^(l+1) times rather than
+// 2^D: the state before each enumerated source is kept in registers and
+// reused by every assignment that agrees on the earlier sources (the
+// checkpoint idea of Algorithm 2 applied at every source).  Control flow is
+// wave-uniform throughout.
+template <int NW, int H, bool PRUNE, bool RUNS, int DMAX, class Leaf>
+__device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, const uint32_t *src,
+                                           uint32_t k0, uint32_t D, uint32_t e_end,
+                                           const Lanes<NW, H> &L, uint32_t kbase,
+                                           const uint32_t (&bin)[NW], double thr, Leaf &&leaf) {
+    Lanes<NW, H> C = L;
+    Lanes<NW, H> S[DMAX];      // S[l]: state before level l's source (l >= 1)
+    const uint32_t nt = 1u << D;
+    for (uint32_t t = 0; t < nt; ++t) {
+        uint32_t l0 = 0;
+        if (t != 0u) {
+            // the levels whose bit changed since t - 1 are l0 .. D-1
+            l0 = D - 1u - static_cast<uint32_t>(__builtin_ctz(t));
+            unroll<DMAX>([&](auto LV) {
+                if (static_cast<uint32_t>(LV.value) == l0) {
+                    if constexpr (LV.value == 0) copy_core(C, L);
+                    else copy_core(C, S[LV.value]);
+                }
+            });
+        }
+        for (uint32_t l = l0; l < D; ++l) {
+            const uint32_t kb = k0 + l - kbase;
+            const uint64_t bit = static_cast<uint64_t>((t >> (D - 1u - l)) & 1u) << kb;
+            unroll<H>([&](auto hh) { C.hb[hh.value] = (C.hb[hh.value] & ~(1ull << kb)) | bit; });
+            const uint32_t a = ld_const(src, k0 + l);
+            const uint32_t b = (l + 1u < D) ? ld_const(src, k0 + l + 1u) : e_end;
+            run_region<NW, H, PRUNE, RUNS>(prog, F, a, b, C, kbase, bin, thr);
+            if (l + 1u < D) {
+                unroll<DMAX>([&](auto LV) {
+                    if constexpr (LV.value > 0)
+                        if (static_cast<uint32_t>(LV.value) == l + 1u) copy_core(S[LV.value], C);
+                });
+            }
+        }
+        leaf(C);
+    }
+}
+
+// Copy the factor slice [lo, hi) of the global table into LDS.
+__device__ __forceinline__ void stage_factors(double *lds, const double *fac, uint32_t lo,
+                                              uint32_t hi) {
+    for (uint32_t i = threadIdx.x; i < hi - lo; i += blockDim.x) lds[i] = fac[lo + i];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// deterministic workgroup reduction of (amp, 4 counters)
+// ---------------------------------------------------------------------------
+
+struct Acc {
+    double re, im;
+    uint64_t nval, sumh, xorh, leaves;
+};
+
+__device__ __forceinline__ void wave_reduce(Acc &a) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a.re += __shfl_xor(a.re, off, 64);
+        a.im += __shfl_xor(a.im, off, 64);
+        a.nval += __shfl_xor(a.nval, off, 64);
+        a.sumh += __shfl_xor(a.sumh, off, 64);
+        a.xorh ^= __shfl_xor(a.xorh, off, 64);
+        a.leaves += __shfl_xor(a.leaves, off, 64);
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void block_reduce_store(Acc a, Acc *lds, Partials part, uint32_t idx) {
+    wave_reduce(a);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc t = lds[0];
+        for (int w = 1; w < NT / 64; ++w) {
+            t.re += lds[w].re;
+            t.im += lds[w].im;
+            t.nval += lds[w].nval;
+            t.sumh += lds[w].sumh;
+            t.xorh ^= lds[w].xorh;
+            t.leaves += lds[w].leaves;
+        }
+        part.amp[idx] = make_double2(t.re, t.im);
+        uint64_t *st = part.st + 4ull * idx;
+        st[0] = t.nval;
+        st[1] = t.sumh;
+        st[2] = t.xorh;
+        st[3] = t.leaves;
+    }
+    __syncthreads();
+}
+
+// Regions policy of the interpreting consumer.
+template <bool RUNS>
+struct Interp {
+    template <int NW, int H, bool PRUNE>
+    __device__ static __forceinline__ void root(const Common &c, const FacRef &F, Lanes<NW, H> &L,
+                                                const uint32_t (&bin)[NW]) {
+        run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.i1, c.i2, L, c.Ap, bin, c.thr);
+    }
+    template <int NW, int H, bool PRUNE>
+    __device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, Lanes<NW, H> &L,
+                                                  const uint32_t (&bin)[NW]) {
+        run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.i2, c.iG, L, c.Ap + c.Ar, bin, c.thr);
+    }
+};
+
+// Once no history of the wave is alive (pruning), stop walking the region.
+template <int NW, int H>
+__device__ __forceinline__ bool wave_alive(const Lanes<NW, H> &L) {
+    bool any = false;
+    unroll<H>([&](auto hh) { any = any || L.ok[hh.value]; });
+    return __any(any);
+}
+
+// The persistent consumer (Algorithm 2, inner loops) over a Regions policy
+// that walks the root region [c1, c2) and the suffix region [c2, G) of a
+// history: Interp decodes the program at run time; the runtime can also
+// compile a policy with the regions' instructions as straight-line code.
+template <class Regions, int NW, int H, bool PRUNE, bool FLDS>
+__device__ __forceinline__ void consume_body(Common c, Table tab, Partials part, uint32_t p0,
+                                             uint32_t B, uint32_t chunk, uint32_t ss,
+                                             uint32_t *counter) {
+    constexpr int NT = kConsumeThreads;
+    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
+    __shared__ uint32_t s_item;
+    __shared__ uint32_t l_st[NW][kMaxChunk];
+    __shared__ double2 l_beta[kMaxChunk];
+    __shared__ double l_M[kMaxChunk];
+    __shared__ uint32_t l_hp[kMaxChunk];
+    __shared__ uint32_t l_wcount[NT / 64];
+    __shared__ Acc l_red[NT / 64];
+
+    FacRef F{c.fac, 0u};
+    if constexpr (FLDS) {
+        stage_factors(l_fac, c.fac, c.f_c1, c.f_G);
+        F = FacRef{l_fac, c.f_c1};
+    }
+    const uint32_t per_pair = 1u << c.Ap;
+    const uint32_t nchunks = (per_pair + chunk - 1) / chunk;
+    const uint32_t n_items = B * nchunks;
+    const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    const uint32_t rmask = (1u << c.Ar) - 1u;
+    const uint32_t smask = (1u << ss) - 1u;
+    const uint64_t n_suffix = 1ull << (c.As - ss);   // suffix assignments per task
+    const uint32_t sshift = c.Ap + c.Ar;
+    const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
+
+    for (;;) {
+        if (t == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= n_items) break;
+        const uint32_t pl = item / nchunks, ch = item - pl * nchunks;
+        const uint32_t p = p0 + pl;
+        const uint32_t hp0 = ch * chunk;
+        const uint32_t cnt = min(chunk, per_pair - hp0);
+
+        // stage the chunk HBM -> registers -> LDS, compacting valid entries
+        bool v = false;
+        uint32_t es[NW];
+        double2 eb = make_double2(0.0, 0.0);
+        double em = 1.0;
+        if (t < cnt) {
+            const uint64_t e = (static_cast<uint64_t>(pl) << c.Ap) + hp0 + t;
+            v = tab.ok[e] != 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) es[w] = tab.st[static_cast<size_t>(w) * E + e];
+            eb = tab.beta[e];
+            if (PRUNE) em = tab.M[e];
+        }
+        const uint64_t bal = __ballot(v);
+        const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) l_wcount[wave] = __popcll(bal);
+        __syncthreads();
+        uint32_t base = 0, nv = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            const uint32_t cw = l_wcount[w];
+            base += (static_cast<uint32_t>(w) < wave) ? cw : 0u;
+            nv += cw;
+        }
+        if (v) {
+            const uint32_t d = base + rank;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) l_st[w][d] = es[w];
+            l_beta[d] = eb;
+            l_M[d] = em;
+            l_hp[d] = hp0 + t;
+        }
+        __syncthreads();
+
+        uint32_t bin[NW];
+        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
+        Acc acc{0.0, 0.0, 0, 0, 0, 0};
+        const uint64_t ntask = static_cast<uint64_t>(nv) << (c.Ar + ss);
+        // uniform loop bounds: the program counter inside stays wave-uniform
+        for (uint64_t tb = 0; tb < ntask; tb += static_cast<uint64_t>(H) * NT) {
+            Lanes<NW, H> R;
+            uint64_t hbase[H], hs0[H];
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                const uint64_t task = tb + t + static_cast<uint64_t>(j) * NT;
+                const bool valid = task < ntask;
+                const uint32_t jx = valid ? static_cast<uint32_t>(task >> (c.Ar + ss)) : 0u;
+                const uint32_t hr = static_cast<uint32_t>(task >> ss) & rmask;
+                hs0[j] = static_cast<uint64_t>(task & smask) * n_suffix;
+                unroll<NW>([&](auto ww) { R.s[j][ww.value] = l_st[ww.value][jx]; });
+                const double2 b = l_beta[jx];
+                R.re[j] = b.x;
+                R.im[j] = b.y;
+                R.M[j] = l_M[jx];
+                R.ok[j] = valid;
+                R.hb[j] = hr;
+                hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
+            });
+            Regions::template root<NW, H, PRUNE>(c, F, R, bin);
+            bool any = false;
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                R.ok[j] = R.ok[j] && check_final<NW>(R.s[j], bin, fin_c2);
+                any = any || R.ok[j];
+            });
+            if (!__any(any)) continue;   // wave-uniform skip
+            for (uint64_t q = 0; q < n_suffix; ++q) {
+                Lanes<NW, H> S2 = R;
+                unroll<H>([&](auto jj) { S2.hb[jj.value] = hs0[jj.value] + q; });
+                Regions::template suffix<NW, H, PRUNE>(c, F, S2, bin);
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
+                    acc.leaves += R.ok[j] ? 1u : 0u;
+                    if (ok2) {
+                        const uint64_t h = hbase[j] | ((hs0[j] + q) << sshift);
+                        acc.re += S2.re[j];
+                        acc.im += S2.im[j];
+                        acc.nval += 1;
+                        acc.sumh += h;
+                        acc.xorh ^= mix64(h);
+                    }
+                });
+            }
+        }
+        block_reduce_store<NT>(acc, l_red, part, item);
+    }
+}
+
+}  // namespace
+}  // namespace fhs

@@ -1,0 +1,161 @@
+// jit.hip -- generation and run-time compilation of the consumer for one
+// program and split (see jit.hpp).
+#include "jit.hpp"
+
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+
+#include "program.hpp"
+
+namespace fhs {
+namespace {
+
+// device.hpp, kernels.hpp and program.hpp as text (written by the build).
+#include "jit_headers.inc"
+
+// One block per instruction: the instruction as a constant and the call of
+// its backward step with the word indices its opcode carries (wsel maps them
+// onto the state registers as the interpreter's dispatch does).
+void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi) {
+    char buf[512];
+    for (uint32_t x = lo; x < hi; ++x) {
+        const Instr &I = dev[x];
+        const uint32_t op = I.hdr & 0xffu;
+        const int base = op_base(op);
+        const int w1 = static_cast<int>((op >> 4) & 3u), w2 = static_cast<int>((op >> 6) & 3u);
+        std::snprintf(buf, sizeof(buf),
+                      "    { constexpr Instr I{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu, "
+                      "{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}, {0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}}; ",
+                      I.hdr, I.k, I.fac, I.run, I.cm[0], I.cm[1], I.cm[2], I.cm[3], I.cv[0], I.cv[1],
+                      I.cv[2], I.cv[3]);
+        o += buf;
+        char call[256];
+        switch (base) {
+            case OP_PERM:
+                std::snprintf(call, sizeof(call), "op_perm<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
+                break;
+            case OP_BRANCH_SRC:
+            case OP_BRANCH_NAT:
+                std::snprintf(call, sizeof(call),
+                              "op_branch<NW, H, PRUNE, wsel<%d, NW>(), %s>(L, I, F, kbase, bin, thr); "
+                              "if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
+                              w1, base == OP_BRANCH_SRC ? "true" : "false");
+                break;
+            case OP_DIAG2:
+                std::snprintf(call, sizeof(call), "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I, F); }\n", w1, w2);
+                break;
+            case OP_DIAG1:
+                std::snprintf(call, sizeof(call), "op_diag1<NW, H, wsel<%d, NW>()>(L, I, F); }\n", w1);
+                break;
+            case OP_MCPHASE:
+                std::snprintf(call, sizeof(call), "op_mcphase<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
+                break;
+            case OP_SWAP:
+                std::snprintf(call, sizeof(call), "op_swap<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
+                break;
+            case OP_DET1:
+                std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>()>(L, I, F); }\n", w1);
+                break;
+            case OP_ADD:
+                std::snprintf(call, sizeof(call), "op_add<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
+                break;
+            default:
+                std::snprintf(call, sizeof(call), "(void)I; }\n");
+                break;
+        }
+        o += call;
+    }
+}
+
+}  // namespace
+
+std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
+                            int NW, int H, bool prune, bool flds) {
+    std::string o;
+    o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
+    o += "struct Compiled {\n";
+    o += "template <int NW, int H, bool PRUNE>\n"
+         "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
+         "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
+         "    const uint32_t kbase = c.Ap; const double thr = c.thr; (void)kbase; (void)thr;\n";
+    emit_region(o, dev, i1, i2);
+    o += "}\n";
+    o += "template <int NW, int H, bool PRUNE>\n"
+         "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
+         "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
+         "    const uint32_t kbase = c.Ap + c.Ar; const double thr = c.thr; (void)kbase; (void)thr;\n";
+    emit_region(o, dev, i2, iG);
+    o += "}\n};\n}  // namespace\n}  // namespace fhs\n";
+    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "extern \"C\" __global__ __launch_bounds__(fhs::kConsumeThreads) void "
+                  "fhs_consume_compiled(fhs::Common c, fhs::Table tab, fhs::Partials part, uint32_t p0, "
+                  "uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter) {\n"
+                  "    fhs::consume_body<fhs::Compiled, %d, %d, %s, %s>(c, tab, part, p0, B, chunk, ss, "
+                  "counter);\n}\n",
+                  NW, H, prune ? "true" : "false", flds ? "true" : "false");
+    o += buf;
+    return o;
+}
+
+bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out, std::string &log) {
+    hiprtcProgram prog = nullptr;
+    const char *headers[] = {kSrcProgramHpp, kSrcKernelsHpp, kSrcDeviceHpp};
+    const char *names[] = {"program.hpp", "kernels.hpp", "device.hpp"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "fhs_consume_compiled.hip", 3, headers, names) !=
+        HIPRTC_SUCCESS) {
+        log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    log.assign(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    if (r != HIPRTC_SUCCESS) {
+        hiprtcDestroyProgram(&prog);
+        return false;
+    }
+    size_t code_size = 0;
+    hiprtcGetCodeSize(prog, &code_size);
+    std::vector<char> code(code_size);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    if (hipModuleLoadData(&out.mod, code.data()) != hipSuccess) {
+        log += "\nhipModuleLoadData failed";
+        out.mod = nullptr;
+        return false;
+    }
+    if (hipModuleGetFunction(&out.fn, out.mod, "fhs_consume_compiled") != hipSuccess) {
+        log += "\nhipModuleGetFunction failed";
+        release(out);
+        return false;
+    }
+    int nb = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, out.fn, kConsumeThreads, shm) !=
+            hipSuccess || nb < 1)
+        nb = 1;
+    out.blocks_per_cu = nb;
+    return true;
+}
+
+void release(CompiledConsumer &k) {
+    if (k.mod) (void)hipModuleUnload(k.mod);
+    k.mod = nullptr;
+    k.fn = nullptr;
+}
+
+hipError_t launch_compiled(const CompiledConsumer &k, const Common &c, Table tab, Partials part,
+                           uint32_t p0, uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter,
+                           uint32_t grid, size_t shm, hipStream_t s) {
+    if (B == 0 || grid == 0) return hipSuccess;
+    Common cc = c;
+    void *args[] = {&cc, &tab, &part, &p0, &B, &chunk, &ss, &counter};
+    return hipModuleLaunchKernel(k.fn, grid, 1, 1, kConsumeThreads, 1, 1, static_cast<unsigned>(shm),
+                                 s, args, nullptr);
+}
+
+}  // namespace fhs

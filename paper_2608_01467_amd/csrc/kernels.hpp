@@ -1,7 +1,9 @@
 // kernels.hpp -- launch parameters shared by the runtime and the kernels.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
+#endif
 
 #include <cstdint>
 
@@ -58,6 +60,7 @@ struct Common {
     double thr;
 };
 
+#if !defined(__HIPCC_RTC__)
 // Launchers (kernels.hip).  NW and pruning are dispatched inside.
 hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
                            uint32_t n_zero, hipStream_t s);
@@ -81,6 +84,8 @@ hipError_t launch_count_valid(const uint32_t *ok, uint64_t n, unsigned long long
 hipError_t launch_finalize(PairRes res, const double *coeffs, uint32_t S, uint32_t M,
                            double *amps, uint64_t *stats, hipStream_t s);
 
+#endif  // !__HIPCC_RTC__
+
 // Workgroup size of the persistent consumer and the plain kernel.
 constexpr int kConsumeThreads = 256;
 constexpr int kPlainThreads = 256;
@@ -89,7 +94,9 @@ constexpr int kDfsMax = 4;       // prefix sources enumerated depth-first inside
 // Factor slices up to this many doubles are staged in LDS by the hot kernels.
 constexpr uint32_t kMaxLdsFactors = 4096;
 
+#if !defined(__HIPCC_RTC__)
 // Occupancy-derived persistent grid for the consumer.
 int consume_blocks_per_cu(const Common &c, int NW, int H);
+#endif
 
 }  // namespace fhs

@@ -16,10 +16,11 @@
 // bit whose natural input segment has been reached can no longer change.
 #pragma once
 
-#include <array>
 #include <cstdint>
+#if !defined(__HIPCC_RTC__)
 #include <string>
 #include <vector>
+#endif
 
 namespace fhs {
 
@@ -81,6 +82,7 @@ struct Mask4 {
     uint32_t w[4];
 };
 
+#if !defined(__HIPCC_RTC__)
 struct HostProgram {
     int n = 0;                 // qubits
     int G = 0;                 // gates
@@ -99,5 +101,6 @@ struct HostProgram {
     std::vector<uint16_t> int_cost;    // per evaluation position: algorithmic int32 ops
     std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };
+#endif  // !__HIPCC_RTC__
 
 }  // namespace fhs

@@ -15,11 +15,13 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/fhs.h"
+#include "jit.hpp"
 #include "kernels.hpp"
 #include "program.hpp"
 
@@ -83,6 +85,8 @@ struct fhs_ctx {
     Mask4 *d_fin = nullptr;
     uint32_t *d_src = nullptr;   // [max(A,1)] device-program index of each source gate
     std::vector<uint32_t> pos2ins;   // [G+1] evaluation position -> device-program index
+    std::vector<Instr> dev_ins;      // host copy of the device program
+    std::map<std::string, CompiledConsumer> compiled;   // consumers compiled for this program
     uint32_t c1 = 0, c2 = 0;
     size_t table_budget = size_t(1) << 30;
     uint64_t generation = 0;
@@ -138,6 +142,8 @@ void free_program(fhs_ctx *c) {
     if (c->d_fac) hipFree(c->d_fac);
     if (c->d_fin) hipFree(c->d_fin);
     if (c->d_src) hipFree(c->d_src);
+    for (auto &kv : c->compiled) release(kv.second);
+    c->compiled.clear();
     c->d_prog = nullptr;
     c->d_fac = nullptr;
     c->d_fin = nullptr;
@@ -296,6 +302,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.i2 = c->pos2ins[pl.c2];
     cm.iG = c->pos2ins[P.G];
     cm.runs = c->dispatch == 1 ? 1u : (c->dispatch == 2 ? 0u : (c->long_runs ? 1u : 0u));
+    if (c->dispatch == 3) cm.runs = 1u;   // the interpreted kernels (prefix, too-long regions)
     cm.Ap = pl.Ap;
     cm.Ar = pl.Ar;
     cm.As = pl.As;
@@ -316,12 +323,47 @@ PairRes pair_res(void *ws, const Plan &pl) {
     return PairRes{at<double2>(ws, pl.off_res_amp), at<uint64_t>(ws, pl.off_res_st)};
 }
 
+// Dynamic LDS of the consumer: the root+suffix factor slice when it fits.
+size_t consume_lds_bytes(const Common &cm) {
+    const uint32_t n = cm.f_G - cm.f_c1;
+    return n <= kMaxLdsFactors ? static_cast<size_t>(n) * sizeof(double) : 0;
+}
+
+// Regions up to this many device instructions are compiled on request.
+constexpr uint32_t kMaxCompiledInstr = 1024;
+
+// The consumer compiled for the loaded program, the plan's regions and the
+// launch shape (dispatch mode 3), or nullptr when the mode is off or the
+// regions are too long; compiled once per program and cached.
+fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, const CompiledConsumer **out) {
+    *out = nullptr;
+    if (c->dispatch != 3 || c->prog.A == 0 || cm.iG - cm.i1 > kMaxCompiledInstr) return FHS_OK;
+    const bool flds = cm.f_G - cm.f_c1 <= kMaxLdsFactors;
+    const bool prune = cm.thr > 0.0;
+    const int NW = nw_of(c->prog);
+    char key[128];
+    std::snprintf(key, sizeof(key), "%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, NW, c->ilp,
+                  prune ? 1 : 0, flds ? 1 : 0);
+    auto it = c->compiled.find(key);
+    if (it == c->compiled.end()) {
+        CompiledConsumer k;
+        std::string log;
+        const std::string src = consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, NW, c->ilp, prune, flds);
+        if (!compile_consumer(src, consume_lds_bytes(cm), k, log))
+            return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
+                        log.c_str());
+        it = c->compiled.emplace(key, k).first;
+    }
+    *out = &it->second;
+    return FHS_OK;
+}
+
 // The batched launch sequence (Algorithm 2): precheck, then per batch the
 // prefix-table build, the persistent consumer and the per-pair reduction,
 // then Eq. (2).
 hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const double *coeffs,
                            double *amps, uint64_t *stats, void *ws, int bpc, bool timed,
-                           hipStream_t s) {
+                           hipStream_t s, const CompiledConsumer *ck = nullptr) {
     const HostProgram &P = c->prog;
     const int NW = nw_of(P);
     PreBufs pre = pre_bufs(ws, pl);
@@ -352,7 +394,9 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
             c->n_entries += static_cast<uint64_t>(B) << pl.Ap;
         }
         if (timed && (e = hipEventRecord(c->events[2 * b], s)) != hipSuccess) return e;
-        e = launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
+        e = ck ? launch_compiled(*ck, cm, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid,
+                                 consume_lds_bytes(cm), s)
+               : launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
         if (timed && (e = hipEventRecord(c->events[2 * b + 1], s)) != hipSuccess) return e;
         e = launch_pair_reduce(pre, part, res, p0, B, pl.nchunks, cm.A, s);
@@ -431,6 +475,7 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     c->long_runs = dev.size() >= 2 * n_runs;
     std::vector<uint32_t> src_dev(P.src_eval.size());
     for (size_t k = 0; k < P.src_eval.size(); ++k) src_dev[k] = c->pos2ins[P.src_eval[k]];
+    c->dev_ins = dev;
     const size_t ni = std::max<size_t>(dev.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
@@ -625,7 +670,7 @@ extern "C" fhs_status fhs_set_launch_config(fhs_ctx *c, const fhs_launch_config 
     const uint32_t h = cfg->histories_per_lane ? cfg->histories_per_lane : 2;
     const uint32_t ch = cfg->chunk ? cfg->chunk : kMaxChunk;
     if (h > 2 || ch > static_cast<uint32_t>(kMaxChunk) || (ch & (ch - 1)) || cfg->blocks_per_cu > 64 ||
-        cfg->dispatch > 2)
+        cfg->dispatch > 3)
         return fail(c, FHS_EINVAL, "launch config out of range");
     c->ilp = static_cast<int>(h);
     c->chunk_max = ch;
@@ -744,7 +789,9 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
         // caller's stream with events around every consumer launch (events
         // recorded inside a captured graph carry no usable timestamps).
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
-        int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
+        const CompiledConsumer *ck = nullptr;
+        if ((st = compiled_consumer(c, cm, &ck)) != FHS_OK) return st;
+        int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         if (timed) {
             FHS_HIP(c, ensure_events(c, pl.n_batches));
@@ -752,17 +799,19 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
             FHS_HIP(c, hipMemsetAsync(c->d_valid, 0, sizeof(unsigned long long), s));
             c->n_entries = 0;
         }
-        FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s));
+        FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s, ck));
         c->n_timed = timed ? pl.n_batches : 0;
         return FHS_OK;
     }
     if (!(c->have_graph && c->key == key)) {
         drop_graph(c);
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
-        int bpc = c->prog.A > 0 ? consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp) : 1;
+        const CompiledConsumer *ck = nullptr;   // compiled before the capture starts
+        if ((st = compiled_consumer(c, cm, &ck)) != FHS_OK) return st;
+        int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         FHS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, false, c->cap_stream);
+        hipError_t e = enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, false, c->cap_stream, ck);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) {

@@ -92,8 +92,8 @@ def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False,
 
 def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int, int], List]:
     """Sweep histories per lane x chunk x blocks per CU (automatic dispatch),
-    then both explicit dispatch granularities at the best shape; keep the
-    fastest."""
+    then the explicit dispatch modes (per run, per instruction, compiled) at
+    the best shape; keep the fastest."""
     log = []
     best, best_t = None, math.inf
     for h in (1, 2):
@@ -105,7 +105,7 @@ def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, 
                 log.append((cfg, t))
                 if t < best_t:
                     best, best_t = cfg, t
-    for dispatch in (1, 2):
+    for dispatch in (1, 2, 3):
         cfg = best[:3] + (dispatch,)
         wl.ctx.set_launch_config(*cfg)
         t = time_split(wl, partition, reps)

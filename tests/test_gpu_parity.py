@@ -249,7 +249,8 @@ def test_folded_ladders(ctx, n, seed):
     o = oracle.Feynman(t)
     ref = o.evaluate([0], [1], outs, threads=THREADS)
     assert np.abs(ref[0]).max() > 0.0          # some amplitudes are nonzero
-    for fuse in (True, False):
+    for fuse, dispatch in ((True, 0), (False, 0), (True, 3), (False, 3)):
+        ctx.set_launch_config(0, 0, 0, dispatch)
         prog = fhs.Program(t, fuse=fuse)
         parts = [prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
                  (0, prog.G), (prog.G, prog.G)]
@@ -260,8 +261,9 @@ def test_folded_ladders(ctx, n, seed):
         for part, plain in [((0, 0), True)] + [(p, False) for p in parts]:
             part = (min(part[0], prog.G), min(part[1], prog.G))
             amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
-            assert np.abs(amps - ref[0]).max() <= TOL, (fuse, part, plain)
-            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (fuse, part)
+            assert np.abs(amps - ref[0]).max() <= TOL, (fuse, dispatch, part, plain)
+            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (fuse, dispatch, part)
+    ctx.set_launch_config(0, 0, 0, 0)
     if n <= 12:
         sv_ref = sv.amplitudes(t, [0], [1], outs)
         assert np.abs(ref[0] - sv_ref).max() <= 1e-12

@@ -60,7 +60,7 @@ def test_launch_shapes(ctx, case):
     for h in (1, 2):
         for chunk in (1, 64, 256):
             for bpc in (0, 1, 3):
-                for dispatch in ((0, 1, 2) if chunk == 64 else (0,)):
+                for dispatch in ((0, 1, 2, 3) if chunk == 64 else (0,)):
                     ctx.set_launch_config(h, chunk, bpc, dispatch)
                     assert ctx.launch_config == (h, chunk, bpc, dispatch)
                     amps, st = _run(ctx, prog, outs, thr, part)
@@ -80,7 +80,7 @@ def test_launch_shapes(ctx, case):
     with pytest.raises(fhs.FhsError):
         ctx.set_launch_config(1, 96, 0)       # not a power of two
     with pytest.raises(fhs.FhsError):
-        ctx.set_launch_config(1, 64, 0, 3)    # no such dispatch mode
+        ctx.set_launch_config(1, 64, 0, 4)    # no such dispatch mode
 
 
 def test_table_batches_and_timing(ctx):
@@ -128,7 +128,7 @@ def test_autotune_launch(ctx):
     wl = tune.Workload(ctx, text, [0], [1.0], outs, thr)
     part = wl.prog.choose_partition(fhs.PART_EQ8)
     best, log = tune.autotune_launch(wl, part, reps=1)
-    assert len(log) == 20 and best in [c for c, _ in log]
+    assert len(log) == 21 and best in [c for c, _ in log]
     assert ctx.launch_config == best
     ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
     wl.run(part)
