@@ -175,7 +175,8 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *                       straight-line code and compiled for gfx950 at the
  *                       first evaluation of each program and split (hipRTC,
  *                       about a second; cached in the context) when they
- *                       hold at most 1024 device instructions, else as 1.
+ *                       hold at most 1024 device instructions (else, and
+ *                       for the other kernels, the automatic rule).
  *                       fhs_evaluate returns FHS_EUNSUPPORTED, with the
  *                       compiler log in fhs_last_error, if that compilation
  *                       fails.

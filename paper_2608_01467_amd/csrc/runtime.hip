@@ -302,7 +302,8 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.i2 = c->pos2ins[pl.c2];
     cm.iG = c->pos2ins[P.G];
     cm.runs = c->dispatch == 1 ? 1u : (c->dispatch == 2 ? 0u : (c->long_runs ? 1u : 0u));
-    if (c->dispatch == 3) cm.runs = 1u;   // the interpreted kernels (prefix, too-long regions)
+    // mode 3 compiles the consumer; the interpreted kernels (prefix, plain,
+    // regions too long to compile) use the automatic rule
     cm.Ap = pl.Ap;
     cm.Ar = pl.Ar;
     cm.As = pl.As;
