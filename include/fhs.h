@@ -82,15 +82,21 @@ const char *fhs_status_string(fhs_status s);
 fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out);
 
 /* fhs_reduce with options; fhs_reduce(t, n, out) == fhs_reduce_ex(t, n,
- * FHS_REDUCE_FUSE, out).  FHS_REDUCE_FUSE folds every ladder of controlled X
- * gates that adds or subtracts one on consecutive qubits (the increment /
- * decrement cascades of the quantum walk, Section V) into one instruction:
- * the same history program step for step, evaluated with a multi-word add
- * instead of one mask test per gate.  Positions, sources, cuts, final-bit
- * masks and Eq. (8) are those of the unfused program; fhs_program_work
- * reports the fused work.  flags = 0 keeps one instruction per gate.
- * FHS_EINVAL on unknown flags. */
-enum { FHS_REDUCE_FUSE = 1 };
+ * FHS_REDUCE_FUSE | FHS_REDUCE_PAIR, out).  FHS_REDUCE_FUSE folds every
+ * ladder of controlled X gates that adds or subtracts one on consecutive
+ * qubits (the increment / decrement cascades of the quantum walk, Section V)
+ * into one instruction: the same history program step for step, evaluated
+ * with a multi-word add instead of one mask test per gate.  FHS_REDUCE_PAIR
+ * (only with FHS_REDUCE_FUSE) then merges two folded ladders that are
+ * adjacent in evaluation order, act on the same field, and whose controls
+ * differ only in the value of one bit outside the field (the walk's shift:
+ * +1 for one coin value, -1 for the other) into one instruction that picks
+ * the sign from that bit: one carry chain per history instead of two.
+ * Positions, sources, cuts, final-bit masks and Eq. (8) are those of the
+ * unfused program; fhs_program_work reports the fused work.  flags = 0 keeps
+ * one instruction per gate.  FHS_EINVAL on unknown flags or PAIR without
+ * FUSE. */
+enum { FHS_REDUCE_FUSE = 1, FHS_REDUCE_PAIR = 2 };
 fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags, fhs_program **out);
 void fhs_program_free(fhs_program *prog);
 fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info);
@@ -112,7 +118,9 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *               3w+1 (w = state words spanned by its controls, at least 1),
  *               swap 3w+4, one-qubit diagonal 1, two-qubit diagonal 3,
  *               anti-diagonal 2, branching 4; a fused ladder on f state
- *               words 3w+1+3f (the gates folded into it 0);
+ *               words 3w+1+3f (3f without controls; the gates folded into
+ *               it 0); a paired ladder 3w+1+2+3f (2+3f without common
+ *               controls; the second ladder 0);
  *   fp64_flops: complex multiply of the running amplitude: 6 for a general
  *               factor table, 2 if every entry is purely real or imaginary,
  *               0 if every entry is 0, +-1 or +-i; a negation counts 0;

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libfhs.so")
 
 PART_NONE, PART_THIRDS, PART_EQ8, PART_MODEL = 0, 1, 2, 3
 REDUCE_FUSE = 1
+REDUCE_PAIR = 2
 
 STATUS = {0: "FHS_OK", 1: "FHS_EINVAL", 2: "FHS_EUNSUPPORTED", 3: "FHS_ERANGE",
           4: "FHS_ENOMEM", 5: "FHS_EHIP", 6: "FHS_ESTATE", 7: "FHS_EPARSE"}
@@ -147,10 +148,13 @@ def _check(st: int, ctx=None) -> None:
 class Program:
     """Host-side reduced-history program (fhs_reduce)."""
 
-    def __init__(self, circuit_text: str, fuse: bool = True):
+    def __init__(self, circuit_text: str, fuse: bool = True, pair: bool = True):
+        """fuse: fold add/subtract ladders (FHS_REDUCE_FUSE); pair: also merge
+        complementary folded ladders (FHS_REDUCE_PAIR, only with fuse)."""
         b = circuit_text.encode()
         h = ctypes.c_void_p()
-        _check(lib().fhs_reduce_ex(b, len(b), REDUCE_FUSE if fuse else 0, ctypes.byref(h)))
+        flags = (REDUCE_FUSE | (REDUCE_PAIR if pair else 0)) if fuse else 0
+        _check(lib().fhs_reduce_ex(b, len(b), flags, ctypes.byref(h)))
         self._h = h
         info = ProgramInfo()
         _check(lib().fhs_program_get_info(h, ctypes.byref(info)))

@@ -17,9 +17,18 @@ LIB = os.path.join(HERE, "libfhs.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# Device code generation features turned off:
+#  - packed FP32 (v_pk_*_f32): every HIP source here is built without it;
+#  - three-input bitwise ops (v_bitop3_b32, new in gfx950): with this ROCm
+#    compiler some and/or/xor chains of the history program were folded into
+#    v_bitop3 with wrong results (a run-time compiled consumer gave the wrong
+#    states on a ladder circuit; the same code without the feature, or at -O1,
+#    was correct), so no kernel here may use it.  jit.hip passes the same
+#    flags to hipRTC.
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xclang", "-target-feature", "-Xclang", "-bitop3-insts",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
@@ -28,7 +37,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-I" +
 def _run(cmd):
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l
-                    and "is not a recognized feature" not in l)
+                    and "bitop3-insts" not in l and "is not a recognized feature" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"build failed: {' '.join(cmd)}\n{out}")
     return out

@@ -184,48 +184,101 @@ __device__ __forceinline__ void op_mcphase(Lanes<NW, H> &L, const Instr &I) {
     });
 }
 
+// Wave-uniform masks of a bit field [lo, hi) of the state (hi <= 128), as
+// four 32-bit words: fm = the field, dp = +2^lo and dn = -2^lo in two's
+// complement over 128 bits (every bit from lo up).
+struct FieldMasks {
+    uint32_t fm[4], dp[4], dn[4];
+};
+__device__ __forceinline__ FieldMasks field_masks(uint32_t lo, uint32_t hi) {
+    FieldMasks f;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t b0 = 32u * static_cast<uint32_t>(w);
+        // bits of word w below lo / below hi
+        const uint32_t blo = lo <= b0 ? 0u : (lo >= b0 + 32u ? ~0u : ((1u << (lo - b0)) - 1u));
+        const uint32_t bhi = hi <= b0 ? 0u : (hi >= b0 + 32u ? ~0u : ((1u << (hi - b0)) - 1u));
+        f.fm[w] = bhi & ~blo;
+        f.dn[w] = ~blo;
+        f.dp[w] = (lo >> 5) == static_cast<uint32_t>(w) ? (1u << (lo & 31u)) : 0u;
+    }
+    return f;
+}
+
+// The control test of a controlled op on history h: all of ((s ^ cv) & cm)
+// over words 0..LW is zero.
+template <int NW, int H, int LW>
+__device__ __forceinline__ bool controls_hold(const Lanes<NW, H> &L, int h, const Instr &I) {
+    uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
+    unroll<NW>([&](auto jj) {
+        constexpr int j = jj.value;
+        if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
+    });
+    return acc == 0u;
+}
+
+// state += d over the state's words with one carry chain, keeping the sum
+// only on the field bits fm: no bit below the field changes (d has no bits
+// there), and whatever the carry does above the field is discarded.
+template <int NW, int H>
+__device__ __forceinline__ void add_into_field(Lanes<NW, H> &L, int h, const uint32_t (&d)[NW],
+                                               const uint32_t (&fm)[4]) {
+    uint32_t carry = 0;
+    unroll<NW>([&](auto ww) {
+        constexpr int w = ww.value;
+        const uint32_t x = L.s[h][w];
+        const uint32_t r = __builtin_addc(x, d[w], carry, &carry);
+        L.s[h][w] = (x & ~fm[w]) | (r & fm[w]);
+    });
+}
+
 // Folded ladder (OP_ADD): when the controls match, add one to (zmask bit
-// 0: subtract one from) the bit field [lo, lo+m) of the state, mod 2^m.  The
-// whole state is added to +-2^lo (two's complement over the state's width)
-// with one carry chain over its 32-bit words: no bit below lo changes, and
-// whatever the carry does above the field is discarded when the field bits
-// of the sum are merged back.
+// 0: subtract one from) the bit field [lo, lo+m) of the state, mod 2^m, as
+// an addition of +-2^lo to the whole state.  A history whose controls do
+// not match adds zero: the addend is selected, not the result, so the cost
+// is one select per history instead of one per state word.
 template <int NW, int H, int LW>
 __device__ __forceinline__ void op_add(Lanes<NW, H> &L, const Instr &I) {
-    const uint32_t lo = hdr_a(I), hi = lo + hdr_b(I);   // field [lo, hi), hi <= 128
-    // 128-bit masks and addend as two 64-bit halves, all wave-uniform
-    auto below = [](uint32_t b, uint64_t &m0, uint64_t &m1) {   // bits [0, b)
-        m0 = b >= 64u ? ~0ull : ((1ull << b) - 1ull);
-        m1 = b >= 128u ? ~0ull : (b > 64u ? ((1ull << (b - 64u)) - 1ull) : 0ull);
-    };
-    uint64_t a0, a1, b0, b1;
-    below(lo, a0, a1);
-    below(hi, b0, b1);
-    const uint64_t f0 = b0 & ~a0, f1 = b1 & ~a1;
-    uint64_t d0 = lo < 64u ? (1ull << lo) : 0ull, d1 = lo >= 64u ? (1ull << (lo - 64u)) : 0ull;
-    if (hdr_z(I) & 1u) {   // -2^lo = ~2^lo + 1 over 128 bits
-        d0 = ~d0 + 1ull;
-        d1 = ~d1 + (d0 == 0ull ? 1ull : 0ull);
-    }
-    const uint32_t fm[4] = {static_cast<uint32_t>(f0), static_cast<uint32_t>(f0 >> 32),
-                            static_cast<uint32_t>(f1), static_cast<uint32_t>(f1 >> 32)};
-    const uint32_t dd[4] = {static_cast<uint32_t>(d0), static_cast<uint32_t>(d0 >> 32),
-                            static_cast<uint32_t>(d1), static_cast<uint32_t>(d1 >> 32)};
+    const uint32_t lo = hdr_a(I);
+    const FieldMasks f = field_masks(lo, lo + hdr_b(I));
+    const bool sub = (hdr_z(I) & 1u) != 0u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
-        uint32_t acc = (L.s[h][0] ^ I.cv[0]) & I.cm[0];
-        unroll<NW>([&](auto jj) {
-            constexpr int j = jj.value;
-            if constexpr (j >= 1 && j <= LW) acc |= (L.s[h][j] ^ I.cv[j]) & I.cm[j];
-        });
-        const bool go = acc == 0u;
-        uint32_t carry = 0;
+        const uint32_t gm = controls_hold<NW, H, LW>(L, h, I) ? ~0u : 0u;
+        uint32_t d[NW];
         unroll<NW>([&](auto ww) {
             constexpr int w = ww.value;
-            const uint32_t x = L.s[h][w];
-            const uint32_t r = __builtin_addc(x, dd[w], carry, &carry);
-            L.s[h][w] = go ? ((x & ~fm[w]) | (r & fm[w])) : x;
+            d[w] = (sub ? f.dn[w] : f.dp[w]) & gm;
         });
+        add_into_field<NW, H>(L, h, d, f.fm);
+    });
+}
+
+// Paired ladders (OP_ADDSEL): when the controls match, add one to the
+// field when state bit k equals s and zmask bit s is clear, subtract one
+// when it is set.  Two folded ladders on the same field under controls that
+// differ only in bit k (outside the field) are mutually exclusive and
+// neither changes what the other tests, so together they are one addition
+// of an addend chosen per history: one carry chain instead of two.
+template <int NW, int H, int LW, int SW>
+__device__ __forceinline__ void op_addsel(Lanes<NW, H> &L, const Instr &I) {
+    const uint32_t lo = hdr_a(I);
+    const FieldMasks f = field_masks(lo, lo + hdr_b(I));
+    const uint32_t z = hdr_z(I), kb = I.k & 31u;
+    uint32_t d0[4], dx[4];   // addend when bit k is 0, and its xor with the addend when it is 1
+    for (int w = 0; w < 4; ++w) {
+        d0[w] = (z & 1u) ? f.dn[w] : f.dp[w];
+        dx[w] = d0[w] ^ ((z & 2u) ? f.dn[w] : f.dp[w]);
+    }
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t gm = controls_hold<NW, H, LW>(L, h, I) ? ~0u : 0u;
+        const uint32_t sel = 0u - ((L.s[h][SW] >> kb) & 1u);   // all ones when bit k is set
+        uint32_t d[NW];
+        unroll<NW>([&](auto ww) {
+            constexpr int w = ww.value;
+            d[w] = (d0[w] ^ (dx[w] & sel)) & gm;
+        });
+        add_into_field<NW, H>(L, h, d, f.fm);
     });
 }
 
@@ -382,6 +435,13 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
             case OP_ADD:
                 with_word<NW>(w1, [&](auto LW) {
                     each([&](const Instr &I) { op_add<NW, H, LW.value>(L, I); });
+                });
+                break;
+            case OP_ADDSEL:
+                with_word<NW>(w1, [&](auto LW) {
+                    with_word<NW>(w2, [&](auto SW) {
+                        each([&](const Instr &I) { op_addsel<NW, H, LW.value, SW.value>(L, I); });
+                    });
                 });
                 break;
             default:

@@ -60,6 +60,10 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
             case OP_ADD:
                 std::snprintf(call, sizeof(call), "op_add<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
                 break;
+            case OP_ADDSEL:
+                std::snprintf(call, sizeof(call),
+                              "op_addsel<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
+                break;
             default:
                 std::snprintf(call, sizeof(call), "(void)I; }\n");
                 break;
@@ -108,9 +112,13 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
         log = "hiprtcCreateProgram failed";
         return false;
     }
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
-                          "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
+    // The same code-generation features as the library build: no packed FP32
+    // and no three-input bitwise ops (v_bitop3_b32 was miscompiled for some
+    // straight-line history programs by this compiler).
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-Xclang", "-target-feature", "-Xclang", "-bitop3-insts"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, static_cast<int>(sizeof(opts) / sizeof(opts[0])), opts);
     size_t n = 0;
     hiprtcGetProgramLogSize(prog, &n);
     log.assign(n, '\0');

@@ -40,6 +40,9 @@ enum Op : uint8_t {
     OP_ADD = 9,         // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) += 1 mod 2^b, or -= 1
                         // when zmask bit 0 is set (a folded ladder of controlled X gates)
     OP_NOP = 10,        // a gate folded into the OP_ADD before it (dropped from the device copy)
+    OP_ADDSEL = 11,     // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) += 1 or -= 1 mod 2^b,
+                        // -= 1 when zmask bit (bit k of the state) is set (two OP_ADDs on one
+                        // field whose controls differ only in bit k, outside the field)
 };
 
 // The opcode byte carries the base op in its low 4 bits; bits 4-5 and 6-7
@@ -47,6 +50,7 @@ enum Op : uint8_t {
 // with compile-time indices only:
 //   PERM     bits 4-5: word of the target bit, 6-7: highest nonzero control word
 //   MCPHASE, ADD  bits 4-5: highest nonzero control word
+//   ADDSEL   bits 4-5: highest nonzero control word, 6-7: word of bit k
 //   SWAP, DIAG2  bits 4-5: word of bit a, 6-7: word of bit b
 //   DET1, DIAG1, BRANCH_*  bits 4-5: word of bit a
 constexpr uint8_t op_code(Op base, int w1, int w2) {
@@ -66,7 +70,8 @@ struct alignas(16) Instr {
     // indices; zmask (branching gates) has bit (2o+i) set when U[o][i] is
     // exactly zero.
     uint32_t hdr;
-    uint32_t k;        // OP_BRANCH_SRC: global source index; OP_PERM: target bit mask
+    uint32_t k;        // OP_BRANCH_SRC: global source index; OP_PERM: target bit mask;
+                       // OP_ADDSEL: the selecting state bit
     uint32_t fac;      // offset into the factor table, in doubles
     uint32_t run;      // instructions from here to the end of this run of identical opcodes
     uint32_t cm[4];    // control mask
@@ -93,6 +98,7 @@ struct HostProgram {
     int n_branch = 0;
     std::vector<Instr> ins;            // evaluation order, size G (fused gates become OP_NOP)
     int n_fused = 0;                   // ladders folded into OP_ADD
+    int n_paired = 0;                  // OP_ADD pairs merged into OP_ADDSEL
     std::vector<double> fac;           // factor table
     std::vector<uint32_t> src_eval;    // evaluation position of source k's gate
     std::vector<Mask4> final_before;   // [G+1]: bits final once e gates are applied

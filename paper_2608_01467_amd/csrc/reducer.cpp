@@ -491,7 +491,9 @@ void fuse_ladders(HostProgram &P) {
         A.hdr = pack_hdr(op_code(OP_ADD, wspan, 0), lo, static_cast<uint32_t>(m), v == 1 ? 1u : 0u);
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
-        P.int_cost[e] = static_cast<uint16_t>(3 * (wspan + 1) + 1 + 3 * wfield);   // test, carry, merge
+        const bool any = (A.cm[0] | A.cm[1] | A.cm[2] | A.cm[3]) != 0u;
+        // test (none without controls), carry, merge
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 3 * wfield);
         for (int j = 1; j < m; ++j) {
             Instr N{};
             N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
@@ -500,6 +502,70 @@ void fuse_ladders(HostProgram &P) {
         }
         ++P.n_fused;
         e += m;
+    }
+}
+
+// Pair folded ladders: two OP_ADDs on the same field [lo, lo+m), adjacent in
+// evaluation order (only folded gates between them), whose controls have the
+// same mask and differ in the value of exactly one bit k, which lies outside
+// the field.  At most one of them applies to a history, and neither changes
+// a bit the other tests, so their composition is one OP_ADDSEL: add or
+// subtract one according to bit k under the common controls.  This is the
+// shift of a coined walk (one direction per coin value, Section V), and of
+// any controlled add-or-subtract.  The second ladder's position becomes an
+// OP_NOP: positions, sources, final-bit masks and Eq. (8) stay as they were;
+// a cut inside the pair runs the whole pair in the region where it starts,
+// as for a single ladder, which is sound because the pair changes field bits
+// only and no field bit can be final before the pair's last gate.
+void pair_ladders(HostProgram &P) {
+    const int G = P.G;
+    P.n_paired = 0;
+    auto hiword = [](const uint32_t *m) {
+        int w = 0;
+        for (int j = 0; j < 4; ++j)
+            if (m[j]) w = j;
+        return w;
+    };
+    for (int e = 0; e < G; ++e) {
+        const Instr &I1 = P.ins[e];
+        if (static_cast<Op>(op_base(I1.hdr & 0xffu)) != OP_ADD) continue;
+        int e2 = e + 1;
+        while (e2 < G && static_cast<Op>(op_base(P.ins[e2].hdr & 0xffu)) == OP_NOP) ++e2;
+        if (e2 >= G) break;
+        const Instr &I2 = P.ins[e2];
+        if (static_cast<Op>(op_base(I2.hdr & 0xffu)) != OP_ADD) continue;
+        const uint32_t lo = (I1.hdr >> 8) & 0xffu, m = (I1.hdr >> 16) & 0xffu;
+        if (((I2.hdr >> 8) & 0xffu) != lo || ((I2.hdr >> 16) & 0xffu) != m) continue;
+        int nd = 0, q = -1;
+        bool same_mask = true;
+        for (int w = 0; w < 4; ++w) {
+            same_mask = same_mask && I1.cm[w] == I2.cm[w];
+            const uint32_t x = I1.cv[w] ^ I2.cv[w];
+            nd += __builtin_popcount(x);
+            if (x) q = 32 * w + __builtin_ctz(x);
+        }
+        if (!same_mask || nd != 1) continue;
+        if (static_cast<uint32_t>(q) >= lo && static_cast<uint32_t>(q) < lo + m) continue;
+        const uint32_t s1 = (I1.hdr >> 24) & 1u, s2 = (I2.hdr >> 24) & 1u;
+        const bool q1 = test_bit(I1.cv, static_cast<uint32_t>(q));   // I1 applies when bit q == q1
+        const uint32_t z = q1 ? (s2 | (s1 << 1)) : (s1 | (s2 << 1));
+        Instr A = I1;
+        A.cm[q >> 5] &= ~(1u << (q & 31));
+        A.cv[q >> 5] &= ~(1u << (q & 31));
+        A.k = static_cast<uint32_t>(q);
+        const bool any = (A.cm[0] | A.cm[1] | A.cm[2] | A.cm[3]) != 0u;
+        const int wspan = hiword(A.cm);
+        A.hdr = pack_hdr(op_code(OP_ADDSEL, wspan, q >> 5), lo, m, z);
+        P.ins[e] = A;
+        const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
+        // test, selecting bit, carry and merge
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 2 + 3 * wfield);
+        Instr N{};
+        N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
+        P.ins[e2] = N;
+        P.int_cost[e2] = 0;
+        ++P.n_paired;
+        e = e2;
     }
 }
 
@@ -544,7 +610,9 @@ extern "C" const char *fhs_status_string(fhs_status s) {
 
 extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags,
                                     fhs_program **out) {
-    if (!text || !out || (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE))) return FHS_EINVAL;
+    if (!text || !out || (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE | FHS_REDUCE_PAIR)) ||
+        ((flags & FHS_REDUCE_PAIR) && !(flags & FHS_REDUCE_FUSE)))
+        return FHS_EINVAL;
     *out = nullptr;
     int n = 0;
     std::vector<Gate> gates;
@@ -558,13 +626,14 @@ extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags
         return st;
     }
     if (flags & FHS_REDUCE_FUSE) fuse_ladders(p->p);
+    if (flags & FHS_REDUCE_PAIR) pair_ladders(p->p);
     set_runs(p->p);
     *out = p;
     return FHS_OK;
 }
 
 extern "C" fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out) {
-    return fhs_reduce_ex(text, len, FHS_REDUCE_FUSE, out);
+    return fhs_reduce_ex(text, len, FHS_REDUCE_FUSE | FHS_REDUCE_PAIR, out);
 }
 
 extern "C" void fhs_program_free(fhs_program *prog) { delete prog; }

@@ -1,6 +1,7 @@
-"""Host checks of ladder folding (fhs_reduce_ex with FHS_REDUCE_FUSE): the
-folded program keeps every position, source, final-bit mask and Eq. (8)
-count of the gate-by-gate program and only its work per history drops."""
+"""Host checks of ladder folding and pairing (fhs_reduce_ex with
+FHS_REDUCE_FUSE and FHS_REDUCE_PAIR): the folded program keeps every
+position, source, final-bit mask and Eq. (8) count of the gate-by-gate
+program and only its work per history drops."""
 import ctypes
 
 import numpy as np
@@ -37,13 +38,20 @@ def test_fused_program_keeps_positions_and_eq8(text):
 def test_walk_ladders_fold_to_one_instruction_each():
     n_pos, steps = 99, 20
     a = fhs.Program(w.quantum_walk(n_pos, steps).to_text(), fuse=False)
-    b = fhs.Program(w.quantum_walk(n_pos, steps).to_text())
+    b = fhs.Program(w.quantum_walk(n_pos, steps).to_text(), pair=False)
+    c = fhs.Program(w.quantum_walk(n_pos, steps).to_text())
     # unfolded: the X on position bit i has controls up to qubit i (w words): 3w+1;
-    # folded: one add per ladder, 3*1+1 for the coin control + 3 per field word
+    # folded: one add per ladder, 3*1+1 for the coin control + 3 per field word;
+    # paired: one add per step, the coin selects the sign: 2 + 3 per field word
     words = lambda hi: hi // 32 + 1
     unfolded = steps * (4 + 2 * sum(3 * words(i) + 1 for i in range(n_pos)))
     assert a.work(0, a.G)["int_ops"] == unfolded
     assert b.work(0, b.G)["int_ops"] == steps * (4 + 2 * (4 + 3 * 4))
+    assert c.work(0, c.G)["int_ops"] == steps * (4 + 2 + 3 * 4)
+    # one instruction per ladder when folded, one per step when paired
+    fb = b.split_features(b.L, b.G, 64, 1)
+    fc = c.split_features(c.L, c.G, 64, 1)
+    assert fc[14] < fb[14]
 
 
 def test_mixed_circuits_without_ladders_are_unchanged():
@@ -56,6 +64,8 @@ def test_mixed_circuits_without_ladders_are_unchanged():
 def test_reduce_ex_rejects_unknown_flags():
     t = b"qubits 2\nH 0\n"
     h = ctypes.c_void_p()
-    assert fhs.lib().fhs_reduce_ex(t, len(t), 2, ctypes.byref(h)) == 1
-    assert fhs.lib().fhs_reduce_ex(t, len(t), 0, ctypes.byref(h)) == 0
-    fhs.lib().fhs_program_free(h)
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 4, ctypes.byref(h)) == 1
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 2, ctypes.byref(h)) == 1   # pair needs fuse
+    for flags in (0, 1, 3):
+        assert fhs.lib().fhs_reduce_ex(t, len(t), flags, ctypes.byref(h)) == 0
+        fhs.lib().fhs_program_free(h)

@@ -196,14 +196,23 @@ def test_walk_small(ctx, n_pos, steps):
 def test_walk_config_full(ctx):
     """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
     against the position-space closed form and the closed-form valid sets
-    (count, index sum, index hash); the padding outputs exactly zero."""
+    (count, index sum, index hash); the padding outputs exactly zero.  Run
+    in the launch shapes the benchmark times: the interpreting and the
+    compiled consumer, one and two histories per lane, the Eq. (8) split and
+    the learned splits; ladders paired (the default) and only folded."""
     cfg = w.CONFIGS["walk_99p_20s"]()
     t = cfg["circuit"].to_text()
     prog = fhs.Program(t)
+    folded = fhs.Program(t, pair=False)
     outs = cfg["outputs"]
     dp = cf.walk_amplitudes(20)
-    for part, plain in [(prog.choose_partition(fhs.PART_EQ8), False), ((0, 0), True)]:
-        amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
+    eq8 = prog.choose_partition(fhs.PART_EQ8)
+    runs = [(prog, eq8, False, (0, 0)), (prog, (0, 0), True, (0, 0)),
+            (prog, (2984, 3581), False, (1, 3)), (prog, (3183, 3581), False, (2, 3)),
+            (prog, eq8, False, (2, 3)), (folded, (2984, 3581), False, (1, 3))]
+    for pg, part, plain, (h, dispatch) in runs:
+        ctx.set_launch_config(h, 0, 0, dispatch)
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=pg)
         for y, a, row in zip(outs[:42], amps[:42], st[:42]):
             x = y >> 1
             x = x - (1 << 99) if x >= (1 << 98) else x
@@ -211,6 +220,7 @@ def test_walk_config_full(ctx):
             assert tuple(int(v) for v in row[:3]) == cf.walk_valid_stats(20, x, y & 1)
         assert abs(np.sum(np.abs(amps[:42]) ** 2) - 1.0) <= 1e-10
         assert (amps[42:] == 0).all() and (st[42:, 0] == 0).all()
+    ctx.set_launch_config(0, 0, 0, 0)
 
 
 def _reachable(circuit, count, seed):
@@ -263,6 +273,42 @@ def test_folded_ladders(ctx, n, seed):
             amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
             assert np.abs(amps - ref[0]).max() <= TOL, (fuse, dispatch, part, plain)
             assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (fuse, dispatch, part)
+    ctx.set_launch_config(0, 0, 0, 0)
+    if n <= 12:
+        sv_ref = sv.amplitudes(t, [0], [1], outs)
+        assert np.abs(ref[0] - sv_ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,seed", [(12, 11), (40, 12), (64, 13), (100, 14)])
+def test_paired_ladders(ctx, n, seed):
+    """Complementary ladder pairs merged into one add-or-subtract (the
+    default), folded but unpaired, and gate by gate: all match the oracle at
+    every cut (cuts inside a pair too), under the interpreted dispatches and
+    the compiled consumer, plain too."""
+    c = w.random_ladder_pairs(n, 10, seed)
+    t = c.to_text()
+    outs = _reachable(c, 24, seed) + w.random_outputs(n, 8, seed + 50)
+    o = oracle.Feynman(t)
+    ref = o.evaluate([0], [1], outs, threads=THREADS)
+    assert np.abs(ref[0]).max() > 0.0
+    paired = fhs.Program(t)
+    assert paired.work(0, paired.G)["int_ops"] < fhs.Program(t, pair=False).work(0, paired.G)["int_ops"]
+    for (fuse, pair), dispatch in [((True, True), 0), ((True, True), 2), ((True, True), 3),
+                                   ((True, False), 3), ((False, False), 0)]:
+        ctx.set_launch_config(0, 0, 0, dispatch)
+        prog = fhs.Program(t, fuse=fuse, pair=pair)
+        parts = [prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
+                 (0, prog.G), (prog.G, prog.G)]
+        src = prog.source_eval_positions
+        if src:
+            parts += [(src[0] + 1, src[-1] + 2), (src[len(src) // 2] + 3, prog.G),
+                      (src[0] + 2 + n // 2, prog.G)]
+        for part, plain in [((0, 0), True)] + [(p, False) for p in parts]:
+            part = (min(part[0], prog.G), min(part[1], prog.G))
+            part = (min(part[0], part[1]), part[1])
+            amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=prog)
+            assert np.abs(amps - ref[0]).max() <= TOL, (fuse, pair, dispatch, part, plain)
+            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (fuse, pair, dispatch, part)
     ctx.set_launch_config(0, 0, 0, 0)
     if n <= 12:
         sv_ref = sv.amplitudes(t, [0], [1], outs)

@@ -202,6 +202,54 @@ def random_ladders(n: int, n_ladders: int, seed: int, n_extra: int = 4) -> Circu
     return c
 
 
+def random_ladder_pairs(n: int, n_pairs: int, seed: int, n_extra: int = 3) -> Circuit:
+    """Random circuit built around pairs of add/subtract-one ladders on one
+    block of consecutive qubits whose controls differ only in the polarity
+    of a selector qubit outside the block (the shape of a coined walk's
+    shift), under 0-2 further common controls of random polarity and with
+    each ladder's direction random.  Every pair is preceded by an H on its
+    selector qubit and a few random gates.  Some pairs are broken on purpose
+    (the second ladder on a shifted block, or with its selector polarity
+    equal to the first's) so that unpairable neighbours occur too."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+
+    def ladder(block, ks, kneg, neg):
+        for i in range(len(block) - 1, -1, -1):
+            c.add("MCX", block[i], *(ks + block[:i]),
+                  negs=tuple([False] + kneg + [neg] * i))
+
+    for _ in range(n_pairs):
+        m = int(rng.integers(2, min(n - 2, 40) + 1))
+        lo = int(rng.integers(0, n - m + 1))
+        block = list(range(lo, lo + m))
+        rest = [q for q in range(n) if q < lo or q >= lo + m]
+        sel = int(rng.choice(rest))
+        c.add("H", sel)
+        for _ in range(int(rng.integers(0, n_extra + 1))):
+            k = ["T", "S", "CX", "CZ", "X"][int(rng.integers(0, 5))]
+            if k in ("CX", "CZ"):
+                a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+                c.add(k, a, b)
+            else:
+                c.add(k, int(rng.integers(0, n)))
+        others = [q for q in rest if q != sel]
+        n_k = int(rng.integers(0, min(2, len(others)) + 1))
+        ks = [int(x) for x in rng.choice(others, size=n_k, replace=False)] if n_k else []
+        kneg = [bool(rng.integers(0, 2)) for _ in ks]
+        p0 = bool(rng.integers(0, 2))
+        broken = rng.random() < 0.2
+        block2 = block
+        p1 = not p0
+        if broken and lo + m < n and lo + m not in [sel] + ks:
+            block2 = list(range(lo + 1, lo + m + 1))
+        elif broken:
+            p1 = p0
+        ladder(block, [sel] + ks, [p0] + kneg, bool(rng.integers(0, 2)))
+        ladder(block2, [sel] + ks, [p1] + kneg, bool(rng.integers(0, 2)))
+    return c
+
+
 def random_clifford_t(n: int = 10, n_gates: int = 40, seed: int = 101) -> Circuit:
     """Random Clifford+T circuit: H 30%, T 20%, S 10%, CNOT 30%, CZ 10%,
     qubits uniform, two-qubit gates on a distinct ordered pair."""
