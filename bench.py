@@ -220,16 +220,18 @@ def main() -> int:
     # Algorithmic work of the consumer per step, summed over the gates that
     # must be evaluated: the root region once for each of the 2^Ar root
     # assignments of every prefix entry still consistent after the prefix
-    # region, the suffix region once per leaf walked (2^As per consistent
-    # root).  Redundant evaluations the kernel makes for parallelism (root
-    # re-runs by the lanes that share a root task, lanes that idle inside a
-    # wave) do not count.
+    # region, the suffix region's integer work once per leaf walked (2^As
+    # per consistent root) and its factor products once per valid history
+    # (a history's amplitude is needed only when it passes the final check).
+    # Redundant evaluations the kernel makes for parallelism (root re-runs
+    # by the lanes that share a root task, lanes that idle inside a wave) do
+    # not count.
     root = prog.work(plan["c1"], plan["c2"])
     suffix = prog.work(plan["c2"], prog.G)
     launches = max(1, len(kt) // max(args.steps, 1))
     n_root = n_valid_entries << plan["Ar"]
     int_ops = (n_root * root["int_ops"] + leaves * suffix["int_ops"]) / launches
-    flops = (n_root * root["fp64_flops"] + leaves * suffix["fp64_flops"]) / launches
+    flops = (n_root * root["fp64_flops"] + valid * suffix["fp64_flops"]) / launches
     avg_launch = sum(kt) / len(kt) / 1e3
     int_rate = int_ops / avg_launch
     fp_rate = flops / avg_launch

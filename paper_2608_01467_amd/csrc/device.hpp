@@ -138,6 +138,7 @@ struct Lanes {
     double re[H], im[H], M[H];
     bool ok[H];
     uint64_t hb[H];     // this region's source bits, per history
+    uint64_t dx[H];     // factor-table indices recorded for a deferred multiply
 };
 
 // Factor tables: `fac` points at the slice [lo, ...) of the global table,
@@ -150,6 +151,21 @@ struct FacRef {
     }
     __device__ __forceinline__ double d(uint32_t off) const { return p[off - lo]; }
 };
+
+// Entry x of a gate's factor table (at offset fac) for history h: multiplied
+// into the running amplitude now (DEFER < 0), or recorded in bits
+// [DEFER, DEFER + 2) of dx[h] and multiplied after the history has passed
+// its final check (the same factors in the same order, so the same result).
+template <int DEFER, int NW, int H>
+__device__ __forceinline__ void take_factor(Lanes<NW, H> &L, int h, const FacRef &F, uint32_t fac,
+                                            uint32_t x) {
+    if constexpr (DEFER < 0) {
+        const double2 f = F.c(fac + 2u * x);
+        cmul(L.re[h], L.im[h], f.x, f.y);
+    } else {
+        L.dx[h] |= static_cast<uint64_t>(x) << DEFER;
+    }
+}
 
 __device__ __forceinline__ uint32_t hdr_a(const Instr &I) { return (I.hdr >> 8) & 0xffu; }
 __device__ __forceinline__ uint32_t hdr_b(const Instr &I) { return (I.hdr >> 16) & 0xffu; }
@@ -299,46 +315,44 @@ __device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
     });
 }
 
-template <int NW, int H, int WA>
+template <int NW, int H, int WA, int DEFER = -1>
 __device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
     constexpr int A = wsel<WA, NW>();
     const uint32_t sh = hdr_a(I) & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         const uint32_t o = (L.s[h][A] >> sh) & 1u;
-        const double2 f = F.c(I.fac + 2u * o);
-        cmul(L.re[h], L.im[h], f.x, f.y);
+        take_factor<DEFER>(L, h, F, I.fac, o);
         L.s[h][A] ^= 1u << sh;
     });
 }
 
-template <int NW, int H, int WA>
+template <int NW, int H, int WA, int DEFER = -1>
 __device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
     constexpr int A = wsel<WA, NW>();
     const uint32_t sh = hdr_a(I) & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         const uint32_t o = (L.s[h][A] >> sh) & 1u;
-        const double2 f = F.c(I.fac + 2u * o);
-        cmul(L.re[h], L.im[h], f.x, f.y);
+        take_factor<DEFER>(L, h, F, I.fac, o);
     });
 }
 
-template <int NW, int H, int WA, int WB>
+template <int NW, int H, int WA, int WB, int DEFER = -1>
 __device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
     constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
     const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         const uint32_t x = ((L.s[h][A] >> sa) & 1u) | (((L.s[h][B] >> sb) & 1u) << 1);
-        const double2 f = F.c(I.fac + 2u * x);
-        cmul(L.re[h], L.im[h], f.x, f.y);
+        take_factor<DEFER>(L, h, F, I.fac, x);
     });
 }
 
-template <int NW, int H, bool PRUNE, int WA, bool SRC>
+template <int NW, int H, bool PRUNE, int WA, bool SRC, int DEFER = -1>
 __device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const FacRef &F,
                                           uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
+    static_assert(!(PRUNE && DEFER >= 0), "pruning needs the moduli as the walk goes");
     constexpr int A = wsel<WA, NW>();
     const uint32_t sh = hdr_a(I) & 31u;
     const uint32_t ks = I.k - kbase;
@@ -347,8 +361,7 @@ __device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const
         const uint32_t o = (L.s[h][A] >> sh) & 1u;
         const uint32_t i = SRC ? static_cast<uint32_t>((L.hb[h] >> ks) & 1u) : (bin[A] >> sh) & 1u;
         const uint32_t x = 2u * o + i;
-        const double2 f = F.c(I.fac + 2u * x);
-        cmul(L.re[h], L.im[h], f.x, f.y);
+        take_factor<DEFER>(L, h, F, I.fac, x);
         if (PRUNE) {
             L.M[h] = L.M[h] * F.d(I.fac + 8u + x);
             L.ok[h] = L.ok[h] && !(L.M[h] < thr);
@@ -580,6 +593,9 @@ __device__ __forceinline__ void block_reduce_store(Acc a, Acc *lds, Partials par
 // Regions policy of the interpreting consumer.
 template <bool RUNS>
 struct Interp {
+    static constexpr bool kDefer = false;   // factors are multiplied as the walk goes
+    template <int NW, int H>
+    __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
     template <int NW, int H, bool PRUNE>
     __device__ static __forceinline__ void root(const Common &c, const FacRef &F, Lanes<NW, H> &L,
                                                 const uint32_t (&bin)[NW]) {
@@ -603,7 +619,9 @@ __device__ __forceinline__ bool wave_alive(const Lanes<NW, H> &L) {
 // The persistent consumer (Algorithm 2, inner loops) over a Regions policy
 // that walks the root region [c1, c2) and the suffix region [c2, G) of a
 // history: Interp decodes the program at run time; the runtime can also
-// compile a policy with the regions' instructions as straight-line code.
+// compile a policy with the regions' instructions as straight-line code,
+// which may defer the suffix's factor multiplications (kDefer) to the
+// histories that pass the final check (suffix_amp).
 template <class Regions, int NW, int H, bool PRUNE, bool FLDS>
 __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part, uint32_t p0,
                                              uint32_t B, uint32_t chunk, uint32_t ss,
@@ -712,13 +730,19 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             if (!__any(any)) continue;   // wave-uniform skip
             for (uint64_t q = 0; q < n_suffix; ++q) {
                 Lanes<NW, H> S2 = R;
-                unroll<H>([&](auto jj) { S2.hb[jj.value] = hs0[jj.value] + q; });
+                unroll<H>([&](auto jj) {
+                    S2.hb[jj.value] = hs0[jj.value] + q;
+                    S2.dx[jj.value] = 0;
+                });
                 Regions::template suffix<NW, H, PRUNE>(c, F, S2, bin);
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
                     const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
                     acc.leaves += R.ok[j] ? 1u : 0u;
                     if (ok2) {
+                        // a policy that deferred the suffix's factors applies them
+                        // now, for the histories that count
+                        if constexpr (Regions::kDefer) Regions::template suffix_amp<NW, H>(F, S2, j);
                         const uint64_t h = hbase[j] | ((hs0[j] + q) << sshift);
                         acc.re += S2.re[j];
                         acc.im += S2.im[j];

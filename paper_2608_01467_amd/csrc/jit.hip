@@ -14,11 +14,34 @@ namespace {
 // device.hpp, kernels.hpp and program.hpp as text (written by the build).
 #include "jit_headers.inc"
 
+// A factor taken by a deferred multiply: its table offset and where its
+// index sits in dx.
+struct Deferred {
+    uint32_t fac;
+    int off, bits;
+};
+
+// Bits of dx a factor op records when deferred (0: no factor).
+int factor_bits(int base) {
+    switch (base) {
+        case OP_BRANCH_SRC:
+        case OP_BRANCH_NAT:
+        case OP_DIAG2: return 2;
+        case OP_DIAG1:
+        case OP_DET1: return 1;
+        default: return 0;
+    }
+}
+
 // One block per instruction: the instruction as a constant and the call of
 // its backward step with the word indices its opcode carries (wsel maps them
-// onto the state registers as the interpreter's dispatch does).
-void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi) {
+// onto the state registers as the interpreter's dispatch does).  With
+// `defer`, factor ops record their table index in dx instead of multiplying
+// (the offsets are appended to `deferred`).
+void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi, bool defer,
+                 std::vector<Deferred> &deferred) {
     char buf[512];
+    int off = 0;
     for (uint32_t x = lo; x < hi; ++x) {
         const Instr &I = dev[x];
         const uint32_t op = I.hdr & 0xffu;
@@ -30,6 +53,12 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
                       I.hdr, I.k, I.fac, I.run, I.cm[0], I.cm[1], I.cm[2], I.cm[3], I.cv[0], I.cv[1],
                       I.cv[2], I.cv[3]);
         o += buf;
+        int d = -1;
+        if (defer && factor_bits(base) > 0) {
+            d = off;
+            deferred.push_back(Deferred{I.fac, off, factor_bits(base)});
+            off += factor_bits(base);
+        }
         char call[256];
         switch (base) {
             case OP_PERM:
@@ -38,15 +67,16 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
             case OP_BRANCH_SRC:
             case OP_BRANCH_NAT:
                 std::snprintf(call, sizeof(call),
-                              "op_branch<NW, H, PRUNE, wsel<%d, NW>(), %s>(L, I, F, kbase, bin, thr); "
+                              "op_branch<NW, H, PRUNE, wsel<%d, NW>(), %s, %d>(L, I, F, kbase, bin, thr); "
                               "if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
-                              w1, base == OP_BRANCH_SRC ? "true" : "false");
+                              w1, base == OP_BRANCH_SRC ? "true" : "false", d);
                 break;
             case OP_DIAG2:
-                std::snprintf(call, sizeof(call), "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I, F); }\n", w1, w2);
+                std::snprintf(call, sizeof(call),
+                              "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %d>(L, I, F); }\n", w1, w2, d);
                 break;
             case OP_DIAG1:
-                std::snprintf(call, sizeof(call), "op_diag1<NW, H, wsel<%d, NW>()>(L, I, F); }\n", w1);
+                std::snprintf(call, sizeof(call), "op_diag1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
                 break;
             case OP_MCPHASE:
                 std::snprintf(call, sizeof(call), "op_mcphase<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
@@ -55,7 +85,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
                 std::snprintf(call, sizeof(call), "op_swap<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
                 break;
             case OP_DET1:
-                std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>()>(L, I, F); }\n", w1);
+                std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
                 break;
             case OP_ADD:
                 std::snprintf(call, sizeof(call), "op_add<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
@@ -75,23 +105,49 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
 }  // namespace
 
 std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
-                            int NW, int H, bool prune, bool flds) {
+                            uint32_t Ap, uint32_t Ar, int NW, int H, bool prune, bool flds) {
+    // defer the suffix's factors when nothing needs them during the walk
+    // (pruning does) and their indices fit in dx
+    int bits = 0;
+    for (uint32_t x = i2; x < iG; ++x) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
+    const bool defer = !prune && bits <= 64;
+    std::vector<Deferred> none, deferred;
     std::string o;
+    char buf[512];
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
-    o += "template <int NW, int H, bool PRUNE>\n"
-         "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
-         "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
-         "    const uint32_t kbase = c.Ap; const double thr = c.thr; (void)kbase; (void)thr;\n";
-    emit_region(o, dev, i1, i2);
+    o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
+    std::snprintf(buf, sizeof(buf),
+                  "template <int NW, int H, bool PRUNE>\n"
+                  "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
+                  "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
+                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n",
+                  Ap);
+    o += buf;
+    emit_region(o, dev, i1, i2, false, none);
     o += "}\n";
-    o += "template <int NW, int H, bool PRUNE>\n"
-         "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
-         "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
-         "    const uint32_t kbase = c.Ap + c.Ar; const double thr = c.thr; (void)kbase; (void)thr;\n";
-    emit_region(o, dev, i2, iG);
-    o += "}\n};\n}  // namespace\n}  // namespace fhs\n";
-    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "template <int NW, int H, bool PRUNE>\n"
+                  "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
+                  "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
+                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n",
+                  Ap + Ar);
+    o += buf;
+    emit_region(o, dev, i2, iG, defer, deferred);
+    o += "}\n";
+    // the deferred factors, in evaluation order: the same products as the walk
+    o += "template <int NW, int H>\n"
+         "__device__ static __forceinline__ void suffix_amp(const FacRef &F, Lanes<NW, H> &L, int h) {\n"
+         "    (void)F; (void)L; (void)h;\n";
+    for (const Deferred &d : deferred) {
+        std::snprintf(buf, sizeof(buf),
+                      "    { const uint32_t x = static_cast<uint32_t>(L.dx[h] >> %d) & %uu; "
+                      "const double2 f = F.c(%uu + 2u * x); cmul(L.re[h], L.im[h], f.x, f.y); }\n",
+                      d.off, (1u << d.bits) - 1u, d.fac);
+        o += buf;
+    }
+    o += "}\n";
+    o += "};\n}  // namespace\n}  // namespace fhs\n";
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ __launch_bounds__(fhs::kConsumeThreads) void "
                   "fhs_consume_compiled(fhs::Common c, fhs::Table tab, fhs::Partials part, uint32_t p0, "

@@ -343,13 +343,14 @@ fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, const CompiledConsume
     const bool prune = cm.thr > 0.0;
     const int NW = nw_of(c->prog);
     char key[128];
-    std::snprintf(key, sizeof(key), "%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, NW, c->ilp,
-                  prune ? 1 : 0, flds ? 1 : 0);
+    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, NW,
+                  c->ilp, prune ? 1 : 0, flds ? 1 : 0);
     auto it = c->compiled.find(key);
     if (it == c->compiled.end()) {
         CompiledConsumer k;
         std::string log;
-        const std::string src = consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, NW, c->ilp, prune, flds);
+        const std::string src =
+            consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, NW, c->ilp, prune, flds);
         if (!compile_consumer(src, consume_lds_bytes(cm), k, log))
             return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
                         log.c_str());
