@@ -596,6 +596,17 @@ struct Interp {
     static constexpr bool kDefer = false;   // factors are multiplied as the walk goes
     template <int NW, int H>
     __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
+    // final-bit checks at c2 and G with the masks read from the program
+    template <int NW>
+    __device__ static __forceinline__ bool final_c2(const uint32_t (&s)[NW], const uint32_t (&bin)[NW],
+                                                    const Mask4 &m) {
+        return check_final<NW>(s, bin, m);
+    }
+    template <int NW>
+    __device__ static __forceinline__ bool final_G(const uint32_t (&s)[NW], const uint32_t (&bin)[NW],
+                                                   const Mask4 &m) {
+        return check_final<NW>(s, bin, m);
+    }
     template <int NW, int H, bool PRUNE>
     __device__ static __forceinline__ void root(const Common &c, const FacRef &F, Lanes<NW, H> &L,
                                                 const uint32_t (&bin)[NW]) {
@@ -724,7 +735,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             bool any = false;
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
-                R.ok[j] = R.ok[j] && check_final<NW>(R.s[j], bin, fin_c2);
+                R.ok[j] = R.ok[j] && Regions::template final_c2<NW>(R.s[j], bin, fin_c2);
                 any = any || R.ok[j];
             });
             if (!__any(any)) continue;   // wave-uniform skip
@@ -737,7 +748,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 Regions::template suffix<NW, H, PRUNE>(c, F, S2, bin);
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
-                    const bool ok2 = S2.ok[j] && check_final<NW>(S2.s[j], bin, fin_G);
+                    const bool ok2 = S2.ok[j] && Regions::template final_G<NW>(S2.s[j], bin, fin_G);
                     acc.leaves += R.ok[j] ? 1u : 0u;
                     if (ok2) {
                         // a policy that deferred the suffix's factors applies them

@@ -105,7 +105,8 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
 }  // namespace
 
 std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
-                            uint32_t Ap, uint32_t Ar, int NW, int H, bool prune, bool flds) {
+                            uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
+                            int H, bool prune, bool flds) {
     // defer the suffix's factors when nothing needs them during the walk
     // (pruning does) and their indices fit in dx
     int bits = 0;
@@ -117,6 +118,19 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
     o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
+    // the final-bit masks as constants: fully checked words become one compare
+    const Mask4 *fm[2] = {&fin_c2, &fin_G};
+    const char *fname[2] = {"final_c2", "final_G"};
+    for (int k = 0; k < 2; ++k) {
+        std::snprintf(buf, sizeof(buf),
+                      "template <int NW>\n"
+                      "__device__ static __forceinline__ bool %s(const uint32_t (&s)[NW], "
+                      "const uint32_t (&bin)[NW], const Mask4 &) {\n"
+                      "    constexpr Mask4 m{{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}};\n"
+                      "    return check_final<NW>(s, bin, m);\n}\n",
+                      fname[k], fm[k]->w[0], fm[k]->w[1], fm[k]->w[2], fm[k]->w[3]);
+        o += buf;
+    }
     std::snprintf(buf, sizeof(buf),
                   "template <int NW, int H, bool PRUNE>\n"
                   "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "

@@ -26,12 +26,14 @@ struct CompiledConsumer {
 };
 
 // Source text of the consumer for device-program regions [i1, i2) (root)
-// and [i2, iG) (suffix) of `dev`, whose first sources are Ap and Ap + Ar.
-// Without pruning, the suffix's factor multiplications are deferred to the
-// histories that pass the final check when their table indices fit in 64
-// bits.
+// and [i2, iG) (suffix) of `dev`, whose first sources are Ap and Ap + Ar;
+// fin_c2 and fin_G are the final-bit masks checked at the ends of the two
+// regions.  Without pruning, the suffix's factor multiplications are
+// deferred to the histories that pass the final check when their table
+// indices fit in 64 bits.
 std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
-                            uint32_t Ap, uint32_t Ar, int NW, int H, bool prune, bool flds);
+                            uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
+                            int H, bool prune, bool flds);
 
 // Compile `src` for gfx950 and load it on the current device.  On failure
 // returns false and puts the compiler log in `log`.

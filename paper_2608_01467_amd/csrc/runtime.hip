@@ -343,14 +343,17 @@ fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, const CompiledConsume
     const bool prune = cm.thr > 0.0;
     const int NW = nw_of(c->prog);
     char key[128];
-    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, NW,
-                  c->ilp, prune ? 1 : 0, flds ? 1 : 0);
+    // the cut positions fix the final-bit masks (two cuts inside one folded
+    // ladder share device indices but not masks)
+    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1, cm.c2,
+                  cm.Ap, cm.Ar, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0);
     auto it = c->compiled.find(key);
     if (it == c->compiled.end()) {
         CompiledConsumer k;
         std::string log;
         const std::string src =
-            consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, NW, c->ilp, prune, flds);
+            consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, c->prog.final_before[cm.c2],
+                            c->prog.final_before[cm.G], NW, c->ilp, prune, flds);
         if (!compile_consumer(src, consume_lds_bytes(cm), k, log))
             return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
                         log.c_str());
