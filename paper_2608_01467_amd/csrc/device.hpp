@@ -498,11 +498,9 @@ __device__ __forceinline__ void copy_core(Lanes<NW, H> &dst, const Lanes<NW, H> 
 // reused by every assignment that agrees on the earlier sources (the
 // checkpoint idea of Algorithm 2 applied at every source).  Control flow is
 // wave-uniform throughout.
-template <int NW, int H, bool PRUNE, bool RUNS, int DMAX, class Leaf>
-__device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, const uint32_t *src,
-                                           uint32_t k0, uint32_t D, uint32_t e_end,
-                                           const Lanes<NW, H> &L, uint32_t kbase,
-                                           const uint32_t (&bin)[NW], double thr, Leaf &&leaf) {
+template <int NW, int H, int DMAX, class Seg, class Leaf>
+__device__ __forceinline__ void dfs_region(uint32_t k0, uint32_t D, const Lanes<NW, H> &L,
+                                           uint32_t kbase, Seg &&seg, Leaf &&leaf) {
     Lanes<NW, H> C = L;
     Lanes<NW, H> S[DMAX];      // S[l]: state before level l's source (l >= 1)
     const uint32_t nt = 1u << D;
@@ -522,9 +520,7 @@ __device__ __forceinline__ void dfs_region(const Instr *prog, const FacRef &F, c
             const uint32_t kb = k0 + l - kbase;
             const uint64_t bit = static_cast<uint64_t>((t >> (D - 1u - l)) & 1u) << kb;
             unroll<H>([&](auto hh) { C.hb[hh.value] = (C.hb[hh.value] & ~(1ull << kb)) | bit; });
-            const uint32_t a = ld_const(src, k0 + l);
-            const uint32_t b = (l + 1u < D) ? ld_const(src, k0 + l + 1u) : e_end;
-            run_region<NW, H, PRUNE, RUNS>(prog, F, a, b, C, kbase, bin, thr);
+            seg(l, C);   // the gates from level l's source up to the next level's
             if (l + 1u < D) {
                 unroll<DMAX>([&](auto LV) {
                     if constexpr (LV.value > 0)
@@ -594,6 +590,22 @@ __device__ __forceinline__ void block_reduce_store(Acc a, Acc *lds, Partials par
 template <bool RUNS>
 struct Interp {
     static constexpr bool kDefer = false;   // factors are multiplied as the walk goes
+    // prefix region: the gates before the first depth-first source, and the
+    // gates of depth-first level l (from its source up to the next level's)
+    template <int NW, bool PRUNE>
+    __device__ static __forceinline__ void prefix_head(const Common &c, const FacRef &F,
+                                                       Lanes<NW, 1> &L, const uint32_t (&bin)[NW],
+                                                       uint32_t e_split) {
+        run_region<NW, 1, PRUNE, RUNS>(c.prog, F, c.iL, e_split, L, 0, bin, c.thr);
+    }
+    template <int NW, bool PRUNE>
+    __device__ static __forceinline__ void prefix_seg(const Common &c, const FacRef &F,
+                                                      Lanes<NW, 1> &C, const uint32_t (&bin)[NW],
+                                                      uint32_t k0, uint32_t D, uint32_t l) {
+        const uint32_t a = ld_const(c.src, k0 + l);
+        const uint32_t b = (l + 1u < D) ? ld_const(c.src, k0 + l + 1u) : c.i1;
+        run_region<NW, 1, PRUNE, RUNS>(c.prog, F, a, b, C, 0, bin, c.thr);
+    }
     template <int NW, int H>
     __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
     // final-bit checks at c2 and G with the masks read from the program
@@ -625,6 +637,65 @@ __device__ __forceinline__ bool wave_alive(const Lanes<NW, H> &L) {
     bool any = false;
     unroll<H>([&](auto hh) { any = any || L.ok[hh.value]; });
     return __any(any);
+}
+
+// The prefix-table build (Algorithm 2, first loop) over a Walk policy
+// (Interp, or the run-time compiled regions): one lane per subtree of prefix
+// assignments; the lane's index fixes the first Ap - Dp prefix sources, the
+// last Dp are enumerated depth-first, 2^Dp entries per lane.
+template <class Walk, int NW, bool PRUNE, bool FLDS>
+__device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, uint32_t p0,
+                                            uint32_t B, uint32_t P, uint32_t Dp) {
+    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
+    FacRef F{c.fac, 0u};
+    if constexpr (FLDS) {
+        stage_factors(l_fac, c.fac, c.f_L, c.f_c1);
+        F = FacRef{l_fac, c.f_L};
+    }
+    const uint32_t lo_bits = c.Ap - Dp;
+    const uint64_t NL = static_cast<uint64_t>(B) << lo_bits;
+    const uint64_t lomask = (1ull << lo_bits) - 1ull;
+    const uint32_t e_split = Dp ? ld_const(c.src, lo_bits) : c.i1;
+    const Mask4 fin_c1 = ld_const(c.fin, c.c1);
+    for (uint64_t lb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; lb < NL;
+         lb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t l_raw = lb + threadIdx.x;
+        const bool live = l_raw < NL;
+        const uint64_t li = live ? l_raw : NL - 1;   // clamp so every lane reads in bounds
+        const uint64_t pl = li >> lo_bits;
+        const uint32_t p = p0 + static_cast<uint32_t>(pl);
+        Lanes<NW, 1> L;
+        uint32_t bin[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) L.s[0][w] = pre.st[static_cast<size_t>(w) * P + p];
+        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
+        const double2 a = pre.amp[p];
+        L.re[0] = a.x;
+        L.im[0] = a.y;
+        L.M[0] = pre.M[p];
+        L.ok[0] = pre.ok[p] == 1u;
+        L.hb[0] = li & lomask;
+        L.dx[0] = 0;
+        Walk::template prefix_head<NW, PRUNE>(c, F, L, bin, e_split);
+        const uint64_t ebase = pl << c.Ap;
+        const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
+        dfs_region<NW, 1, kDfsMax>(
+            lo_bits, Dp, L, 0u,
+            [&](uint32_t l, Lanes<NW, 1> &C) {
+                Walk::template prefix_seg<NW, PRUNE>(c, F, C, bin, lo_bits, Dp, l);
+            },
+            [&](Lanes<NW, 1> &C) {
+                const bool ok = C.ok[0] && check_final<NW>(C.s[0], bin, fin_c1);
+                if (live) {
+                    const uint64_t e = ebase | C.hb[0];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = C.s[0][w];
+                    tab.beta[e] = make_double2(C.re[0], C.im[0]);
+                    if (PRUNE) tab.M[e] = C.M[0];
+                    tab.ok[e] = ok ? 1u : 0u;
+                }
+            });
+    }
 }
 
 // The persistent consumer (Algorithm 2, inner loops) over a Regions policy

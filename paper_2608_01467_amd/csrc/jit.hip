@@ -106,7 +106,8 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
 
 std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
                             uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
-                            int H, bool prune, bool flds) {
+                            int H, bool prune, bool flds, bool prefix_ok, uint32_t iL,
+                            const std::vector<uint32_t> &src_dev, uint32_t Dp, bool pflds) {
     // defer the suffix's factors when nothing needs them during the walk
     // (pruning does) and their indices fit in dx
     int bits = 0;
@@ -161,6 +162,33 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
         o += buf;
     }
     o += "}\n";
+    if (prefix_ok) {
+        // the prefix region: head [iL, first depth-first source), then one
+        // straight-line case per depth-first level (sources numbered from 0)
+        const uint32_t lo_bits = Ap - Dp;
+        const uint32_t e_split = Dp ? src_dev[lo_bits] : i1;
+        o += "template <int NW, bool PRUNE>\n"
+             "__device__ static __forceinline__ void prefix_head(const Common &c, const FacRef &F, "
+             "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t) {\n"
+             "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
+             "(void)kbase; (void)thr; (void)bin;\n";
+        emit_region(o, dev, iL, e_split, false, none);
+        o += "}\n";
+        o += "template <int NW, bool PRUNE>\n"
+             "__device__ static __forceinline__ void prefix_seg(const Common &c, const FacRef &F, "
+             "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t, uint32_t, uint32_t l) {\n"
+             "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
+             "(void)kbase; (void)thr; (void)bin;\n"
+             "    switch (l) {\n";
+        for (uint32_t l = 0; l < Dp; ++l) {
+            const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;
+            std::snprintf(buf, sizeof(buf), "    case %uu: {\n", l);
+            o += buf;
+            emit_region(o, dev, a, b, false, none);
+            o += "    } break;\n";
+        }
+        o += "    default: break;\n    }\n}\n";
+    }
     o += "};\n}  // namespace\n}  // namespace fhs\n";
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ __launch_bounds__(fhs::kConsumeThreads) void "
@@ -170,6 +198,15 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "counter);\n}\n",
                   NW, H, prune ? "true" : "false", flds ? "true" : "false");
     o += buf;
+    if (prefix_ok) {
+        std::snprintf(buf, sizeof(buf),
+                      "extern \"C\" __global__ __launch_bounds__(256) void "
+                      "fhs_prefix_compiled(fhs::Common c, fhs::PreBufs pre, fhs::Table tab, uint32_t p0, "
+                      "uint32_t B, uint32_t P, uint32_t Dp) {\n"
+                      "    fhs::prefix_body<fhs::Compiled, %d, %s, %s>(c, pre, tab, p0, B, P, Dp);\n}\n",
+                      NW, prune ? "true" : "false", pflds ? "true" : "false");
+        o += buf;
+    }
     return o;
 }
 
@@ -212,6 +249,12 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
         release(out);
         return false;
     }
+    if (src.find("fhs_prefix_compiled") != std::string::npos &&
+        hipModuleGetFunction(&out.pfn, out.mod, "fhs_prefix_compiled") != hipSuccess) {
+        log += "\nhipModuleGetFunction (prefix) failed";
+        release(out);
+        return false;
+    }
     int nb = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, out.fn, kConsumeThreads, shm) !=
             hipSuccess || nb < 1)
@@ -224,6 +267,21 @@ void release(CompiledConsumer &k) {
     if (k.mod) (void)hipModuleUnload(k.mod);
     k.mod = nullptr;
     k.fn = nullptr;
+    k.pfn = nullptr;
+}
+
+hipError_t launch_prefix_compiled(const CompiledConsumer &k, const Common &c, PreBufs pre, Table tab,
+                                  uint32_t p0, uint32_t B, uint32_t Dp, size_t shm, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    if (!k.pfn || Dp > c.Ap || Dp > static_cast<uint32_t>(kDfsMax)) return hipErrorInvalidValue;
+    const uint64_t NL = static_cast<uint64_t>(B) << (c.Ap - Dp);
+    uint64_t blocks = (NL + 255) / 256;
+    if (blocks > (1u << 20)) blocks = 1u << 20;
+    Common cc = c;
+    uint32_t P = c.M * c.S;
+    void *args[] = {&cc, &pre, &tab, &p0, &B, &P, &Dp};
+    return hipModuleLaunchKernel(k.pfn, static_cast<uint32_t>(blocks), 1, 1, 256, 1, 1,
+                                 static_cast<unsigned>(shm), s, args, nullptr);
 }
 
 hipError_t launch_compiled(const CompiledConsumer &k, const Common &c, Table tab, Partials part,

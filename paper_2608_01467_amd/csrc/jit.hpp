@@ -21,7 +21,8 @@ namespace fhs {
 
 struct CompiledConsumer {
     hipModule_t mod = nullptr;
-    hipFunction_t fn = nullptr;
+    hipFunction_t fn = nullptr;    // the consumer
+    hipFunction_t pfn = nullptr;   // the prefix-table build (null: the interpreting one is used)
     int blocks_per_cu = 1;   // occupancy limit at the given dynamic LDS size
 };
 
@@ -31,15 +32,26 @@ struct CompiledConsumer {
 // regions.  Without pruning, the suffix's factor multiplications are
 // deferred to the histories that pass the final check when their table
 // indices fit in 64 bits.
+//
+// With prefix_ok, the module also holds the prefix-table build for device
+// region [iL, i1): the gates before the first depth-first source
+// src_dev[Ap - Dp], then the Dp depth-first levels (src_dev: device index of
+// every source's gate); pflds stages the prefix's factors in LDS.
 std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
                             uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
-                            int H, bool prune, bool flds);
+                            int H, bool prune, bool flds, bool prefix_ok, uint32_t iL,
+                            const std::vector<uint32_t> &src_dev, uint32_t Dp, bool pflds);
 
 // Compile `src` for gfx950 and load it on the current device.  On failure
 // returns false and puts the compiler log in `log`.
 bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out, std::string &log);
 
 void release(CompiledConsumer &k);
+
+// Launch the compiled prefix-table build (k.pfn) with the interpreting
+// one's grid: one lane per subtree, B << (Ap - Dp) lanes.
+hipError_t launch_prefix_compiled(const CompiledConsumer &k, const Common &c, PreBufs pre, Table tab,
+                                  uint32_t p0, uint32_t B, uint32_t Dp, size_t shm, hipStream_t s);
 
 hipError_t launch_compiled(const CompiledConsumer &k, const Common &c, Table tab, Partials part,
                            uint32_t p0, uint32_t B, uint32_t chunk, uint32_t ss, uint32_t *counter,

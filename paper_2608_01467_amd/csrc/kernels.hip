@@ -58,54 +58,7 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
 template <int NW, bool PRUNE, bool FLDS, bool RUNS>
 __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab, uint32_t p0,
                                                 uint32_t B, uint32_t P, uint32_t Dp) {
-    extern __shared__ __attribute__((aligned(16))) double l_fac[];  // 16-byte entries: ds_read_b128
-    FacRef F{c.fac, 0u};
-    if constexpr (FLDS) {
-        stage_factors(l_fac, c.fac, c.f_L, c.f_c1);
-        F = FacRef{l_fac, c.f_L};
-    }
-    // One lane per subtree: the lane's index fixes the first Ap - Dp prefix
-    // sources, the last Dp are enumerated depth-first; 2^Dp entries per lane.
-    const uint32_t lo_bits = c.Ap - Dp;
-    const uint64_t NL = static_cast<uint64_t>(B) << lo_bits;
-    const uint64_t lomask = (1ull << lo_bits) - 1ull;
-    const uint32_t e_split = Dp ? ld_const(c.src, lo_bits) : c.i1;
-    const Mask4 fin_c1 = ld_const(c.fin, c.c1);
-    for (uint64_t lb = static_cast<uint64_t>(blockIdx.x) * blockDim.x; lb < NL;
-         lb += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint64_t l_raw = lb + threadIdx.x;
-        const bool live = l_raw < NL;
-        const uint64_t li = live ? l_raw : NL - 1;   // clamp so every lane reads in bounds
-        const uint64_t pl = li >> lo_bits;
-        const uint32_t p = p0 + static_cast<uint32_t>(pl);
-        Lanes<NW, 1> L;
-        uint32_t bin[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) L.s[0][w] = pre.st[static_cast<size_t>(w) * P + p];
-        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
-        const double2 a = pre.amp[p];
-        L.re[0] = a.x;
-        L.im[0] = a.y;
-        L.M[0] = pre.M[p];
-        L.ok[0] = pre.ok[p] == 1u;
-        L.hb[0] = li & lomask;
-        run_region<NW, 1, PRUNE, RUNS>(c.prog, F, c.iL, e_split, L, 0, bin, c.thr);
-        const uint64_t ebase = pl << c.Ap;
-        const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
-        dfs_region<NW, 1, PRUNE, RUNS, kDfsMax>(c.prog, F, c.src, lo_bits, Dp, c.i1, L, 0u, bin,
-                                                c.thr,
-                                        [&](Lanes<NW, 1> &C) {
-            const bool ok = C.ok[0] && check_final<NW>(C.s[0], bin, fin_c1);
-            if (live) {
-                const uint64_t e = ebase | C.hb[0];
-#pragma unroll
-                for (int w = 0; w < NW; ++w) tab.st[static_cast<size_t>(w) * E + e] = C.s[0][w];
-                tab.beta[e] = make_double2(C.re[0], C.im[0]);
-                if (PRUNE) tab.M[e] = C.M[0];
-                tab.ok[e] = ok ? 1u : 0u;
-            }
-        });
-    }
+    prefix_body<Interp<RUNS>, NW, PRUNE, FLDS>(c, pre, tab, p0, B, P, Dp);
 }
 
 template <int NW, int H, bool PRUNE, bool FLDS, bool RUNS>

@@ -86,6 +86,7 @@ struct fhs_ctx {
     uint32_t *d_src = nullptr;   // [max(A,1)] device-program index of each source gate
     std::vector<uint32_t> pos2ins;   // [G+1] evaluation position -> device-program index
     std::vector<Instr> dev_ins;      // host copy of the device program
+    std::vector<uint32_t> src_dev;   // device-program index of each source's gate
     std::map<std::string, CompiledConsumer> compiled;   // consumers compiled for this program
     uint32_t c1 = 0, c2 = 0;
     size_t table_budget = size_t(1) << 30;
@@ -330,30 +331,42 @@ size_t consume_lds_bytes(const Common &cm) {
     return n <= kMaxLdsFactors ? static_cast<size_t>(n) * sizeof(double) : 0;
 }
 
+// Dynamic LDS of the prefix-table build: the prefix region's factors.
+size_t prefix_lds_bytes(const Common &cm) {
+    const uint32_t n = cm.f_c1 - cm.f_L;
+    return n <= kMaxLdsFactors ? static_cast<size_t>(n) * sizeof(double) : 0;
+}
+
 // Regions up to this many device instructions are compiled on request.
 constexpr uint32_t kMaxCompiledInstr = 1024;
 
 // The consumer compiled for the loaded program, the plan's regions and the
 // launch shape (dispatch mode 3), or nullptr when the mode is off or the
-// regions are too long; compiled once per program and cached.
-fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, const CompiledConsumer **out) {
+// regions are too long; compiled once per program and cached.  Its module
+// also holds the prefix-table build when the prefix region is short enough
+// (pfn; otherwise the interpreting k_prefix runs).
+fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, uint32_t Dp, const CompiledConsumer **out) {
     *out = nullptr;
     if (c->dispatch != 3 || c->prog.A == 0 || cm.iG - cm.i1 > kMaxCompiledInstr) return FHS_OK;
     const bool flds = cm.f_G - cm.f_c1 <= kMaxLdsFactors;
     const bool prune = cm.thr > 0.0;
+    const bool prefix_ok = cm.i1 - cm.iL <= kMaxCompiledInstr;
+    const bool pflds = cm.f_c1 - cm.f_L <= kMaxLdsFactors;
     const int NW = nw_of(c->prog);
-    char key[128];
+    char key[160];
     // the cut positions fix the final-bit masks (two cuts inside one folded
-    // ladder share device indices but not masks)
-    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1, cm.c2,
-                  cm.Ap, cm.Ar, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0);
+    // ladder share device indices but not masks); Dp fixes the prefix's
+    // depth-first levels
+    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1,
+                  cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0);
     auto it = c->compiled.find(key);
     if (it == c->compiled.end()) {
         CompiledConsumer k;
         std::string log;
         const std::string src =
             consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, c->prog.final_before[cm.c2],
-                            c->prog.final_before[cm.G], NW, c->ilp, prune, flds);
+                            c->prog.final_before[cm.G], NW, c->ilp, prune, flds, prefix_ok, cm.iL,
+                            c->src_dev, Dp, pflds);
         if (!compile_consumer(src, consume_lds_bytes(cm), k, log))
             return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
                         log.c_str());
@@ -390,7 +403,8 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         const uint64_t items = static_cast<uint64_t>(B) * pl.nchunks;
         uint32_t grid = static_cast<uint32_t>(std::max(c->num_cu, 1)) * static_cast<uint32_t>(bpc);
         if (items < grid) grid = static_cast<uint32_t>(items);
-        e = launch_prefix(cm, NW, pre, tab, p0, B, pl.Dp, s);
+        e = (ck && ck->pfn) ? launch_prefix_compiled(*ck, cm, pre, tab, p0, B, pl.Dp, prefix_lds_bytes(cm), s)
+                            : launch_prefix(cm, NW, pre, tab, p0, B, pl.Dp, s);
         if (e != hipSuccess) return e;
         if (timed) {
             // outside the timed interval: how many entries the consumer expands
@@ -481,6 +495,7 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     std::vector<uint32_t> src_dev(P.src_eval.size());
     for (size_t k = 0; k < P.src_eval.size(); ++k) src_dev[k] = c->pos2ins[P.src_eval[k]];
     c->dev_ins = dev;
+    c->src_dev = src_dev;
     const size_t ni = std::max<size_t>(dev.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
@@ -795,7 +810,7 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
         // recorded inside a captured graph carry no usable timestamps).
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
         const CompiledConsumer *ck = nullptr;
-        if ((st = compiled_consumer(c, cm, &ck)) != FHS_OK) return st;
+        if ((st = compiled_consumer(c, cm, pl.Dp, &ck)) != FHS_OK) return st;
         int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         if (timed) {
@@ -812,7 +827,7 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
         drop_graph(c);
         const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
         const CompiledConsumer *ck = nullptr;   // compiled before the capture starts
-        if ((st = compiled_consumer(c, cm, &ck)) != FHS_OK) return st;
+        if ((st = compiled_consumer(c, cm, pl.Dp, &ck)) != FHS_OK) return st;
         int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
         if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
         FHS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
