@@ -179,15 +179,17 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *                       dispatch per run of identical opcodes, 2 one per
  *                       instruction, 0 automatic (per run when the program's
  *                       runs average two or more instructions), 3 compiled:
- *                       the consumer's root and suffix regions are emitted as
+ *                       the consumer's root and suffix regions (and the
+ *                       prefix-table build's region, when it also holds at
+ *                       most 1024 device instructions) are emitted as
  *                       straight-line code and compiled for gfx950 at the
  *                       first evaluation of each program and split (hipRTC,
- *                       about a second; cached in the context) when they
- *                       hold at most 1024 device instructions (else, and
- *                       for the other kernels, the automatic rule).
- *                       fhs_evaluate returns FHS_EUNSUPPORTED, with the
- *                       compiler log in fhs_last_error, if that compilation
- *                       fails.
+ *                       about a second; cached in the context; see
+ *                       fhs_precompile) when they hold at most 1024 device
+ *                       instructions (else, and for the other kernels, the
+ *                       automatic rule).  fhs_evaluate returns
+ *                       FHS_EUNSUPPORTED, with the compiler log in
+ *                       fhs_last_error, if that compilation fails.
  * Affects speed and the grouping of the amplitude sums (so their last bits),
  * never the history counts.  FHS_EINVAL for values out of range. */
 typedef struct {
@@ -199,6 +201,22 @@ typedef struct {
 
 fhs_status fhs_set_launch_config(fhs_ctx *ctx, const fhs_launch_config *cfg);
 fhs_status fhs_get_launch_config(const fhs_ctx *ctx, fhs_launch_config *cfg);
+
+/* Compile ahead of time, under the current launch configuration (dispatch
+ * mode 3 only; otherwise nothing to do), the consumers that fhs_evaluate
+ * would compile for the n splits (c1[i], c2[i]) at M outputs, S inputs and
+ * the given threshold, so that timing many splits (autotuning, the learned
+ * split's shortlist, training data) does not pay one compilation per split
+ * in turn.  The hipRTC compilations run on `threads` host threads; the
+ * modules are loaded on ctx's device and cached in ctx (kept until the next
+ * fhs_load_program).  Splits whose plan does not fit (the table budget) or
+ * whose consumer is already cached are skipped; *n_compiled (may be NULL)
+ * receives the number compiled.  The context's partition is unchanged.
+ * FHS_EINVAL for a split outside c1 <= c2 <= G or zero M, S or threads;
+ * FHS_ESTATE without a program; FHS_EUNSUPPORTED (log in fhs_last_error) if
+ * a compilation fails. */
+fhs_status fhs_precompile(fhs_ctx *ctx, const uint32_t *c1, const uint32_t *c2, uint32_t n, uint32_t M,
+                          uint32_t S, double threshold, uint32_t threads, uint32_t *n_compiled);
 
 /* Kernel timing.  When enabled, every later evaluation records HIP events
  * around each launch of its hot kernel (the persistent consumer of

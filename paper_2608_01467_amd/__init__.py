@@ -38,7 +38,7 @@ EXPORTS = [
     "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
     "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_kernel_counts", "fhs_get_plan",
     "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
-    "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
+    "fhs_precompile", "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
     "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam",
 ]
 
@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
         L.fhs_load_cost_model.argtypes = [P, pD, ctypes.c_size_t]
         L.fhs_choose_partition_ctx.argtypes = [P, I32, U32, U32, pU32, pU32]
         L.fhs_predict_splits.argtypes = [P, U32, U32, pU32, pU32, U32, pD]
+        L.fhs_precompile.argtypes = [P, pU32, pU32, U32, U32, U32, ctypes.c_double, U32, pU32]
         pS = ctypes.POINTER(MlpShape)
         L.fhs_mlp_param_count.argtypes = [pS, ctypes.POINTER(ctypes.c_size_t)]
         L.fhs_mlp_workspace_size.argtypes = [pS, U32, ctypes.POINTER(ctypes.c_size_t)]
@@ -259,6 +260,19 @@ class Context:
                           blocks_per_cu: int = 0, dispatch: int = 0) -> None:
         cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu, dispatch)
         _check(lib().fhs_set_launch_config(self._h, ctypes.byref(cfg)), self)
+
+    def precompile(self, splits, M: int, S: int, threshold: float = 0.0, threads: int = 16) -> int:
+        """Compile the dispatch-mode-3 consumers for these splits ahead of
+        time on `threads` host threads (fhs_precompile); returns how many
+        were compiled (0 in the other dispatch modes)."""
+        splits = list(splits)
+        n = len(splits)
+        a = (ctypes.c_uint32 * max(n, 1))(*[int(c[0]) for c in splits])
+        b = (ctypes.c_uint32 * max(n, 1))(*[int(c[1]) for c in splits])
+        done = ctypes.c_uint32(0)
+        _check(lib().fhs_precompile(self._h, a, b, n, M, S, float(threshold), threads,
+                                    ctypes.byref(done)), self)
+        return done.value
 
     @property
     def launch_config(self) -> Tuple[int, int, int, int]:

@@ -210,7 +210,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
     return o;
 }
 
-bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out, std::string &log) {
+bool compile_code(const std::string &src, std::vector<char> &code, std::string &log) {
     hiprtcProgram prog = nullptr;
     const char *headers[] = {kSrcProgramHpp, kSrcKernelsHpp, kSrcDeviceHpp};
     const char *names[] = {"program.hpp", "kernels.hpp", "device.hpp"};
@@ -236,9 +236,14 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
     }
     size_t code_size = 0;
     hiprtcGetCodeSize(prog, &code_size);
-    std::vector<char> code(code_size);
+    code.resize(code_size);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
+    return true;
+}
+
+bool load_consumer(const std::vector<char> &code, bool has_prefix, size_t shm, CompiledConsumer &out,
+                   std::string &log) {
     if (hipModuleLoadData(&out.mod, code.data()) != hipSuccess) {
         log += "\nhipModuleLoadData failed";
         out.mod = nullptr;
@@ -249,8 +254,7 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
         release(out);
         return false;
     }
-    if (src.find("fhs_prefix_compiled") != std::string::npos &&
-        hipModuleGetFunction(&out.pfn, out.mod, "fhs_prefix_compiled") != hipSuccess) {
+    if (has_prefix && hipModuleGetFunction(&out.pfn, out.mod, "fhs_prefix_compiled") != hipSuccess) {
         log += "\nhipModuleGetFunction (prefix) failed";
         release(out);
         return false;
@@ -261,6 +265,12 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
         nb = 1;
     out.blocks_per_cu = nb;
     return true;
+}
+
+bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out, std::string &log) {
+    std::vector<char> code;
+    if (!compile_code(src, code, log)) return false;
+    return load_consumer(code, src.find("fhs_prefix_compiled") != std::string::npos, shm, out, log);
 }
 
 void release(CompiledConsumer &k) {

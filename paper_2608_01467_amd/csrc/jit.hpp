@@ -46,6 +46,13 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
 // returns false and puts the compiler log in `log`.
 bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out, std::string &log);
 
+// The two halves of compile_consumer: hipRTC to a code object (no HIP
+// calls; safe to run for different sources on several threads at once),
+// then the module load on the calling thread's current device.
+bool compile_code(const std::string &src, std::vector<char> &code, std::string &log);
+bool load_consumer(const std::vector<char> &code, bool has_prefix, size_t shm, CompiledConsumer &out,
+                   std::string &log);
+
 void release(CompiledConsumer &k);
 
 // Launch the compiled prefix-table build (k.pfn) with the interpreting

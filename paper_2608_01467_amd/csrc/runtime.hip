@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +19,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fhs.h"
@@ -345,29 +347,42 @@ constexpr uint32_t kMaxCompiledInstr = 1024;
 // regions are too long; compiled once per program and cached.  Its module
 // also holds the prefix-table build when the prefix region is short enough
 // (pfn; otherwise the interpreting k_prefix runs).
-fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, uint32_t Dp, const CompiledConsumer **out) {
-    *out = nullptr;
-    if (c->dispatch != 3 || c->prog.A == 0 || cm.iG - cm.i1 > kMaxCompiledInstr) return FHS_OK;
+// Cache key and source of the compiled consumer for `cm` and Dp; false when
+// dispatch mode 3 does not apply (mode off, no sources, regions too long).
+bool consumer_job(const fhs_ctx *c, const Common &cm, uint32_t Dp, std::string &key, std::string *src,
+                  size_t &shm) {
+    if (c->dispatch != 3 || c->prog.A == 0 || cm.iG - cm.i1 > kMaxCompiledInstr) return false;
     const bool flds = cm.f_G - cm.f_c1 <= kMaxLdsFactors;
     const bool prune = cm.thr > 0.0;
     const bool prefix_ok = cm.i1 - cm.iL <= kMaxCompiledInstr;
     const bool pflds = cm.f_c1 - cm.f_L <= kMaxLdsFactors;
     const int NW = nw_of(c->prog);
-    char key[160];
+    char buf[160];
     // the cut positions fix the final-bit masks (two cuts inside one folded
     // ladder share device indices but not masks); Dp fixes the prefix's
     // depth-first levels
-    std::snprintf(key, sizeof(key), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1,
+    std::snprintf(buf, sizeof(buf), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1,
                   cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0);
+    key = buf;
+    shm = consume_lds_bytes(cm);
+    if (src)
+        *src = consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, c->prog.final_before[cm.c2],
+                               c->prog.final_before[cm.G], NW, c->ilp, prune, flds, prefix_ok, cm.iL,
+                               c->src_dev, Dp, pflds);
+    return true;
+}
+
+fhs_status compiled_consumer(fhs_ctx *c, const Common &cm, uint32_t Dp, const CompiledConsumer **out) {
+    *out = nullptr;
+    std::string key, src;
+    size_t shm = 0;
+    if (!consumer_job(c, cm, Dp, key, nullptr, shm)) return FHS_OK;
     auto it = c->compiled.find(key);
     if (it == c->compiled.end()) {
+        consumer_job(c, cm, Dp, key, &src, shm);
         CompiledConsumer k;
         std::string log;
-        const std::string src =
-            consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, c->prog.final_before[cm.c2],
-                            c->prog.final_before[cm.G], NW, c->ilp, prune, flds, prefix_ok, cm.iL,
-                            c->src_dev, Dp, pflds);
-        if (!compile_consumer(src, consume_lds_bytes(cm), k, log))
+        if (!compile_consumer(src, shm, k, log))
             return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
                         log.c_str());
         it = c->compiled.emplace(key, k).first;
@@ -676,6 +691,68 @@ extern "C" fhs_status fhs_get_partition(const fhs_ctx *c, uint32_t *c1, uint32_t
     if (!c->loaded) return FHS_ESTATE;
     *c1 = c->c1;
     *c2 = c->c2;
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_precompile(fhs_ctx *c, const uint32_t *c1, const uint32_t *c2, uint32_t n,
+                                     uint32_t M, uint32_t S, double threshold, uint32_t threads,
+                                     uint32_t *n_compiled) {
+    if (!c || (n && (!c1 || !c2)) || M == 0 || S == 0 || !(threshold >= 0.0) || threads == 0)
+        return FHS_EINVAL;
+    c->err.clear();
+    if (!c->loaded) return fail(c, FHS_ESTATE, "no program loaded");
+    for (uint32_t i = 0; i < n; ++i)
+        if (c1[i] > c2[i] || c2[i] > static_cast<uint32_t>(c->prog.G))
+            return fail(c, FHS_EINVAL, "split %u: need c1 <= c2 <= G", i);
+    struct Job {
+        std::string key, src, log;
+        size_t shm = 0;
+        std::vector<char> code;
+        bool ok = false;
+    };
+    std::vector<Job> jobs;
+    const uint32_t s1 = c->c1, s2 = c->c2;
+    for (uint32_t i = 0; i < n; ++i) {
+        c->c1 = c1[i];
+        c->c2 = c2[i];
+        Plan pl;
+        if (make_plan(c, M, S, pl) != FHS_OK) continue;   // not evaluable at this size: nothing to compile
+        const Common cm = make_common(c, pl, nullptr, S, nullptr, M, threshold);
+        Job j;
+        if (!consumer_job(c, cm, pl.Dp, j.key, nullptr, j.shm) || c->compiled.count(j.key)) continue;
+        bool dup = false;
+        for (const Job &o : jobs) dup = dup || o.key == j.key;
+        if (dup) continue;
+        consumer_job(c, cm, pl.Dp, j.key, &j.src, j.shm);
+        jobs.push_back(std::move(j));
+    }
+    c->c1 = s1;
+    c->c2 = s2;
+    c->err.clear();
+    // hipRTC on a pool of host threads (no HIP calls there), modules loaded here
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t i; (i = next.fetch_add(1)) < jobs.size();)
+            jobs[i].ok = compile_code(jobs[i].src, jobs[i].code, jobs[i].log);
+    };
+    std::vector<std::thread> pool;
+    const size_t nt = std::min<size_t>(threads, jobs.size());
+    for (size_t t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool) t.join();
+    FHS_HIP(c, hipSetDevice(c->device));
+    uint32_t done = 0;
+    for (Job &j : jobs) {
+        if (!j.ok)
+            return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
+                        j.log.c_str());
+        CompiledConsumer k;
+        if (!load_consumer(j.code, j.src.find("fhs_prefix_compiled") != std::string::npos, j.shm, k, j.log))
+            return fail(c, FHS_EUNSUPPORTED, "loading the compiled consumer failed: %.400s", j.log.c_str());
+        c->compiled.emplace(j.key, k);
+        ++done;
+    }
+    if (n_compiled) *n_compiled = done;
     return FHS_OK;
 }
 

@@ -93,7 +93,8 @@ def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False,
 def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int, int], List]:
     """Sweep histories per lane x chunk x blocks per CU (automatic dispatch),
     then the explicit dispatch modes (per run, per instruction, compiled) at
-    the best shape; keep the fastest."""
+    the best shape, then histories per lane x chunk for the compiled
+    consumer; keep the fastest."""
     log = []
     best, best_t = None, math.inf
     for h in (1, 2):
@@ -112,6 +113,18 @@ def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, 
         log.append((cfg, t))
         if t < best_t:
             best, best_t = cfg, t
+    # the compiled consumer's own best lane shape and chunk
+    done = {cfg for cfg, _ in log}
+    for h in (1, 2):
+        for chunk in (128, 256):
+            cfg = (h, chunk, best[2], 3)
+            if cfg in done:
+                continue
+            wl.ctx.set_launch_config(*cfg)
+            t = time_split(wl, partition, reps)
+            log.append((cfg, t))
+            if t < best_t:
+                best, best_t = cfg, t
     wl.ctx.set_launch_config(*best)
     return best, log
 
@@ -142,6 +155,9 @@ def candidates(wl: Workload, max_cost_ratio: float = 64.0, extra: int = 8,
     return keep
 
 
+PRECOMPILE_BATCH = 32   # splits whose compiled consumers are built together
+
+
 def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2, log=None,
                slow_factor: float = 8.0, budget: Optional[float] = None):
     """Time every split (in the given order, best guesses first); returns
@@ -152,11 +168,16 @@ def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2, l
     rows = []
     t0 = time.perf_counter()
     best = math.inf
+    splits = list(splits)
+    compiled = wl.ctx.launch_config[3] == 3
     for i, c in enumerate(splits):
         if budget is not None and rows and time.perf_counter() - t0 > budget:
             if log is not None:
                 log(f"  budget reached: {len(rows)}/{len(splits)} splits timed")
             break
+        if compiled and i % PRECOMPILE_BATCH == 0:
+            # compile the next batch's consumers in parallel, not one per timing
+            wl.ctx.precompile(splits[i:i + PRECOMPILE_BATCH], wl.M, wl.S, wl.thr)
         t = time_split(wl, c, reps, cutoff=slow_factor * best if best < math.inf else None)
         rows.append((c, t))
         best = min(best, t)

@@ -128,7 +128,10 @@ def test_autotune_launch(ctx):
     wl = tune.Workload(ctx, text, [0], [1.0], outs, thr)
     part = wl.prog.choose_partition(fhs.PART_EQ8)
     best, log = tune.autotune_launch(wl, part, reps=1)
-    assert len(log) == 21 and best in [c for c, _ in log]
+    # 18 automatic-dispatch shapes, 3 dispatch modes, then the compiled
+    # consumer's histories-per-lane x chunk (one may repeat an earlier entry)
+    cfgs = [c for c, _ in log]
+    assert len(log) in (24, 25) and len(set(cfgs)) == len(cfgs) and best in cfgs
     assert ctx.launch_config == best
     ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
     wl.run(part)
@@ -158,3 +161,29 @@ def test_literal_aa16_split_choice(ctx):
     with pytest.raises(fhs.FhsError) as e:
         ctx.choose_partition(fhs.PART_MODEL, 64, 1)
     assert e.value.status == 3
+
+
+def test_precompile(ctx):
+    """fhs_precompile builds the compiled consumers of many splits on host
+    threads; the evaluations then use them (and still match the oracle)."""
+    name, text, outs, thr = _cases()[1]
+    prog = fhs.Program(text)
+    ctx.load(prog)
+    cand = prog.candidate_splits()[:12]
+    ctx.set_launch_config(1, 0, 0, 0)
+    assert ctx.precompile(cand, len(outs), 1, thr) == 0          # not compiled mode: nothing to do
+    ctx.set_launch_config(1, 0, 0, 3)
+    n = ctx.precompile(cand, len(outs), 1, thr, threads=8)
+    assert 1 <= n <= len(cand)
+    assert ctx.precompile(cand, len(outs), 1, thr) == 0          # all cached now
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    for c in cand[:4]:
+        ctx.set_partition(*c)
+        amps, st = ctx.evaluate([0], [1], outs, threshold=thr)
+        torch.cuda.synchronize()
+        a = amps.cpu().numpy()
+        assert np.abs(a[:, 0] + 1j * a[:, 1] - ref[0]).max() <= 1e-12, c
+        assert np.array_equal(st.cpu().numpy().view(np.uint64)[:, :3], ref[1][:, :3].astype(np.uint64))
+    with pytest.raises(fhs.FhsError):
+        ctx.precompile([(5, 2)], len(outs), 1, thr)
+    ctx.set_launch_config(0, 0, 0, 0)
