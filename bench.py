@@ -156,13 +156,19 @@ def main() -> int:
     how = args.partition
     t_setup = time.perf_counter()
     blob = None
+    model_launch = None
     if args.cuts:
         part = tuple(int(v) for v in args.cuts.split(","))
         how = "fixed"
     elif args.partition == "model":
-        blob = tune.load_model(args.cost_model) if args.cost_model else tune.load_model()
+        model_path = args.cost_model or tune.MODEL_PATH
+        blob = tune.load_model(model_path)
         # the model's three best predictions and the Eq. (8) optimum, timed
-        # once each on this workload (or every candidate without a model)
+        # once each on this workload under the launch configuration the
+        # model was trained under (or every candidate without a model)
+        model_launch = tune.model_launch(model_path)
+        if model_launch is not None and prog.A > 0:
+            ctx.set_launch_config(*model_launch)
         part, how = tune.choose(wl, blob, reps=1, shortlist=3) if blob is not None else \
             (part_eq8, "eq8 (no cost model)")
     else:
@@ -179,9 +185,9 @@ def main() -> int:
         launch, _ = tune.autotune_launch(sub, part, reps=2)
         ctx.load(prog)
         del sub
-        if launch[3] != 0 and args.partition == "model" and not args.cuts and blob is not None:
-            # the shortlist again under the chosen dispatch mode (the model was
-            # trained on interpreted timings)
+        if (args.partition == "model" and not args.cuts and blob is not None
+                and launch != model_launch):
+            # the shortlist again under the tuned launch configuration
             part, how = tune.choose(wl, blob, reps=1, shortlist=3)
     t_setup = time.perf_counter() - t_setup
     ctx.set_partition(*part)

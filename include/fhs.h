@@ -207,9 +207,12 @@ fhs_status fhs_get_launch_config(const fhs_ctx *ctx, fhs_launch_config *cfg);
  * would compile for the n splits (c1[i], c2[i]) at M outputs, S inputs and
  * the given threshold, so that timing many splits (autotuning, the learned
  * split's shortlist, training data) does not pay one compilation per split
- * in turn.  The hipRTC compilations run on `threads` host threads; the
- * modules are loaded on ctx's device and cached in ctx (kept until the next
- * fhs_load_program).  Splits whose plan does not fit (the table budget) or
+ * in turn.  hipRTC serialises compilations inside a process, so they run
+ * in up to `threads` child processes of the helper fhs_rtc built next to the
+ * library (started with posix_spawn, descriptors from 3 up closed; they make
+ * no HIP call), or one at a time in this process when the helper is absent
+ * or threads is 1; the modules are loaded on ctx's device and cached in ctx
+ * (kept until the next fhs_load_program).  Splits whose plan does not fit (the table budget) or
  * whose consumer is already cached are skipped; *n_compiled (may be NULL)
  * receives the number compiled.  The context's partition is unchanged.
  * FHS_EINVAL for a split outside c1 <= c2 <= G or zero M, S or threads;

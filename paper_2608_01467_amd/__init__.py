@@ -263,8 +263,8 @@ class Context:
 
     def precompile(self, splits, M: int, S: int, threshold: float = 0.0, threads: int = 16) -> int:
         """Compile the dispatch-mode-3 consumers for these splits ahead of
-        time on `threads` host threads (fhs_precompile); returns how many
-        were compiled (0 in the other dispatch modes)."""
+        time in up to `threads` helper processes (fhs_precompile); returns
+        how many were compiled (0 in the other dispatch modes)."""
         splits = list(splits)
         n = len(splits)
         a = (ctypes.c_uint32 * max(n, 1))(*[int(c[0]) for c in splits])

@@ -14,6 +14,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfhs.so")
+RTC = os.path.join(HERE, "fhs_rtc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -72,6 +73,14 @@ def build(verbose: bool = False) -> str:
         out = LIB + f".tmp{os.getpid()}"
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs + ["-lhiprtc"])
         os.replace(out, LIB)
+        # fhs_rtc: one hipRTC compilation per process (fhs_precompile runs
+        # several at once), linked against the library next to it
+        w = os.path.join(tmp, "rtc_worker.o")
+        _run([HIPCC] + HIP_FLAGS + ["-I" + tmp, "-c", os.path.join(CSRC, "rtc_worker.cpp"), "-o", w])
+        out = RTC + f".tmp{os.getpid()}"
+        _run([HIPCC, "--offload-arch=gfx950", "-o", out, w, "-L" + HERE, "-lfhs", "-lhiprtc",
+              "-Wl,-rpath,$ORIGIN"])
+        os.replace(out, RTC)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if verbose:

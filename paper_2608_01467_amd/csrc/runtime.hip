@@ -7,19 +7,24 @@
 // counter: the persistent consumer pops (pair, prefix-chunk) work items until
 // the counter passes the item count.  The launch sequence of one evaluation
 // is captured once into a HIP graph and replayed while its arguments repeat.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
+#include <spawn.h>
+#include <sys/wait.h>
+#include <unistd.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <iterator>
 #include <limits>
 #include <map>
 #include <new>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "../../include/fhs.h"
@@ -694,6 +699,98 @@ extern "C" fhs_status fhs_get_partition(const fhs_ctx *c, uint32_t *c1, uint32_t
     return FHS_OK;
 }
 
+namespace {
+
+// One consumer to compile ahead of time.
+struct CompileJob {
+    std::string key, src, log;
+    size_t shm = 0;
+    std::vector<char> code;
+    bool ok = false;
+};
+
+// Directory of this library: the fhs_rtc helper is built next to it.
+std::string library_dir() {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void *>(&library_dir), &info) && info.dli_fname) {
+        const std::string p(info.dli_fname);
+        const size_t k = p.rfind('/');
+        if (k != std::string::npos) return p.substr(0, k);
+    }
+    return ".";
+}
+
+bool read_file(const std::string &path, std::vector<char> &out) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    out.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+    return true;
+}
+
+// Compile the jobs with up to `procs` fhs_rtc child processes at a time
+// (hipRTC serialises compilations inside one process).  The children are
+// started with posix_spawn, every descriptor from 3 up closed, and never
+// touch the GPU.  Returns false, having compiled nothing, when the helper
+// or a temporary directory is not available.
+bool compile_in_processes(std::vector<CompileJob> &jobs, uint32_t procs) {
+    const std::string helper = library_dir() + "/fhs_rtc";
+    if (access(helper.c_str(), X_OK) != 0) return false;
+    const char *t = std::getenv("TMPDIR");
+    std::string tmpl = std::string(t && *t ? t : "/tmp") + "/fhs_rtc_XXXXXX";
+    std::vector<char> dirbuf(tmpl.begin(), tmpl.end());
+    dirbuf.push_back('\0');
+    if (!mkdtemp(dirbuf.data())) return false;
+    const std::string dir(dirbuf.data());
+    auto path = [&](size_t i, const char *ext) { return dir + "/" + std::to_string(i) + ext; };
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        std::ofstream f(path(i, ".hip"), std::ios::binary);
+        f << jobs[i].src;
+    }
+    posix_spawn_file_actions_t fa;
+    posix_spawn_file_actions_init(&fa);
+    posix_spawn_file_actions_addclosefrom_np(&fa, 3);
+    std::vector<std::pair<pid_t, size_t>> running;
+    size_t next = 0;
+    while (next < jobs.size() || !running.empty()) {
+        while (next < jobs.size() && running.size() < procs) {
+            const std::string src = path(next, ".hip"), out = path(next, ".co"), log = path(next, ".log");
+            char *argv[] = {const_cast<char *>(helper.c_str()), const_cast<char *>(src.c_str()),
+                            const_cast<char *>(out.c_str()), const_cast<char *>(log.c_str()), nullptr};
+            pid_t pid = 0;
+            if (posix_spawn(&pid, helper.c_str(), &fa, nullptr, argv, environ) == 0)
+                running.emplace_back(pid, next);
+            else
+                jobs[next].ok = compile_code(jobs[next].src, jobs[next].code, jobs[next].log);
+            ++next;
+        }
+        bool reaped = false;
+        for (size_t r = 0; r < running.size();) {
+            int status = 0;
+            const pid_t w = waitpid(running[r].first, &status, WNOHANG);
+            if (w == 0) {
+                ++r;
+                continue;
+            }
+            CompileJob &j = jobs[running[r].second];
+            std::vector<char> lg;
+            if (read_file(path(running[r].second, ".log"), lg)) j.log.assign(lg.begin(), lg.end());
+            j.ok = w > 0 && WIFEXITED(status) && WEXITSTATUS(status) == 0 &&
+                   read_file(path(running[r].second, ".co"), j.code) && !j.code.empty();
+            if (!j.ok && j.log.empty()) j.log = "fhs_rtc failed";
+            running.erase(running.begin() + static_cast<long>(r));
+            reaped = true;
+        }
+        if (!reaped && !running.empty()) usleep(2000);
+    }
+    posix_spawn_file_actions_destroy(&fa);
+    for (size_t i = 0; i < jobs.size(); ++i)
+        for (const char *ext : {".hip", ".co", ".log"}) std::remove(path(i, ext).c_str());
+    rmdir(dir.c_str());
+    return true;
+}
+
+}  // namespace
+
 extern "C" fhs_status fhs_precompile(fhs_ctx *c, const uint32_t *c1, const uint32_t *c2, uint32_t n,
                                      uint32_t M, uint32_t S, double threshold, uint32_t threads,
                                      uint32_t *n_compiled) {
@@ -704,13 +801,7 @@ extern "C" fhs_status fhs_precompile(fhs_ctx *c, const uint32_t *c1, const uint3
     for (uint32_t i = 0; i < n; ++i)
         if (c1[i] > c2[i] || c2[i] > static_cast<uint32_t>(c->prog.G))
             return fail(c, FHS_EINVAL, "split %u: need c1 <= c2 <= G", i);
-    struct Job {
-        std::string key, src, log;
-        size_t shm = 0;
-        std::vector<char> code;
-        bool ok = false;
-    };
-    std::vector<Job> jobs;
+    std::vector<CompileJob> jobs;
     const uint32_t s1 = c->c1, s2 = c->c2;
     for (uint32_t i = 0; i < n; ++i) {
         c->c1 = c1[i];
@@ -718,10 +809,10 @@ extern "C" fhs_status fhs_precompile(fhs_ctx *c, const uint32_t *c1, const uint3
         Plan pl;
         if (make_plan(c, M, S, pl) != FHS_OK) continue;   // not evaluable at this size: nothing to compile
         const Common cm = make_common(c, pl, nullptr, S, nullptr, M, threshold);
-        Job j;
+        CompileJob j;
         if (!consumer_job(c, cm, pl.Dp, j.key, nullptr, j.shm) || c->compiled.count(j.key)) continue;
         bool dup = false;
-        for (const Job &o : jobs) dup = dup || o.key == j.key;
+        for (const CompileJob &o : jobs) dup = dup || o.key == j.key;
         if (dup) continue;
         consumer_job(c, cm, pl.Dp, j.key, &j.src, j.shm);
         jobs.push_back(std::move(j));
@@ -729,20 +820,11 @@ extern "C" fhs_status fhs_precompile(fhs_ctx *c, const uint32_t *c1, const uint3
     c->c1 = s1;
     c->c2 = s2;
     c->err.clear();
-    // hipRTC on a pool of host threads (no HIP calls there), modules loaded here
-    std::atomic<size_t> next{0};
-    auto work = [&]() {
-        for (size_t i; (i = next.fetch_add(1)) < jobs.size();)
-            jobs[i].ok = compile_code(jobs[i].src, jobs[i].code, jobs[i].log);
-    };
-    std::vector<std::thread> pool;
-    const size_t nt = std::min<size_t>(threads, jobs.size());
-    for (size_t t = 1; t < nt; ++t) pool.emplace_back(work);
-    work();
-    for (std::thread &t : pool) t.join();
+    if (jobs.empty() || threads < 2 || !compile_in_processes(jobs, threads))
+        for (CompileJob &j : jobs) j.ok = compile_code(j.src, j.code, j.log);
     FHS_HIP(c, hipSetDevice(c->device));
     uint32_t done = 0;
-    for (Job &j : jobs) {
+    for (CompileJob &j : jobs) {
         if (!j.ok)
             return fail(c, FHS_EUNSUPPORTED, "run-time compilation of the consumer failed: %.400s",
                         j.log.c_str());

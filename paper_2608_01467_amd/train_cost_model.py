@@ -6,7 +6,9 @@ Times every candidate split near the Eq. (8) optimum (plus a few far ones)
 on a set of training circuits drawn from the paper's families, with output
 counts sized so that one evaluation is about 2e11 algorithmic int32 ops, trains the network on the device, writes
 paper_2608_01467_amd/cost_model.json and a JSON report of the data and of the
-regret on held-out circuits (exhaustive best vs model vs Eq. (8)).
+regret on held-out circuits (exhaustive best vs model vs Eq. (8)).  Every
+split is timed under one launch configuration (--launch; by default the
+compiled consumer, whose modules are built in batches on host threads).
 """
 from __future__ import annotations
 
@@ -127,9 +129,13 @@ def main() -> int:
                     help="seconds of exhaustive timing per held-out circuit (cheapest Eq. (8) first)")
     ap.add_argument("--evaluate", default=None,
                     help="skip training: measure the held-out regret of this saved model")
+    ap.add_argument("--launch", default="1,256,0,3",
+                    help="launch configuration every split is timed under: histories per lane, "
+                         "chunk, blocks per CU, dispatch (3: the compiled consumer)")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     ctx = Context(0)
+    ctx.set_launch_config(*(int(v) for v in args.launch.split(",")))
     report = {"train": [], "held_out": []}
     if args.evaluate:
         blob = tune.load_model(args.evaluate)
@@ -171,6 +177,7 @@ def main() -> int:
     blob, loss = tune.train(X, y, epochs=args.epochs, lr=3e-3)
     print(f"trained on {len(y)} rows, loss {loss:.4f}", flush=True)
     tune.save_model(blob, {"rows": int(len(y)), "loss": loss, "epochs": args.epochs,
+                           "launch": args.launch,
                            "train": [[n, kw] for n, kw in TRAIN[: args.cases]]},
                     path=args.model_out)
     in_sample(blob, X, y, case, report)

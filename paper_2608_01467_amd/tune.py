@@ -283,6 +283,18 @@ def load_model(path: str = MODEL_PATH) -> Optional[np.ndarray]:
     return blob
 
 
+def model_launch(path: str = MODEL_PATH) -> Optional[Tuple[int, int, int, int]]:
+    """The launch configuration the saved model's timings were taken under
+    (None if the file does not record one)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        meta = json.load(f).get("meta", {})
+    if "launch" not in meta:
+        return None
+    return tuple(int(v) for v in str(meta["launch"]).split(","))
+
+
 def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
            budget: Optional[float] = None, shortlist: int = 0) -> Tuple[Tuple[int, int], str]:
     """The split to run.  With a model whose training range covers the

@@ -169,6 +169,9 @@ def test_learned_split_gains_over_eq8(dev):
     c = w.random_clifford_t(16, 80, seed=13)
     outs = w.random_outputs(16, 8192, seed=80)
     ctx = fhs.Context(0)
+    launch = tune.model_launch()
+    if launch is not None:
+        ctx.set_launch_config(*launch)      # the configuration the model was trained under
     wl = tune.Workload(ctx, c.to_text(), [0], [1.0], outs)
     eq8 = wl.prog.choose_partition(fhs.PART_EQ8)
     model, how = tune.choose(wl, blob, reps=2)
