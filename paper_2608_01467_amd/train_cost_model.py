@@ -74,6 +74,8 @@ TRAIN = [
     ("qaoa", dict(nv=14, p=1)), ("qaoa", dict(nv=8, p=3)), ("qaoa", dict(nv=6, p=3)),
     ("aa", dict(k=6, s=2)), ("clifford_t", dict(n=20, g=100, seed=7)),
     ("clifford_t", dict(n=12, g=60, seed=9)),
+    ("clifford_t", dict(n=18, g=90, seed=21)), ("clifford_t", dict(n=22, g=110, seed=22)),
+    ("clifford_t", dict(n=14, g=70, seed=23)), ("qaoa", dict(nv=12, p=2, gseed=31, aseed=32)),
 ]
 HELD_OUT = [
     ("walk", dict(n_pos=99, steps=20)), ("qaoa", dict(nv=12, p=2)), ("aa", dict(k=4, s=3)),
@@ -129,6 +131,8 @@ def main() -> int:
                     help="seconds of exhaustive timing per held-out circuit (cheapest Eq. (8) first)")
     ap.add_argument("--evaluate", default=None,
                     help="skip training: measure the held-out regret of this saved model")
+    ap.add_argument("--no-held-out", action="store_true",
+                    help="train and save only (measure the regret later with --evaluate)")
     ap.add_argument("--launch", default="1,256,0,3",
                     help="launch configuration every split is timed under: histories per lane, "
                          "chunk, blocks per CU, dispatch (3: the compiled consumer)")
@@ -181,7 +185,8 @@ def main() -> int:
                            "train": [[n, kw] for n, kw in TRAIN[: args.cases]]},
                     path=args.model_out)
     in_sample(blob, X, y, case, report)
-    held_out(ctx, blob, args, report)
+    if not args.no_held_out:
+        held_out(ctx, blob, args, report)
     with open(os.path.join(args.out, "report.json"), "w") as f:
         json.dump(report, f, indent=1, default=str)
     return 0
