@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 METRIC = "histories/s & amplitudes/s, batched+learned vs plain, 1 MI355X, |err|≤1e-12"
 
 # MI355X peaks (AMD published figures; see the design doc for the derivations)
+SHORTLIST = 5                # the learned split: model predictions timed before the run
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 # 32-bit integer VALU ops/s: simple ops (add, xor, and, or, shifts, compares,
 # selects) issue at the FP32 vector rate, 128 lanes per cycle per CU
@@ -163,13 +164,13 @@ def main() -> int:
     elif args.partition == "model":
         model_path = args.cost_model or tune.MODEL_PATH
         blob = tune.load_model(model_path)
-        # the model's three best predictions and the Eq. (8) optimum, timed
-        # once each on this workload under the launch configuration the
-        # model was trained under (or every candidate without a model)
+        # the model's five best predictions and the Eq. (8) optimum, each
+        # timed (best of 3) on this workload under the launch configuration
+        # the model was trained under (or every candidate without a model)
         model_launch = tune.model_launch(model_path)
         if model_launch is not None and prog.A > 0:
             ctx.set_launch_config(*model_launch)
-        part, how = tune.choose(wl, blob, reps=1, shortlist=3) if blob is not None else \
+        part, how = tune.choose(wl, blob, reps=3, shortlist=SHORTLIST) if blob is not None else \
             (part_eq8, "eq8 (no cost model)")
     else:
         mode = {"eq8": fhs.PART_EQ8, "thirds": fhs.PART_THIRDS, "none": fhs.PART_NONE}
@@ -188,7 +189,7 @@ def main() -> int:
         if (args.partition == "model" and not args.cuts and blob is not None
                 and launch != model_launch):
             # the shortlist again under the tuned launch configuration
-            part, how = tune.choose(wl, blob, reps=1, shortlist=3)
+            part, how = tune.choose(wl, blob, reps=3, shortlist=SHORTLIST)
     t_setup = time.perf_counter() - t_setup
     ctx.set_partition(*part)
     d_in, d_out, d_cf = wl.d_in, wl.d_out, wl.d_cf

@@ -51,7 +51,7 @@ def main() -> int:
     for t in (float(x) for x in args.thresholds.split(",")):
         wl = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
                            cfg["outputs"], threshold=t)
-        split, how = tune.choose(wl, tune.load_model(), reps=1, shortlist=3)
+        split, how = tune.choose(wl, tune.load_model(), reps=1, shortlist=5)
         sec = tune.time_split(wl, split, reps=args.reps)
         wl.run(split)
         torch.cuda.synchronize()

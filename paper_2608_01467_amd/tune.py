@@ -325,7 +325,7 @@ def choose(wl: Workload, blob: Optional[np.ndarray], reps: int = 2, log=None,
 
 
 def regret(wl: Workload, blob: np.ndarray, splits, reps: int = 2, log=None,
-           shortlist: int = 3, budget: Optional[float] = None) -> Dict:
+           shortlist: int = 5, budget: Optional[float] = None) -> Dict:
     """Time the model's choice, the model's shortlist verified by timing,
     Eq. (8)'s choice and the exhaustive best.  The best time is the minimum
     over every timing taken, so that a regret is never negative."""
