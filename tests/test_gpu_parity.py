@@ -397,3 +397,61 @@ def test_errors(ctx):
     with pytest.raises(fhs.FhsError) as ei:
         fresh.set_partition(0, 0)
     assert ei.value.status == 6
+
+
+def _phase_heavy(n_cp: int, seed: int):
+    """6 qubits: a Hadamard on every wire, then n_cp random controlled-phase
+    gates (a factor table of 8 doubles per gate) with six more Hadamards
+    (artificial sources) spread through them, so that the regions' factors
+    exceed what the kernels stage in LDS while their instructions stay short
+    enough to be compiled."""
+    rng = np.random.default_rng(seed)
+    c = w.Circuit(6)
+    for q in range(6):
+        c.add("H", q)
+    hs = {k * n_cp // 7: k - 1 for k in range(1, 7)}
+    for i in range(n_cp):
+        if i in hs:
+            c.add("H", hs[i])
+        a, b = (int(x) for x in rng.choice(6, size=2, replace=False))
+        c.add("CP", a, b, angle=float(rng.uniform(-np.pi, np.pi)))
+    return c
+
+
+@pytest.mark.parametrize("family", ["clifford_t", "qaoa", "qaoa_pruned", "aa", "phase_heavy"])
+def test_compiled_consumer_families(ctx, family):
+    """The run-time compiled consumer and prefix build (dispatch mode 3, one
+    and two histories per lane) against the oracle on each circuit family,
+    at several splits: deferred suffix factors without pruning, factors as
+    the walk goes with it, and factors read from HBM when the suffix's table
+    is too large for LDS."""
+    thr = 0.0
+    if family == "clifford_t":
+        c = w.random_clifford_t(10, 60, seed=31)
+        outs = list(range(0, 1024, 17))
+    elif family in ("qaoa", "qaoa_pruned"):
+        c = w.qaoa_maxcut(8, 2, 41, 42)[0]
+        outs = list(range(0, 256, 5))
+        thr = 1e-3 if family == "qaoa_pruned" else 0.0
+    elif family == "aa":
+        c, _ = w.amplitude_amplification(3, 3)
+        outs = list(range(0, 1 << c.n, max(1, (1 << c.n) // 48)))
+    else:
+        c = _phase_heavy(600, 51)
+        outs = list(range(64))
+    t = c.to_text()
+    o = oracle.Feynman(t)
+    ref = o.evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    prog = fhs.Program(t)
+    parts = [prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
+             (0, prog.G)]
+    src = prog.source_eval_positions
+    if len(src) >= 2:
+        parts.append((src[0] + 1, src[-1] + 1))
+    for h in (1, 2):
+        ctx.set_launch_config(h, 0, 0, 3)
+        for part in parts:
+            amps, st = gpu_eval(ctx, t, [0], [1], outs, thr=thr, partition=part, prog=prog)
+            assert np.abs(amps - ref[0]).max() <= TOL, (family, h, part)
+            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (family, h, part)
+    ctx.set_launch_config(0, 0, 0, 0)
