@@ -47,6 +47,9 @@ def main() -> int:
     text = cfg["circuit"].to_text()
     ctx = Context(0)
     ctx.set_table_budget(32 << 30)
+    launch = tune.model_launch()
+    if launch is not None:
+        ctx.set_launch_config(*launch)     # the configuration the cost model was trained under
     base = None
     for t in (float(x) for x in args.thresholds.split(",")):
         wl = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
@@ -64,6 +67,7 @@ def main() -> int:
         n0, nt = float(np.sum(np.abs(a0) ** 2)), float(np.sum(np.abs(amp) ** 2))
         fid = 0.0 if nt == 0.0 else float(abs(np.vdot(a0, amp)) ** 2 / (n0 * nt))
         print(json.dumps({"workload": args.workload, "threshold": t, "split": list(split),
+                          "launch_config": list(ctx.launch_config),
                           "split_mode": how, "ms_per_eval": sec * 1e3, "fidelity": fid,
                           "retained_norm": nt / n0 if n0 else 0.0, "norm": nt,
                           "valid_histories": valid, "kept_fraction": valid / v0 if v0 else 0.0,
