@@ -33,20 +33,78 @@ int factor_bits(int base) {
     }
 }
 
+// The state bits an instruction reads or writes.
+void touched_bits(const Instr &I, uint32_t (&m)[4]) {
+    const int base = op_base(I.hdr & 0xffu);
+    const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+    for (int w = 0; w < 4; ++w) m[w] = 0;
+    auto bit = [&](uint32_t q) {
+        if (q < 128) m[q >> 5] |= 1u << (q & 31);
+    };
+    auto controls = [&]() {
+        for (int w = 0; w < 4; ++w) m[w] |= I.cm[w];
+    };
+    switch (base) {
+        case OP_PERM: bit(a); controls(); break;
+        case OP_SWAP: bit(a); bit(b); controls(); break;
+        case OP_DET1:
+        case OP_DIAG1:
+        case OP_BRANCH_SRC:
+        case OP_BRANCH_NAT: bit(a); break;
+        case OP_DIAG2: bit(a); bit(b); break;
+        case OP_MCPHASE: controls(); break;
+        case OP_ADDSEL: bit(I.k); [[fallthrough]];
+        case OP_ADD:
+            controls();
+            for (uint32_t q = a; q < a + b; ++q) bit(q);
+            break;
+        default: break;
+    }
+}
+
 // One block per instruction: the instruction as a constant and the call of
 // its backward step with the word indices its opcode carries (wsel maps them
 // onto the state registers as the interpreter's dispatch does).  With
 // `defer`, factor ops record their table index in dx instead of multiplying
-// (the offsets are appended to `deferred`).
+// (the offsets are appended to `deferred`).  Folded and paired ladders on one
+// field accumulate in the region's pk counters and are added to the field
+// before the next instruction that touches it and at the region's end.
 void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi, bool defer,
                  std::vector<Deferred> &deferred) {
     char buf[512];
     int off = 0;
+    bool pending = false;
+    uint32_t plo = 0, phi = 0;
+    auto flush = [&]() {
+        if (!pending) return;
+        std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk);\n", plo, phi);
+        o += buf;
+        pending = false;
+    };
     for (uint32_t x = lo; x < hi; ++x) {
         const Instr &I = dev[x];
         const uint32_t op = I.hdr & 0xffu;
         const int base = op_base(op);
         const int w1 = static_cast<int>((op >> 4) & 3u), w2 = static_cast<int>((op >> 6) & 3u);
+        const bool is_add = base == OP_ADD || base == OP_ADDSEL;
+        const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+        if (pending) {
+            uint32_t m[4];
+            touched_bits(I, m);
+            bool hit = false;
+            for (uint32_t q = plo; q < phi && !hit; ++q) {
+                // an add on the pending field itself only reads its controls
+                // and selector, which lie outside the field
+                if (is_add && a == plo && a + b == phi && q >= a && q < a + b) {
+                    uint32_t c[4] = {I.cm[0], I.cm[1], I.cm[2], I.cm[3]};
+                    if (base == OP_ADDSEL && I.k < 128) c[I.k >> 5] |= 1u << (I.k & 31);
+                    hit = (c[q >> 5] >> (q & 31)) & 1u;
+                } else {
+                    hit = (m[q >> 5] >> (q & 31)) & 1u;
+                }
+            }
+            if (hit || (is_add && (a != plo || a + b != phi))) flush();
+        }
         std::snprintf(buf, sizeof(buf),
                       "    { constexpr Instr I{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu, "
                       "{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}, {0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}}; ",
@@ -88,18 +146,24 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
                 std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
                 break;
             case OP_ADD:
-                std::snprintf(call, sizeof(call), "op_add<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
+                std::snprintf(call, sizeof(call), "pend_add<NW, H, wsel<%d, NW>()>(L, I, pk); }\n", w1);
                 break;
             case OP_ADDSEL:
                 std::snprintf(call, sizeof(call),
-                              "op_addsel<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
+                              "pend_addsel<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I, pk); }\n", w1, w2);
                 break;
             default:
                 std::snprintf(call, sizeof(call), "(void)I; }\n");
                 break;
         }
         o += call;
+        if (is_add) {
+            pending = true;
+            plo = a;
+            phi = a + b;
+        }
     }
+    flush();
 }
 
 }  // namespace
@@ -136,7 +200,8 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "template <int NW, int H, bool PRUNE>\n"
                   "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
-                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n",
+                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
+                  "    int32_t pk[H] = {}; (void)pk;\n",
                   Ap);
     o += buf;
     emit_region(o, dev, i1, i2, false, none);
@@ -145,7 +210,8 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "template <int NW, int H, bool PRUNE>\n"
                   "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
-                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n",
+                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
+                  "    int32_t pk[H] = {}; (void)pk;\n",
                   Ap + Ar);
     o += buf;
     emit_region(o, dev, i2, iG, defer, deferred);
@@ -171,7 +237,8 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
              "__device__ static __forceinline__ void prefix_head(const Common &c, const FacRef &F, "
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
-             "(void)kbase; (void)thr; (void)bin;\n";
+             "(void)kbase; (void)thr; (void)bin;\n"
+             "    int32_t pk[H] = {}; (void)pk;\n";
         emit_region(o, dev, iL, e_split, false, none);
         o += "}\n";
         o += "template <int NW, bool PRUNE>\n"
@@ -179,6 +246,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t, uint32_t, uint32_t l) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
+             "    int32_t pk[H] = {}; (void)pk;\n"
              "    switch (l) {\n";
         for (uint32_t l = 0; l < Dp; ++l) {
             const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;
