@@ -33,35 +33,6 @@ int factor_bits(int base) {
     }
 }
 
-// The state bits an instruction reads or writes.
-void touched_bits(const Instr &I, uint32_t (&m)[4]) {
-    const int base = op_base(I.hdr & 0xffu);
-    const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
-    for (int w = 0; w < 4; ++w) m[w] = 0;
-    auto bit = [&](uint32_t q) {
-        if (q < 128) m[q >> 5] |= 1u << (q & 31);
-    };
-    auto controls = [&]() {
-        for (int w = 0; w < 4; ++w) m[w] |= I.cm[w];
-    };
-    switch (base) {
-        case OP_PERM: bit(a); controls(); break;
-        case OP_SWAP: bit(a); bit(b); controls(); break;
-        case OP_DET1:
-        case OP_DIAG1:
-        case OP_BRANCH_SRC:
-        case OP_BRANCH_NAT: bit(a); break;
-        case OP_DIAG2: bit(a); bit(b); break;
-        case OP_MCPHASE: controls(); break;
-        case OP_ADDSEL: bit(I.k); [[fallthrough]];
-        case OP_ADD:
-            controls();
-            for (uint32_t q = a; q < a + b; ++q) bit(q);
-            break;
-        default: break;
-    }
-}
-
 // One block per instruction: the instruction as a constant and the call of
 // its backward step with the word indices its opcode carries (wsel maps them
 // onto the state registers as the interpreter's dispatch does).  With
@@ -88,23 +59,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
         const int w1 = static_cast<int>((op >> 4) & 3u), w2 = static_cast<int>((op >> 6) & 3u);
         const bool is_add = base == OP_ADD || base == OP_ADDSEL;
         const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
-        if (pending) {
-            uint32_t m[4];
-            touched_bits(I, m);
-            bool hit = false;
-            for (uint32_t q = plo; q < phi && !hit; ++q) {
-                // an add on the pending field itself only reads its controls
-                // and selector, which lie outside the field
-                if (is_add && a == plo && a + b == phi && q >= a && q < a + b) {
-                    uint32_t c[4] = {I.cm[0], I.cm[1], I.cm[2], I.cm[3]};
-                    if (base == OP_ADDSEL && I.k < 128) c[I.k >> 5] |= 1u << (I.k & 31);
-                    hit = (c[q >> 5] >> (q & 31)) & 1u;
-                } else {
-                    hit = (m[q >> 5] >> (q & 31)) & 1u;
-                }
-            }
-            if (hit || (is_add && (a != plo || a + b != phi))) flush();
-        }
+        if (pending && ends_field_run(I, plo, phi)) flush();
         std::snprintf(buf, sizeof(buf),
                       "    { constexpr Instr I{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu, "
                       "{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}, {0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}}; ",

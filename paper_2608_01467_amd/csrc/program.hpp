@@ -88,6 +88,59 @@ struct Mask4 {
 };
 
 #if !defined(__HIPCC_RTC__)
+// The state bits an instruction reads or writes (host side: the compiled
+// regions' accumulation of ladder steps and its work count follow it).
+inline void touched_bits(const Instr &I, uint32_t (&m)[4]) {
+    const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+    const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+    for (int w = 0; w < 4; ++w) m[w] = 0;
+    auto bit = [&](uint32_t q) {
+        if (q < 128) m[q >> 5] |= 1u << (q & 31);
+    };
+    auto controls = [&]() {
+        for (int w = 0; w < 4; ++w) m[w] |= I.cm[w];
+    };
+    switch (base) {
+        case OP_PERM: bit(a); controls(); break;
+        case OP_SWAP: bit(a); bit(b); controls(); break;
+        case OP_DET1:
+        case OP_DIAG1:
+        case OP_BRANCH_SRC:
+        case OP_BRANCH_NAT: bit(a); break;
+        case OP_DIAG2: bit(a); bit(b); break;
+        case OP_MCPHASE: controls(); break;
+        case OP_ADDSEL: bit(I.k); [[fallthrough]];
+        case OP_ADD:
+            controls();
+            for (uint32_t q = a; q < a + b; ++q) bit(q);
+            break;
+        default: break;
+    }
+}
+
+// Whether `I` ends a pending accumulation of ladder steps on the field
+// [lo, hi): it touches a field bit other than as a further step of the same
+// field (an add on the field itself only reads its controls and selector).
+inline bool ends_field_run(const Instr &I, uint32_t lo, uint32_t hi) {
+    const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+    const bool is_add = base == OP_ADD || base == OP_ADDSEL;
+    const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+    uint32_t m[4];
+    if (is_add && a == lo && a + b == hi) {
+        for (int w = 0; w < 4; ++w) m[w] = I.cm[w];
+        if (base == OP_ADDSEL && I.k < 128) m[I.k >> 5] |= 1u << (I.k & 31);
+    } else if (is_add) {
+        return true;   // an add on another field
+    } else {
+        touched_bits(I, m);
+    }
+    for (uint32_t q = lo; q < hi; ++q)
+        if ((m[q >> 5] >> (q & 31)) & 1u) return true;
+    return false;
+}
+
+constexpr uint32_t kNoPrev = 0xffffffffu;
+
 struct HostProgram {
     int n = 0;                 // qubits
     int G = 0;                 // gates
@@ -104,6 +157,11 @@ struct HostProgram {
     std::vector<Mask4> final_before;   // [G+1]: bits final once e gates are applied
     std::vector<uint8_t> role;         // per evaluation position: 0 preserve, 1 det, 2 branch
     std::vector<uint16_t> fp_cost;     // per evaluation position: algorithmic FP64 flops
+    // Folded ladders: the carry chain that applies a run of accumulated steps
+    // on one field (int32 ops), and the position of the run's previous step
+    // (kNoPrev when this step starts the run).
+    std::vector<uint16_t> flush_cost;
+    std::vector<uint32_t> run_prev;
     std::vector<uint16_t> int_cost;    // per evaluation position: algorithmic int32 ops
     std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };

@@ -276,6 +276,8 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
     P.role.assign(G, 0);
     P.fp_cost.assign(G, 0);
     P.int_cost.assign(G, 0);
+    P.flush_cost.assign(G, 0);
+    P.run_prev.assign(G, kNoPrev);
     P.fac.clear();
     P.src_eval.clear();
     P.final_before.assign(G + 1, Mask4{{0, 0, 0, 0}});
@@ -492,13 +494,16 @@ void fuse_ladders(HostProgram &P) {
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
         const bool any = (A.cm[0] | A.cm[1] | A.cm[2] | A.cm[3]) != 0u;
-        // test (none without controls), carry, merge
-        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 3 * wfield);
+        // the step: control test (none without controls), addend, accumulate;
+        // the run's carry chain and merge are counted once (flush_cost)
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 2);
+        P.flush_cost[e] = static_cast<uint16_t>(3 * wfield);
         for (int j = 1; j < m; ++j) {
             Instr N{};
             N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
             P.ins[e + j] = N;
             P.int_cost[e + j] = 0;
+            P.flush_cost[e + j] = 0;
         }
         ++P.n_fused;
         e += m;
@@ -558,15 +563,52 @@ void pair_ladders(HostProgram &P) {
         A.hdr = pack_hdr(op_code(OP_ADDSEL, wspan, q >> 5), lo, m, z);
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
-        // test, selecting bit, carry and merge
-        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 2 + 3 * wfield);
+        // the step: control test, selecting bit, addend, accumulate; the run's
+        // carry chain and merge are counted once (flush_cost)
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 3);
+        P.flush_cost[e] = static_cast<uint16_t>(3 * wfield);
         Instr N{};
         N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
         P.ins[e2] = N;
         P.int_cost[e2] = 0;
+        P.flush_cost[e2] = 0;
         ++P.n_paired;
         e = e2;
     }
+}
+
+// Runs of folded-ladder steps on one field with nothing touching the field
+// in between (ends_field_run): the compiled regions accumulate such a run and
+// apply it with one carry chain, so each step records the previous step of
+// its run (run_prev) and a range's work counts one carry chain per run that
+// starts inside it.
+void set_field_runs(HostProgram &P) {
+    bool pending = false;
+    uint32_t lo = 0, hi = 0, last = 0;
+    for (int e = 0; e < P.G; ++e) {
+        const Instr &I = P.ins[e];
+        const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+        if (base == OP_NOP) continue;
+        if (pending && ends_field_run(I, lo, hi)) pending = false;
+        if (base == OP_ADD || base == OP_ADDSEL) {
+            const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+            P.run_prev[e] = pending ? last : kNoPrev;
+            pending = true;
+            lo = a;
+            hi = a + b;
+            last = static_cast<uint32_t>(e);
+        }
+    }
+}
+
+// Algorithmic int32 ops of evaluation positions [lo, hi) for one history.
+uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
+    uint64_t ops = 0;
+    for (uint32_t e = lo; e < hi; ++e) {
+        ops += P.int_cost[e];
+        if (P.flush_cost[e] && (P.run_prev[e] == kNoPrev || P.run_prev[e] < lo)) ops += P.flush_cost[e];
+    }
+    return ops;
 }
 
 // Runs of identical opcodes: the device dispatches once per run.
@@ -627,6 +669,7 @@ extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags
     }
     if (flags & FHS_REDUCE_FUSE) fuse_ladders(p->p);
     if (flags & FHS_REDUCE_PAIR) pair_ladders(p->p);
+    set_field_runs(p->p);
     set_runs(p->p);
     *out = p;
     return FHS_OK;
@@ -683,10 +726,10 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     fhs_work w{0, 0, 0, 0};
     for (uint32_t e = e0; e < e1; ++e) {
         w.gates += 1;
-        w.int_ops += P.int_cost[e];
         w.fp64_flops += P.fp_cost[e];
         w.branch += P.role[e] == 2 ? 1 : 0;
     }
+    w.int_ops = range_int_ops(P, e0, e1);
     *out = w;
     return FHS_OK;
 }
@@ -703,11 +746,9 @@ extern "C" fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, u
     uint32_t a3[3];
     region_sources(P, c1, c2, a3);
     auto work = [&](uint32_t lo, uint32_t hi, double &iops, double &flops) {
-        iops = flops = 0.0;
-        for (uint32_t e = lo; e < hi; ++e) {
-            iops += P.int_cost[e];
-            flops += P.fp_cost[e];
-        }
+        flops = 0.0;
+        for (uint32_t e = lo; e < hi; ++e) flops += P.fp_cost[e];
+        iops = static_cast<double>(range_int_ops(P, lo, hi));
     };
     // instructions the device walks (folded gates excluded) and opcode runs
     // among them: the decode work, a first-order cost once ladders are folded
