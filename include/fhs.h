@@ -117,9 +117,9 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *   int_ops:    32-bit integer operations: controlled permutation or phase
  *               3w+1 (w = state words spanned by its controls, at least 1),
  *               swap 3w+4, one-qubit diagonal 1, two-qubit diagonal 3,
- *               anti-diagonal 2, branching 4; a fused ladder 3w+1+2 (2
+ *               anti-diagonal 2, branching 4; a fused ladder 3w+1+1 (1
  *               without controls; the gates folded into it 0) and a paired
- *               ladder 3w+1+3 (3 without common controls; the second ladder
+ *               ladder 3w+1+2 (2 without common controls; the second ladder
  *               0) for the step, plus 3f (f state words spanned by the
  *               field) once per run of such steps on one field that starts
  *               in [e0, e1) with nothing touching the field in between

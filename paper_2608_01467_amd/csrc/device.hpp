@@ -301,11 +301,16 @@ __device__ __forceinline__ void op_addsel(Lanes<NW, H> &L, const Instr &I) {
 // Pending field additions (straight-line regions).  Folded ladders on one
 // field, with nothing between them that reads or writes a field bit, add up:
 // (x + d1 + d2) mod 2^m = ((x + d1) mod 2^m + d2) mod 2^m.  The compiled
-// regions therefore accumulate each history's +-1 steps as a signed count pk
-// and add pk * 2^lo to the field with one carry chain (flush_field) before
-// the next instruction that touches the field, and at the region's end.
+// regions therefore accumulate each history's +-1 steps as signed counts and
+// add (pk + 2 pb) * 2^lo to the field with one carry chain (flush_field)
+// before the next instruction that touches the field, and at the region's
+// end: pk sums the steps' values when their selecting bit is 0, pb counts
+// (with sign) the steps whose selecting bit flips that value, so a run of
+// steps costs a bit extract and an add each, with no selects.
 template <int NW, int H, int LW>
-__device__ __forceinline__ void pend_add(const Lanes<NW, H> &L, const Instr &I, int32_t (&pk)[H]) {
+__device__ __forceinline__ void pend_add(const Lanes<NW, H> &L, const Instr &I, int32_t (&pk)[H],
+                                         int32_t (&pb)[H]) {
+    (void)pb;
     const int32_t d = (hdr_z(I) & 1u) ? -1 : 1;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
@@ -315,28 +320,34 @@ __device__ __forceinline__ void pend_add(const Lanes<NW, H> &L, const Instr &I, 
 }
 
 template <int NW, int H, int LW, int SW>
-__device__ __forceinline__ void pend_addsel(const Lanes<NW, H> &L, const Instr &I, int32_t (&pk)[H]) {
+__device__ __forceinline__ void pend_addsel(const Lanes<NW, H> &L, const Instr &I, int32_t (&pk)[H],
+                                            int32_t (&pb)[H]) {
     const uint32_t z = hdr_z(I), kb = I.k & 31u;
     const int32_t d0 = (z & 1u) ? -1 : 1, d1 = (z & 2u) ? -1 : 1;   // step when bit k is 0 / 1
+    const int32_t half = (d1 - d0) / 2;                             // -1, 0 or 1
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
-        const int32_t sel = -static_cast<int32_t>((L.s[h][SW] >> kb) & 1u);   // all ones when set
+        const int32_t bit = static_cast<int32_t>((L.s[h][SW] >> kb) & 1u);
         const int32_t gm = controls_hold<NW, H, LW>(L, h, I) ? -1 : 0;
-        pk[h] += (d0 + ((d1 - d0) & sel)) & gm;
+        pk[h] += d0 & gm;
+        if (half > 0) pb[h] += bit & gm;
+        if (half < 0) pb[h] -= bit & gm;
     });
 }
 
 template <int NW, int H>
-__device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H]) {
+__device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H],
+                                            int32_t (&pb)[H]) {
     const FieldMasks f = field_masks(lo, hi);
     const uint32_t wl = lo >> 5, sh = lo & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
-        // pk * 2^lo in two's complement over the state's words
-        const int64_t v = static_cast<int64_t>(pk[h]) * (static_cast<int64_t>(1) << sh);
+        const int32_t n = pk[h] + 2 * pb[h];
+        // n * 2^lo in two's complement over the state's words
+        const int64_t v = static_cast<int64_t>(n) * (static_cast<int64_t>(1) << sh);
         const uint32_t lo32 = static_cast<uint32_t>(static_cast<uint64_t>(v));
         const uint32_t hi32 = static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32);
-        const uint32_t sgn = pk[h] < 0 ? ~0u : 0u;
+        const uint32_t sgn = n < 0 ? ~0u : 0u;
         uint32_t d[NW];
         unroll<NW>([&](auto ww) {
             constexpr uint32_t w = static_cast<uint32_t>(ww.value);
@@ -344,6 +355,7 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
         });
         add_into_field<NW, H>(L, h, d, f.fm);
         pk[h] = 0;
+        pb[h] = 0;
     });
 }
 

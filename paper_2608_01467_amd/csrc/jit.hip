@@ -48,7 +48,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
     uint32_t plo = 0, phi = 0;
     auto flush = [&]() {
         if (!pending) return;
-        std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk);\n", plo, phi);
+        std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk, pb);\n", plo, phi);
         o += buf;
         pending = false;
     };
@@ -101,11 +101,11 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
                 std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
                 break;
             case OP_ADD:
-                std::snprintf(call, sizeof(call), "pend_add<NW, H, wsel<%d, NW>()>(L, I, pk); }\n", w1);
+                std::snprintf(call, sizeof(call), "pend_add<NW, H, wsel<%d, NW>()>(L, I, pk, pb); }\n", w1);
                 break;
             case OP_ADDSEL:
                 std::snprintf(call, sizeof(call),
-                              "pend_addsel<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I, pk); }\n", w1, w2);
+                              "pend_addsel<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I, pk, pb); }\n", w1, w2);
                 break;
             default:
                 std::snprintf(call, sizeof(call), "(void)I; }\n");
@@ -156,7 +156,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
                   "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
-                  "    int32_t pk[H] = {}; (void)pk;\n",
+                  "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
                   Ap);
     o += buf;
     emit_region(o, dev, i1, i2, false, none);
@@ -166,7 +166,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
                   "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
-                  "    int32_t pk[H] = {}; (void)pk;\n",
+                  "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
                   Ap + Ar);
     o += buf;
     emit_region(o, dev, i2, iG, defer, deferred);
@@ -193,7 +193,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
-             "    int32_t pk[H] = {}; (void)pk;\n";
+             "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n";
         emit_region(o, dev, iL, e_split, false, none);
         o += "}\n";
         o += "template <int NW, bool PRUNE>\n"
@@ -201,7 +201,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t, uint32_t, uint32_t l) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
-             "    int32_t pk[H] = {}; (void)pk;\n"
+             "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n"
              "    switch (l) {\n";
         for (uint32_t l = 0; l < Dp; ++l) {
             const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;

@@ -494,9 +494,10 @@ void fuse_ladders(HostProgram &P) {
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
         const bool any = (A.cm[0] | A.cm[1] | A.cm[2] | A.cm[3]) != 0u;
-        // the step: control test (none without controls), addend, accumulate;
-        // the run's carry chain and merge are counted once (flush_cost)
-        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 2);
+        // the step: control test (none without controls) and the masked add of
+        // its +-1 to the run's count; the run's carry chain and merge are
+        // counted once (flush_cost)
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 1);
         P.flush_cost[e] = static_cast<uint16_t>(3 * wfield);
         for (int j = 1; j < m; ++j) {
             Instr N{};
@@ -563,9 +564,10 @@ void pair_ladders(HostProgram &P) {
         A.hdr = pack_hdr(op_code(OP_ADDSEL, wspan, q >> 5), lo, m, z);
         P.ins[e] = A;
         const int wfield = static_cast<int>(((lo + m - 1) >> 5) - (lo >> 5)) + 1;
-        // the step: control test, selecting bit, addend, accumulate; the run's
+        // the step: control test, the selecting bit's extraction and its add to
+        // the run's count (the sign is a compile-time constant); the run's
         // carry chain and merge are counted once (flush_cost)
-        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 3);
+        P.int_cost[e] = static_cast<uint16_t>((any ? 3 * (wspan + 1) + 1 : 0) + 2);
         P.flush_cost[e] = static_cast<uint16_t>(3 * wfield);
         Instr N{};
         N.hdr = pack_hdr(op_code(OP_NOP, 0, 0), 0, 0, 0);
