@@ -294,18 +294,28 @@ def main() -> int:
         "roofline": roof,
     }
     if tuple(part) != tuple(part_eq8) and not args.no_eq8:
-        # the paper's own choice, Eq. (8), on the same inputs
+        # the paper's own choice, Eq. (8), on the same inputs, at its own best
+        # chunk (the launch shape was tuned for the learned split)
+        saved = ctx.launch_config
         ctx.set_partition(*part_eq8)
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(max(1, min(args.steps, 3))):
+        best_e = None
+        for chunk in dict.fromkeys((saved[1], 64, 128, 256)):
+            ctx.set_launch_config(saved[0], chunk, saved[2], saved[3])
             step()
-        torch.cuda.synchronize()
-        Te = (time.perf_counter() - t0) / max(1, min(args.steps, 3))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(max(1, min(args.steps, 3))):
+                step()
+            torch.cuda.synchronize()
+            te = (time.perf_counter() - t0) / max(1, min(args.steps, 3))
+            if best_e is None or te < best_e[0]:
+                best_e = (te, chunk)
+        ctx.set_launch_config(*saved)
         ctx.set_partition(*part)
+        Te = best_e[0]
         out["eq8_split"] = {"partition": list(part_eq8), "ms_per_step": Te * 1e3,
-                            "histories_per_s": cand / Te, "learned_speedup": Te / T}
+                            "chunk": best_e[1], "histories_per_s": cand / Te,
+                            "learned_speedup": Te / T}
     if not args.no_plain:
         # Algorithm 1 at its own best lane shape (histories per lane 1 or 2,
         # interpreted dispatch), one timed pass each after a warm-up pass.
