@@ -117,14 +117,18 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *   int_ops:    32-bit integer operations: controlled permutation or phase
  *               3w+1 (w = state words spanned by its controls, at least 1),
  *               swap 3w+4, one-qubit diagonal 1, two-qubit diagonal 3,
- *               anti-diagonal 2, branching 4; a fused ladder 3w+1+1 (1
+ *               anti-diagonal 2, branching 2 (4 when the gate has zero
+ *               entries: the index and its test); a fused ladder 3w+1+1 (1
  *               without controls; the gates folded into it 0) and a paired
  *               ladder 3w+1+2 (2 without common controls; the second ladder
  *               0) for the step, plus 3f (f state words spanned by the
  *               field) once per run of such steps on one field that starts
  *               in [e0, e1) with nothing touching the field in between
  *               (the steps of a run add up and are applied with one carry
- *               chain);
+ *               chain); when e1 is the end of the program and the final
+ *               check compares the whole field of the run still pending
+ *               there, that run costs 2 instead of 3f (its count is
+ *               compared with the field's residue);
  *   fp64_flops: complex multiply of the running amplitude: 6 for a general
  *               factor table, 2 if every entry is purely real or imaginary,
  *               0 if every entry is 0, +-1 or +-i; a negation counts 0;

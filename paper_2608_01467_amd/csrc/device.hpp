@@ -359,6 +359,58 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
     });
 }
 
+// The last pending run of a region after which the final check compares
+// every bit of the field with the output: (x + n) mod 2^m equals the target
+// t iff n = (t - x) mod 2^m, so instead of adding n 2^lo to the field and
+// comparing its words, compare the step count n with that residue.  The
+// residue reads only the field and the output; when nothing earlier in the
+// region writes the field it is the same for every suffix assignment and the
+// compiler computes it once per root history, leaving one compare per
+// history.  The field's bits are left as they were, so the final check that
+// follows must leave them out (nothing else reads them after the region).
+template <int NW, int H>
+__device__ __forceinline__ void flush_check(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H],
+                                            int32_t (&pb)[H], const uint32_t (&bin)[NW]) {
+    const FieldMasks f = field_masks(lo, hi);
+    const FieldMasks g = field_masks(lo + 32u < hi ? lo + 32u : hi, hi);   // bits [lo+32, hi)
+    const uint32_t m = hi - lo, wl = lo >> 5, sh = lo & 31u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        // (output - state) on the field bits: bits [lo, hi) of d hold the residue
+        uint32_t d[NW], borrow = 0;
+        unroll<NW>([&](auto ww) {
+            constexpr int w = ww.value;
+            d[w] = __builtin_subc(bin[w] & f.fm[w], L.s[h][w] & f.fm[w], borrow, &borrow);
+        });
+        uint32_t x0 = 0, x1 = 0, zhi = 0, ohi = 0;
+        unroll<NW>([&](auto ww) {
+            constexpr uint32_t w = static_cast<uint32_t>(ww.value);
+            if (w == wl) x0 = d[w];
+            if (w == wl + 1u) x1 = d[w];
+            zhi |= d[w] & g.fm[w];
+            ohi |= ~d[w] & g.fm[w];
+        });
+        const uint32_t e32 = sh ? (x0 >> sh) | (x1 << (32u - sh)) : x0;   // bits [lo, lo+32) of d
+        const int32_t n = pk[h] + 2 * pb[h];
+        bool hit;
+        if (m <= 32u) {
+            const uint32_t up = 32u - m;   // only the field's m low bits count
+            hit = (static_cast<uint32_t>(n) << up) == (e32 << up);
+        } else {
+            // n sign-extended to m bits equals the residue iff their low 32
+            // bits agree and bits [lo+32, hi) all repeat bit 31: the residue
+            // as an int32 when it is one, else a value no step count reaches
+            // (|n| is at most the number of steps)
+            const bool fits = static_cast<int32_t>(e32) < 0 ? ohi == 0u : zhi == 0u;
+            const int32_t en = fits ? static_cast<int32_t>(e32) : static_cast<int32_t>(0x80000000u);
+            hit = n == en;
+        }
+        L.ok[h] = L.ok[h] && hit;
+        pk[h] = 0;
+        pb[h] = 0;
+    });
+}
+
 template <int NW, int H, int WA, int WB>
 __device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
     constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
@@ -871,6 +923,8 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 any = any || R.ok[j];
             });
             if (!__any(any)) continue;   // wave-uniform skip
+            // every suffix assignment of a consistent root is a leaf walked
+            unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n_suffix : 0u; });
             for (uint64_t q = 0; q < n_suffix; ++q) {
                 Lanes<NW, H> S2 = R;
                 unroll<H>([&](auto jj) {
@@ -881,7 +935,6 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
                     const bool ok2 = S2.ok[j] && Regions::template final_G<NW>(S2.s[j], bin, fin_G);
-                    acc.leaves += R.ok[j] ? 1u : 0u;
                     if (ok2) {
                         // a policy that deferred the suffix's factors applies them
                         // now, for the histories that count

@@ -39,9 +39,14 @@ int factor_bits(int base) {
 // `defer`, factor ops record their table index in dx instead of multiplying
 // (the offsets are appended to `deferred`).  Folded and paired ladders on one
 // field accumulate in the region's pk counters and are added to the field
-// before the next instruction that touches it and at the region's end.
+// before the next instruction that touches it and at the region's end.  With
+// `check` (the final-bit mask that follows the region), a run still pending
+// at the end on a field that mask covers whole is compared with the output
+// instead (flush_check); its field is returned in `checked`, for the final
+// check to leave out.
 void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi, bool defer,
-                 std::vector<Deferred> &deferred) {
+                 std::vector<Deferred> &deferred, const Mask4 *check = nullptr,
+                 Mask4 *checked = nullptr) {
     char buf[512];
     int off = 0;
     bool pending = false;
@@ -118,6 +123,18 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
             phi = a + b;
         }
     }
+    if (pending && check) {
+        Mask4 fm{{0u, 0u, 0u, 0u}};
+        for (uint32_t q = plo; q < phi; ++q) fm.w[q >> 5] |= 1u << (q & 31u);
+        bool covered = true;
+        for (int w = 0; w < 4; ++w) covered = covered && (fm.w[w] & ~check->w[w]) == 0u;
+        if (covered) {
+            std::snprintf(buf, sizeof(buf), "    flush_check<NW, H>(L, %uu, %uu, pk, pb, bin);\n", plo, phi);
+            o += buf;
+            pending = false;
+            if (checked) *checked = fm;
+        }
+    }
     flush();
 }
 
@@ -139,7 +156,13 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
     o += "struct Compiled {\n";
     o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
     // the final-bit masks as constants: fully checked words become one compare
-    const Mask4 *fm[2] = {&fin_c2, &fin_G};
+    // the suffix first: its last ladder run may take over part of the final check
+    std::string sfx;
+    Mask4 checked{{0u, 0u, 0u, 0u}};
+    emit_region(sfx, dev, i2, iG, defer, deferred, &fin_G, &checked);
+    Mask4 fin_rest = fin_G;
+    for (int w = 0; w < 4; ++w) fin_rest.w[w] &= ~checked.w[w];
+    const Mask4 *fm[2] = {&fin_c2, &fin_rest};
     const char *fname[2] = {"final_c2", "final_G"};
     for (int k = 0; k < 2; ++k) {
         std::snprintf(buf, sizeof(buf),
@@ -169,7 +192,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
                   Ap + Ar);
     o += buf;
-    emit_region(o, dev, i2, iG, defer, deferred);
+    o += sfx;
     o += "}\n";
     // the deferred factors, in evaluation order: the same products as the walk
     o += "template <int NW, int H>\n"

@@ -162,6 +162,11 @@ struct HostProgram {
     // (kNoPrev when this step starts the run).
     std::vector<uint16_t> flush_cost;
     std::vector<uint32_t> run_prev;
+    // The run still pending after the last position (its last step, or
+    // kNoPrev) and whether the final-bit mask there covers its whole field:
+    // then the run is compared with the output instead of applied.
+    uint32_t tail_last = kNoPrev;
+    bool tail_checked = false;
     std::vector<uint16_t> int_cost;    // per evaluation position: algorithmic int32 ops
     std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };

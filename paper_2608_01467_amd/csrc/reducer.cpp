@@ -411,7 +411,11 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
                 case OP_DIAG1: ops = 1; break;
                 case OP_DIAG2: ops = 3; break;
                 case OP_DET1: ops = 2; break;
-                default: ops = 4; break;   // branching
+                // branching: the source (or input) bit into the state; forming
+                // the table index and testing it for a zero entry only when
+                // the gate has zero entries (the factor itself takes the index
+                // where the multiply is made)
+                default: ops = zmask ? 4 : 2; break;
             }
             P.int_cost[e] = static_cast<uint16_t>(ops);
         }
@@ -583,10 +587,12 @@ void pair_ladders(HostProgram &P) {
 // in between (ends_field_run): the compiled regions accumulate such a run and
 // apply it with one carry chain, so each step records the previous step of
 // its run (run_prev) and a range's work counts one carry chain per run that
-// starts inside it.
+// starts inside it.  A run still pending at the end of the program, on a
+// field the final check compares whole, costs a compare of its step count
+// with the field's residue instead (kCheckCost).
 void set_field_runs(HostProgram &P) {
     bool pending = false;
-    uint32_t lo = 0, hi = 0, last = 0;
+    uint32_t lo = 0, hi = 0, last = kNoPrev;
     for (int e = 0; e < P.G; ++e) {
         const Instr &I = P.ins[e];
         const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
@@ -601,7 +607,17 @@ void set_field_runs(HostProgram &P) {
             last = static_cast<uint32_t>(e);
         }
     }
+    P.tail_last = pending ? last : kNoPrev;
+    P.tail_checked = false;
+    if (pending) {
+        const Mask4 &fin = P.final_before[P.G];
+        bool covered = true;
+        for (uint32_t q = lo; q < hi; ++q) covered = covered && ((fin.w[q >> 5] >> (q & 31u)) & 1u);
+        P.tail_checked = covered;
+    }
 }
+
+constexpr uint64_t kCheckCost = 2;   // n = pk + 2 pb, and one compare
 
 // Algorithmic int32 ops of evaluation positions [lo, hi) for one history.
 uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
@@ -609,6 +625,13 @@ uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
     for (uint32_t e = lo; e < hi; ++e) {
         ops += P.int_cost[e];
         if (P.flush_cost[e] && (P.run_prev[e] == kNoPrev || P.run_prev[e] < lo)) ops += P.flush_cost[e];
+    }
+    // a range that reaches the final check: the run pending there, from its
+    // first step inside the range, is compared instead of applied
+    if (hi == static_cast<uint32_t>(P.G) && P.tail_checked && P.tail_last >= lo) {
+        uint32_t f = P.tail_last;
+        while (P.run_prev[f] != kNoPrev && P.run_prev[f] >= lo) f = P.run_prev[f];
+        ops = ops - P.flush_cost[f] + kCheckCost;
     }
     return ops;
 }

@@ -193,6 +193,39 @@ def test_walk_small(ctx, n_pos, steps):
         assert abs(a - dp.get((x, y & 1), 0)) <= TOL
 
 
+@pytest.mark.parametrize("n_pos", [10, 31, 32, 33, 63, 64])
+def test_walk_field_widths(ctx, n_pos):
+    """The compiled consumer ends the suffix by comparing the pending count of
+    position steps with the position field's residue against the output
+    rather than adding it.  Fields narrower than, as wide as and wider than a
+    word, ending inside a word and crossing into the next; outputs reachable
+    (negative positions: the residue wraps), one and two steps out of reach,
+    and random (residues that no count reaches); cuts that put the whole run,
+    part of it or none of it in the suffix; one and two histories per lane.
+    Against the position-space closed form and the closed-form valid sets."""
+    steps = 6
+    t = w.quantum_walk(n_pos, steps).to_text()
+    outs = w.walk_outputs(n_pos, steps, 2 * (steps + 1) + 12, seed=n_pos)
+    outs += [y for y in (w.walk_state(n_pos, x, c) for x in (-steps - 2, -steps - 1, steps + 1, steps + 2)
+                         for c in (0, 1)) if y not in outs]
+    dp = cf.walk_amplitudes(steps)
+    prog = fhs.Program(t)
+    src = prog.source_eval_positions
+    parts = [(0, 0), (0, src[2] + 1), (src[1] + 1, src[3] + 1), (src[0] + 1, src[-1]),
+             prog.choose_partition(fhs.PART_EQ8), (prog.G, prog.G)]
+    for h in (1, 2):
+        ctx.set_launch_config(h, 0, 0, 3)
+        for part in parts:
+            amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, prog=prog)
+            for y, a, row in zip(outs, amps, st):
+                x = y >> 1
+                x = x - (1 << n_pos) if x >= (1 << (n_pos - 1)) else x
+                assert abs(a - dp.get((x, y & 1), 0)) <= TOL, (n_pos, h, part, y)
+                assert tuple(int(v) for v in row[:3]) == cf.walk_valid_stats(steps, x, y & 1), \
+                    (n_pos, h, part, y)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_walk_config_full(ctx):
     """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
     against the position-space closed form and the closed-form valid sets
