@@ -117,7 +117,7 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *   int_ops:    32-bit integer operations: controlled permutation or phase
  *               3w+1 (w = state words spanned by its controls, at least 1),
  *               swap 3w+4, one-qubit diagonal 1, two-qubit diagonal 3,
- *               anti-diagonal 2, branching 2 (4 when the gate has zero
+ *               anti-diagonal 2, branching 1 (3 when the gate has zero
  *               entries: the index and its test); a fused ladder 3w+1+1 (1
  *               without controls; the gates folded into it 0) and a paired
  *               ladder 3w+1+2 (2 without common controls; the second ladder

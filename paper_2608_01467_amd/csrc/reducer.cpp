@@ -415,7 +415,7 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
                 // the table index and testing it for a zero entry only when
                 // the gate has zero entries (the factor itself takes the index
                 // where the multiply is made)
-                default: ops = zmask ? 4 : 2; break;
+                default: ops = zmask ? 3 : 1; break;
             }
             P.int_cost[e] = static_cast<uint16_t>(ops);
         }

@@ -40,7 +40,7 @@ def test_walk_ladders_fold_to_one_instruction_each():
     a = fhs.Program(w.quantum_walk(n_pos, steps).to_text(), fuse=False)
     b = fhs.Program(w.quantum_walk(n_pos, steps).to_text(), pair=False)
     c = fhs.Program(w.quantum_walk(n_pos, steps).to_text())
-    # the coin's H: its source bit into the state (2);
+    # the coin's H: its source bit into the state (1);
     # unfolded: the X on position bit i has controls up to qubit i (w words): 3w+1;
     # folded: one add per ladder, 3*1+1 for the coin control + 1 for the step;
     # paired: one add per walk step, the coin bit added to the count: 2; either way
@@ -50,10 +50,10 @@ def test_walk_ladders_fold_to_one_instruction_each():
     # costs a compare of its count with the field's residue (2), not a carry
     # chain (3 * 4)
     words = lambda hi: hi // 32 + 1
-    unfolded = steps * (2 + 2 * sum(3 * words(i) + 1 for i in range(n_pos)))
+    unfolded = steps * (1 + 2 * sum(3 * words(i) + 1 for i in range(n_pos)))
     assert a.work(0, a.G)["int_ops"] == unfolded
-    assert b.work(0, b.G)["int_ops"] == steps * (2 + 2 * (4 + 1)) + 2
-    assert c.work(0, c.G)["int_ops"] == steps * (2 + 2) + 2
+    assert b.work(0, b.G)["int_ops"] == steps * (1 + 2 * (4 + 1)) + 2
+    assert c.work(0, c.G)["int_ops"] == steps * (1 + 2) + 2
     # a range that starts inside the run pays its own compare, and the range
     # that holds the run's start but stops short of the end applies its part
     # with a carry chain
