@@ -65,10 +65,108 @@ def traffic_from_profile(workload: str, partition):
     return entry.get("bytes_per_launch") if entry else None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu), for the CPU baseline's record."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+# The oracle leg: the only part of this script that touches oracle/.  It
+# checks the timed step's outputs against what the paper's mathematics fixes
+# for the workload, and times the CPU oracle on a bounded sample.
+# ---------------------------------------------------------------------------
+
+_MIX = (0xBF58476D1CE4E5B9, 0x94D049BB133111EB)
+
+
+def _all_history_stats(A: int):
+    """(count, sum of h mod 2^64, xor of SplitMix64(h)) over every h < 2^A."""
+    import numpy as np
+    h = np.arange(1 << A, dtype=np.uint64)
+    z = (h ^ (h >> np.uint64(30))) * np.uint64(_MIX[0])
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(_MIX[1])
+    z = z ^ (z >> np.uint64(31))
+    return 1 << A, int(h.sum(dtype=np.uint64)), int(np.bitwise_xor.reduce(z))
+
+
+def oracle_check(workload, cfg, text, amps, stats, thr, partition, A, max_candidates=1 << 33):
+    """Compare the benchmark's own outputs with references that do not come
+    from the library: the position-space closed form and closed-form valid
+    sets for the quantum walk (Eq. (7): every reachable output, padding
+    outputs exactly zero), the 2^n state vector and the all-histories
+    statistics for QAOA at t = 0, and otherwise the CPU oracle (Algorithm 2,
+    same cuts) on a sample of outputs when its candidate count is small
+    enough.  Returns a dict with max_abs_err, stats_exact and what was
+    compared."""
+    import numpy as np
+
+    import oracle
+    from oracle import closed_forms as cf
+    from oracle import statevector as sv
+
+    a = amps[:, 0] + 1j * amps[:, 1]
+    st = stats.view(np.uint64) if stats.dtype != np.uint64 else stats
+    outs = cfg["outputs"]
+    if workload.startswith("walk_") and thr == 0.0 and cfg["inputs"] == [0]:
+        c = cfg["circuit"]
+        n_pos, steps = c.n - 1, sum(1 for g in c.gates if g.name == "H")
+        dp = cf.walk_amplitudes(steps)
+        err, exact, n_reach = 0.0, True, 0
+        for j, y in enumerate(outs):
+            x = y >> 1
+            x = x - (1 << n_pos) if x >= (1 << (n_pos - 1)) else x
+            ref = dp.get((x, y & 1))
+            if ref is None:          # unreachable: exactly zero, no valid history
+                exact = exact and a[j] == 0 and all(int(v) == 0 for v in st[j, :3])
+                continue
+            n_reach += 1
+            err = max(err, abs(a[j] - ref))
+            exact = exact and tuple(int(v) for v in st[j, :3]) == cf.walk_valid_stats(steps, x, y & 1)
+        return {"max_abs_err": float(err), "stats_exact": bool(exact), "checked_outputs": len(outs),
+                "against": f"walk closed form ({n_reach} reachable outputs; {len(outs) - n_reach} "
+                           "padding outputs exactly 0)"}
+    if cfg["circuit"].n <= 16 and thr == 0.0:
+        coeffs = [complex(*z) for z in cfg["coeffs"]]
+        ref = sv.amplitudes(text, cfg["inputs"], coeffs, outs)
+        err = float(np.abs(a - ref).max()) if len(outs) else 0.0
+        res = {"max_abs_err": err, "checked_outputs": len(outs),
+               "against": "state vector (every output)"}
+        if workload.startswith("qaoa_") and A <= 30:
+            # every history of a QAOA pair is valid at t = 0
+            want = _all_history_stats(A)
+            res["stats_exact"] = bool(all(tuple(int(v) for v in row[:3]) == want for row in st))
+            res["against"] += "; valid sets: all 2^A histories"
+        return res
+    k = min(len(outs), 8)
+    if len(outs) == 0 or k * len(cfg["inputs"]) * (1 << A) > max_candidates:
+        return {"max_abs_err": None, "stats_exact": None, "checked_outputs": 0,
+                "against": "not checked (the oracle would take too long)"}
+    idx = np.linspace(0, len(outs) - 1, k).astype(int)
+    sample = [outs[i] for i in idx]
+    coeffs = [complex(*z) for z in cfg["coeffs"]]
+    cores = len(os.sched_getaffinity(0))
+    ref_a, ref_st = oracle.Feynman(text).evaluate(cfg["inputs"], coeffs, sample, threshold=thr,
+                                                  partition=tuple(partition), threads=cores)
+    err = float(np.abs(a[idx] - ref_a).max())
+    exact = bool(np.array_equal(st[idx, :3], ref_st[:, :3].astype(np.uint64)))
+    return {"max_abs_err": err, "stats_exact": exact, "checked_outputs": k,
+            "against": f"CPU oracle (Algorithm 2, same cuts) on {k} sampled outputs"}
+
+
 def cpu_baseline(text, inputs, outputs, partition, threshold, seconds_target=15.0):
     """The CPU oracle (Algorithm 2, same cuts) on a bounded sample: a slice of
     prefix assignments for several outputs, OpenMP over outputs on every
-    core this process may use."""
+    core this process may use.  The rate is the sample's, projected to the
+    whole workload's unit (candidate histories per second)."""
     import oracle
 
     cores = len(os.sched_getaffinity(0))
@@ -89,12 +187,77 @@ def cpu_baseline(text, inputs, outputs, partition, threshold, seconds_target=15.
     cand = len(outs) * hp * per_prefix
     return {
         "value": cand / wall,
-        "unit": "histories/s",
+        "unit": "histories/s (projected from a timed sample)",
         "cores": cores,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": (f"Algorithm 2 with the same cuts on {len(outs)} outputs, prefix assignments "
-                   f"h_p < {hp} of {1 << ap} ({cand} candidate histories, {wall:.1f} s wall)"),
+                   f"h_p < {hp} of {1 << ap} ({cand} candidate histories, {wall:.1f} s wall); "
+                   f"the full workload would take "
+                   f"{len(outputs) * len(inputs) * (1 << (ap + ar + as_)) / (cand / wall):.3g} s"),
     }
+
+
+def sweep(args, cfg) -> int:
+    """Threshold-pruning sweep (Section V, QAOA): for each threshold t the
+    batched evaluation of every requested output, at the split the learned
+    shortlist picks for that t (timed on the workload), timed by graph
+    replay; its outputs compared with the oracle leg's references, and
+    fidelity F(t) = |sum_y conj(a(y)) a_t(y)|^2 / (sum |a|^2 sum |a_t|^2)
+    (0 when every amplitude is pruned) against the exact amplitudes a: the
+    state vector when the circuit is small enough, else the t = 0 run.
+    One JSON line per threshold."""
+    import numpy as np
+    import torch
+
+    import paper_2608_01467_amd as fhs
+    from paper_2608_01467_amd import tune
+
+    text = cfg["circuit"].to_text()
+    coeffs = [complex(*z) for z in cfg["coeffs"]]
+    ctx = fhs.Context(0)
+    ctx.set_table_budget(32 << 30)
+    launch = tune.model_launch()
+    if launch is not None:
+        ctx.set_launch_config(*launch)     # the configuration the cost model was trained under
+    exact = None
+    if cfg["circuit"].n <= 16:
+        from oracle import statevector as sv   # oracle leg: the exact amplitudes
+        exact = sv.amplitudes(text, cfg["inputs"], coeffs, cfg["outputs"])
+        exact_src = "state vector"
+    base_valid = None
+    for t in (float(x) for x in args.sweep.split(",")):
+        wl = tune.Workload(ctx, text, cfg["inputs"], coeffs, cfg["outputs"], threshold=t)
+        split, how = tune.choose(wl, tune.load_model(), reps=1, shortlist=SHORTLIST)
+        sec = tune.time_split(wl, split, reps=max(1, args.steps))
+        wl.run(split)
+        torch.cuda.synchronize()
+        a = wl.amps.cpu().numpy().copy()
+        st = wl.stats.cpu().numpy()
+        amp = a[:, 0] + 1j * a[:, 1]
+        valid = int(st[:, 0].sum())
+        leaves = int(st[:, 3].sum())
+        if exact is None:
+            exact, exact_src = amp.copy(), "t = 0 run"
+        if base_valid is None:
+            base_valid = valid
+        n0, nt = float(np.sum(np.abs(exact) ** 2)), float(np.sum(np.abs(amp) ** 2))
+        fid = 0.0 if nt == 0.0 else float(abs(np.vdot(exact, amp)) ** 2 / (n0 * nt))
+        line = {"workload": cfg.get("name", args.workload), "threshold": t, "split": list(split),
+                "split_mode": how, "launch_config": list(ctx.launch_config),
+                "ms_per_eval": sec * 1e3, "fidelity": fid, "fidelity_against": exact_src,
+                "retained_norm": nt / n0 if n0 else 0.0, "valid_histories": valid,
+                "leaf_histories": leaves,
+                "kept_fraction": valid / base_valid if base_valid else 0.0,
+                "outputs": len(cfg["outputs"])}
+        if not args.no_check:
+            chk = oracle_check(args.workload, cfg | {"threshold": t}, text, a, st, t, split,
+                               wl.prog.A)
+            line["max_abs_err"] = chk.pop("max_abs_err")
+            line["stats_exact"] = chk.pop("stats_exact", None)
+            line["check"] = chk
+        print(json.dumps(line), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -110,6 +273,8 @@ def main() -> int:
                     help="fix the split (evaluation positions); overrides --partition")
     ap.add_argument("--cost-model", default=None, help="cost model file (default: the package's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip checking the timed step's outputs against the oracle leg's references")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape instead of sweeping it")
     ap.add_argument("--no-fuse", action="store_true",
@@ -119,6 +284,12 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-eq8", action="store_true",
                     help="skip timing the Eq. (8) split when the chosen split differs")
+    ap.add_argument("--threshold", type=float, default=None,
+                    help="pruning threshold t (default: the workload's own, 0 for every workload)")
+    ap.add_argument("--sweep", default=None, metavar="T1,T2,...",
+                    help="threshold sweep (Section V, QAOA): one JSON line per threshold with run "
+                         "time, fidelity against the state vector and the oracle check; replaces "
+                         "the single benchmark line")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -144,6 +315,10 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     cfg = w.CONFIGS[args.workload]()
+    if args.threshold is not None:
+        cfg["threshold"] = args.threshold
+    if args.sweep:
+        return sweep(args, cfg)
     text = cfg["circuit"].to_text()
     ctx = fhs.Context(0)
     M, S = len(cfg["outputs"]), len(cfg["inputs"])
@@ -207,6 +382,7 @@ def main() -> int:
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / max(args.steps, 1)
     st = stats.cpu()
+    amps_host = amps.cpu().numpy().copy()
     # Dominant-kernel durations: the same K steps again with HIP events
     # around every consumer launch (direct launches instead of the graph).
     ctx.set_kernel_timing(True)
@@ -290,7 +466,9 @@ def main() -> int:
         "amplitudes_per_s": M * S / T,
         "leaf_histories_per_s": leaves / T,
         "valid_histories_per_s": valid / T,
-        "gate_ops_per_s": M * S * prog.partition_cost(*part)[0] / T,
+        # Eq. (8) gate evaluations per second: the paper's work measure, counted gate
+        # by gate (folded ladders count every gate they replace)
+        "eq8_gate_ops_per_s": M * S * prog.partition_cost(*part)[0] / T,
         "roofline": roof,
     }
     if tuple(part) != tuple(part_eq8) and not args.no_eq8:
@@ -317,8 +495,12 @@ def main() -> int:
                             "chunk": best_e[1], "histories_per_s": cand / Te,
                             "learned_speedup": Te / T}
     if not args.no_plain:
-        # Algorithm 1 at its own best lane shape (histories per lane 1 or 2,
-        # interpreted dispatch), one timed pass each after a warm-up pass.
+        # Algorithm 1 (no checkpoint) in two code generations: the plain
+        # kernel with the interpreted program on a static grid (the baseline
+        # form, at its own best lane shape: 1 or 2 histories per lane), and
+        # the same straight-line compiled regions as the batched form with
+        # cuts (0, 0), so that the learned split's gain is also measured
+        # like for like.  One timed pass each after a warm-up pass.
         saved = ctx.launch_config
         best = None
         for h in (1, 2):
@@ -331,11 +513,33 @@ def main() -> int:
             tp = time.perf_counter() - t0
             if best is None or tp < best[0]:
                 best = (tp, h)
-        ctx.set_launch_config(*saved)
         Tp = best[0]
         out["plain"] = {"ms_per_step": Tp * 1e3, "histories_per_s": cand / Tp,
                         "amplitudes_per_s": M * S / Tp, "batched_speedup": Tp / T,
-                        "histories_per_lane": best[1]}
+                        "histories_per_lane": best[1], "dispatch": "interpreted (k_plain)"}
+        if saved[3] == 3 and prog.A > 0:
+            ctx.set_launch_config(*saved)
+            ctx.set_partition(0, 0)
+            try:
+                step()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                step()
+                torch.cuda.synchronize()
+                tc = time.perf_counter() - t0
+                out["plain_compiled"] = {
+                    "ms_per_step": tc * 1e3, "histories_per_s": cand / tc,
+                    "batched_speedup": tc / T, "partition": [0, 0],
+                    "dispatch": "compiled regions (fhs_consume_compiled), cuts (0, 0)"}
+            except fhs.FhsError as e:      # a region too long to compile, or no table space
+                out["plain_compiled"] = {"skipped": str(e)}
+            ctx.set_partition(*part)
+        ctx.set_launch_config(*saved)
+    if not args.no_check:
+        chk = oracle_check(args.workload, cfg, text, amps_host, st.numpy(), thr, part, prog.A)
+        out["max_abs_err"] = chk.pop("max_abs_err")
+        out["stats_exact"] = chk.pop("stats_exact", None)
+        out["check"] = chk
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(text, cfg["inputs"], cfg["outputs"], part, thr)
     print(json.dumps(out), flush=True)

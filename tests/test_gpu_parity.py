@@ -175,6 +175,50 @@ def test_qaoa_pruning_sampled(ctx, thr):
         assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64))
 
 
+@pytest.mark.parametrize("thr", [1e-6, 1e-4])
+def test_qaoa12_config_thresholds(ctx, thr):
+    """The 12-vertex QAOA workload at its own pruning thresholds: 16 sampled
+    outputs of the 4096, the plain form and the batched form at Eq. (8)'s
+    split and at the cost model's three best predicted splits for the whole
+    workload (the splits the benchmark's shortlist times), under the
+    compiled consumer (one and two histories per lane) and the interpreter;
+    amplitudes and valid sets against the oracle.  Pruning decisions are
+    bit-exact: at 1e-6 about 85% of each output's 2^24 histories survive, at
+    1e-4 none does (every amplitude exactly 0)."""
+    from paper_2608_01467_amd import tune
+    cfg = w.CONFIGS["qaoa_12v_p2"]()
+    t = cfg["circuit"].to_text()
+    prog = fhs.Program(t)
+    rng = np.random.default_rng(11)
+    outs = sorted(int(x) for x in rng.choice(4096, size=16, replace=False))
+    eq8 = prog.choose_partition(fhs.PART_EQ8)
+    ref_a, ref_st = oracle.Feynman(t).evaluate([0], [1], outs, threshold=thr, partition=eq8,
+                                               threads=THREADS)
+    if thr == 1e-4:
+        assert (ref_st[:, 0] == 0).all() and (ref_a == 0).all()
+    else:
+        assert (ref_st[:, 0] > 0).all()
+    splits = [eq8]
+    blob = tune.load_model()
+    if blob is not None:
+        ctx.load(prog)
+        ctx.load_cost_model(blob)
+        cand = prog.candidate_splits()
+        pred = ctx.predict_splits(cand, len(cfg["outputs"]), 1)
+        order = [cand[i] for i in np.argsort(np.where(np.isnan(pred), np.inf, pred), kind="stable")
+                 if not np.isnan(pred[i])]
+        splits += [c for c in order[:3] if c != eq8]
+    runs = [((0, 0), True, (0, 0, 0))]
+    runs += [(p, False, launch) for p in splits for launch in ((1, 256, 3), (2, 256, 3))]
+    runs += [(eq8, False, (2, 256, 0))]
+    for part, plain, (h, chunk, dispatch) in runs:
+        ctx.set_launch_config(h, chunk, 0, dispatch)
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, thr=thr, partition=part, plain=plain, prog=prog)
+        assert np.abs(amps - ref_a).max() <= TOL, (thr, part, plain, h, dispatch)
+        assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), (thr, part, plain, h)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_qaoa8_pruning_all_partitions(ctx):
     t = w.qaoa_maxcut(8, 2, 411, 412)[0].to_text()
     for thr in (0.0, 1e-4, 3e-3):
@@ -240,11 +284,17 @@ def test_walk_config_full(ctx):
     outs = cfg["outputs"]
     dp = cf.walk_amplitudes(20)
     eq8 = prog.choose_partition(fhs.PART_EQ8)
-    runs = [(prog, eq8, False, (0, 0)), (prog, (0, 0), True, (0, 0)),
-            (prog, (2984, 3581), False, (1, 3)), (prog, (3183, 3581), False, (2, 3)),
-            (prog, eq8, False, (2, 3)), (folded, (2984, 3581), False, (1, 3))]
-    for pg, part, plain, (h, dispatch) in runs:
-        ctx.set_launch_config(h, 0, 0, dispatch)
+    runs = [(prog, eq8, False, (0, 0, 0)), (prog, (0, 0), True, (0, 0, 0)),
+            (prog, (2984, 3581), False, (1, 0, 3)), (prog, (3183, 3581), False, (2, 0, 3)),
+            (prog, eq8, False, (2, 0, 3)), (folded, (2984, 3581), False, (1, 0, 3))]
+    # the splits the learned shortlist picks for this workload, in the launch
+    # shape the benchmark's autotuner settles on (2 histories per lane, chunk
+    # 256, compiled consumer and prefix build): each split is its own
+    # compiled module
+    shortlist = [(1989, 2785), (1989, 2984), (2188, 2785), (2188, 2984)]
+    runs += [(prog, p, False, (2, 256, 3)) for p in shortlist]
+    for pg, part, plain, (h, chunk, dispatch) in runs:
+        ctx.set_launch_config(h, chunk, 0, dispatch)
         amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=pg)
         for y, a, row in zip(outs[:42], amps[:42], st[:42]):
             x = y >> 1
