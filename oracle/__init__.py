@@ -54,6 +54,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.orc_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(P)]
+        lib.orc_load_ex.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P)]
         lib.orc_free.argtypes = [P]
         lib.orc_free.restype = None
         lib.orc_info.argtypes = [P] + [ctypes.POINTER(ctypes.c_int)] * 4
@@ -90,14 +91,22 @@ def _check(rc: int, what: str) -> None:
 
 
 class Feynman:
-    """O2: the paper's reduced-history method on the CPU (plain C)."""
+    """O2: the paper's reduced-history method on the CPU (plain C).
+
+    placement: "backward" (the paper's sweep from the output, Section IV-A)
+    or "forward" (the sweep from the input, Table I's other column); the
+    sweep direction is also the evaluation order that the cuts of
+    Algorithm 2 index."""
 
     ROLE_PRESERVE, ROLE_DET, ROLE_BRANCH = 0, 1, 2
 
-    def __init__(self, circuit_text: str):
+    def __init__(self, circuit_text: str, placement: str = "backward"):
         lib = _load()
         h = ctypes.c_void_p()
-        _check(lib.orc_load(circuit_text.encode(), ctypes.byref(h)), "orc_load")
+        if placement not in ("backward", "forward"):
+            raise ValueError(f"unknown placement {placement!r}")
+        _check(lib.orc_load_ex(circuit_text.encode(), 1 if placement == "forward" else 0,
+                               ctypes.byref(h)), "orc_load")
         self._h = h
         n, G, A, ns = (ctypes.c_int() for _ in range(4))
         lib.orc_info(h, ctypes.byref(n), ctypes.byref(G), ctypes.byref(A), ctypes.byref(ns))

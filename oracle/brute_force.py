@@ -8,8 +8,10 @@ circuits of a few qubits and gates.  It knows nothing of wire segments,
 sources or propagation, which is what lets it pin the C oracle's counts.
 
 Threshold rule (the same reading as the C oracle): a history is kept iff the
-product, in evaluation order (output to input), of min(1, |factor|) over the
-gates that branch (a matrix column with more than one nonzero) is >= t.
+product, in evaluation order, of min(1, |factor|) over the gates that branch
+(a matrix column with more than one nonzero) is >= t.  The evaluation order
+runs from the output to the input (the backward sweep), or from the input to
+the output when the sources are placed by the forward sweep.
 """
 from __future__ import annotations
 
@@ -37,9 +39,10 @@ def _gate_unitaries(text: str):
     return n, us, branch
 
 
-def path_sum(text: str, b_in: int, b_out: int, threshold: float = 0.0
+def path_sum(text: str, b_in: int, b_out: int, threshold: float = 0.0, forward: bool = False
              ) -> Tuple[complex, int]:
-    """(amplitude, number of kept histories) for one input/output pair."""
+    """(amplitude, number of kept histories) for one input/output pair;
+    forward: evaluation order from the input."""
     n, us, branch = _gate_unitaries(text)
     m = len(us)
     total = 0j
@@ -53,7 +56,7 @@ def path_sum(text: str, b_in: int, b_out: int, threshold: float = 0.0
                 return
             amp = 1 + 0j
             M = 1.0
-            for s in range(m - 1, -1, -1):         # evaluation order
+            for s in (range(m) if forward else range(m - 1, -1, -1)):   # evaluation order
                 f = us[s][path[s + 1], path[s]]
                 amp = amp * f
                 if branch[s]:

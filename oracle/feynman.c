@@ -11,13 +11,22 @@
  *     preserving incidences (diagonal gates, control roles) keep the segment;
  *   - gate roles (Section II-A): diagonal -> wire-preserving, exactly one
  *     nonzero per column -> deterministic, otherwise branching;
- *   - backward source placement (Section IV-A): an artificial source sits on
- *     the input-side segment of every branching gate whose input segment is
- *     not a natural input segment; sources are numbered in the output->input
- *     sweep order, source k being bit k of the history index h;
- *   - Algorithm 1 (SetBoundaryWires, PropagateKnownValues, SetArtificialSources,
- *     EvaluateHistory) and Algorithm 2 (AdvanceCheckpoint over the prefix,
- *     root and suffix regions, in evaluation order from the output);
+ *   - source placement by one sweep (Section IV-A; Section IV-F, Table I):
+ *     backward (the paper's choice): an artificial source sits on the
+ *     input-side segment of every branching gate whose input segment is not
+ *     a natural input segment, numbered in the output->input sweep order;
+ *     forward: on the output-side segment of every branching gate whose
+ *     output segment is not a natural output segment, numbered in the
+ *     input->output sweep order; source k is bit k of the history index h,
+ *     and the sweep direction is the evaluation order;
+ *   - the reduced sum of Eq. (7) (Algorithm 1) and its checkpointed form
+ *     (Algorithm 2), both as one walk over evaluation-order regions: the
+ *     boundary values and everything they imply are fixed first; then, region
+ *     by region, each assignment of the region's sources is fixed, what it
+ *     implies is propagated inside the region, and the region's gate factors
+ *     are multiplied in, before the later regions are walked; one region is
+ *     Algorithm 1, the cuts c1 <= c2 give Algorithm 2's prefix, root and
+ *     suffix;
  *   - Eq. (8) gate-operation estimate and its argmin over all cut pairs
  *     (Section IV-C, "Autotuned Partitioning"), in exact 128-bit integers.
  *
@@ -28,7 +37,7 @@
  *
  * Readings where the paper leaves the arithmetic open:
  *   - threshold pruning: a history is dropped iff M < t, where M is the
- *     product, in evaluation order (output->input), of min(1, |U_g[out,in]|)
+ *     product, in evaluation order, of min(1, |U_g[out,in]|)
  *     over branching gates g; M never grows, so where the test sits does not
  *     change the result; t = 0 prunes nothing;
  *   - a history is valid iff propagation never conflicts, no gate factor is an
@@ -74,6 +83,7 @@ typedef struct {
 
 typedef struct {
     int n, G, A, nseg;
+    int forward;            /* 1: forward placement, evaluation order = time order */
     ogate *g;               /* time order */
     int out_seg[ORC_MAXQ];  /* segment carrying each qubit at the output */
     int *src_seg;           /* [A] segment fixed by source k */
@@ -235,8 +245,9 @@ void orc_free(orc_circuit *c) {
     free(c);
 }
 
-int orc_load(const char *text, orc_circuit **out) {
+int orc_load_ex(const char *text, int forward, orc_circuit **out) {
     *out = NULL;
+    if (forward != 0 && forward != 1) return ORC_EINVAL;
     orc_circuit *c = (orc_circuit *)calloc(1, sizeof(orc_circuit));
     int cap = 64, rc = ORC_OK;
     c->g = (ogate *)calloc(cap, sizeof(ogate));
@@ -306,28 +317,36 @@ int orc_load(const char *text, orc_circuit **out) {
     for (int q = 0; q < c->n; ++q) c->out_seg[q] = cur[q];
     c->nseg = next;
 
-    /* backward placement: sweep from the output; a branching gate whose
-     * input-side segment is not an input segment gets a source */
+    /* source placement: one sweep; a branching gate whose segment on the
+     * side the sweep reaches last (input side for the backward sweep,
+     * output side for the forward one) is not a boundary segment gets a
+     * source there */
+    c->forward = forward;
     c->src_seg = (int *)malloc(sizeof(int) * (c->G + 1));
     c->src_gate = (int *)malloc(sizeof(int) * (c->G + 1));
     c->src_eval = (int *)malloc(sizeof(int) * (c->G + 1));
     c->A = 0;
-    for (int t = c->G - 1; t >= 0; --t) {
+    for (int e = 0; e < c->G; ++e) {
+        int t = forward ? e : c->G - 1 - e;
         ogate *g = &c->g[t];
         if (g->role != ROLE_BRANCH) continue;
         for (int j = 0; j < g->k; ++j) {
             if (local_preserved(g, j)) continue;
-            if (g->in_seg[j] < c->n) continue;        /* natural input segment */
+            int seg = forward ? g->out_seg[j] : g->in_seg[j];
+            int natural = forward ? seg == c->out_seg[g->q[j]] : seg < c->n;
+            if (natural) continue;
             if (c->A >= c->G) { orc_free(c); return ORC_EINTERNAL; }
-            c->src_seg[c->A] = g->in_seg[j];
+            c->src_seg[c->A] = seg;
             c->src_gate[c->A] = t;
-            c->src_eval[c->A] = c->G - 1 - t;
+            c->src_eval[c->A] = e;
             c->A++;
         }
     }
     *out = c;
     return ORC_OK;
 }
+
+int orc_load(const char *text, orc_circuit **out) { return orc_load_ex(text, 0, out); }
 
 int orc_info(const orc_circuit *c, int *n, int *G, int *A, int *nseg) {
     *n = c->n; *G = c->G; *A = c->A; *nseg = c->nseg;
@@ -465,11 +484,22 @@ static double modulus1(cplx z) {
     return m > 1.0 ? 1.0 : m;
 }
 
-/* EvaluateHistory restricted to time indices [t0,t1), walked from t1-1 down
- * to t0 (evaluation order).  Returns 0 ok, 1 zero factor, 2 pruned. */
-static int evaluate(const orc_circuit *c, const signed char *val, int t0, int t1,
+/* Time index of evaluation position e (backward sweep: from the output). */
+static int time_of(const orc_circuit *c, int e) { return c->forward ? e : c->G - 1 - e; }
+
+/* The time indices [t0, t1) that evaluation positions [e0, e1) cover. */
+static void time_span(const orc_circuit *c, int e0, int e1, int *t0, int *t1) {
+    if (c->forward) { *t0 = e0; *t1 = e1; }
+    else { *t0 = c->G - e1; *t1 = c->G - e0; }
+}
+
+/* Multiply the gate factors of evaluation positions [e0, e1), in evaluation
+ * order, into the partial history (Eq. (4)); every wire must be resolved.
+ * Returns 0 ok, 1 zero factor, 2 pruned. */
+static int evaluate(const orc_circuit *c, const signed char *val, int e0, int e1,
                     double thr, partial *pa, uint64_t *gate_evals) {
-    for (int t = t1 - 1; t >= t0; --t) {
+    for (int e = e0; e < e1; ++e) {
+        const int t = time_of(c, e);
         const ogate *g = &c->g[t];
         cplx f;
         for (int j = 0; j < g->k; ++j) {
@@ -538,70 +568,74 @@ static void acc_history(acc_t *a, cplx amp, uint64_t h) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 1 and Algorithm 2 for one (b_in, b_out) pair              */
+/* the reduced sum over artificial sources, region by region            */
 /* ------------------------------------------------------------------ */
 
-static void alg1(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
-                 double thr, acc_t *a) {
-    signed char *c0 = (signed char *)malloc((size_t)c->nseg);
-    signed char *ch = (signed char *)malloc((size_t)c->nseg);
-    if (set_boundary(c, c0, bin, bout) == 0 && propagate(c, c0, 0, c->G) == 0) {
-        uint64_t nh = 1ULL << c->A;
-        for (uint64_t h = 0; h < nh; ++h) {
-            memcpy(ch, c0, (size_t)c->nseg);
-            if (set_sources(c, ch, 0, c->A, h)) continue;
-            if (propagate(c, ch, 0, c->G)) continue;
-            partial pa = {{1.0, 0.0}, 1.0};
-            if (evaluate(c, ch, 0, c->G, thr, &pa, &a->gate_evals)) continue;
-            acc_history(a, pa.amp, h);
-        }
+/* Evaluation-order regions [cut[r], cut[r+1]) and the sources whose gates
+ * they contain: na[r] consecutive source numbers from k0[r] (sources are
+ * numbered in evaluation order). */
+typedef struct { int nr; int cut[4]; int k0[3]; int na[3]; } regions_t;
+
+static void make_regions(const orc_circuit *c, const int *cuts, int nr, regions_t *R) {
+    R->nr = nr;
+    for (int r = 0; r <= nr; ++r) R->cut[r] = cuts[r];
+    int k = 0;
+    for (int r = 0; r < nr; ++r) {
+        R->k0[r] = k;
+        R->na[r] = 0;
+        while (k < c->A && c->src_eval[k] < cuts[r + 1]) { ++R->na[r]; ++k; }
     }
-    free(c0); free(ch);
 }
 
-/* AdvanceCheckpoint: assign the region's sources, propagate inside the
- * region, multiply the region's factors.  Region = time indices [t0,t1),
- * sources [k0, k0+na).  Returns 0 on success (dst filled). */
-static int advance(const orc_circuit *c, const signed char *src, signed char *dst,
-                   int t0, int t1, int k0, int na, uint64_t hbits, double thr,
-                   partial *pa, uint64_t *gate_evals) {
-    memcpy(dst, src, (size_t)c->nseg);
-    if (set_sources(c, dst, k0, na, hbits)) return -1;
-    if (propagate(c, dst, t0, t1)) return -1;
-    if (evaluate(c, dst, t0, t1, thr, pa, gate_evals)) return -1;
-    return 0;
+/* Add to `acc` every valid history that extends a partial one: `val` holds
+ * the wire values fixed by the boundary and by the sources of regions
+ * before r (with everything they imply), `pa` the product of those regions'
+ * factors and `h` their source bits.  Each assignment of region r's sources
+ * (only those in [lo, hi) for the first region) is fixed and propagated
+ * inside the region, the region's factors are multiplied in, and the later
+ * regions are walked the same way; a conflict, a zero factor or a pruned
+ * product drops the subtree.  bufs[r] is region r's scratch copy. */
+static void walk_regions(const orc_circuit *c, const regions_t *R, int r, const signed char *val,
+                         partial pa, uint64_t h, uint64_t lo, uint64_t hi, double thr, acc_t *acc,
+                         signed char **bufs) {
+    if (r == R->nr) {
+        acc_history(acc, pa.amp, h);
+        return;
+    }
+    const uint64_t n = 1ULL << R->na[r];
+    const uint64_t x0 = r == 0 ? lo : 0, x1 = (r == 0 && hi < n) ? hi : n;
+    int t0, t1;
+    time_span(c, R->cut[r], R->cut[r + 1], &t0, &t1);
+    signed char *v = bufs[r];
+    for (uint64_t x = x0; x < x1; ++x) {
+        memcpy(v, val, (size_t)c->nseg);
+        if (set_sources(c, v, R->k0[r], R->na[r], x)) continue;
+        if (propagate(c, v, t0, t1)) continue;
+        partial p2 = pa;
+        if (evaluate(c, v, R->cut[r], R->cut[r + 1], thr, &p2, &acc->gate_evals)) continue;
+        walk_regions(c, R, r + 1, v, p2, h | (x << R->k0[r]), lo, hi, thr, acc, bufs);
+    }
 }
 
-static void alg2(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
-                 double thr, int c1, int c2, uint64_t hp_lo, uint64_t hp_hi, acc_t *a) {
-    /* eval cuts -> time ranges: prefix = [G-c1, G), root = [G-c2, G-c1), suffix = [0, G-c2) */
-    int G = c->G;
-    int Ap = 0, Ar = 0, As = 0;
-    for (int k = 0; k < c->A; ++k) {
-        int e = c->src_eval[k];
-        if (e < c1) ++Ap; else if (e < c2) ++Ar; else ++As;
-    }
+/* The transition amplitude of one (b_in, b_out) pair as the reduced sum of
+ * Eq. (7), walked over the given evaluation-order cuts (nr regions; first
+ * region's assignments restricted to [lo, hi)).  The boundary values and
+ * what they imply are fixed once; a pair they already contradict has no
+ * valid history. */
+static void reduced_sum(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout, double thr,
+                        const int *cuts, int nr, uint64_t lo, uint64_t hi, acc_t *acc) {
+    regions_t R;
+    make_regions(c, cuts, nr, &R);
     size_t ns = (size_t)c->nseg;
-    signed char *s0 = (signed char *)malloc(ns), *sp = (signed char *)malloc(ns);
-    signed char *sr = (signed char *)malloc(ns), *ss = (signed char *)malloc(ns);
-    if (set_boundary(c, s0, bin, bout) == 0 && propagate(c, s0, 0, G) == 0) {
-        if (hp_hi > (1ULL << Ap)) hp_hi = 1ULL << Ap;
-        for (uint64_t hp = hp_lo; hp < hp_hi; ++hp) {
-            partial pp = {{1.0, 0.0}, 1.0};
-            if (advance(c, s0, sp, G - c1, G, 0, Ap, hp, thr, &pp, &a->gate_evals)) continue;
-            for (uint64_t hr = 0; hr < (1ULL << Ar); ++hr) {
-                partial pr = pp;
-                if (advance(c, sp, sr, G - c2, G - c1, Ap, Ar, hr, thr, &pr, &a->gate_evals)) continue;
-                for (uint64_t hs = 0; hs < (1ULL << As); ++hs) {
-                    partial ps = pr;
-                    if (advance(c, sr, ss, 0, G - c2, Ap + Ar, As, hs, thr, &ps, &a->gate_evals)) continue;
-                    uint64_t h = hp | (hr << Ap) | (hs << (Ap + Ar));
-                    acc_history(a, ps.amp, h);
-                }
-            }
-        }
+    signed char *v0 = (signed char *)malloc(ns);
+    signed char *bufs[3];
+    for (int r = 0; r < 3; ++r) bufs[r] = (signed char *)malloc(ns);
+    if (set_boundary(c, v0, bin, bout) == 0 && propagate(c, v0, 0, c->G) == 0) {
+        partial one = {{1.0, 0.0}, 1.0};
+        walk_regions(c, &R, 0, v0, one, 0, lo, hi, thr, acc, bufs);
     }
-    free(s0); free(sp); free(sr); free(ss);
+    free(v0);
+    for (int r = 0; r < 3; ++r) free(bufs[r]);
 }
 
 /* One transition amplitude.  c1 < 0 selects Algorithm 1.
@@ -613,8 +647,13 @@ int orc_pair(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
     if (c1 >= 0 && (c1 > c2 || c2 > c->G)) return ORC_EINVAL;
     acc_t a;
     memset(&a, 0, sizeof(a));
-    if (c1 < 0) alg1(c, bin, bout, thr, &a);
-    else alg2(c, bin, bout, thr, c1, c2, 0, ~0ULL, &a);
+    if (c1 < 0) {
+        const int cuts[2] = {0, c->G};               /* Algorithm 1: one region */
+        reduced_sum(c, bin, bout, thr, cuts, 1, 0, ~0ULL, &a);
+    } else {
+        const int cuts[4] = {0, c1, c2, c->G};       /* Algorithm 2: prefix, root, suffix */
+        reduced_sum(c, bin, bout, thr, cuts, 3, 0, ~0ULL, &a);
+    }
     amp[0] = a.re.s + a.re.c;
     amp[1] = a.im.s + a.im.c;
     stats[0] = a.n_valid; stats[1] = a.sum_h; stats[2] = a.xor_h; stats[3] = a.gate_evals;
@@ -674,7 +713,8 @@ int orc_sample(const orc_circuit *c, const uint64_t *bin, const uint64_t *output
     for (int j = 0; j < M; ++j) {
         acc_t a;
         memset(&a, 0, sizeof(a));
-        alg2(c, bin, outputs + (size_t)j * W, thr, c1, c2, hp_lo, hp_hi, &a);
+        const int cuts[4] = {0, c1, c2, c->G};
+        reduced_sum(c, bin, outputs + (size_t)j * W, thr, cuts, 3, hp_lo, hp_hi, &a);
         amps[2 * j] = a.re.s + a.re.c;
         amps[2 * j + 1] = a.im.s + a.im.c;
         stats[4 * (size_t)j] = a.n_valid;

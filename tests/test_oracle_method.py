@@ -37,6 +37,23 @@ def test_alg2_equals_alg1_every_split(seed):
             assert got[1:4] == ref[1:4], (c1, c2)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_alg2_equals_alg1_every_split_forward(seed):
+    """The same invariant under forward placement: cuts index time order."""
+    n = 2 + seed % 4
+    c = w.random_mixed(n, 5 + seed % 7, 800 + seed)
+    F = oracle.Feynman(c.to_text(), "forward")
+    rng = np.random.default_rng(seed)
+    b_in = int(rng.integers(0, 1 << n))
+    thr = [0.0, 0.1][seed % 2]
+    for b_out in range(1 << n):
+        ref = F.pair(b_in, b_out, threshold=thr)
+        for c1, c2 in _all_splits(F.G):
+            got = F.pair(b_in, b_out, threshold=thr, partition=(c1, c2))
+            assert abs(got[0] - ref[0]) <= 1e-12
+            assert got[1:4] == ref[1:4], (c1, c2)
+
+
 def test_eq8_equals_gate_evaluations_qaoa():
     # QAOA has no exact-pruning failures: every history is valid at t = 0
     c, *_ = w.qaoa_maxcut(4, 1, 3, 4)
@@ -57,6 +74,19 @@ def test_eq8_equals_gate_evaluations_aa():
         _, nv, _, _, evals = F.pair(0, 0b101, partition=(c1, c2))
         assert nv == 1 << F.A
         assert evals == F.eq8(c1, c2)
+
+
+def test_eq8_equals_gate_evaluations_forward():
+    """Under forward placement QAOA's sources are the Hadamard layer and
+    every RX layer but the last; with nothing pruned the instrumented count
+    is again Eq. (8) at every cut pair (cuts in time order)."""
+    c, *_ = w.qaoa_maxcut(4, 2, 3, 4)
+    F = oracle.Feynman(c.to_text(), "forward")
+    assert F.A == 8
+    for c1, c2 in list(_all_splits(F.G))[::7]:
+        _, nv, _, _, evals = F.pair(0, 0b0110, partition=(c1, c2))
+        assert nv == 1 << F.A
+        assert evals == F.eq8(c1, c2), (c1, c2)
 
 
 def _eq8_py(G, pos, c1, c2):

@@ -165,6 +165,62 @@ def test_table1_backward_source_counts():
             assert oracle.Feynman(w.quantum_walk(n_pos, s).to_text()).A == s - 1
 
 
+def test_table1_forward_source_counts():
+    """Table I's forward column.  QFT: a source on the output side of every
+    Hadamard whose qubit reaches the output through the final swaps (n for
+    even n; for odd n the middle qubit is not swapped, its Hadamard's output
+    segment is natural, n - 1).  Amplitude amplification and QAOA: the last
+    layer of branching gates reaches the output directly, as the first layer
+    reaches the input backward, so both columns agree.  Quantum walk: s when
+    the coin-0 shift is written with X gates on the coin, which end the last
+    Hadamard's output segment; with negatively controlled gates the coin
+    reaches the output unchanged and the count is s - 1 both ways."""
+    g = golden("table1_sources")
+    assert g["A_forward"] == {"qft": "n", "amplitude_amplification": "2*s*n", "qaoa": "s*n",
+                              "quantum_walk": "s"}
+    for n in range(2, 13):
+        assert oracle.Feynman(w.qft(n).to_text(), "forward").A == (n if n % 2 == 0 else n - 1)
+    for k in (3, 4, 5, 6):
+        for s in (1, 2, 3):
+            c, _ = w.amplitude_amplification(k, s, 4, seed=7 + k)
+            assert oracle.Feynman(c.to_text(), "forward").A == 2 * s * k
+    for nv in (4, 6, 8, 12, 24):
+        for p in (1, 2, 3):
+            c, *_ = w.qaoa_maxcut(nv, p, 11, 12)
+            assert oracle.Feynman(c.to_text(), "forward").A == p * nv
+    for n_pos in (3, 8, 99):
+        for s in (1, 2, 5, 20):
+            xw = w.quantum_walk_xcoin(n_pos, s).to_text()
+            assert oracle.Feynman(xw, "forward").A == s
+            assert oracle.Feynman(xw).A == s - 1
+            assert oracle.Feynman(w.quantum_walk(n_pos, s).to_text(), "forward").A == s - 1
+
+
+def test_walk_constructions_agree():
+    """The two walk constructions are the same unitary."""
+    for n_pos, s in ((2, 3), (4, 4), (5, 2)):
+        a = sv.unitary(w.quantum_walk(n_pos, s).to_text())
+        b = sv.unitary(w.quantum_walk_xcoin(n_pos, s).to_text())
+        assert np.abs(a - b).max() <= 1e-15
+
+
+def test_forward_sources_on_output_side():
+    """Forward placement on the paper's Fig. 2 circuit: sources sit on the
+    output side of the Hadamards whose output segment does not reach the
+    output, numbered from the input, and the amplitudes equal the backward
+    placement's and the state vector's."""
+    g = golden("fig2_four_qubit")
+    t = g["circuit"]
+    Fb, Ff = oracle.Feynman(t), oracle.Feynman(t, "forward")
+    pos = Ff.source_eval_positions
+    assert pos == sorted(pos)
+    U = sv.unitary(t)
+    for i in range(16):
+        ab, _ = Fb.evaluate([i], [1], list(range(16)))
+        af, _ = Ff.evaluate([i], [1], list(range(16)))
+        assert np.abs(af - U[:, i]).max() <= 1e-15 and np.abs(af - ab).max() <= 1e-15
+
+
 # --------------------------------------------------------------------------
 # closed forms (pin O1 and O2 at sizes the state vector cannot reach)
 # --------------------------------------------------------------------------
@@ -290,5 +346,42 @@ def test_counts_and_threshold_against_brute_force(seed):
         for b_out in range(1 << n):
             amp, nv, *_ = F.pair(b_in, b_out, threshold=thr)
             amp_b, nv_b = bf.path_sum(t, b_in, b_out, threshold=thr)
+            assert nv == nv_b, (thr, b_out)
+            assert abs(amp - amp_b) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(0, 300))
+def test_forward_random_against_statevector(seed):
+    """Forward placement (Table I's other column) reaches the same exact
+    amplitudes on random circuits over the whole gate vocabulary."""
+    n = 1 + seed % 6
+    c = w.random_mixed(n, 4 + seed % 11, 7000 + seed)
+    t = c.to_text()
+    F = oracle.Feynman(t, "forward")
+    rng = np.random.default_rng(seed)
+    S = 1 + seed % 3
+    inputs = [int(v) for v in rng.choice(1 << n, size=min(S, 1 << n), replace=False)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in inputs]
+    outs = list(range(1 << n))
+    amps, _ = F.evaluate(inputs, coeffs, outs)
+    ref = sv.amplitudes(t, inputs, coeffs, outs)
+    assert np.abs(amps - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_forward_counts_and_threshold_against_brute_force(seed):
+    """Valid-history counts and thresholded amplitudes under forward
+    placement against the naive path sum with the modulus product taken from
+    the input."""
+    n = 1 + seed % 4
+    c = w.random_mixed(n, 3 + seed % 6, 3000 + seed)
+    t = c.to_text()
+    F = oracle.Feynman(t, "forward")
+    rng = np.random.default_rng(seed)
+    b_in = int(rng.integers(0, 1 << n))
+    for thr in (0.0, 0.05, 0.3, 0.6):
+        for b_out in range(1 << n):
+            amp, nv, *_ = F.pair(b_in, b_out, threshold=thr)
+            amp_b, nv_b = bf.path_sum(t, b_in, b_out, threshold=thr, forward=True)
             assert nv == nv_b, (thr, b_out)
             assert abs(amp - amp_b) <= 1e-12

@@ -34,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "Gate", "Circuit", "random_clifford_t", "random_mixed", "random_ladders", "qft", "amplitude_amplification",
-    "qaoa_maxcut", "quantum_walk", "random_outputs", "bits_to_words",
+    "qaoa_maxcut", "quantum_walk", "quantum_walk_xcoin", "random_outputs", "bits_to_words",
     "words_to_bits", "n_words", "three_regular_graph", "CONFIGS",
 ]
 
@@ -402,6 +402,27 @@ def quantum_walk(n_pos: int, steps: int) -> Circuit:
         for i in range(n_pos - 1, -1, -1):
             ctrls = [0] + pos[:i]
             c.add("MCX", pos[i], *ctrls, negs=(False,) + (True,) * len(ctrls))
+    return c
+
+
+def quantum_walk_xcoin(n_pos: int, steps: int) -> Circuit:
+    """The same walk with the coin-0 shift written as X on the coin, the
+    positively controlled decrement cascade, and X on the coin again (the
+    same unitary as quantum_walk; the X gates are deterministic, so the coin
+    wire's segments end at them)."""
+    n = n_pos + 1
+    c = Circuit(n)
+    pos = list(range(1, n))
+    for _ in range(steps):
+        c.add("H", 0)
+        for i in range(n_pos - 1, -1, -1):
+            ctrls = [0] + pos[:i]
+            c.add("MCX", pos[i], *ctrls, negs=(False,) * (1 + len(ctrls)))
+        c.add("X", 0)
+        for i in range(n_pos - 1, -1, -1):
+            ctrls = [0] + pos[:i]
+            c.add("MCX", pos[i], *ctrls, negs=(False, False) + (True,) * (len(ctrls) - 1))
+        c.add("X", 0)
     return c
 
 
