@@ -302,6 +302,32 @@ fhs_status fhs_evaluate_plain(fhs_ctx *ctx,
                               double *d_amps, uint64_t *d_stats,
                               void *d_ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as fhs_evaluate, with no workspace argument.  Its workspace is
+ * a static device array of FHS_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library, one copy per GPU, held from the library's first use on that GPU
+ * until the process ends.  Output pairs are batched so that the whole
+ * workspace fits it (smaller batches than fhs_evaluate may use).  The call
+ * allocates nothing: no hipMalloc or hipFree, no graph instantiation (the
+ * launch sequence is enqueued directly on `stream`), no compilation (dispatch
+ * mode 3 uses a consumer only if fhs_evaluate or fhs_precompile already
+ * compiled it for this program, split, batch layout and launch shape;
+ * otherwise the interpreting kernels run); kernel timing is not recorded.
+ * The caller still owns and passes inputs and outputs (device pointers, as
+ * for fhs_evaluate).  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind (the kernels clear what must start at zero):
+ * calls that overlap on one GPU, from any context or stream, race and give
+ * undefined results; serialize them.  Errors as fhs_evaluate, plus
+ * FHS_ENOMEM when even one output pair per batch does not fit the array,
+ * and FHS_EHIP when the array's address could not be obtained on this
+ * device. */
+#define FHS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+fhs_status fhs_evaluate_noalloc(fhs_ctx *ctx,
+                                const uint64_t *d_inputs, const double *d_coeffs, uint32_t S,
+                                const uint64_t *d_outputs, uint32_t M, double threshold,
+                                double *d_amps, uint64_t *d_stats, void *stream);
+
 /* ---------------------------------------------------------------------
  * Learned split (cost model).  The paper picks the checkpoint partition by
  * minimising Eq. (8) (Section IV-C); here a small network, trained on the

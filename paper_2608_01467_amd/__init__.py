@@ -39,8 +39,10 @@ EXPORTS = [
     "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_kernel_counts", "fhs_get_plan",
     "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
     "fhs_precompile", "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
-    "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam",
+    "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam", "fhs_evaluate_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # FHS_NOALLOC_SCRATCH_BYTES
 
 N_FEATURES = 16
 
@@ -134,6 +136,7 @@ def lib() -> ctypes.CDLL:
         ev = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P, ctypes.c_size_t, P]
         L.fhs_evaluate.argtypes = ev
         L.fhs_evaluate_plain.argtypes = ev
+        L.fhs_evaluate_noalloc.argtypes = [P, P, P, U32, P, U32, ctypes.c_double, P, P, P]
         _lib = L
     return _lib
 
@@ -377,6 +380,28 @@ class Context:
         _check(fn(self._h, d_in.data_ptr(), d_cf.data_ptr(), S, d_out.data_ptr(), M,
                   float(threshold), amps.data_ptr(), stats.data_ptr(), ws.data_ptr(),
                   ws.numel(), ctypes.c_void_p(stream)), self)
+        return amps, stats
+
+    def evaluate_noalloc(self, inputs, coeffs, outputs, threshold: float = 0.0, out=None,
+                         stream=None):
+        """As evaluate(), through fhs_evaluate_noalloc: the library's static
+        scratch instead of a workspace, nothing allocated by the call (the
+        argument tensors are created here when not given as device tensors)."""
+        torch = self._torch
+        d_in = self.device_bits(inputs)
+        d_out = self.device_bits(outputs)
+        d_cf = self.device_coeffs(coeffs)
+        S, M = d_in.shape[0], d_out.shape[0]
+        if out is None:
+            amps = torch.empty((M, 2), dtype=torch.float64, device=d_out.device)
+            stats = torch.empty((M, 4), dtype=torch.int64, device=d_out.device)
+        else:
+            amps, stats = out
+        if stream is None:
+            stream = torch.cuda.current_stream(d_out.device).cuda_stream
+        _check(lib().fhs_evaluate_noalloc(self._h, d_in.data_ptr(), d_cf.data_ptr(), S,
+                                          d_out.data_ptr(), M, float(threshold), amps.data_ptr(),
+                                          stats.data_ptr(), ctypes.c_void_p(stream)), self)
         return amps, stats
 
 

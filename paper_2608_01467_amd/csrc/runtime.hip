@@ -23,6 +23,7 @@
 #include <iterator>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -121,7 +122,39 @@ struct fhs_ctx {
     uint32_t n_timed = 0;
     unsigned long long *d_valid = nullptr;  // timing mode: consistent prefix entries
     uint64_t n_entries = 0;                 // timing mode: prefix entries built
+    void *scratch = nullptr;                // this device's copy of the no-alloc scratch
 };
+
+// Workspace of fhs_evaluate_noalloc, for callers that cannot allocate: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host it is only
+// a stand-in for the symbol); it uses the address hipGetSymbolAddress gives
+// for the current device, looked up once per device when the first context
+// on it is created.
+static __device__ __align__(256) unsigned char scratch[FHS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];   // per device; nullptr until looked up
+
+// The device address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -180,8 +213,9 @@ void drop_graph(fhs_ctx *c) {
 
 int nw_of(const HostProgram &P) { return P.NW; }
 
-// Work layout for M outputs x S inputs under the context's program and cuts.
-fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
+// Work layout for M outputs x S inputs under the context's program and cuts,
+// with pairs batched so that one batch's prefix table fits `budget` bytes.
+fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t budget) {
     const HostProgram &P = c->prog;
     const uint64_t pairs = static_cast<uint64_t>(M) * S;
     if (pairs > 0xffffffffull / 4) return FHS_ERANGE;
@@ -216,8 +250,8 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
         if (pl.Ap > 30 || pl.Ar > 30) return FHS_ERANGE;
         const uint64_t per_pair = 1ull << pl.Ap;
         const size_t entry_bytes = sizeof(uint32_t) * NW + sizeof(double2) + sizeof(double) + sizeof(uint32_t);
-        if (per_pair * entry_bytes > c->table_budget) return FHS_ERANGE;   // one pair's table must fit
-        uint64_t B = c->table_budget / (per_pair * entry_bytes);
+        if (per_pair * entry_bytes > budget) return FHS_ERANGE;   // one pair's table must fit
+        uint64_t B = budget / (per_pair * entry_bytes);
         B = std::max<uint64_t>(1, std::min<uint64_t>(B, n_pairs));
         pl.B = static_cast<uint32_t>(B);
         pl.n_batches = (n_pairs + pl.B - 1) / pl.B;
@@ -261,9 +295,32 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
     return FHS_OK;
 }
 
+fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl) {
+    return make_plan(c, M, S, pl, c->table_budget);
+}
+
+// The plan with the largest table budget (at most the context's) whose whole
+// workspace fits `limit` bytes: the budget shrinks by the excess until it
+// fits.  FHS_ENOMEM when not even one pair per batch fits.
+fhs_status plan_within(const fhs_ctx *c, uint32_t M, uint32_t S, size_t limit, Plan &pl) {
+    size_t budget = std::min(c->table_budget, limit);
+    for (int it = 0; it < 64; ++it) {
+        const fhs_status st = make_plan(c, M, S, pl, budget);
+        if (st == FHS_ERANGE && budget < c->table_budget) return FHS_ENOMEM;   // one pair's table no longer fits
+        if (st != FHS_OK) return st;
+        if (pl.bytes <= limit) return FHS_OK;
+        const size_t excess = pl.bytes - limit;
+        const size_t next = budget > excess ? std::min(budget - excess, budget - budget / 16) : 0;
+        if (next < (size_t(1) << 10)) return FHS_ENOMEM;
+        budget = next;
+    }
+    return FHS_ENOMEM;
+}
+
 fhs_status check_eval_args(fhs_ctx *c, const uint64_t *in, const double *cf, uint32_t S,
                            const uint64_t *out, uint32_t M, double thr, double *amps,
-                           uint64_t *stats, void *ws, size_t ws_bytes, Plan &pl) {
+                           uint64_t *stats, void *ws, size_t ws_bytes, Plan &pl,
+                           bool fit_workspace = false) {
     if (!c) return FHS_EINVAL;
     c->err.clear();
     if (!c->loaded) return fail(c, FHS_ESTATE, "no program loaded");
@@ -272,7 +329,10 @@ fhs_status check_eval_args(fhs_ctx *c, const uint64_t *in, const double *cf, uin
     if (M == 0) return FHS_OK;
     if (S == 0) return fail(c, FHS_EINVAL, "S must be >= 1");
     if (!in || !cf || !out || !amps || !stats) return fail(c, FHS_EINVAL, "NULL buffer");
-    fhs_status st = make_plan(c, M, S, pl);
+    fhs_status st = fit_workspace ? plan_within(c, M, S, ws_bytes, pl) : make_plan(c, M, S, pl);
+    if (st == FHS_ENOMEM)
+        return fail(c, st, "the evaluation needs more than the %zu-byte workspace even one pair per batch",
+                    ws_bytes);
     if (st != FHS_OK)
         return fail(c, st, "work layout out of range (prefix table of 2^Ap entries exceeds the table budget, or too many pairs)");
     if (!ws || ws_bytes < pl.bytes)
@@ -464,6 +524,9 @@ extern "C" fhs_status fhs_ctx_create(int device, fhs_ctx **out) {
         delete c;
         return FHS_EHIP;
     }
+    // the no-alloc scratch of this device (a failure only disables
+    // fhs_evaluate_noalloc, which then reports it)
+    if (scratch_address(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
     *out = c;
     return FHS_OK;
 }
@@ -1041,5 +1104,35 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
         FHS_HIP(c, launch_pair_reduce(pre, part, res, 0, pl.P, pl.bpp, cm.A, s));
     }
     FHS_HIP(c, launch_finalize(res, d_cf, S, M, d_amps, d_stats, s));
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_evaluate_noalloc(fhs_ctx *c, const uint64_t *d_in, const double *d_cf,
+                                           uint32_t S, const uint64_t *d_out, uint32_t M, double thr,
+                                           double *d_amps, uint64_t *d_stats, void *stream) {
+    if (!c) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->scratch) return fail(c, FHS_EHIP, "no-alloc scratch unavailable on device %d", c->device);
+    Plan pl;
+    fhs_status st = check_eval_args(c, d_in, d_cf, S, d_out, M, thr, d_amps, d_stats, c->scratch,
+                                    FHS_NOALLOC_SCRATCH_BYTES, pl, true);
+    if (st != FHS_OK || M == 0) return st;
+    FHS_HIP(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+    // A compiled consumer only if one is already cached for this program,
+    // split and launch shape (compiling and loading a module allocates);
+    // otherwise the interpreting kernels.
+    const CompiledConsumer *ck = nullptr;
+    std::string key;
+    size_t shm = 0;
+    if (consumer_job(c, cm, pl.Dp, key, nullptr, shm)) {
+        auto it = c->compiled.find(key);
+        if (it != c->compiled.end()) ck = &it->second;
+    }
+    int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
+    if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
+    // enqueued directly (instantiating a graph allocates), never timed
+    FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, c->scratch, bpc, false, s, ck));
     return FHS_OK;
 }
