@@ -10,6 +10,7 @@ import os
 import shutil
 import subprocess
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -66,10 +67,13 @@ def build(verbose: bool = False) -> str:
         _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "reducer.cpp"), "-o", o])
         objs.append(o)
         _write_jit_headers(os.path.join(tmp, "jit_headers.inc"))
-        for src in ("kernels.hip", "runtime.hip", "mlp.hip", "jit.hip"):
-            o = os.path.join(tmp, src.replace(".hip", ".o"))
-            _run([HIPCC] + HIP_FLAGS + ["-I" + tmp, "-c", os.path.join(CSRC, src), "-o", o])
-            objs.append(o)
+        # the HIP sources compile independently: one hipcc process each, in parallel
+        srcs = ("kernels.hip", "runtime.hip", "mlp.hip", "jit.hip")
+        outs = [os.path.join(tmp, src.replace(".hip", ".o")) for src in srcs]
+        with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+            list(ex.map(lambda so: _run([HIPCC] + HIP_FLAGS + ["-I" + tmp, "-c", os.path.join(CSRC, so[0]),
+                                                             "-o", so[1]]), zip(srcs, outs)))
+        objs += outs
         out = LIB + f".tmp{os.getpid()}"
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs + ["-lhiprtc"])
         os.replace(out, LIB)

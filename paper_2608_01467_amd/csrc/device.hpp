@@ -152,12 +152,24 @@ struct FacRef {
     __device__ __forceinline__ double d(uint32_t off) const { return p[off - lo]; }
 };
 
+// The same with the slice's start a compile-time constant (the compiled
+// regions): a table entry's address is then the lane's index times 16 plus
+// an immediate offset.
+template <uint32_t LO>
+struct FacRefC {
+    const double *p;
+    __device__ __forceinline__ double2 c(uint32_t off) const {
+        return *reinterpret_cast<const double2 *>(p + (off - LO));
+    }
+    __device__ __forceinline__ double d(uint32_t off) const { return p[off - LO]; }
+};
+
 // Entry x of a gate's factor table (at offset fac) for history h: multiplied
 // into the running amplitude now (DEFER < 0), or recorded in bits
 // [DEFER, DEFER + 2) of dx[h] and multiplied after the history has passed
 // its final check (the same factors in the same order, so the same result).
-template <int DEFER, int NW, int H>
-__device__ __forceinline__ void take_factor(Lanes<NW, H> &L, int h, const FacRef &F, uint32_t fac,
+template <int DEFER, int NW, int H, class FR>
+__device__ __forceinline__ void take_factor(Lanes<NW, H> &L, int h, const FR &F, uint32_t fac,
                                             uint32_t x) {
     if constexpr (DEFER < 0) {
         const double2 f = F.c(fac + 2u * x);
@@ -428,8 +440,8 @@ __device__ __forceinline__ void op_swap(Lanes<NW, H> &L, const Instr &I) {
     });
 }
 
-template <int NW, int H, int WA, int DEFER = -1>
-__device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+template <int NW, int H, int WA, int DEFER = -1, class FR = FacRef>
+__device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const FR &F) {
     constexpr int A = wsel<WA, NW>();
     const uint32_t sh = hdr_a(I) & 31u;
     unroll<H>([&](auto hh) {
@@ -440,8 +452,8 @@ __device__ __forceinline__ void op_det1(Lanes<NW, H> &L, const Instr &I, const F
     });
 }
 
-template <int NW, int H, int WA, int DEFER = -1>
-__device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+template <int NW, int H, int WA, int DEFER = -1, class FR = FacRef>
+__device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const FR &F) {
     constexpr int A = wsel<WA, NW>();
     const uint32_t sh = hdr_a(I) & 31u;
     unroll<H>([&](auto hh) {
@@ -451,8 +463,8 @@ __device__ __forceinline__ void op_diag1(Lanes<NW, H> &L, const Instr &I, const 
     });
 }
 
-template <int NW, int H, int WA, int WB, int DEFER = -1>
-__device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const FacRef &F) {
+template <int NW, int H, int WA, int WB, int DEFER = -1, class FR = FacRef>
+__device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const FR &F) {
     constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
     const uint32_t sa = hdr_a(I) & 31u, sb = hdr_b(I) & 31u;
     unroll<H>([&](auto hh) {
@@ -462,8 +474,8 @@ __device__ __forceinline__ void op_diag2(Lanes<NW, H> &L, const Instr &I, const 
     });
 }
 
-template <int NW, int H, bool PRUNE, int WA, bool SRC, int DEFER = -1>
-__device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const FacRef &F,
+template <int NW, int H, bool PRUNE, int WA, bool SRC, int DEFER = -1, class FR = FacRef>
+__device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const FR &F,
                                           uint32_t kbase, const uint32_t (&bin)[NW], double thr) {
     static_assert(!(PRUNE && DEFER >= 0), "pruning needs the moduli as the walk goes");
     constexpr int A = wsel<WA, NW>();
@@ -481,6 +493,88 @@ __device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const
         }
         L.ok[h] = L.ok[h] && !((hdr_z(I) >> x) & 1u);
         L.s[h][A] ^= (o ^ i) << sh;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Factor steps with the gate's table as compile-time constants (the compiled
+// regions): for the table shapes below the factor is formed in registers from
+// the selecting bits instead of being read from a table per lane.  Each
+// computes the same product as the table step: the same factor entry
+// multiplied into the running amplitude in the same order.
+// ---------------------------------------------------------------------------
+
+// x with its sign flipped where bit 31 of f is set.
+__device__ __forceinline__ double flip_sign(double x, uint32_t f) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x) ^ (static_cast<uint64_t>(f & 0x80000000u) << 32);
+    return __builtin_bit_cast(double, b);
+}
+
+// Diagonal gate whose two distinct entries are a complex-conjugate pair
+// (C, S) and (C, -S), selected by one bit (DIAG1: entry 0 when bit a is 0)
+// or by the parity of two (DIAG2 tables {t, u, u, t}: entry 0 when bits a
+// and b agree), e.g. RZ and RZZ: the selecting bit moved to bit 31 flips the
+// sign of S, then one complex multiply.
+template <int NW, int H, int WA, int WB, bool TWO>
+__device__ __forceinline__ void op_conj(Lanes<NW, H> &L, uint32_t sa, uint32_t sb, double C, double S) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        uint32_t f = L.s[h][A] << (31u - sa);
+        if constexpr (TWO) f ^= L.s[h][B] << (31u - sb);
+        cmul(L.re[h], L.im[h], C, flip_sign(S, f));
+    });
+}
+
+// Branching gate whose four entries U[o][i] are real, of one magnitude r
+// and one modulus m (e.g. H): the factor is r times the sign of entry
+// x = 2o + i (neg has bit x set when U[o][i] < 0).  The amplitude is
+// multiplied by r, and the sign goes into sg: a word whose popcount parity
+// is the product of the region's signs so far, applied once at the region's
+// end (apply_signs).  Negation is exact and commutes with every rounding of
+// the complex and real multiplies, so this is the same amplitude as
+// multiplying by the signed entry at the gate.  The input bit comes from the
+// source (SRC) or from the input bitstring and replaces bit a of the state.
+// No entry is zero.
+template <int NW, int H, bool PRUNE, int WA, bool SRC>
+__device__ __forceinline__ void op_branch_real(Lanes<NW, H> &L, uint32_t (&sg)[H], uint32_t sa, uint32_t ks,
+                                               const uint32_t (&bin)[NW], double thr, double r,
+                                               uint32_t neg, double m) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t bit = 1u << sa;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t s0 = L.s[h][A];
+        uint32_t snew;
+        if constexpr (SRC) {
+            const uint32_t i = static_cast<uint32_t>(L.hb[h] >> ks) & 1u;
+            sg[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + i)) & 1u;   // the entry's sign
+            snew = (s0 & ~bit) | (i << sa);
+        } else {
+            if (neg == 8u) sg[h] ^= s0 & bin[A] & bit;      // negative only at o = i = 1
+            else if (neg != 0u) sg[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + ((bin[A] >> sa) & 1u))) & 1u;
+            snew = (s0 & ~bit) | (bin[A] & bit);
+        }
+        L.re[h] *= r;
+        L.im[h] *= r;
+        if (PRUNE) {
+            L.M[h] = L.M[h] * m;
+            L.ok[h] = L.ok[h] && !(L.M[h] < thr);
+        }
+        L.s[h][A] = snew;
+    });
+}
+
+// The signs op_branch_real collected: negate the amplitude where the parity
+// of sg is odd, and start over.
+template <int NW, int H>
+__device__ __forceinline__ void apply_signs(Lanes<NW, H> &L, uint32_t (&sg)[H]) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t f = static_cast<uint32_t>(__popc(sg[h])) << 31;
+        L.re[h] = flip_sign(L.re[h], f);
+        L.im[h] = flip_sign(L.im[h], f);
+        sg[h] = 0u;
     });
 }
 

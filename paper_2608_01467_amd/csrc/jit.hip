@@ -4,6 +4,7 @@
 
 #include <hip/hiprtc.h>
 
+#include <cmath>
 #include <cstdio>
 
 #include "program.hpp"
@@ -33,6 +34,48 @@ int factor_bits(int base) {
     }
 }
 
+// How a factor op of the compiled regions forms its factor when it is not
+// deferred: from the gate's table as compile-time constants for the shapes
+// the device has a step for (op_conj, op_branch_real), else by a per-lane
+// table read.
+struct FacShape {
+    enum Kind { TABLE, CONJ, REAL } kind = TABLE;
+    double C = 0.0, S = 0.0;    // CONJ: entry 0 = (C, S), the other = (C, -S)
+    double r = 0.0, m = 0.0;    // REAL: magnitude and modulus of every entry
+    uint32_t neg = 0;           // REAL: bit x set when entry x is negative
+};
+
+FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
+    FacShape f;
+    const int base = op_base(I.hdr & 0xffu);
+    const double *t = fac.data() + I.fac;
+    auto re = [&](int x) { return t[2 * x]; };
+    auto im = [&](int x) { return t[2 * x + 1]; };
+    auto conj_of = [&](int x, int y) { return re(x) == re(y) && im(x) == -im(y); };
+    if (base == OP_DIAG1 && conj_of(0, 1)) {
+        f.kind = FacShape::CONJ;
+    } else if (base == OP_DIAG2 && re(0) == re(3) && im(0) == im(3) && re(1) == re(2) && im(1) == im(2) &&
+               conj_of(0, 1)) {
+        f.kind = FacShape::CONJ;
+    } else if ((base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) && (I.hdr >> 24) == 0u) {
+        bool real = true;
+        for (int x = 0; x < 4; ++x)
+            real = real && im(x) == 0.0 && std::fabs(re(x)) == std::fabs(re(0)) && t[8 + x] == t[8];
+        if (real && re(0) != 0.0) {
+            f.kind = FacShape::REAL;
+            f.r = std::fabs(re(0));
+            f.m = t[8];
+            for (int x = 0; x < 4; ++x)
+                if (std::signbit(re(x))) f.neg |= 1u << x;
+        }
+    }
+    if (f.kind == FacShape::CONJ) {
+        f.C = re(0);
+        f.S = im(0);
+    }
+    return f;
+}
+
 // One block per instruction: the instruction as a constant and the call of
 // its backward step with the word indices its opcode carries (wsel maps them
 // onto the state registers as the interpreter's dispatch does).  With
@@ -44,11 +87,15 @@ int factor_bits(int base) {
 // at the end on a field that mask covers whole is compared with the output
 // instead (flush_check); its field is returned in `checked`, for the final
 // check to leave out.
-void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uint32_t hi, bool defer,
-                 std::vector<Deferred> &deferred, const Mask4 *check = nullptr,
-                 Mask4 *checked = nullptr) {
+void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vector<double> &fac,
+                 uint32_t fac_lo, uint32_t lo, uint32_t hi, bool defer, std::vector<Deferred> &deferred,
+                 const Mask4 *check = nullptr, Mask4 *checked = nullptr) {
     char buf[512];
     int off = 0;
+    std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n"
+                                    "    uint32_t sg[H] = {}; (void)sg;\n", fac_lo);
+    o += buf;
+    bool signs = false;   // a real-entry branch collected a sign to apply at the end
     bool pending = false;
     uint32_t plo = 0, phi = 0;
     auto flush = [&]() {
@@ -77,7 +124,26 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
             deferred.push_back(Deferred{I.fac, off, factor_bits(base)});
             off += factor_bits(base);
         }
-        char call[256];
+        char call[512];
+        const FacShape fs = d < 0 ? fac_shape(I, fac) : FacShape{};
+        const uint32_t sa = a & 31u, sb = b & 31u;
+        if (fs.kind == FacShape::CONJ) {
+            std::snprintf(call, sizeof(call),
+                          "(void)I; op_conj<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %s>(L, %uu, %uu, %a, %a); }\n",
+                          w1, base == OP_DIAG2 ? w2 : w1, base == OP_DIAG2 ? "true" : "false", sa,
+                          base == OP_DIAG2 ? sb : 0u, fs.C, fs.S);
+            o += call;
+            continue;
+        }
+        if (fs.kind == FacShape::REAL) {
+            std::snprintf(call, sizeof(call),
+                          "op_branch_real<NW, H, PRUNE, wsel<%d, NW>(), %s>(L, sg, %uu, I.k - kbase, bin, thr, "
+                          "%a, %uu, %a); if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
+                          w1, base == OP_BRANCH_SRC ? "true" : "false", sa, fs.r, fs.neg, fs.m);
+            o += call;
+            signs = true;
+            continue;
+        }
         switch (base) {
             case OP_PERM:
                 std::snprintf(call, sizeof(call), "op_perm<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
@@ -85,16 +151,16 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
             case OP_BRANCH_SRC:
             case OP_BRANCH_NAT:
                 std::snprintf(call, sizeof(call),
-                              "op_branch<NW, H, PRUNE, wsel<%d, NW>(), %s, %d>(L, I, F, kbase, bin, thr); "
+                              "op_branch<NW, H, PRUNE, wsel<%d, NW>(), %s, %d>(L, I, Fc, kbase, bin, thr); "
                               "if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
                               w1, base == OP_BRANCH_SRC ? "true" : "false", d);
                 break;
             case OP_DIAG2:
                 std::snprintf(call, sizeof(call),
-                              "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %d>(L, I, F); }\n", w1, w2, d);
+                              "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %d>(L, I, Fc); }\n", w1, w2, d);
                 break;
             case OP_DIAG1:
-                std::snprintf(call, sizeof(call), "op_diag1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
+                std::snprintf(call, sizeof(call), "op_diag1<NW, H, wsel<%d, NW>(), %d>(L, I, Fc); }\n", w1, d);
                 break;
             case OP_MCPHASE:
                 std::snprintf(call, sizeof(call), "op_mcphase<NW, H, wsel<%d, NW>()>(L, I); }\n", w1);
@@ -103,7 +169,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
                 std::snprintf(call, sizeof(call), "op_swap<NW, H, wsel<%d, NW>(), wsel<%d, NW>()>(L, I); }\n", w1, w2);
                 break;
             case OP_DET1:
-                std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>(), %d>(L, I, F); }\n", w1, d);
+                std::snprintf(call, sizeof(call), "op_det1<NW, H, wsel<%d, NW>(), %d>(L, I, Fc); }\n", w1, d);
                 break;
             case OP_ADD:
                 std::snprintf(call, sizeof(call), "pend_add<NW, H, wsel<%d, NW>()>(L, I, pk, pb); }\n", w1);
@@ -136,32 +202,74 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, uint32_t lo, uin
         }
     }
     flush();
+    if (signs) o += "    apply_signs<NW, H>(L, sg);\n";
 }
 
 }  // namespace
 
-std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
-                            uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
-                            int H, bool prune, bool flds, bool prefix_ok, uint32_t iL,
-                            const std::vector<uint32_t> &src_dev, uint32_t Dp, bool pflds) {
-    // defer the suffix's factors when nothing needs them during the walk
-    // (pruning does) and their indices fit in dx
-    int bits = 0;
-    for (uint32_t x = i2; x < iG; ++x) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
-    const bool defer = !prune && bits <= 64;
+std::string consumer_source(const std::vector<Instr> &dev, const std::vector<double> &fac, uint32_t i1,
+                            uint32_t i2, uint32_t iG, uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2,
+                            const Mask4 &fin_G, int NW, int H, bool prune, bool flds, uint32_t fac_lo,
+                            bool prefix_ok, uint32_t iL, const std::vector<uint32_t> &src_dev, uint32_t Dp,
+                            bool pflds, uint32_t pfac_lo) {
     std::vector<Deferred> none, deferred;
     std::string o;
     char buf[512];
+    // The final check at G: a pending ladder run the check covers whole is
+    // compared with the output instead (flush_check, the `checked` field);
+    // a bit whose last write in the suffix is a branching gate on a natural
+    // input segment was set from the input and always matches it.
+    std::string sfx;
+    Mask4 checked{{0u, 0u, 0u, 0u}};
+    emit_region(sfx, dev, fac, fac_lo, i2, iG, false, none, &fin_G, &checked);
+    Mask4 natw{{0u, 0u, 0u, 0u}};
+    bool zero_entries = false;
+    for (uint32_t x = i2; x < iG; ++x) {
+        const int base = op_base(dev[x].hdr & 0xffu);
+        const uint32_t a = (dev[x].hdr >> 8) & 0xffu;
+        const bool writes = base != OP_DIAG1 && base != OP_DIAG2 && base != OP_MCPHASE;
+        if (writes) {
+            // a written bit: the target, both swapped bits, the field of a
+            // ladder step (controls are only read)
+            uint32_t wm[4] = {0u, 0u, 0u, 0u};
+            if (base == OP_ADD || base == OP_ADDSEL) {
+                const uint32_t b = (dev[x].hdr >> 16) & 0xffu;
+                for (uint32_t q = a; q < a + b; ++q) wm[q >> 5] |= 1u << (q & 31u);
+            } else if (base == OP_SWAP) {
+                const uint32_t b = (dev[x].hdr >> 16) & 0xffu;
+                wm[a >> 5] |= 1u << (a & 31u);
+                wm[b >> 5] |= 1u << (b & 31u);
+            } else {
+                wm[a >> 5] |= 1u << (a & 31u);
+            }
+            for (int w = 0; w < 4; ++w) {
+                if (base == OP_BRANCH_NAT) natw.w[w] |= wm[w];
+                else natw.w[w] &= ~wm[w];
+            }
+        }
+        if ((base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) && (dev[x].hdr >> 24) != 0u) zero_entries = true;
+    }
+    Mask4 fin_rest = fin_G;
+    bool check_left = false;
+    for (int w = 0; w < 4; ++w) {
+        fin_rest.w[w] &= ~(checked.w[w] | natw.w[w]);
+        check_left = check_left || fin_rest.w[w] != 0u || checked.w[w] != 0u;
+    }
+    // Defer the suffix's factors (record their table indices, multiply only
+    // for the histories that pass the final check) when nothing needs them
+    // during the walk (pruning does), their indices fit in dx, and a history
+    // can still fail after the root; when none can, deferring only adds work.
+    int bits = 0;
+    for (uint32_t x = i2; x < iG; ++x) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
+    const bool defer = !prune && bits <= 64 && (check_left || zero_entries);
+    if (defer) {
+        sfx.clear();
+        emit_region(sfx, dev, fac, fac_lo, i2, iG, true, deferred, &fin_G, &checked);
+    }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
     o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
     // the final-bit masks as constants: fully checked words become one compare
-    // the suffix first: its last ladder run may take over part of the final check
-    std::string sfx;
-    Mask4 checked{{0u, 0u, 0u, 0u}};
-    emit_region(sfx, dev, i2, iG, defer, deferred, &fin_G, &checked);
-    Mask4 fin_rest = fin_G;
-    for (int w = 0; w < 4; ++w) fin_rest.w[w] &= ~checked.w[w];
     const Mask4 *fm[2] = {&fin_c2, &fin_rest};
     const char *fname[2] = {"final_c2", "final_G"};
     for (int k = 0; k < 2; ++k) {
@@ -182,7 +290,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
                   "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
                   Ap);
     o += buf;
-    emit_region(o, dev, i1, i2, false, none);
+    emit_region(o, dev, fac, fac_lo, i1, i2, false, none);
     o += "}\n";
     std::snprintf(buf, sizeof(buf),
                   "template <int NW, int H, bool PRUNE>\n"
@@ -198,10 +306,12 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
     o += "template <int NW, int H>\n"
          "__device__ static __forceinline__ void suffix_amp(const FacRef &F, Lanes<NW, H> &L, int h) {\n"
          "    (void)F; (void)L; (void)h;\n";
+    std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n", fac_lo);
+    o += buf;
     for (const Deferred &d : deferred) {
         std::snprintf(buf, sizeof(buf),
                       "    { const uint32_t x = static_cast<uint32_t>(L.dx[h] >> %d) & %uu; "
-                      "const double2 f = F.c(%uu + 2u * x); cmul(L.re[h], L.im[h], f.x, f.y); }\n",
+                      "const double2 f = Fc.c(%uu + 2u * x); cmul(L.re[h], L.im[h], f.x, f.y); }\n",
                       d.off, (1u << d.bits) - 1u, d.fac);
         o += buf;
     }
@@ -217,7 +327,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
              "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n";
-        emit_region(o, dev, iL, e_split, false, none);
+        emit_region(o, dev, fac, pfac_lo, iL, e_split, false, none);
         o += "}\n";
         o += "template <int NW, bool PRUNE>\n"
              "__device__ static __forceinline__ void prefix_seg(const Common &c, const FacRef &F, "
@@ -230,7 +340,7 @@ std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t
             const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;
             std::snprintf(buf, sizeof(buf), "    case %uu: {\n", l);
             o += buf;
-            emit_region(o, dev, a, b, false, none);
+            emit_region(o, dev, fac, pfac_lo, a, b, false, none);
             o += "    } break;\n";
         }
         o += "    default: break;\n    }\n}\n";

@@ -29,18 +29,27 @@ struct CompiledConsumer {
 // Source text of the consumer for device-program regions [i1, i2) (root)
 // and [i2, iG) (suffix) of `dev`, whose first sources are Ap and Ap + Ar;
 // fin_c2 and fin_G are the final-bit masks checked at the ends of the two
-// regions.  Without pruning, the suffix's factor multiplications are
-// deferred to the histories that pass the final check when their table
-// indices fit in 64 bits.
+// regions; `fac` is the program's factor table, of which the kernel sees
+// the slice from fac_lo on (staged in LDS when flds, else read from HBM
+// with fac_lo = 0).  Factors whose tables have a shape the device forms in
+// registers (a complex-conjugate pair selected by one bit or a parity;
+// real entries of one magnitude) are emitted with the table's values as
+// constants; the others read their table per lane.  Without pruning, when a
+// history can still fail after the root (a final-bit check left, a ladder
+// run compared with the output, a zero table entry), the suffix's factor
+// multiplications are deferred to the histories that pass the final check
+// if their table indices fit in 64 bits.
 //
 // With prefix_ok, the module also holds the prefix-table build for device
 // region [iL, i1): the gates before the first depth-first source
 // src_dev[Ap - Dp], then the Dp depth-first levels (src_dev: device index of
-// every source's gate); pflds stages the prefix's factors in LDS.
-std::string consumer_source(const std::vector<Instr> &dev, uint32_t i1, uint32_t i2, uint32_t iG,
-                            uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2, const Mask4 &fin_G, int NW,
-                            int H, bool prune, bool flds, bool prefix_ok, uint32_t iL,
-                            const std::vector<uint32_t> &src_dev, uint32_t Dp, bool pflds);
+// every source's gate); pflds stages the prefix's factors in LDS (from
+// pfac_lo on).
+std::string consumer_source(const std::vector<Instr> &dev, const std::vector<double> &fac, uint32_t i1,
+                            uint32_t i2, uint32_t iG, uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2,
+                            const Mask4 &fin_G, int NW, int H, bool prune, bool flds, uint32_t fac_lo,
+                            bool prefix_ok, uint32_t iL, const std::vector<uint32_t> &src_dev, uint32_t Dp,
+                            bool pflds, uint32_t pfac_lo);
 
 // Compile `src` for gfx950 and load it on the current device.  On failure
 // returns false and puts the compiler log in `log`.

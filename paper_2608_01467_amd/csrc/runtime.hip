@@ -431,9 +431,10 @@ bool consumer_job(const fhs_ctx *c, const Common &cm, uint32_t Dp, std::string &
     key = buf;
     shm = consume_lds_bytes(cm);
     if (src)
-        *src = consumer_source(c->dev_ins, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar, c->prog.final_before[cm.c2],
-                               c->prog.final_before[cm.G], NW, c->ilp, prune, flds, prefix_ok, cm.iL,
-                               c->src_dev, Dp, pflds);
+        *src = consumer_source(c->dev_ins, c->prog.fac, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar,
+                               c->prog.final_before[cm.c2], c->prog.final_before[cm.G], NW, c->ilp, prune,
+                               flds, flds ? cm.f_c1 : 0u, prefix_ok, cm.iL, c->src_dev, Dp, pflds,
+                               pflds ? cm.f_L : 0u);
     return true;
 }
 

@@ -538,3 +538,75 @@ def test_compiled_consumer_families(ctx, family):
             assert np.abs(amps - ref[0]).max() <= TOL, (family, h, part)
             assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (family, h, part)
     ctx.set_launch_config(0, 0, 0, 0)
+
+
+def _branchy(n: int, layers: int, seed: int):
+    """Random layered circuit with a few branching gates per layer (H, RX,
+    RY), diagonal two-qubit gates with conjugate-pair tables (RZZ) and
+    without (CZ, CP), one-qubit phases (RZ, T, S, Z, P), and permutations
+    (X, CX, SWAP, CCX): past the first layer most branching gates carry
+    artificial sources."""
+    rng = np.random.default_rng(seed)
+    c = w.Circuit(n)
+    for _ in range(layers):
+        for q in rng.choice(n, size=min(n, 3), replace=False):
+            g = str(rng.choice(["H", "H", "RX", "RY"]))
+            if g == "H":
+                c.add(g, int(q))
+            else:
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+        for _ in range(n):
+            a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+            g = str(rng.choice(["RZZ", "RZZ", "CZ", "CP", "CX", "SWAP"]))
+            if g in ("RZZ", "CP"):
+                c.add(g, a, b, angle=float(rng.uniform(-np.pi, np.pi)))
+            else:
+                c.add(g, a, b)
+        for q in rng.choice(n, size=min(n, 3), replace=False):
+            g = str(rng.choice(["RZ", "T", "S", "Z", "X", "P"]))
+            if g in ("RZ", "P"):
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+            else:
+                c.add(g, int(q))
+        if n >= 3:
+            a, b, t3 = (int(x) for x in rng.choice(n, size=3, replace=False))
+            c.add("CCX", a, b, t3)
+    return c
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_compiled_random_mixed(ctx, seed):
+    """The compiled consumer and prefix build on random layered circuits with
+    random inputs: factors formed in registers from constant tables
+    (conjugate pairs such as RZ and RZZ, real branching tables such as H
+    with input bits 0 and 1, whose signs are applied at the region's end),
+    the other tables read per lane, deferred and immediate suffix factors,
+    with and without pruning, at several splits."""
+    n = [4, 6, 7, 9, 12, 33, 64, 100][seed]
+    c = _branchy(n, 3 + seed % 2, 9000 + seed)
+    t = c.to_text()
+    o = oracle.Feynman(t)
+    assert 3 <= o.A <= 14, o.A
+    rng = np.random.default_rng(100 + seed)
+    S = 1 + seed % 3
+    inputs = [int(rng.integers(0, 1 << min(n, 62))) for _ in range(S)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in range(S)]
+    outs = [int(rng.integers(0, 1 << min(n, 62))) for _ in range(16)]
+    if n <= 12:
+        psi = sv.evolve(t, inputs[0])
+        outs += [int(x) for x in np.argsort(-np.abs(psi))[:8]]
+    prog = fhs.Program(t)
+    parts = [prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
+             (0, prog.G), (prog.G, prog.G)]
+    src = prog.source_eval_positions
+    if len(src) >= 2:
+        parts.append((src[0] + 1, src[-1] + 1))
+    for thr in (0.0, 0.02):
+        ref = o.evaluate(inputs, coeffs, outs, threshold=thr, threads=THREADS)
+        for h in (1, 2):
+            ctx.set_launch_config(h, 0, 0, 3)
+            for part in parts:
+                amps, st = gpu_eval(ctx, t, inputs, coeffs, outs, thr=thr, partition=part, prog=prog)
+                assert np.abs(amps - ref[0]).max() <= TOL, (seed, thr, h, part)
+                assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (seed, thr, h, part)
+    ctx.set_launch_config(0, 0, 0, 0)
