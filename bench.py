@@ -116,10 +116,14 @@ def oracle_check(workload, cfg, text, amps, stats, thr, partition, A, max_candid
     a = amps[:, 0] + 1j * amps[:, 1]
     st = stats.view(np.uint64) if stats.dtype != np.uint64 else stats
     outs = cfg["outputs"]
-    if workload.startswith("walk_") and thr == 0.0 and cfg["inputs"] == [0]:
+    if workload.startswith("walk_") and thr == 0.0 and all(b >> 1 == 0 for b in cfg["inputs"]):
+        # inputs at position 0: the coin state is what their coefficients say
         c = cfg["circuit"]
         n_pos, steps = c.n - 1, sum(1 for g in c.gates if g.name == "H")
-        dp = cf.walk_amplitudes(steps)
+        coin = [0j, 0j]
+        for b, z in zip(cfg["inputs"], cfg["coeffs"]):
+            coin[b & 1] += complex(*z)
+        dp = cf.walk_amplitudes(steps, tuple(coin))
         err, exact, n_reach = 0.0, True, 0
         for j, y in enumerate(outs):
             x = y >> 1
@@ -130,7 +134,12 @@ def oracle_check(workload, cfg, text, amps, stats, thr, partition, A, max_candid
                 continue
             n_reach += 1
             err = max(err, abs(a[j] - ref))
-            exact = exact and tuple(int(v) for v in st[j, :3]) == cf.walk_valid_stats(steps, x, y & 1)
+            # every input coin has the same valid set (the sources are the
+            # later coin values); the statistics add over the inputs
+            n1, s1, x1 = cf.walk_valid_stats(steps, x, y & 1)
+            S = len(cfg["inputs"])
+            want = (S * n1, (S * s1) % (1 << 64), x1 if S % 2 else 0)
+            exact = exact and tuple(int(v) for v in st[j, :3]) == want
         return {"max_abs_err": float(err), "stats_exact": bool(exact), "checked_outputs": len(outs),
                 "against": f"walk closed form ({n_reach} reachable outputs; {len(outs) - n_reach} "
                            "padding outputs exactly 0)"}

@@ -62,6 +62,7 @@ typedef struct {
     uint32_t n_words;     /* W = ceil(n/64) */
     uint32_t n_leading;   /* gates before the first source gate, evaluation order */
     uint32_t n_branch;    /* branching gates, natural ones included */
+    uint32_t forward;     /* 1: sources placed by the forward sweep (FHS_REDUCE_FORWARD) */
 } fhs_program_info;
 
 /* Human-readable name of a status code (static storage). */
@@ -95,8 +96,22 @@ fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out);
  * Positions, sources, cuts, final-bit masks and Eq. (8) are those of the
  * unfused program; fhs_program_work reports the fused work.  flags = 0 keeps
  * one instruction per gate.  FHS_EINVAL on unknown flags or PAIR without
- * FUSE. */
-enum { FHS_REDUCE_FUSE = 1, FHS_REDUCE_PAIR = 2 };
+ * FUSE.  (Ladder folding recognises the cascades in evaluation order, so a
+ * cascade written most significant bit first is folded only when walked
+ * from the output.) */
+/* FHS_REDUCE_FORWARD (Section IV-F, Table I's forward column) places the
+ * artificial sources by one sweep from the input instead: a branching gate
+ * whose output-side segment is not a natural output segment (a wire from the
+ * gate to the output with only wire-preserving incidences) gets a source on
+ * that segment, numbered from the input.  The evaluation order is then the
+ * time order: a history starts from b_in, walks the gates input -> output
+ * and is checked against b_out; every evaluation position, cut and source
+ * position of this API counts from the input (gate position e is time index
+ * e).  The amplitudes are the same; the history indices, and so the valid
+ * sets, are those of the forward placement.  Internally the program is the
+ * backward one of the transposed circuit (gates reversed, matrices
+ * transposed), since <b_out|C|b_in> = <b_in|C^T|b_out>. */
+enum { FHS_REDUCE_FUSE = 1, FHS_REDUCE_PAIR = 2, FHS_REDUCE_FORWARD = 4 };
 fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags, fhs_program **out);
 void fhs_program_free(fhs_program *prog);
 fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info);
@@ -128,7 +143,10 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *               chain); when e1 is the end of the program and the final
  *               check compares the whole field of the run still pending
  *               there, that run costs 2 instead of 3f (its count is
- *               compared with the field's residue);
+ *               compared with the field's residue); a paired step without
+ *               controls whose selecting bit holds a source bit set by a
+ *               branching gate earlier in [e0, e1) costs 0, its run 2 per
+ *               sign of such steps (one popcount of the source index);
  *   fp64_flops: complex multiply of the running amplitude: 6 for a general
  *               factor table, 2 if every entry is purely real or imaginary,
  *               0 if every entry is 0, +-1 or +-i; a negation counts 0;
@@ -247,6 +265,21 @@ fhs_status fhs_kernel_times(fhs_ctx *ctx, float *ms, uint32_t cap, uint32_t *cou
  * each table build, outside the timed interval.  Blocks until that count
  * is available.  FHS_ESTATE if timing is off or nothing was timed. */
 fhs_status fhs_kernel_counts(fhs_ctx *ctx, uint64_t *prefix_entries, uint64_t *prefix_valid);
+
+/* Per-work-item timestamps of the most recent fhs_evaluate run in timing
+ * mode, for the cost distribution over outputs (Section V: time against the
+ * number of sources, time per requested bitstring): the persistent
+ * consumer's work item (pair p, chunk j of its prefix entries) has index
+ * p * items_per_pair + j, pairs numbered p = j_out * S + i_in; stamps[2 k]
+ * and stamps[2 k + 1] receive the device's constant-rate clock when a
+ * workgroup popped item k and when it stored the item's sums (ticks_per_s
+ * ticks per second; comparable across compute units).  Writes min(count,
+ * cap) items (blocking copy).  Outputs with no work (a pair rejected before
+ * enumeration) still have their items, which take almost no time.
+ * FHS_ESTATE if timing is off or the last timed call was not a batched
+ * evaluation with sources. */
+fhs_status fhs_item_stamps(fhs_ctx *ctx, uint64_t *stamps, size_t cap, size_t *count,
+                           uint32_t *items_per_pair, uint64_t *ticks_per_s);
 
 /* Work layout fhs_evaluate would use for M outputs and S inputs.  The cuts
  * are the effective ones: the source-free gates nearest the output run once

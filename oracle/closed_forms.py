@@ -1,6 +1,7 @@
 """Textbook closed forms that pin the oracle at any size (test infrastructure).
 
-  * QFT: <y|QFT_n|x> = 2^{-n/2} exp(2 pi i (x y mod 2^n) / 2^n);
+  * QFT: <y|QFT_n|x> = 2^{-n/2} exp(2 pi i (x y mod 2^n) / 2^n), and for a
+    dense input the discrete Fourier transform of its amplitudes (FFT);
   * amplitude amplification with the diffusion written as H X MCZ X H (which
     is I - 2|s><s|, the negative of the usual Grover reflection): after s
     iterations each of the m marked states holds (-1)^s sin((2s+1)theta)/sqrt(m)
@@ -42,12 +43,14 @@ def aa_success_probability(k: int, iterations: int, m: int) -> float:
     return math.sin((2 * iterations + 1) * theta) ** 2
 
 
-def walk_amplitudes(steps: int) -> Dict[Tuple[int, int], complex]:
-    """Hadamard walk from position 0, coin 0: each step maps the coin
-    (a0, a1) -> ((a0 + a1)/sqrt2, (a0 - a1)/sqrt2), then moves coin-1
-    amplitude to x+1 and coin-0 amplitude to x-1."""
+def walk_amplitudes(steps: int, coin: Tuple[complex, complex] = (1.0, 0.0)
+                    ) -> Dict[Tuple[int, int], complex]:
+    """Hadamard walk from position 0 with coin state coin[0]|0> + coin[1]|1>
+    (default |0>; the paper's large walk starts from (|0> + i|1>)/sqrt2):
+    each step maps the coin (a0, a1) -> ((a0 + a1)/sqrt2, (a0 - a1)/sqrt2),
+    then moves coin-1 amplitude to x+1 and coin-0 amplitude to x-1."""
     h = 1.0 / math.sqrt(2.0)
-    amp = {(0, 0): 1.0 + 0j}
+    amp = {(0, c): complex(coin[c]) for c in (0, 1) if coin[c] != 0}
     for _ in range(steps):
         nxt: Dict[Tuple[int, int], complex] = {}
         for (x, c), a in amp.items():
@@ -97,3 +100,12 @@ def walk_n_valid(steps: int, x: int, c: int) -> int:
     if ones < 0 or ones > steps - 1:
         return 0
     return math.comb(steps - 1, ones)
+
+
+def qft_dense(n: int, psi):
+    """<y|QFT_n|psi> for every y and a dense input psi (2^n entries):
+    2^{-n/2} sum_x psi_x e^{2 pi i x y / 2^n}, which is 2^{n/2} times numpy's
+    inverse FFT of psi."""
+    import numpy as np
+    psi = np.asarray(psi, dtype=complex)
+    return np.fft.ifft(psi) * math.sqrt(float(1 << n))

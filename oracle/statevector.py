@@ -153,6 +153,17 @@ def evolve(text: str, b_in: int) -> np.ndarray:
     return psi
 
 
+def evolve_state(text: str, psi: np.ndarray) -> np.ndarray:
+    """C|psi> for a dense input vector (Eq. (2) for every output at once)."""
+    n, gates = parse(text)
+    if n > MAX_QUBITS or psi.shape != (1 << n,):
+        raise ValueError("state vector size")
+    psi = np.asarray(psi, dtype=complex)
+    for g in gates:
+        psi = apply_gate(psi, n, g)
+    return psi
+
+
 def amplitudes(text: str, inputs: Sequence[int], coeffs: Sequence[complex],
                outputs: Sequence[int]) -> np.ndarray:
     """Eq. (2): <b_out|C|psi> for psi = sum_i coeff_i |b_in_i>."""

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libfhs.so")
 PART_NONE, PART_THIRDS, PART_EQ8, PART_MODEL = 0, 1, 2, 3
 REDUCE_FUSE = 1
 REDUCE_PAIR = 2
+REDUCE_FORWARD = 4
 
 STATUS = {0: "FHS_OK", 1: "FHS_EINVAL", 2: "FHS_EUNSUPPORTED", 3: "FHS_ERANGE",
           4: "FHS_ENOMEM", 5: "FHS_EHIP", 6: "FHS_ESTATE", 7: "FHS_EPARSE"}
@@ -40,6 +41,7 @@ EXPORTS = [
     "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
     "fhs_precompile", "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
     "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam", "fhs_evaluate_noalloc",
+    "fhs_item_stamps",
 ]
 
 NOALLOC_SCRATCH_BYTES = 256 << 20   # FHS_NOALLOC_SCRATCH_BYTES
@@ -56,7 +58,8 @@ class FhsError(RuntimeError):
 class ProgramInfo(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("n_gates", ctypes.c_uint32),
                 ("n_sources", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
-                ("n_leading", ctypes.c_uint32), ("n_branch", ctypes.c_uint32)]
+                ("n_leading", ctypes.c_uint32), ("n_branch", ctypes.c_uint32),
+                ("forward", ctypes.c_uint32)]
 
 
 class Work(ctypes.Structure):
@@ -117,6 +120,8 @@ def lib() -> ctypes.CDLL:
         L.fhs_get_plan.argtypes = [P, U32, U32, ctypes.POINTER(Plan)]
         L.fhs_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), U32, ctypes.POINTER(U32)]
         L.fhs_kernel_counts.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        L.fhs_item_stamps.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), pU32,
+                                      ctypes.POINTER(ctypes.c_uint64)]
         L.fhs_set_launch_config.argtypes = [P, ctypes.POINTER(LaunchConfig)]
         pD = ctypes.POINTER(ctypes.c_double)
         L.fhs_split_features.argtypes = [P, U32, U32, U32, U32, pD]
@@ -152,12 +157,16 @@ def _check(st: int, ctx=None) -> None:
 class Program:
     """Host-side reduced-history program (fhs_reduce)."""
 
-    def __init__(self, circuit_text: str, fuse: bool = True, pair: bool = True):
+    def __init__(self, circuit_text: str, fuse: bool = True, pair: bool = True,
+                 forward: bool = False):
         """fuse: fold add/subtract ladders (FHS_REDUCE_FUSE); pair: also merge
-        complementary folded ladders (FHS_REDUCE_PAIR, only with fuse)."""
+        complementary folded ladders (FHS_REDUCE_PAIR, only with fuse);
+        forward: place the sources by the sweep from the input
+        (FHS_REDUCE_FORWARD; positions and cuts then count from the input)."""
         b = circuit_text.encode()
         h = ctypes.c_void_p()
         flags = (REDUCE_FUSE | (REDUCE_PAIR if pair else 0)) if fuse else 0
+        flags |= REDUCE_FORWARD if forward else 0
         _check(lib().fhs_reduce_ex(b, len(b), flags, ctypes.byref(h)))
         self._h = h
         info = ProgramInfo()
@@ -168,6 +177,7 @@ class Program:
         self.W = info.n_words
         self.L = info.n_leading
         self.n_branch = info.n_branch
+        self.forward = bool(info.forward)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -317,6 +327,19 @@ class Context:
         a, b = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().fhs_kernel_counts(self._h, ctypes.byref(a), ctypes.byref(b)), self)
         return a.value, b.value
+
+    def item_stamps(self):
+        """(stamps uint64 [items, 2] start/end, items per pair, clock ticks
+        per second) of the last batched evaluation in timing mode."""
+        n = ctypes.c_size_t()
+        ipp = ctypes.c_uint32()
+        tps = ctypes.c_uint64()
+        _check(lib().fhs_item_stamps(self._h, None, 0, ctypes.byref(n), ctypes.byref(ipp),
+                                     ctypes.byref(tps)), self)
+        arr = np.zeros((n.value, 2), dtype=np.uint64)
+        _check(lib().fhs_item_stamps(self._h, arr.ctypes.data, n.value, ctypes.byref(n),
+                                     ctypes.byref(ipp), ctypes.byref(tps)), self)
+        return arr, ipp.value, tps.value
 
     def kernel_times(self) -> list:
         """Durations (ms) of the hot-kernel launches of the last evaluation."""

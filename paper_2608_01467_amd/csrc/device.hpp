@@ -131,6 +131,16 @@ __device__ __forceinline__ bool load_bits(const uint64_t *src, uint32_t W, uint3
     return bad;
 }
 
+// The bitstrings of pair p = j S + i (output j, input i): a history starts
+// from the one at the evaluation order's start (the output; the input for a
+// program placed by the forward sweep) and is checked against the other.
+__device__ __forceinline__ const uint64_t *start_bits(const Common &c, uint32_t p) {
+    return c.fwd ? c.inputs + static_cast<size_t>(p % c.S) * c.W : c.outputs + static_cast<size_t>(p / c.S) * c.W;
+}
+__device__ __forceinline__ const uint64_t *check_bits(const Common &c, uint32_t p) {
+    return c.fwd ? c.outputs + static_cast<size_t>(p / c.S) * c.W : c.inputs + static_cast<size_t>(p % c.S) * c.W;
+}
+
 // Per-history registers of H histories.
 template <int NW, int H>
 struct Lanes {
@@ -344,6 +354,27 @@ __device__ __forceinline__ void pend_addsel(const Lanes<NW, H> &L, const Instr &
         pk[h] += d0 & gm;
         if (half > 0) pb[h] += bit & gm;
         if (half < 0) pb[h] -= bit & gm;
+    });
+}
+
+// Ladder steps of a pending run without controls whose selecting bit holds
+// a source bit of the region (set by a branching gate earlier in the region,
+// not written since): each adds its constant part d0 and, for a source bit
+// of 1, d1 - d0 = +-2, so together they add kc to pk and the popcount of the
+// source index over `pos` minus that over `neg` to pb (n = pk + 2 pb).
+template <int NW, int H>
+__device__ __forceinline__ void pend_src(const Lanes<NW, H> &L, int32_t (&pk)[H], int32_t (&pb)[H], int32_t kc,
+                                         uint64_t pos, uint64_t neg) {
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        pk[h] += kc;
+        if ((pos | neg) >> 32) {
+            pb[h] += __popcll(L.hb[h] & pos) - __popcll(L.hb[h] & neg);
+        } else {
+            const uint32_t hb = static_cast<uint32_t>(L.hb[h]);
+            if (pos) pb[h] += __popc(hb & static_cast<uint32_t>(pos));
+            if (neg) pb[h] -= __popc(hb & static_cast<uint32_t>(neg));
+        }
     });
 }
 
@@ -875,7 +906,7 @@ __device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, ui
         uint32_t bin[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) L.s[0][w] = pre.st[static_cast<size_t>(w) * P + p];
-        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
+        load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
         const double2 a = pre.amp[p];
         L.re[0] = a.x;
         L.im[0] = a.y;
@@ -946,6 +977,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
         __syncthreads();
         const uint32_t item = s_item;
         if (item >= n_items) break;
+        if (part.stamps && t == 0) part.stamps[2ull * item] = wall_clock64();
         const uint32_t pl = item / nchunks, ch = item - pl * nchunks;
         const uint32_t p = p0 + pl;
         const uint32_t hp0 = ch * chunk;
@@ -986,7 +1018,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
         __syncthreads();
 
         uint32_t bin[NW];
-        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
+        load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
         Acc acc{0.0, 0.0, 0, 0, 0, 0};
         const uint64_t ntask = static_cast<uint64_t>(nv) << (c.Ar + ss);
         // uniform loop bounds: the program counter inside stays wave-uniform
@@ -1044,6 +1076,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             }
         }
         block_reduce_store<NT>(acc, l_red, part, item);
+        if (part.stamps && t == 0) part.stamps[2ull * item + 1] = wall_clock64();
     }
 }
 

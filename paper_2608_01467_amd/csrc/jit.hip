@@ -88,8 +88,8 @@ FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
 // instead (flush_check); its field is returned in `checked`, for the final
 // check to leave out.
 void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vector<double> &fac,
-                 uint32_t fac_lo, uint32_t lo, uint32_t hi, bool defer, std::vector<Deferred> &deferred,
-                 const Mask4 *check = nullptr, Mask4 *checked = nullptr) {
+                 uint32_t fac_lo, uint32_t kbase, uint32_t lo, uint32_t hi, bool defer,
+                 std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr) {
     char buf[512];
     int off = 0;
     std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n"
@@ -98,8 +98,23 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
     bool signs = false;   // a real-entry branch collected a sign to apply at the end
     bool pending = false;
     uint32_t plo = 0, phi = 0;
+    // ladder steps of the pending run whose selecting bit holds a source bit
+    // of this region: their constant parts and the sources they add (+1) or
+    // subtract (-1), summed as popcounts of the source index at the flush
+    SourceBits sbits;
+    int32_t pkc = 0;
+    uint64_t spos = 0, sneg = 0;
+    auto flush_src = [&]() {
+        if (pkc == 0 && spos == 0 && sneg == 0) return;
+        std::snprintf(buf, sizeof(buf), "    pend_src<NW, H>(L, pk, pb, %d, 0x%llxull, 0x%llxull);\n", pkc,
+                      static_cast<unsigned long long>(spos), static_cast<unsigned long long>(sneg));
+        o += buf;
+        pkc = 0;
+        spos = sneg = 0;
+    };
     auto flush = [&]() {
         if (!pending) return;
+        flush_src();
         std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk, pb);\n", plo, phi);
         o += buf;
         pending = false;
@@ -112,6 +127,20 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         const bool is_add = base == OP_ADD || base == OP_ADDSEL;
         const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
         if (pending && ends_field_run(I, plo, phi)) flush();
+        const int sel_src = sbits.selector_source(I);
+        sbits.step(I, kbase);
+        if (sel_src >= 0) {
+            // a step selected by source bit j: d0 when the bit is 0, d1 when 1
+            const uint32_t z = I.hdr >> 24;
+            const int32_t d0 = (z & 1u) ? -1 : 1, d1 = (z & 2u) ? -1 : 1;
+            pkc += d0;
+            if (d1 > d0) spos |= 1ull << sel_src;
+            if (d1 < d0) sneg |= 1ull << sel_src;
+            pending = true;
+            plo = a;
+            phi = a + b;
+            continue;
+        }
         std::snprintf(buf, sizeof(buf),
                       "    { constexpr Instr I{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu, "
                       "{0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}, {0x%08xu, 0x%08xu, 0x%08xu, 0x%08xu}}; ",
@@ -195,6 +224,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         bool covered = true;
         for (int w = 0; w < 4; ++w) covered = covered && (fm.w[w] & ~check->w[w]) == 0u;
         if (covered) {
+            flush_src();
             std::snprintf(buf, sizeof(buf), "    flush_check<NW, H>(L, %uu, %uu, pk, pb, bin);\n", plo, phi);
             o += buf;
             pending = false;
@@ -221,31 +251,16 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // input segment was set from the input and always matches it.
     std::string sfx;
     Mask4 checked{{0u, 0u, 0u, 0u}};
-    emit_region(sfx, dev, fac, fac_lo, i2, iG, false, none, &fin_G, &checked);
+    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked);
     Mask4 natw{{0u, 0u, 0u, 0u}};
     bool zero_entries = false;
     for (uint32_t x = i2; x < iG; ++x) {
         const int base = op_base(dev[x].hdr & 0xffu);
-        const uint32_t a = (dev[x].hdr >> 8) & 0xffu;
-        const bool writes = base != OP_DIAG1 && base != OP_DIAG2 && base != OP_MCPHASE;
-        if (writes) {
-            // a written bit: the target, both swapped bits, the field of a
-            // ladder step (controls are only read)
-            uint32_t wm[4] = {0u, 0u, 0u, 0u};
-            if (base == OP_ADD || base == OP_ADDSEL) {
-                const uint32_t b = (dev[x].hdr >> 16) & 0xffu;
-                for (uint32_t q = a; q < a + b; ++q) wm[q >> 5] |= 1u << (q & 31u);
-            } else if (base == OP_SWAP) {
-                const uint32_t b = (dev[x].hdr >> 16) & 0xffu;
-                wm[a >> 5] |= 1u << (a & 31u);
-                wm[b >> 5] |= 1u << (b & 31u);
-            } else {
-                wm[a >> 5] |= 1u << (a & 31u);
-            }
-            for (int w = 0; w < 4; ++w) {
-                if (base == OP_BRANCH_NAT) natw.w[w] |= wm[w];
-                else natw.w[w] &= ~wm[w];
-            }
+        uint32_t wm[4];
+        written_bits(dev[x], wm);
+        for (int w = 0; w < 4; ++w) {
+            if (base == OP_BRANCH_NAT) natw.w[w] |= wm[w];
+            else natw.w[w] &= ~wm[w];
         }
         if ((base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) && (dev[x].hdr >> 24) != 0u) zero_entries = true;
     }
@@ -264,7 +279,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     const bool defer = !prune && bits <= 64 && (check_left || zero_entries);
     if (defer) {
         sfx.clear();
-        emit_region(sfx, dev, fac, fac_lo, i2, iG, true, deferred, &fin_G, &checked);
+        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked);
     }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
@@ -290,7 +305,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
                   Ap);
     o += buf;
-    emit_region(o, dev, fac, fac_lo, i1, i2, false, none);
+    emit_region(o, dev, fac, fac_lo, Ap, i1, i2, false, none);
     o += "}\n";
     std::snprintf(buf, sizeof(buf),
                   "template <int NW, int H, bool PRUNE>\n"
@@ -327,7 +342,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
              "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n";
-        emit_region(o, dev, fac, pfac_lo, iL, e_split, false, none);
+        emit_region(o, dev, fac, pfac_lo, 0u, iL, e_split, false, none);
         o += "}\n";
         o += "template <int NW, bool PRUNE>\n"
              "__device__ static __forceinline__ void prefix_seg(const Common &c, const FacRef &F, "
@@ -340,7 +355,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
             const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;
             std::snprintf(buf, sizeof(buf), "    case %uu: {\n", l);
             o += buf;
-            emit_region(o, dev, fac, pfac_lo, a, b, false, none);
+            emit_region(o, dev, fac, pfac_lo, 0u, a, b, false, none);
             o += "    } break;\n";
         }
         o += "    default: break;\n    }\n}\n";

@@ -35,11 +35,10 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < n_zero) zero_words[p] = 0u;
     if (p >= P) return;
-    const uint32_t j = p / c.S, i = p % c.S;
     Lanes<NW, 1> L;
     uint32_t bin[NW];
-    const bool bad_o = load_bits<NW>(c.outputs + static_cast<size_t>(j) * c.W, c.W, c.n, L.s[0]);
-    const bool bad_i = load_bits<NW>(c.inputs + static_cast<size_t>(i) * c.W, c.W, c.n, bin);
+    const bool bad_o = load_bits<NW>(start_bits(c, p), c.W, c.n, L.s[0]);
+    const bool bad_i = load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
     L.re[0] = 1.0;
     L.im[0] = 0.0;
     L.M[0] = 1.0;
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
         uint32_t s0[NW], bin[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) s0[w] = pre.st[static_cast<size_t>(w) * P + p];
-        load_bits<NW>(c.inputs + static_cast<size_t>(p % c.S) * c.W, c.W, c.n, bin);
+        load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
         const double2 a = pre.amp[p];
         const double M0 = pre.M[p];
         const uint64_t NH = 1ull << c.A;

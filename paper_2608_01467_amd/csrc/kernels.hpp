@@ -37,6 +37,9 @@ struct Table {
 struct Partials {
     double2 *amp;      // [items]
     uint64_t *st;      // [items][4]
+    // timing mode only (else null): per item, the device's constant-rate
+    // clock when a workgroup popped it and when its sums were stored
+    unsigned long long *stamps;   // [items][2]
 };
 
 struct Common {
@@ -58,6 +61,10 @@ struct Common {
     uint32_t Ap, Ar, As;
     uint32_t f_L, f_c1, f_c2, f_G;   // factor-table offsets of evaluation positions L, c1, c2, G
     double thr;
+    // 1: the program was placed by the forward sweep and walks the circuit
+    // from the input: a history starts from the input bitstring and ends at
+    // the check against the output (the roles of the two swap)
+    uint32_t fwd;
 };
 
 #if !defined(__HIPCC_RTC__)

@@ -118,6 +118,56 @@ inline void touched_bits(const Instr &I, uint32_t (&m)[4]) {
     }
 }
 
+// The state bits an instruction writes (the target of a permutation, both
+// swapped bits, the bit a branching gate sets, a ladder step's field).
+inline void written_bits(const Instr &I, uint32_t (&m)[4]) {
+    const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+    const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+    for (int w = 0; w < 4; ++w) m[w] = 0;
+    auto bit = [&](uint32_t q) {
+        if (q < 128) m[q >> 5] |= 1u << (q & 31);
+    };
+    switch (base) {
+        case OP_PERM:
+        case OP_DET1:
+        case OP_BRANCH_SRC:
+        case OP_BRANCH_NAT: bit(a); break;
+        case OP_SWAP: bit(a); bit(b); break;
+        case OP_ADD:
+        case OP_ADDSEL:
+            for (uint32_t q = a; q < a + b; ++q) bit(q);
+            break;
+        default: break;
+    }
+}
+
+// Which state bits hold a source bit of the current region, as the region
+// is walked in order: a branching gate with a source sets its bit to source
+// k; any other write clears the association.  A ladder step without
+// controls whose selecting bit holds source k adds a constant plus +-1 times
+// that source bit, so the compiled regions sum such steps' selecting bits
+// as a popcount of the region's source index (and the work count follows).
+struct SourceBits {
+    int src[kMaxQubits];
+    SourceBits() {
+        for (int &x : src) x = -1;
+    }
+    void step(const Instr &I, uint32_t kbase) {
+        uint32_t m[4];
+        written_bits(I, m);
+        for (int q = 0; q < kMaxQubits; ++q)
+            if ((m[q >> 5] >> (q & 31)) & 1u) src[q] = -1;
+        if (op_base(static_cast<uint8_t>(I.hdr & 0xffu)) == OP_BRANCH_SRC)
+            src[(I.hdr >> 8) & 0xffu] = static_cast<int>(I.k - kbase);
+    }
+    // the region-relative source a controls-free paired step selects on, or -1
+    int selector_source(const Instr &I) const {
+        if (op_base(static_cast<uint8_t>(I.hdr & 0xffu)) != OP_ADDSEL || I.k >= 128) return -1;
+        if (I.cm[0] | I.cm[1] | I.cm[2] | I.cm[3]) return -1;
+        return src[I.k];
+    }
+};
+
 // Whether `I` ends a pending accumulation of ladder steps on the field
 // [lo, hi): it touches a field bit other than as a further step of the same
 // field (an add on the field itself only reads its controls and selector).
@@ -149,6 +199,7 @@ struct HostProgram {
     int NW = 1;                // 32-bit words per device state (1, 2 or 4)
     int L = 0;                 // leading source-free gates (evaluation order)
     int n_branch = 0;
+    bool forward = false;      // placed by the forward sweep: evaluation order = time order
     std::vector<Instr> ins;            // evaluation order, size G (fused gates become OP_NOP)
     int n_fused = 0;                   // ladders folded into OP_ADD
     int n_paired = 0;                  // OP_ADD pairs merged into OP_ADDSEL

@@ -619,12 +619,35 @@ void set_field_runs(HostProgram &P) {
 
 constexpr uint64_t kCheckCost = 2;   // n = pk + 2 pb, and one compare
 
+constexpr uint64_t kPopcountCost = 2;   // the source index masked, its popcount
+
 // Algorithmic int32 ops of evaluation positions [lo, hi) for one history.
+// A paired ladder step without controls whose selecting bit holds a source
+// bit set earlier in the range (SourceBits) adds a constant plus that bit
+// with a fixed sign: such steps cost nothing each, and their run pays one
+// popcount of the source index per sign that occurs.
 uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
     uint64_t ops = 0;
+    SourceBits sb;
+    bool pos_used = false, neg_used = false;
     for (uint32_t e = lo; e < hi; ++e) {
-        ops += P.int_cost[e];
-        if (P.flush_cost[e] && (P.run_prev[e] == kNoPrev || P.run_prev[e] < lo)) ops += P.flush_cost[e];
+        const Instr &I = P.ins[e];
+        const bool starts_run = P.flush_cost[e] && (P.run_prev[e] == kNoPrev || P.run_prev[e] < lo);
+        if (starts_run) pos_used = neg_used = false;
+        const int j = sb.selector_source(I);
+        sb.step(I, 0);
+        if (j >= 0) {
+            const uint32_t z = I.hdr >> 24;
+            const int d0 = (z & 1u) ? -1 : 1, d1 = (z & 2u) ? -1 : 1;
+            bool &used = d1 > d0 ? pos_used : neg_used;
+            if (d1 != d0 && !used) {
+                ops += kPopcountCost;
+                used = true;
+            }
+        } else {
+            ops += P.int_cost[e];
+        }
+        if (starts_run) ops += P.flush_cost[e];
     }
     // a range that reaches the final check: the run pending there, from its
     // first step inside the range, is compared instead of applied
@@ -677,7 +700,8 @@ extern "C" const char *fhs_status_string(fhs_status s) {
 
 extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags,
                                     fhs_program **out) {
-    if (!text || !out || (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE | FHS_REDUCE_PAIR)) ||
+    if (!text || !out ||
+        (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE | FHS_REDUCE_PAIR | FHS_REDUCE_FORWARD)) ||
         ((flags & FHS_REDUCE_PAIR) && !(flags & FHS_REDUCE_FUSE)))
         return FHS_EINVAL;
     *out = nullptr;
@@ -685,9 +709,20 @@ extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags
     std::vector<Gate> gates;
     fhs_status st = parse(text, len, n, gates);
     if (st != FHS_OK) return st;
+    if (flags & FHS_REDUCE_FORWARD) {
+        // <b_out|C|b_in> = <b_in|C^T|b_out>: the forward sweep over C is the
+        // backward sweep over the transpose, whose gates are C's in reverse
+        // order with transposed matrices (MCX and MCZ are symmetric); its
+        // natural input segments are C's natural output segments
+        std::reverse(gates.begin(), gates.end());
+        for (Gate &g : gates)
+            for (int a = 0; a < (1 << g.k); ++a)
+                for (int b = 0; b < a; ++b) std::swap(g.m[a][b], g.m[b][a]);
+    }
     fhs_program *p = new (std::nothrow) fhs_program;
     if (!p) return FHS_ENOMEM;
     st = emit(n, gates, p->p);
+    p->p.forward = (flags & FHS_REDUCE_FORWARD) != 0;
     if (st != FHS_OK) {
         delete p;
         return st;
@@ -715,6 +750,7 @@ extern "C" fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_
     info->n_words = static_cast<uint32_t>(P.W);
     info->n_leading = static_cast<uint32_t>(P.L);
     info->n_branch = static_cast<uint32_t>(P.n_branch);
+    info->forward = P.forward ? 1u : 0u;
     return FHS_OK;
 }
 

@@ -123,6 +123,10 @@ struct fhs_ctx {
     unsigned long long *d_valid = nullptr;  // timing mode: consistent prefix entries
     uint64_t n_entries = 0;                 // timing mode: prefix entries built
     void *scratch = nullptr;                // this device's copy of the no-alloc scratch
+    unsigned long long *d_stamps = nullptr; // timing mode: per work item start/end clock
+    size_t stamps_cap = 0;                  // items d_stamps holds
+    uint64_t n_stamped = 0;                 // items of the last timed evaluation
+    uint32_t stamp_ipp = 0;                 // items per pair of the last timed evaluation
 };
 
 // Workspace of fhs_evaluate_noalloc, for callers that cannot allocate: a
@@ -380,6 +384,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.f_c2 = P.fac_begin[pl.c2];
     cm.f_G = P.fac_begin[P.G];
     cm.thr = thr;
+    cm.fwd = P.forward ? 1u : 0u;
     return cm;
 }
 
@@ -471,16 +476,18 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
     hipError_t e = launch_precheck(cm, NW, pre, pl.P, counters, P.A > 0 ? pl.n_batches : 0, s);
     if (e != hipSuccess) return e;
     if (P.A == 0) {
-        e = launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s);
+        e = launch_pair_reduce(pre, Partials{nullptr, nullptr, nullptr}, res, 0, pl.P, 0, 0, s);
         if (e != hipSuccess) return e;
         return launch_finalize(res, coeffs, cm.S, cm.M, amps, stats, s);
     }
     Table tab{at<uint32_t>(ws, pl.off_tab_st), at<double2>(ws, pl.off_tab_beta),
               at<double>(ws, pl.off_tab_M), at<uint32_t>(ws, pl.off_tab_ok)};
-    Partials part{at<double2>(ws, pl.off_part_amp), at<uint64_t>(ws, pl.off_part_st)};
+    Partials part{at<double2>(ws, pl.off_part_amp), at<uint64_t>(ws, pl.off_part_st), nullptr};
     for (uint32_t b = 0; b < pl.n_batches; ++b) {
         const uint32_t p0 = b * pl.B;
         const uint32_t B = std::min(pl.B, pl.P - p0);
+        // timing mode: this batch's items in the stamp buffer (pair-major)
+        part.stamps = timed && c->d_stamps ? c->d_stamps + 2ull * p0 * pl.nchunks : nullptr;
         const uint64_t items = static_cast<uint64_t>(B) * pl.nchunks;
         uint32_t grid = static_cast<uint32_t>(std::max(c->num_cu, 1)) * static_cast<uint32_t>(bpc);
         if (items < grid) grid = static_cast<uint32_t>(items);
@@ -540,6 +547,7 @@ extern "C" void fhs_ctx_destroy(fhs_ctx *c) {
     fhs_program_free(c->prog_copy);
     if (c->d_model) hipFree(c->d_model);
     if (c->d_valid) hipFree(c->d_valid);
+    if (c->d_stamps) hipFree(c->d_stamps);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
@@ -965,6 +973,7 @@ extern "C" fhs_status fhs_set_kernel_timing(fhs_ctx *c, int enable) {
     c->timing = enable != 0;
     c->n_timed = 0;
     c->n_entries = 0;
+    c->n_stamped = 0;
     drop_graph(c);
     return FHS_OK;
 }
@@ -1041,6 +1050,17 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
             // not captured: a plain memset is fine here
             FHS_HIP(c, hipMemsetAsync(c->d_valid, 0, sizeof(unsigned long long), s));
             c->n_entries = 0;
+            const size_t items = static_cast<size_t>(pl.P) * pl.nchunks;
+            if (items > c->stamps_cap) {
+                FHS_HIP(c, hipStreamSynchronize(s));
+                if (c->d_stamps) FHS_HIP(c, hipFree(c->d_stamps));
+                c->d_stamps = nullptr;
+                c->stamps_cap = 0;
+                FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_stamps), 2 * sizeof(unsigned long long) * items));
+                c->stamps_cap = items;
+            }
+            c->n_stamped = items;
+            c->stamp_ipp = pl.nchunks;
         }
         FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s, ck));
         c->n_timed = timed ? pl.n_batches : 0;
@@ -1092,9 +1112,9 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
     PairRes res = pair_res(d_ws, pl);
     FHS_HIP(c, launch_precheck(cm, NW, pre, pl.P, nullptr, 0, s));
     if (P.A == 0) {
-        FHS_HIP(c, launch_pair_reduce(pre, Partials{nullptr, nullptr}, res, 0, pl.P, 0, 0, s));
+        FHS_HIP(c, launch_pair_reduce(pre, Partials{nullptr, nullptr, nullptr}, res, 0, pl.P, 0, 0, s));
     } else {
-        Partials part{at<double2>(d_ws, pl.off_plain_amp), at<uint64_t>(d_ws, pl.off_plain_st)};
+        Partials part{at<double2>(d_ws, pl.off_plain_amp), at<uint64_t>(d_ws, pl.off_plain_st), nullptr};
         if (c->timing) {
             FHS_HIP(c, ensure_events(c, 1));
             FHS_HIP(c, hipEventRecord(c->events[0], s));
@@ -1102,6 +1122,7 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
         FHS_HIP(c, launch_plain(cm, NW, c->ilp, pre, part, pl.P, pl.bpp, s));
         if (c->timing) FHS_HIP(c, hipEventRecord(c->events[1], s));
         c->n_timed = c->timing ? 1 : 0;
+        c->n_stamped = 0;
         FHS_HIP(c, launch_pair_reduce(pre, part, res, 0, pl.P, pl.bpp, cm.A, s));
     }
     FHS_HIP(c, launch_finalize(res, d_cf, S, M, d_amps, d_stats, s));
@@ -1135,5 +1156,23 @@ extern "C" fhs_status fhs_evaluate_noalloc(fhs_ctx *c, const uint64_t *d_in, con
     if (c->blocks_per_cu > 0) bpc = std::min<int>(bpc, static_cast<int>(c->blocks_per_cu));
     // enqueued directly (instantiating a graph allocates), never timed
     FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, c->scratch, bpc, false, s, ck));
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_item_stamps(fhs_ctx *c, uint64_t *stamps, size_t cap, size_t *count,
+                                      uint32_t *items_per_pair, uint64_t *ticks_per_s) {
+    if (!c || !count || (!stamps && cap)) return FHS_EINVAL;
+    c->err.clear();
+    if (!c->timing || c->n_timed == 0 || c->n_stamped == 0) return fail(c, FHS_ESTATE, "no timed launch");
+    FHS_HIP(c, hipSetDevice(c->device));
+    *count = c->n_stamped;
+    if (items_per_pair) *items_per_pair = c->stamp_ipp;
+    if (ticks_per_s) {
+        int khz = 0;
+        FHS_HIP(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+        *ticks_per_s = static_cast<uint64_t>(khz) * 1000u;
+    }
+    const size_t n = std::min(cap, static_cast<size_t>(c->n_stamped));
+    if (n) FHS_HIP(c, hipMemcpy(stamps, c->d_stamps, 2 * sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
     return FHS_OK;
 }

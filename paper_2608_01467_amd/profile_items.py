@@ -1,0 +1,153 @@
+"""Where the time goes across outputs (Section V: time against the number of
+artificial sources on the quantum walk; time per requested bitstring).
+
+    python -m paper_2608_01467_amd.profile_items items [--workload walk_99p_20s]
+    python -m paper_2608_01467_amd.profile_items sources [--steps 10-20]
+
+`items`: one batched evaluation of the workload in timing mode at its
+Eq. (8) split (or --cuts); the persistent consumer's per-item clock stamps
+(fhs_item_stamps) give each output's cost (the summed durations of its
+items), their distribution, and how well the atomic work queue kept the
+workgroups busy: the makespan against the summed item time divided by the
+number of resident workgroups.  `sources`: the walk at 10..20 steps (A = s-1
+sources) with the same output count, consumer time per output and per
+candidate history against A.  One JSON line per result.  Everything here
+drives the C ABI; no computation of the method happens in Python.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as w  # noqa: E402
+
+from . import PART_EQ8, Context, Program  # noqa: E402
+
+
+def _quantiles(x: np.ndarray) -> dict:
+    if x.size == 0:
+        return {}
+    q = np.quantile(x, [0.0, 0.1, 0.5, 0.9, 0.99, 1.0])
+    return {"min": float(q[0]), "p10": float(q[1]), "median": float(q[2]), "p90": float(q[3]),
+            "p99": float(q[4]), "max": float(q[5]), "mean": float(x.mean()),
+            "cv": float(x.std() / x.mean()) if x.mean() > 0 else 0.0}
+
+
+def _histogram(x: np.ndarray, bins: int = 12) -> list:
+    """Counts over log-spaced bins between the smallest and largest value."""
+    x = x[x > 0]
+    if x.size == 0:
+        return []
+    lo, hi = float(x.min()), float(x.max())
+    if hi <= lo:
+        return [{"from": lo, "to": hi, "count": int(x.size)}]
+    edges = np.geomspace(lo, hi * (1 + 1e-12), bins + 1)
+    counts, _ = np.histogram(x, bins=edges)
+    return [{"from": float(edges[i]), "to": float(edges[i + 1]), "count": int(c)}
+            for i, c in enumerate(counts)]
+
+
+def timed_evaluation(ctx: Context, prog: Program, cfg: dict, cuts, launch=None, reps: int = 2):
+    """Evaluate in timing mode; returns (consumer ms per launch, stamps,
+    items per pair, ticks per second, amps, stats) of the last repetition."""
+    import torch
+    if launch is not None:
+        ctx.set_launch_config(*launch)
+    ctx.load(prog)
+    ctx.set_partition(*cuts)
+    d_in = ctx.device_bits(cfg["inputs"])
+    d_out = ctx.device_bits(cfg["outputs"])
+    d_cf = ctx.device_coeffs([complex(*z) for z in cfg["coeffs"]])
+    M = len(cfg["outputs"])
+    amps = torch.empty((M, 2), dtype=torch.float64, device="cuda:0")
+    stats = torch.empty((M, 4), dtype=torch.int64, device="cuda:0")
+    ctx.evaluate(d_in, d_cf, d_out, threshold=cfg["threshold"], out=(amps, stats))   # compile, warm up
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    for _ in range(reps):
+        ctx.evaluate(d_in, d_cf, d_out, threshold=cfg["threshold"], out=(amps, stats))
+        torch.cuda.synchronize()
+    ms = ctx.kernel_times()
+    stamps, ipp, tps = ctx.item_stamps()
+    ctx.set_kernel_timing(False)
+    return (sum(ms) / len(ms), stamps, ipp, tps, amps.cpu().numpy(),
+            stats.cpu().numpy().view(np.uint64))
+
+
+def items(args) -> int:
+    cfg = w.CONFIGS[args.workload]()
+    text = cfg["circuit"].to_text()
+    prog = Program(text)
+    ctx = Context(0)
+    ctx.set_table_budget(32 << 30)
+    cuts = tuple(int(v) for v in args.cuts.split(",")) if args.cuts else prog.choose_partition(PART_EQ8)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    ms, stamps, ipp, tps, _, st = timed_evaluation(ctx, prog, cfg, cuts, launch)
+    S = len(cfg["inputs"])
+    start = stamps[:, 0].astype(np.int64)
+    dur = (stamps[:, 1].astype(np.int64) - start) / tps * 1e6           # microseconds
+    per_out = dur.reshape(-1, S * ipp).sum(axis=1)                       # outputs x (inputs x items)
+    leaves = st[:, 3].astype(np.float64)
+    makespan = (stamps[:, 1].max() - stamps[:, 0].min()) / tps * 1e6
+    plan = ctx.plan(len(cfg["outputs"]), S)
+    lc = ctx.launch_config
+    valid = st[:, 0] > 0
+    line = {"workload": args.workload, "partition": list(cuts), "launch_config": list(lc),
+            "regions": [plan["Ap"], plan["Ar"], plan["As"]], "items": int(stamps.shape[0]),
+            "items_per_pair": ipp, "consumer_ms": ms, "makespan_us": float(makespan),
+            "item_us": _quantiles(dur), "output_us": _quantiles(per_out),
+            "output_us_histogram": _histogram(per_out),
+            "output_us_valid": _quantiles(per_out[valid]),
+            "output_us_no_valid_history": _quantiles(per_out[~valid]),
+            "leaves_per_output": _quantiles(leaves),
+            # the queue's balance: summed item time over the workgroups that
+            # ran it, against the makespan
+            "sum_item_us": float(dur.sum())}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def sources(args) -> int:
+    lo, hi = (int(v) for v in args.steps.split("-"))
+    ctx = Context(0)
+    ctx.set_table_budget(32 << 30)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else (2, 256, 0, 3)
+    for s in range(lo, hi + 1):
+        c = w.quantum_walk(99, s)
+        cfg = {"circuit": c, "inputs": [0], "coeffs": [(1.0, 0.0)],
+               "outputs": w.walk_outputs(99, s, args.outputs, seed=501), "threshold": 0.0}
+        prog = Program(c.to_text())
+        cuts = prog.choose_partition(PART_EQ8)
+        ms, stamps, ipp, tps, _, st = timed_evaluation(ctx, prog, cfg, cuts, launch)
+        dur = (stamps[:, 1].astype(np.int64) - stamps[:, 0].astype(np.int64)) / tps * 1e6
+        per_out = dur.reshape(-1, ipp).sum(axis=1)
+        M = len(cfg["outputs"])
+        print(json.dumps({"steps": s, "sources": prog.A, "outputs": M, "partition": list(cuts),
+                          "consumer_ms": ms, "ms_per_output": ms / M,
+                          "ns_per_candidate": ms * 1e6 / (M * (1 << prog.A)),
+                          "output_us": _quantiles(per_out)}), flush=True)
+    return 0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["items", "sources"])
+    ap.add_argument("--workload", default="walk_99p_20s")
+    ap.add_argument("--cuts", default=None, metavar="C1,C2")
+    ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC,DISPATCH")
+    ap.add_argument("--steps", default="10-20")
+    ap.add_argument("--outputs", type=int, default=8192)
+    args = ap.parse_args()
+    return items(args) if args.mode == "items" else sources(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -43,23 +43,26 @@ def test_walk_ladders_fold_to_one_instruction_each():
     # the coin's H: its source bit into the state (1);
     # unfolded: the X on position bit i has controls up to qubit i (w words): 3w+1;
     # folded: one add per ladder, 3*1+1 for the coin control + 1 for the step;
-    # paired: one add per walk step, the coin bit added to the count: 2; either way
-    # every step adds to the same 4-word position field and only the coin's H
-    # (outside the field) lies between them: one run.  The run is still pending
-    # at the end, where every position bit is compared with the input, so it
-    # costs a compare of its count with the field's residue (2), not a carry
-    # chain (3 * 4)
+    # paired: one add per walk step, the coin bit added to the count: 2, except
+    # that a step whose coin still holds the source bit the Hadamard before it
+    # (in evaluation order) set costs nothing and the run sums those bits with
+    # one popcount of the source index (2): only the first step, whose coin
+    # comes from the output, pays 2.  Either way every step adds to the same
+    # 4-word position field and only the coin's H (outside the field) lies
+    # between them: one run.  The run is still pending at the end, where
+    # every position bit is compared with the input, so it costs a compare of
+    # its count with the field's residue (2), not a carry chain (3 * 4)
     words = lambda hi: hi // 32 + 1
     unfolded = steps * (1 + 2 * sum(3 * words(i) + 1 for i in range(n_pos)))
     assert a.work(0, a.G)["int_ops"] == unfolded
     assert b.work(0, b.G)["int_ops"] == steps * (1 + 2 * (4 + 1)) + 2
-    assert c.work(0, c.G)["int_ops"] == steps * (1 + 2) + 2
-    # a range that starts inside the run pays its own compare, and the range
-    # that holds the run's start but stops short of the end applies its part
-    # with a carry chain
+    assert c.work(0, c.G)["int_ops"] == steps * 1 + 2 + 2 + 2
+    # a range that starts inside the run pays its own popcount and compare,
+    # and the range that holds the run's start but stops short of the end
+    # applies its part with a carry chain
     half = c.source_eval_positions[len(c.source_eval_positions) // 2]
     assert c.work(half, c.G)["int_ops"] + c.work(0, half)["int_ops"] == \
-        c.work(0, c.G)["int_ops"] + 3 * 4
+        c.work(0, c.G)["int_ops"] + 3 * 4 + 2
     # one instruction per ladder when folded, one per step when paired
     fb = b.split_features(b.L, b.G, 64, 1)
     fc = c.split_features(c.L, c.G, 64, 1)
@@ -76,8 +79,8 @@ def test_mixed_circuits_without_ladders_are_unchanged():
 def test_reduce_ex_rejects_unknown_flags():
     t = b"qubits 2\nH 0\n"
     h = ctypes.c_void_p()
-    assert fhs.lib().fhs_reduce_ex(t, len(t), 4, ctypes.byref(h)) == 1
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 8, ctypes.byref(h)) == 1
     assert fhs.lib().fhs_reduce_ex(t, len(t), 2, ctypes.byref(h)) == 1   # pair needs fuse
-    for flags in (0, 1, 3):
+    for flags in (0, 1, 3, 4, 7):
         assert fhs.lib().fhs_reduce_ex(t, len(t), flags, ctypes.byref(h)) == 0
         fhs.lib().fhs_program_free(h)

@@ -610,3 +610,104 @@ def test_compiled_random_mixed(ctx, seed):
                 assert np.abs(amps - ref[0]).max() <= TOL, (seed, thr, h, part)
                 assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (seed, thr, h, part)
     ctx.set_launch_config(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("case", ["fig2", "qft8", "qaoa6", "walk_xcoin", "aa3", "branchy1", "branchy3"])
+def test_forward_placement(ctx, case):
+    """Sources placed by the forward sweep (FHS_REDUCE_FORWARD, Table I's
+    other column): the plain form and the batched form (interpreted and
+    compiled, cuts counted from the input) against the oracle's forward
+    placement, valid sets included; the amplitudes also equal the backward
+    program's."""
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case == "fig2":
+        t = ("qubits 4\nCX 1 0\nH 1\nSWAP 2 3\nH 3\nP 2 " + math.pi.hex() +
+             "\nCX 0 1\nH 0\nSWAP 1 2\n")
+    elif case == "qft8":
+        t = w.qft(8).to_text()
+    elif case == "qaoa6":
+        t = w.qaoa_maxcut(6, 2, 61, 62)[0].to_text()
+    elif case == "walk_xcoin":
+        t = w.quantum_walk_xcoin(12, 7).to_text()
+    elif case == "aa3":
+        t = w.amplitude_amplification(3, 1, 2, seed=9)[0].to_text()
+    else:
+        seed = int(case[-1])
+        t = _branchy([4, 6, 7, 9][seed], 3 + seed % 2, 9000 + seed).to_text()
+    of, ob = oracle.Feynman(t, "forward"), oracle.Feynman(t)
+    n = of.n
+    S = 1 + len(case) % 2
+    inputs = [0] + [int(rng.integers(0, 1 << min(n, 62))) for _ in range(S - 1)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in range(S)]
+    outs = list(range(1 << n)) if n <= 8 else [int(rng.integers(0, 1 << n)) for _ in range(48)]
+    if case == "walk_xcoin":
+        outs = w.walk_outputs(12, 7, 40, seed=3)
+    ref_a, ref_st = of.evaluate(inputs, coeffs, outs, threads=THREADS)
+    bwd_a, _ = ob.evaluate(inputs, coeffs, outs, threads=THREADS)
+    assert np.abs(ref_a - bwd_a).max() <= TOL
+    prog = fhs.Program(t, forward=True)
+    assert prog.forward and prog.A == of.A
+    parts = [(0, 0), prog.choose_partition(fhs.PART_EQ8), prog.choose_partition(fhs.PART_THIRDS),
+             (prog.G, prog.G)]
+    runs = [((0, 0), True, 0, 1)] + [(p, False, d, h) for p in parts for d, h in ((0, 2), (3, 1), (3, 2))]
+    for part, plain, dispatch, h in runs:
+        ctx.set_launch_config(h, 0, 0, dispatch)
+        amps, st = gpu_eval(ctx, t, inputs, coeffs, outs, partition=part, plain=plain, prog=prog)
+        assert np.abs(amps - ref_a).max() <= TOL, (case, part, plain, dispatch, h)
+        assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), (case, part, plain, dispatch)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
+def test_walk_paper_coin_s2(ctx):
+    """The paper's large walk: 100 qubits, 16 steps, the coin starting in
+    (|0> + i|1>)/sqrt2 as two input bitstrings (S = 2, A = 15 per pair),
+    2000 requested outputs: the reachable ones against the position-space
+    closed form with that coin (normalised), their valid sets summed over
+    both inputs (count and index sum doubled, xor-hash cancelled), padding
+    exactly zero; at Eq. (8)'s split and at splits around it, interpreted
+    and compiled."""
+    cfg = w.CONFIGS["walk_99p_16s_s2"]()
+    t = cfg["circuit"].to_text()
+    coeffs = [complex(*z) for z in cfg["coeffs"]]
+    prog = fhs.Program(t)
+    r = 1 / math.sqrt(2)
+    dp = cf.walk_amplitudes(16, (r, 1j * r))
+    outs = cfg["outputs"]
+    eq8 = prog.choose_partition(fhs.PART_EQ8)
+    src = prog.source_eval_positions
+    parts = [eq8, (src[4], src[9]), (src[6], src[11]), (0, 0)]
+    for part in parts:
+        for launch in ((0, 0, 0, 0), (2, 256, 0, 3), (1, 128, 0, 3)):
+            ctx.set_launch_config(*launch)
+            amps, st = gpu_eval(ctx, t, cfg["inputs"], coeffs, outs, partition=part, prog=prog)
+            total = 0.0
+            for y, a, row in zip(outs, amps, st):
+                x = y >> 1
+                x = x - (1 << 99) if x >= (1 << 98) else x
+                ref = dp.get((x, y & 1))
+                if ref is None:
+                    assert a == 0 and int(row[0]) == 0, (part, launch, y)
+                    continue
+                total += abs(a) ** 2
+                assert abs(a - ref) <= TOL, (part, launch, x, y & 1)
+                n, sh, _ = cf.walk_valid_stats(16, x, y & 1)
+                assert (int(row[0]), int(row[1]), int(row[2])) == (2 * n, (2 * sh) % (1 << 64), 0)
+            assert abs(total - 1.0) <= 1e-10
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
+def test_qft_dense_signal(ctx):
+    """A dense real signal on 12 qubits (every basis state an input,
+    S = 4096 pairs per output, one history each): every frequency bin
+    against the discrete Fourier transform of the signal; only the two
+    tones and their mirror bins are nonzero."""
+    cfg = w.CONFIGS["qft_12q_dense"]()
+    t = cfg["circuit"].to_text()
+    coeffs = [complex(*z) for z in cfg["coeffs"]]
+    x = np.array([c.real for c in coeffs])
+    ref = cf.qft_dense(12, x)
+    for plain in (False, True):
+        amps, st = gpu_eval(ctx, t, cfg["inputs"], coeffs, cfg["outputs"], plain=plain)
+        assert np.abs(amps - ref).max() <= TOL, plain
+        assert sorted(np.nonzero(np.abs(amps) > 1e-9)[0].tolist()) == [5, 2001, 2095, 4091]
+        assert (st[:, 0] == 4096).all()          # one valid history per (input, output) pair

@@ -67,6 +67,34 @@ def test_reducer_matches_oracle_placement(name, text):
     assert p.choose_partition(fhs.PART_NONE) == (0, 0)
 
 
+def _forward_circuits():
+    for seed in range(30):
+        n = [1, 3, 6, 12, 33, 64, 65, 100, 128][seed % 9]
+        yield f"mixed{seed}", w.random_mixed(n, 10 + seed % 30, 1900 + seed, max_controls=5).to_text()
+    for n in (4, 7, 12):
+        yield f"qft{n}", w.qft(n).to_text()
+    yield "aa4", w.amplitude_amplification(4, 3, 4, 301)[0].to_text()
+    yield "qaoa12", w.qaoa_maxcut(12, 2)[0].to_text()
+    yield "walk_xcoin", w.quantum_walk_xcoin(20, 6).to_text()
+
+
+@pytest.mark.parametrize("name,text", list(_forward_circuits()), ids=[c[0] for c in _forward_circuits()])
+def test_forward_reducer_matches_oracle(name, text):
+    """FHS_REDUCE_FORWARD places the same sources, at the same positions
+    (counted from the input), as the oracle's forward sweep; Eq. (8) over
+    time-order cuts agrees."""
+    p = fhs.Program(text, forward=True)
+    o = oracle.Feynman(text, "forward")
+    assert p.forward
+    assert (p.n, p.G, p.A) == (o.n, o.G, o.A)
+    assert p.source_eval_positions == o.source_eval_positions
+    rng = np.random.default_rng(len(text))
+    for _ in range(10):
+        c1, c2 = sorted(int(x) for x in rng.integers(0, p.G + 1, size=2))
+        assert p.partition_cost(c1, c2)[0] == o.eq8(c1, c2)
+        assert p.partition_cost(c1, c2)[1][3:] == o.region_sources(c1, c2)
+
+
 def test_walk_eq8_argmin_matches_oracle():
     t = w.quantum_walk(99, 20).to_text()
     p, o = fhs.Program(t), oracle.Feynman(t)

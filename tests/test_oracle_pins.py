@@ -385,3 +385,69 @@ def test_forward_counts_and_threshold_against_brute_force(seed):
             amp_b, nv_b = bf.path_sum(t, b_in, b_out, threshold=thr, forward=True)
             assert nv == nv_b, (thr, b_out)
             assert abs(amp - amp_b) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# sparse and dense input states (Eq. (2) with S > 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_pos,steps", [(5, 4), (6, 5), (7, 6)])
+def test_walk_complex_coin_statevector(n_pos, steps):
+    """The walk from position 0 with the coin in (|0> + i|1>)/sqrt2 (the
+    paper's large walk, Section V), as S = 2 basis inputs: the position-space
+    recursion with that initial coin against the state vector of the
+    superposition, and the oracle (Eq. (2)) against both."""
+    r = 1 / math.sqrt(2)
+    t = w.quantum_walk(n_pos, steps).to_text()
+    ins = [w.walk_state(n_pos, 0, 0), w.walk_state(n_pos, 0, 1)]
+    psi = np.zeros(1 << (n_pos + 1), dtype=complex)
+    psi[ins[0]], psi[ins[1]] = r, 1j * r
+    full = sv.evolve_state(t, psi)
+    dp = cf.walk_amplitudes(steps, (r, 1j * r))
+    assert abs(sum(abs(a) ** 2 for a in dp.values()) - 1.0) <= 1e-14
+    for (x, c), a in dp.items():
+        assert abs(full[w.walk_state(n_pos, x, c)] - a) <= 1e-14
+    outs = list(range(1 << (n_pos + 1)))
+    amps, _ = oracle.Feynman(t).evaluate(ins, [r, 1j * r], outs)
+    assert np.abs(amps - full).max() <= 1e-13
+
+
+def test_walk_complex_coin_large_closed_form():
+    """The 100-qubit, 16-step walk from the paper's coin state: normalised
+    over its reachable outputs; the oracle agrees on a sample of them, and
+    each output's valid set (summed over the two inputs) is twice the
+    single-input set: count and index sum doubled, xor-hash cancelled."""
+    cfg = w.CONFIGS["walk_99p_16s_s2"]()
+    t = cfg["circuit"].to_text()
+    r = 1 / math.sqrt(2)
+    dp = cf.walk_amplitudes(16, (r, 1j * r))
+    assert len(dp) == 32 and abs(sum(abs(a) ** 2 for a in dp.values()) - 1.0) <= 1e-13
+    F = oracle.Feynman(t)
+    assert F.A == 15
+    sample = [w.walk_state(99, x, c) for x, c in ((0, 0), (2, 1), (-6, 0), (14, 1), (16, 1))]
+    amps, st = F.evaluate(cfg["inputs"], [complex(*z) for z in cfg["coeffs"]], sample, threads=4)
+    for y, a, row in zip(sample, amps, st):
+        x = y >> 1
+        x = x - (1 << 99) if x >= (1 << 98) else x
+        assert abs(a - dp[(x, y & 1)]) <= 1e-13
+        n, sh, _ = cf.walk_valid_stats(16, x, y & 1)
+        assert (int(row[0]), int(row[1]), int(row[2])) == (2 * n, (2 * sh) % (1 << 64), 0)
+
+
+@pytest.mark.parametrize("n", [3, 6, 9, 12])
+def test_qft_dense_input(n):
+    """QFT of a dense real input: the state vector of the superposition
+    against the discrete Fourier transform (FFT) of its amplitudes, and, at
+    12 qubits, the workload's two tones at bins 5 and 2001 (with their
+    mirror bins 4091 and 2095 for a real signal)."""
+    rng = np.random.default_rng(n)
+    psi = rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    t = w.qft(n).to_text()
+    assert np.abs(sv.evolve_state(t, psi.astype(complex)) - cf.qft_dense(n, psi)).max() <= 1e-13
+    if n == 12:
+        cfg = w.CONFIGS["qft_12q_dense"]()
+        x = np.array([z[0] for z in cfg["coeffs"]])
+        a = cf.qft_dense(12, x)
+        assert sorted(np.nonzero(np.abs(a) > 1e-12)[0].tolist()) == [5, 2001, 2095, 4091]
+        assert abs(np.sum(np.abs(a) ** 2) - 1.0) <= 1e-13

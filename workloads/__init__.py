@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "Gate", "Circuit", "random_clifford_t", "random_mixed", "random_ladders", "qft", "amplitude_amplification",
     "qaoa_maxcut", "quantum_walk", "quantum_walk_xcoin", "random_outputs", "bits_to_words",
-    "words_to_bits", "n_words", "three_regular_graph", "CONFIGS",
+    "words_to_bits", "n_words", "three_regular_graph", "reachable_outputs", "CONFIGS",
 ]
 
 
@@ -455,6 +455,43 @@ def _cfg_clifford_t():
                 outputs=random_outputs(10, 16, seed=102), threshold=0.0)
 
 
+def reachable_outputs(c: Circuit, count: int, seed: int) -> List[int]:
+    """Up to `count` distinct outputs reachable from |0...0>: the circuit
+    followed forward with a random bit after every branching gate (H, RX,
+    RY) and every permutation applied (phases ignored)."""
+    rng = np.random.default_rng(seed)
+    outs: List[int] = []
+    seen = set()
+    for _ in range(count * 8):
+        x = 0
+        for g in c.gates:
+            q = g.qubits
+            if g.name in ("H", "RX", "RY"):
+                x = (x & ~(1 << q[0])) | (int(rng.integers(0, 2)) << q[0])
+            elif g.name == "X":
+                x ^= 1 << q[0]
+            elif g.name == "CX" and (x >> q[0]) & 1:
+                x ^= 1 << q[1]
+            elif g.name == "SWAP" and ((x >> q[0]) ^ (x >> q[1])) & 1:
+                x ^= (1 << q[0]) | (1 << q[1])
+        if x not in seen:
+            seen.add(x)
+            outs.append(x)
+            if len(outs) >= count:
+                break
+    return outs
+
+
+def _cfg_clifford_t_large(n: int = 20, n_gates: int = 90, n_out: int = 4096):
+    """A larger random Clifford+T circuit (same gate mix) for the cost
+    distribution over outputs: half the outputs reachable from |0>, half
+    uniform (most of which exact pruning rejects early)."""
+    c = random_clifford_t(n, n_gates, seed=101)
+    reach = reachable_outputs(c, n_out // 2, seed=103)
+    outs = reach + random_outputs(n, n_out - len(reach), seed=102, exclude=reach)
+    return dict(circuit=c, inputs=[0], coeffs=[(1.0, 0.0)], outputs=outs, threshold=0.0)
+
+
 def _cfg_qft(n: int = 20, n_out: int = 256):
     rng = np.random.default_rng(201)
     x = int(rng.integers(0, 1 << n))
@@ -490,8 +527,33 @@ def _cfg_walk(n_pos: int = 99, steps: int = 20, total: int = 8192):
                 outputs=walk_outputs(n_pos, steps, total, seed=501), threshold=0.0)
 
 
+def _cfg_walk_coin(n_pos: int = 99, steps: int = 16, total: int = 2000):
+    """The paper's large walk (Section V): position 0 with the coin in
+    (|0> + i|1>)/sqrt2, i.e. two input bitstrings (S = 2), 16 steps
+    (A = 15 per pair), 2000 requested outputs (the reachable ones first)."""
+    c = quantum_walk(n_pos, steps)
+    r = 1.0 / math.sqrt(2.0)
+    return dict(circuit=c, inputs=[walk_state(n_pos, 0, 0), walk_state(n_pos, 0, 1)],
+                coeffs=[(r, 0.0), (0.0, r)], outputs=walk_outputs(n_pos, steps, total, seed=502),
+                threshold=0.0)
+
+
+def _cfg_qft_dense(n: int = 12):
+    """QFT of a dense real signal on 12 qubits (every basis state an input,
+    S = 4096), the shape of the paper's frequency-analysis example (its
+    signal is not given): two tones at bins 5 and 2001, amplitudes
+    normalised; every bin requested."""
+    N = 1 << n
+    t = np.arange(N)
+    x = np.cos(2 * math.pi * 5 * t / N) + 0.5 * np.cos(2 * math.pi * 2001 * t / N)
+    x = x / np.linalg.norm(x)
+    return dict(circuit=qft(n), inputs=list(range(N)), coeffs=[(float(v), 0.0) for v in x],
+                outputs=list(range(N)), threshold=0.0)
+
+
 CONFIGS = {
     "clifford_t_10q_40g": _cfg_clifford_t,
+    "clifford_t_20q_90g": _cfg_clifford_t_large,
     "qft_20q": _cfg_qft,
     "aa_k4_s3": lambda: _cfg_aa(4, 3),
     "aa_k5_s3": lambda: _cfg_aa(5, 3),
@@ -499,4 +561,6 @@ CONFIGS = {
     "qaoa_12v_p2": lambda: _cfg_qaoa(12, 2, 4096),
     "qaoa_24v_p2": lambda: _cfg_qaoa(24, 2, 4096),
     "walk_99p_20s": _cfg_walk,
+    "walk_99p_16s_s2": _cfg_walk_coin,
+    "qft_12q_dense": _cfg_qft_dense,
 }
