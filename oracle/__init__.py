@@ -96,17 +96,22 @@ class Feynman:
     placement: "backward" (the paper's sweep from the output, Section IV-A)
     or "forward" (the sweep from the input, Table I's other column); the
     sweep direction is also the evaluation order that the cuts of
-    Algorithm 2 index."""
+    Algorithm 2 index.  "optimal" and "greedy" (Section IV-B, Fig. 3):
+    sources on the input segments of branching gates, as few as let
+    determinism reach every internal wire (exhaustive search, or one
+    candidate at a time by the most wires reached); CNOT, SWAP and one-qubit
+    gates only; evaluated by Algorithm 1, propagation over the whole
+    circuit."""
 
     ROLE_PRESERVE, ROLE_DET, ROLE_BRANCH = 0, 1, 2
 
     def __init__(self, circuit_text: str, placement: str = "backward"):
         lib = _load()
         h = ctypes.c_void_p()
-        if placement not in ("backward", "forward"):
+        modes = {"backward": 0, "forward": 1, "optimal": 2, "greedy": 3}
+        if placement not in modes:
             raise ValueError(f"unknown placement {placement!r}")
-        _check(lib.orc_load_ex(circuit_text.encode(), 1 if placement == "forward" else 0,
-                               ctypes.byref(h)), "orc_load")
+        _check(lib.orc_load_ex(circuit_text.encode(), modes[placement], ctypes.byref(h)), "orc_load")
         self._h = h
         n, G, A, ns = (ctypes.c_int() for _ in range(4))
         lib.orc_info(h, ctypes.byref(n), ctypes.byref(G), ctypes.byref(A), ctypes.byref(ns))

@@ -84,6 +84,8 @@ typedef struct {
 typedef struct {
     int n, G, A, nseg;
     int forward;            /* 1: forward placement, evaluation order = time order */
+    int global;             /* 1: placement by reachability (sources anywhere the sweep
+                               reaches them): propagation always spans the whole circuit */
     ogate *g;               /* time order */
     int out_seg[ORC_MAXQ];  /* segment carrying each qubit at the output */
     int *src_seg;           /* [A] segment fixed by source k */
@@ -245,9 +247,166 @@ void orc_free(orc_circuit *c) {
     free(c);
 }
 
+/* ------------------------------------------------------------------ */
+/* source placement by reachability (Section IV-B, Fig. 3)              */
+/* ------------------------------------------------------------------ */
+
+/* Determinism-propagation relations between internal-wire segments,
+ * independent of the values: a pair (one segment fixes the other: a
+ * one-qubit deterministic gate, the two swapped wires of a SWAP) or a triple
+ * (a CNOT's control, target input and target output: any two fix the
+ * third).  Returns -1 for a circuit outside the gate set this analysis
+ * covers (branching gates on one qubit; deterministic gates on one qubit,
+ * CNOT and SWAP). */
+typedef struct { int n; int seg[3]; } relation;
+
+static int is_swap_matrix(const ogate *g) {
+    for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+            int sw = ((x & 1) << 1) | ((x >> 1) & 1);
+            if (is_zero(M_AT(g, y, x)) != (y != sw)) return 0;
+        }
+    return 1;
+}
+
+static int build_relations(const orc_circuit *c, relation *rel, int *nrel) {
+    int nr = 0;
+    for (int t = 0; t < c->G; ++t) {
+        const ogate *g = &c->g[t];
+        if (g->role == ROLE_PRESERVE) continue;
+        if (g->role == ROLE_BRANCH) {
+            if (g->k != 1) return -1;
+            continue;
+        }
+        if (g->k == 1) {
+            rel[nr].n = 2; rel[nr].seg[0] = g->in_seg[0]; rel[nr].seg[1] = g->out_seg[0]; ++nr;
+        } else if (g->k == 2 && g->kind == KIND_MCX) {          /* MCX with one control */
+            rel[nr].n = 3;
+            rel[nr].seg[0] = g->in_seg[1]; rel[nr].seg[1] = g->in_seg[0]; rel[nr].seg[2] = g->out_seg[0];
+            ++nr;
+        } else if (g->k == 2 && g->kind == KIND_DENSE && local_preserved(g, 0) != local_preserved(g, 1)) {
+            int jc = local_preserved(g, 0) ? 0 : 1, jt = 1 - jc;
+            rel[nr].n = 3;
+            rel[nr].seg[0] = g->in_seg[jc]; rel[nr].seg[1] = g->in_seg[jt]; rel[nr].seg[2] = g->out_seg[jt];
+            ++nr;
+        } else if (g->k == 2 && g->kind == KIND_DENSE && is_swap_matrix(g)) {
+            rel[nr].n = 2; rel[nr].seg[0] = g->in_seg[0]; rel[nr].seg[1] = g->out_seg[1]; ++nr;
+            rel[nr].n = 2; rel[nr].seg[0] = g->in_seg[1]; rel[nr].seg[1] = g->out_seg[0]; ++nr;
+        } else {
+            return -1;
+        }
+    }
+    *nrel = nr;
+    return 0;
+}
+
+/* Mark everything the relations reach from the segments already marked;
+ * returns how many are marked. */
+static int reach(const orc_circuit *c, const relation *rel, int nrel, unsigned char *known) {
+    for (;;) {
+        int changed = 0;
+        for (int r = 0; r < nrel; ++r) {
+            const relation *x = &rel[r];
+            int nk = 0, miss = -1;
+            for (int i = 0; i < x->n; ++i) {
+                if (known[x->seg[i]]) ++nk;
+                else miss = x->seg[i];
+            }
+            if (nk == x->n - 1 && miss >= 0) { known[miss] = 1; changed = 1; }
+        }
+        if (!changed) break;
+    }
+    int total = 0;
+    for (int i = 0; i < c->nseg; ++i) total += known[i];
+    return total;
+}
+
+/* The natural sources (input and output boundary segments) plus the chosen
+ * candidates, closed under the relations. */
+static int reach_from(const orc_circuit *c, const relation *rel, int nrel, const int *cand,
+                      const int *pick, int npick, unsigned char *known) {
+    memset(known, 0, (size_t)c->nseg);
+    for (int q = 0; q < c->n; ++q) { known[q] = 1; known[c->out_seg[q]] = 1; }
+    for (int i = 0; i < npick; ++i) known[cand[pick[i]]] = 1;
+    return reach(c, rel, nrel, known);
+}
+
+/* Sources on the input segments of branching gates (the values the sweep
+ * from the output needs), as few as reach every segment: `greedy` adds, one
+ * at a time, the candidate that reaches the most segments (the smallest
+ * evaluation position on ties); otherwise the smallest set by exhaustive
+ * search in increasing size (candidates in evaluation order, the first set
+ * found kept).  Sources are numbered in evaluation order of their gates. */
+static int place_by_reach(orc_circuit *c, int greedy) {
+    relation *rel = (relation *)malloc(sizeof(relation) * (size_t)(2 * c->G + 1));
+    int nrel = 0;
+    if (build_relations(c, rel, &nrel)) { free(rel); return ORC_EINVAL; }
+    int *cand = (int *)malloc(sizeof(int) * (size_t)(c->G + 1));
+    int *cgate = (int *)malloc(sizeof(int) * (size_t)(c->G + 1));
+    int nc = 0;
+    for (int e = 0; e < c->G; ++e) {                 /* evaluation order: from the output */
+        int t = c->G - 1 - e;
+        const ogate *g = &c->g[t];
+        if (g->role != ROLE_BRANCH || g->in_seg[0] < c->n) continue;
+        cand[nc] = g->in_seg[0]; cgate[nc] = t; ++nc;
+    }
+    unsigned char *known = (unsigned char *)malloc((size_t)c->nseg);
+    int *pick = (int *)malloc(sizeof(int) * (size_t)(nc + 1));
+    int npick = 0, rc = ORC_OK;
+    if (greedy) {
+        unsigned char *used = (unsigned char *)calloc((size_t)nc + 1, 1);
+        while (reach_from(c, rel, nrel, cand, pick, npick, known) < c->nseg) {
+            int best = -1, best_n = -1;
+            for (int i = 0; i < nc; ++i) {
+                if (used[i]) continue;
+                pick[npick] = i;
+                int m = reach_from(c, rel, nrel, cand, pick, npick + 1, known);
+                if (m > best_n) { best_n = m; best = i; }
+            }
+            used[best] = 1;
+            pick[npick++] = best;
+        }
+        free(used);
+        /* evaluation order */
+        for (int i = 1; i < npick; ++i)
+            for (int j = i; j > 0 && pick[j - 1] > pick[j]; --j) { int tmp = pick[j]; pick[j] = pick[j - 1]; pick[j - 1] = tmp; }
+    } else {
+        long budget = 20000000;
+        int found = 0;
+        for (int k = 0; k <= nc && !found; ++k) {
+            for (int i = 0; i < k; ++i) pick[i] = i;
+            for (;;) {
+                if (--budget < 0) { rc = ORC_ERANGE; break; }
+                if (reach_from(c, rel, nrel, cand, pick, k, known) == c->nseg) { found = 1; npick = k; break; }
+                int i = k - 1;                       /* next combination, lexicographic */
+                while (i >= 0 && pick[i] == nc - k + i) --i;
+                if (i < 0) break;
+                ++pick[i];
+                for (int j = i + 1; j < k; ++j) pick[j] = pick[j - 1] + 1;
+            }
+            if (rc) break;
+        }
+        if (!found && !rc) rc = ORC_EINTERNAL;
+    }
+    if (rc == ORC_OK) {
+        c->A = npick;
+        for (int i = 0; i < npick; ++i) {
+            c->src_seg[i] = cand[pick[i]];
+            c->src_gate[i] = cgate[pick[i]];
+            c->src_eval[i] = c->G - 1 - cgate[pick[i]];
+        }
+    }
+    free(rel); free(cand); free(cgate); free(known); free(pick);
+    return rc;
+}
+
 int orc_load_ex(const char *text, int forward, orc_circuit **out) {
     *out = NULL;
-    if (forward != 0 && forward != 1) return ORC_EINVAL;
+    /* placement: 0 backward sweep, 1 forward sweep, 2 fewest sources by
+     * reachability (exhaustive), 3 greedy by reachability */
+    const int mode = forward;
+    if (mode < 0 || mode > 3) return ORC_EINVAL;
+    forward = mode == 1;
     orc_circuit *c = (orc_circuit *)calloc(1, sizeof(orc_circuit));
     int cap = 64, rc = ORC_OK;
     c->g = (ogate *)calloc(cap, sizeof(ogate));
@@ -341,6 +500,11 @@ int orc_load_ex(const char *text, int forward, orc_circuit **out) {
             c->src_eval[c->A] = e;
             c->A++;
         }
+    }
+    if (mode >= 2) {
+        c->global = 1;
+        int prc = place_by_reach(c, mode == 3);
+        if (prc) { orc_free(c); return prc; }
     }
     *out = c;
     return ORC_OK;
@@ -606,6 +770,7 @@ static void walk_regions(const orc_circuit *c, const regions_t *R, int r, const 
     const uint64_t x0 = r == 0 ? lo : 0, x1 = (r == 0 && hi < n) ? hi : n;
     int t0, t1;
     time_span(c, R->cut[r], R->cut[r + 1], &t0, &t1);
+    if (c->global) { t0 = 0; t1 = c->G; }
     signed char *v = bufs[r];
     for (uint64_t x = x0; x < x1; ++x) {
         memcpy(v, val, (size_t)c->nseg);
@@ -645,6 +810,7 @@ int orc_pair(const orc_circuit *c, const uint64_t *bin, const uint64_t *bout,
     if (!(thr >= 0.0) || !isfinite(thr)) return ORC_EINVAL;
     if (c->A > 62) return ORC_ERANGE;
     if (c1 >= 0 && (c1 > c2 || c2 > c->G)) return ORC_EINVAL;
+    if (c1 >= 0 && c->global) return ORC_EINVAL;     /* reachability placements: Algorithm 1 only */
     acc_t a;
     memset(&a, 0, sizeof(a));
     if (c1 < 0) {

@@ -451,3 +451,90 @@ def test_qft_dense_input(n):
         a = cf.qft_dense(12, x)
         assert sorted(np.nonzero(np.abs(a) > 1e-12)[0].tolist()) == [5, 2001, 2095, 4091]
         assert abs(np.sum(np.abs(a) ** 2) - 1.0) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# source placement by reachability (Section IV-B, Fig. 3)
+# --------------------------------------------------------------------------
+
+def test_fig3_optimal_and_greedy_one_source():
+    """Fig. 3: the backward sweep places two sources, the optimum one (on
+    the merged node {w1, w2, w4, w5}; here the input segment of the final
+    Hadamard on q1); both placements give the exact amplitudes and the same
+    number of valid histories per pair (consistent wire assignments do not
+    depend on where the sources sit)."""
+    g = golden("fig3_three_qubit")
+    t = g["circuit"]
+    U = sv.unitary(t)
+    Fb = oracle.Feynman(t)
+    for pl in ("optimal", "greedy"):
+        F = oracle.Feynman(t, pl)
+        assert F.A == g["A_optimal"] == 1
+        assert F.source_eval_positions == [0]
+        for i in range(8):
+            amps, st = F.evaluate([i], [1], list(range(8)))
+            _, stb = Fb.evaluate([i], [1], list(range(8)))
+            assert np.abs(amps - U[:, i]).max() <= 1e-15
+            assert np.array_equal(st[:, 0], stb[:, 0])
+
+
+def _cnot_layers(n, layers, seed):
+    """Random circuit from the gate set the placement analysis covers:
+    Hadamards and RX/RY (branching), X/Z/T/P (one-qubit), CNOT and SWAP."""
+    rng = np.random.default_rng(seed)
+    c = w.Circuit(n)
+    for _ in range(layers):
+        for q in rng.choice(n, size=max(1, n // 2), replace=False):
+            g = str(rng.choice(["H", "H", "RX", "RY"]))
+            if g == "H":
+                c.add(g, int(q))
+            else:
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+        for _ in range(n):
+            a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+            c.add(str(rng.choice(["CX", "CX", "CX", "SWAP"])), a, b)
+        for q in rng.choice(n, size=max(1, n // 3), replace=False):
+            g = str(rng.choice(["X", "Z", "T", "P"]))
+            if g == "P":
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+            else:
+                c.add(g, int(q))
+    return c
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_reachability_placement_random(seed):
+    """On random CNOT + one-qubit circuits: optimal <= greedy <= backward
+    source counts, exact amplitudes against the state vector, and the
+    valid-history counts of the backward placement and of the naive path
+    sum."""
+    n = 2 + seed % 4
+    c = _cnot_layers(n, 2 + seed % 3, 4400 + seed)
+    t = c.to_text()
+    Fb, Fo, Fg = (oracle.Feynman(t, p) for p in ("backward", "optimal", "greedy"))
+    assert Fo.A <= Fg.A <= Fb.A
+    rng = np.random.default_rng(seed)
+    b_in = int(rng.integers(0, 1 << n))
+    U = sv.evolve(t, b_in)
+    outs = list(range(1 << n))
+    ab, stb = Fb.evaluate([b_in], [1], outs)
+    for F in (Fo, Fg):
+        amps, st = F.evaluate([b_in], [1], outs)
+        assert np.abs(amps - U).max() <= 1e-12
+        assert np.array_equal(st[:, 0], stb[:, 0])
+    if n <= 3 and len(c) <= 24:
+        for y in outs:
+            _, nv_b = bf.path_sum(t, b_in, y)
+            assert int(stb[y, 0]) == nv_b
+
+
+def test_reachability_placement_paper_families():
+    """Section IV-B closes with backward propagation attaining the optimum
+    on the paper's benchmark families; on the ones made of CNOT-like,
+    diagonal and one-qubit gates (QFT, QAOA) the exhaustive search agrees."""
+    for n in (3, 4, 6):
+        assert oracle.Feynman(w.qft(n).to_text(), "optimal").A == 0
+    for nv, p in ((4, 1), (4, 2), (6, 1), (6, 2)):
+        t = w.qaoa_maxcut(nv, p, 11, 12)[0].to_text()
+        assert oracle.Feynman(t, "optimal").A == oracle.Feynman(t).A == p * nv
+        assert oracle.Feynman(t, "greedy").A == p * nv
