@@ -111,7 +111,29 @@ fhs_status fhs_reduce(const char *text, size_t len, fhs_program **out);
  * sets, are those of the forward placement.  Internally the program is the
  * backward one of the transposed circuit (gates reversed, matrices
  * transposed), since <b_out|C|b_in> = <b_in|C^T|b_out>. */
-enum { FHS_REDUCE_FUSE = 1, FHS_REDUCE_PAIR = 2, FHS_REDUCE_FORWARD = 4 };
+/* FHS_REDUCE_OPTIMAL and FHS_REDUCE_GREEDY (Section IV-B, Fig. 3) place the
+ * sources by determinism reachability instead of the sweep: the three
+ * internal wires around a CNOT are symmetric (any two fix the third), so
+ * some of the backward sweep's sources are implied by the others.  The
+ * sources are chosen among the input segments of branching gates, as few
+ * as let the relations (CNOT, SWAP, one-qubit deterministic gates) reach
+ * every internal wire: OPTIMAL by exhaustive search in increasing size
+ * (the first set found with candidates in evaluation order; FHS_ERANGE if
+ * the search exceeds its budget), GREEDY adding the candidate that reaches
+ * the most wires at each step.  Sources are numbered in evaluation order of
+ * their gates.  Every other branching gate's input bit is an affine
+ * function over GF(2) of the sources and the boundary bits, evaluated per
+ * history (OP_BRANCH_AFF); the evaluation order stays output -> input.
+ * Cuts may not separate an affine input from a deeper source its form
+ * uses: fhs_set_partition returns FHS_EINVAL for such a cut, and
+ * fhs_choose_partition / fhs_candidate_splits avoid them.  Gate set:
+ * branching gates on one qubit, deterministic gates on one qubit, CNOT
+ * (MCX with one control) and SWAP, diagonal gates of any size; otherwise
+ * FHS_EUNSUPPORTED.  Not combinable with FHS_REDUCE_FORWARD. */
+enum {
+    FHS_REDUCE_FUSE = 1, FHS_REDUCE_PAIR = 2, FHS_REDUCE_FORWARD = 4,
+    FHS_REDUCE_OPTIMAL = 8, FHS_REDUCE_GREEDY = 16
+};
 fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags, fhs_program **out);
 void fhs_program_free(fhs_program *prog);
 fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info);
@@ -119,6 +141,16 @@ fhs_status fhs_program_get_info(const fhs_program *prog, fhs_program_info *info)
 /* Evaluation positions of the gates that carry sources 0..A-1 (ascending),
  * written to eval_pos[0..min(A,cap)-1]. */
 fhs_status fhs_program_sources(const fhs_program *prog, uint32_t *eval_pos, uint32_t cap);
+
+/* Whether a cut may fall at evaluation position c (0 <= c <= G): *allowed =
+ * 1, or 0 when the cut would put an affine branching input (placement by
+ * reachability) in a region evaluated before the region of a source its
+ * form uses.  Positions 0 and G, and every position of a program placed by
+ * a sweep, are allowed.  A cut below the leading source-free gates acts at
+ * their end (n_leading).  fhs_set_partition refuses a split whose acting
+ * cuts are not allowed (FHS_EINVAL); fhs_candidate_splits and
+ * fhs_choose_partition offer allowed ones only. */
+fhs_status fhs_cut_allowed(const fhs_program *prog, uint32_t c, int *allowed);
 
 /* Eq. (8): Gate_ops = 2^Ap (Gp + 2^Ar (Gr + 2^As Gs)) for cuts c1 <= c2 <= G,
  * prefix = evaluation positions [0,c1), root [c1,c2), suffix [c2,G).  The
@@ -295,6 +327,8 @@ typedef struct {
     uint32_t lanes_per_root_task;  /* lanes that share one (entry, h_r) root task */
     uint32_t plain_blocks_per_pair;
     uint64_t table_bytes;          /* prefix-table bytes per batch */
+    uint32_t prefix_depth_first;   /* prefix sources enumerated depth first inside a lane */
+    uint32_t reserved;
 } fhs_plan;
 
 fhs_status fhs_get_plan(const fhs_ctx *ctx, uint32_t M, uint32_t S, fhs_plan *plan);

@@ -27,6 +27,9 @@ PART_NONE, PART_THIRDS, PART_EQ8, PART_MODEL = 0, 1, 2, 3
 REDUCE_FUSE = 1
 REDUCE_PAIR = 2
 REDUCE_FORWARD = 4
+REDUCE_OPTIMAL = 8
+REDUCE_GREEDY = 16
+PLACEMENTS = {"backward": 0, "forward": REDUCE_FORWARD, "optimal": REDUCE_OPTIMAL, "greedy": REDUCE_GREEDY}
 
 STATUS = {0: "FHS_OK", 1: "FHS_EINVAL", 2: "FHS_EUNSUPPORTED", 3: "FHS_ERANGE",
           4: "FHS_ENOMEM", 5: "FHS_EHIP", 6: "FHS_ESTATE", 7: "FHS_EPARSE"}
@@ -38,7 +41,7 @@ EXPORTS = [
     "fhs_get_partition", "fhs_set_table_budget", "fhs_workspace_size", "fhs_evaluate",
     "fhs_evaluate_plain", "fhs_set_launch_config", "fhs_get_launch_config",
     "fhs_program_work", "fhs_set_kernel_timing", "fhs_kernel_times", "fhs_kernel_counts", "fhs_get_plan",
-    "fhs_split_features", "fhs_candidate_splits", "fhs_load_cost_model",
+    "fhs_split_features", "fhs_candidate_splits", "fhs_cut_allowed", "fhs_load_cost_model",
     "fhs_precompile", "fhs_choose_partition_ctx", "fhs_predict_splits", "fhs_mlp_param_count", "fhs_mlp_workspace_size",
     "fhs_mlp_forward", "fhs_mlp_backward", "fhs_mlp_adam", "fhs_evaluate_noalloc",
     "fhs_item_stamps",
@@ -70,7 +73,8 @@ class Work(ctypes.Structure):
 class Plan(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
-        "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)]
+        "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)] + [
+        ("prefix_depth_first", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class MlpShape(ctypes.Structure):
@@ -126,6 +130,7 @@ def lib() -> ctypes.CDLL:
         pD = ctypes.POINTER(ctypes.c_double)
         L.fhs_split_features.argtypes = [P, U32, U32, U32, U32, pD]
         L.fhs_candidate_splits.argtypes = [P, pU32, pU32, U32, pU32]
+        L.fhs_cut_allowed.argtypes = [P, U32, ctypes.POINTER(ctypes.c_int)]
         L.fhs_load_cost_model.argtypes = [P, pD, ctypes.c_size_t]
         L.fhs_choose_partition_ctx.argtypes = [P, I32, U32, U32, pU32, pU32]
         L.fhs_predict_splits.argtypes = [P, U32, U32, pU32, pU32, U32, pD]
@@ -158,15 +163,23 @@ class Program:
     """Host-side reduced-history program (fhs_reduce)."""
 
     def __init__(self, circuit_text: str, fuse: bool = True, pair: bool = True,
-                 forward: bool = False):
+                 forward: bool = False, placement: str = "backward"):
         """fuse: fold add/subtract ladders (FHS_REDUCE_FUSE); pair: also merge
         complementary folded ladders (FHS_REDUCE_PAIR, only with fuse);
-        forward: place the sources by the sweep from the input
-        (FHS_REDUCE_FORWARD; positions and cuts then count from the input)."""
+        placement: "backward" (the sweep from the output), "forward" (the
+        sweep from the input, FHS_REDUCE_FORWARD; positions and cuts then
+        count from the input), "optimal" or "greedy" (by determinism
+        reachability, FHS_REDUCE_OPTIMAL / FHS_REDUCE_GREEDY); forward=True
+        is placement="forward"."""
+        if placement not in PLACEMENTS:
+            raise ValueError(f"placement must be one of {sorted(PLACEMENTS)}")
+        if forward:
+            placement = "forward"
         b = circuit_text.encode()
         h = ctypes.c_void_p()
         flags = (REDUCE_FUSE | (REDUCE_PAIR if pair else 0)) if fuse else 0
-        flags |= REDUCE_FORWARD if forward else 0
+        flags |= PLACEMENTS[placement]
+        self.placement = placement
         _check(lib().fhs_reduce_ex(b, len(b), flags, ctypes.byref(h)))
         self._h = h
         info = ProgramInfo()
@@ -214,6 +227,12 @@ class Program:
         b = (ctypes.c_uint32 * max(1, n.value))()
         _check(lib().fhs_candidate_splits(self._h, a, b, n.value, ctypes.byref(n)))
         return list(zip(a[: n.value], b[: n.value]))
+
+    def cut_allowed(self, c: int) -> bool:
+        """Whether a cut may fall at evaluation position c (fhs_cut_allowed)."""
+        ok = ctypes.c_int()
+        _check(lib().fhs_cut_allowed(self._h, c, ctypes.byref(ok)))
+        return bool(ok.value)
 
     def choose_partition(self, mode: int = PART_EQ8) -> Tuple[int, int]:
         c1, c2 = ctypes.c_uint32(), ctypes.c_uint32()

@@ -1,6 +1,6 @@
 """Build the native library libfhs.so in-tree for gfx950.
 
-Host reducer (reducer.cpp) is compiled by g++ with FP contraction off (its
+Host reducer (reducer.cpp, placement.cpp) is compiled by g++ with FP contraction off (its
 moduli decide pruning and must round exactly as written); the kernels and
 the runtime by hipcc for gfx950.  Every call rebuilds.
 """
@@ -63,9 +63,10 @@ def build(verbose: bool = False) -> str:
     tmp = tempfile.mkdtemp(prefix="fhs_build_")
     try:
         objs = []
-        o = os.path.join(tmp, "reducer.o")
-        _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "reducer.cpp"), "-o", o])
-        objs.append(o)
+        for src in ("reducer.cpp", "placement.cpp"):
+            o = os.path.join(tmp, src.replace(".cpp", ".o"))
+            _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+            objs.append(o)
         _write_jit_headers(os.path.join(tmp, "jit_headers.inc"))
         # the HIP sources compile independently: one hipcc process each, in parallel
         srcs = ("kernels.hip", "runtime.hip", "mlp.hip", "jit.hip")

@@ -149,6 +149,8 @@ struct Lanes {
     bool ok[H];
     uint64_t hb[H];     // this region's source bits, per history
     uint64_t dx[H];     // factor-table indices recorded for a deferred multiply
+    uint64_t hf[H];     // the source bits of the earlier regions (their global positions)
+    uint64_t aff;       // the pair's boundary bits of the affine inputs' forms
 };
 
 // Factor tables: `fac` points at the slice [lo, ...) of the global table,
@@ -609,6 +611,53 @@ __device__ __forceinline__ void apply_signs(Lanes<NW, H> &L, uint32_t (&sg)[H]) 
     });
 }
 
+// Branching gate whose input bit is an affine form (sources placed by
+// reachability): the parity of the history index over the form's sources
+// (cm[0], cm[1]), xor the pair's boundary bit k of the form; otherwise as
+// op_branch.
+template <int NW, int H, bool PRUNE, int WA, int DEFER = -1, class FR = FacRef>
+__device__ __forceinline__ void op_branch_aff(Lanes<NW, H> &L, const Instr &I, const FR &F, uint32_t kbase,
+                                              double thr) {
+    static_assert(!(PRUNE && DEFER >= 0), "pruning needs the moduli as the walk goes");
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t sh = hdr_a(I) & 31u;
+    const uint64_t smask = static_cast<uint64_t>(I.cm[0]) | (static_cast<uint64_t>(I.cm[1]) << 32);
+    const uint32_t cbit = static_cast<uint32_t>(L.aff >> I.k) & 1u;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sh) & 1u;
+        const uint64_t full = L.hf[h] | (L.hb[h] << kbase);
+        const uint32_t i = (static_cast<uint32_t>(__popcll(full & smask)) & 1u) ^ cbit;
+        const uint32_t x = 2u * o + i;
+        take_factor<DEFER>(L, h, F, I.fac, x);
+        if (PRUNE) {
+            L.M[h] = L.M[h] * F.d(I.fac + 8u + x);
+            L.ok[h] = L.ok[h] && !(L.M[h] < thr);
+        }
+        L.ok[h] = L.ok[h] && !((hdr_z(I) >> x) & 1u);
+        L.s[h][A] ^= (o ^ i) << sh;
+    });
+}
+
+// The boundary bits of the affine forms for one pair: bit j = parity of the
+// check bitstring over form j's input-bit mask, xor the parity of the start
+// bitstring over its output-bit mask, xor its constant.
+template <int NW>
+__device__ __forceinline__ uint64_t affine_bits(const Common &c, const uint32_t (&bin)[NW],
+                                                const uint32_t (&bout)[NW]) {
+    uint64_t bits = 0;
+    for (uint32_t j = 0; j < c.n_aff; ++j) {
+        const uint32_t *f = c.aff_tab + 9u * j;
+        uint32_t p = f[8];
+        unroll<NW>([&](auto ww) {
+            constexpr int w = ww.value;
+            p ^= static_cast<uint32_t>(__popc(bin[w] & f[w])) ^ static_cast<uint32_t>(__popc(bout[w] & f[4 + w]));
+        });
+        bits |= static_cast<uint64_t>(p & 1u) << j;
+    }
+    return bits;
+}
+
 // Walk evaluation positions [e0, e1) of the history program backward for H
 // histories at once.  Source k of history h reads bit (k - kbase) of hb[h];
 // bin is the input bitstring (the same for every history of a lane).  The
@@ -652,6 +701,11 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
             case OP_BRANCH_NAT:
                 with_word<NW>(w1, [&](auto WA) {
                     each([&](const Instr &I) { op_branch<NW, H, PRUNE, WA.value, false>(L, I, F, kbase, bin, thr); });
+                });
+                break;
+            case OP_BRANCH_AFF:
+                with_word<NW>(w1, [&](auto WA) {
+                    each([&](const Instr &I) { op_branch_aff<NW, H, PRUNE, WA.value>(L, I, F, kbase, thr); });
                 });
                 break;
             case OP_DIAG2:
@@ -703,7 +757,7 @@ __device__ __forceinline__ void run_region(const Instr *prog_generic, const FacR
         // the wave is alive the rest of the region cannot change any result.
         if constexpr (PRUNE) {
             const uint32_t base = op & 15u;
-            if (base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) {
+            if (base == OP_BRANCH_SRC || base == OP_BRANCH_NAT || base == OP_BRANCH_AFF) {
                 bool any = false;
                 unroll<H>([&](auto hh) { any = any || L.ok[hh.value]; });
                 if (!__any(any)) return;
@@ -914,6 +968,8 @@ __device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, ui
         L.ok[0] = pre.ok[p] == 1u;
         L.hb[0] = li & lomask;
         L.dx[0] = 0;
+        L.hf[0] = 0;
+        L.aff = c.n_aff ? pre.aff[p] : 0ull;
         Walk::template prefix_head<NW, PRUNE>(c, F, L, bin, e_split);
         const uint64_t ebase = pl << c.Ap;
         const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
@@ -1019,6 +1075,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
 
         uint32_t bin[NW];
         load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
+        const uint64_t paff = c.n_aff ? c.pair_aff[p] : 0ull;
         Acc acc{0.0, 0.0, 0, 0, 0, 0};
         const uint64_t ntask = static_cast<uint64_t>(nv) << (c.Ar + ss);
         // uniform loop bounds: the program counter inside stays wave-uniform
@@ -1039,8 +1096,10 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 R.M[j] = l_M[jx];
                 R.ok[j] = valid;
                 R.hb[j] = hr;
+                R.hf[j] = l_hp[jx];
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
+            R.aff = paff;
             Regions::template root<NW, H, PRUNE>(c, F, R, bin);
             bool any = false;
             unroll<H>([&](auto jj) {
@@ -1056,6 +1115,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 unroll<H>([&](auto jj) {
                     S2.hb[jj.value] = hs0[jj.value] + q;
                     S2.dx[jj.value] = 0;
+                    S2.hf[jj.value] = hbase[jj.value];
                 });
                 Regions::template suffix<NW, H, PRUNE>(c, F, S2, bin);
                 unroll<H>([&](auto jj) {

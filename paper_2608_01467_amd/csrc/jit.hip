@@ -27,6 +27,7 @@ int factor_bits(int base) {
     switch (base) {
         case OP_BRANCH_SRC:
         case OP_BRANCH_NAT:
+        case OP_BRANCH_AFF:
         case OP_DIAG2: return 2;
         case OP_DIAG1:
         case OP_DET1: return 1;
@@ -184,6 +185,12 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
                               "if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
                               w1, base == OP_BRANCH_SRC ? "true" : "false", d);
                 break;
+            case OP_BRANCH_AFF:
+                std::snprintf(call, sizeof(call),
+                              "op_branch_aff<NW, H, PRUNE, wsel<%d, NW>(), %d>(L, I, Fc, kbase, thr); "
+                              "if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
+                              w1, d);
+                break;
             case OP_DIAG2:
                 std::snprintf(call, sizeof(call),
                               "op_diag2<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %d>(L, I, Fc); }\n", w1, w2, d);
@@ -262,7 +269,8 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
             if (base == OP_BRANCH_NAT) natw.w[w] |= wm[w];
             else natw.w[w] &= ~wm[w];
         }
-        if ((base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) && (dev[x].hdr >> 24) != 0u) zero_entries = true;
+        if ((base == OP_BRANCH_SRC || base == OP_BRANCH_NAT || base == OP_BRANCH_AFF) && (dev[x].hdr >> 24) != 0u)
+            zero_entries = true;
     }
     Mask4 fin_rest = fin_G;
     bool check_left = false;

@@ -44,6 +44,12 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     L.M[0] = 1.0;
     L.ok[0] = !(bad_o || bad_i);
     L.hb[0] = 0;
+    L.hf[0] = 0;
+    L.aff = 0;
+    if (c.n_aff) {
+        L.aff = affine_bits<NW>(c, bin, L.s[0]);   // the start bits, before any gate
+        pre.aff[p] = L.aff;
+    }
     const FacRef F{c.fac, 0u};
     run_region<NW, 1, PRUNE, true>(c.prog, F, 0, c.iL, L, 0, bin, c.thr);
     const bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
@@ -101,8 +107,10 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
                 L.im[j] = a.y;
                 L.M[j] = M0;
                 L.hb[j] = h0 + j * stride;
+                L.hf[j] = 0;
                 L.ok[j] = L.hb[j] < NH;
             });
+            L.aff = c.n_aff ? pre.aff[p] : 0ull;
             run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.iL, c.iG, L, 0, bin, c.thr);
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;

@@ -17,6 +17,7 @@ struct PreBufs {
     double2 *amp;      // [P]     partial amplitude (beta_0)
     double *M;         // [P]     running modulus product
     uint32_t *ok;      // [P]     1 = consistent so far
+    uint64_t *aff;     // [P]     bit j: the boundary part of affine input j's form
 };
 
 // One output pair's finished result.
@@ -65,6 +66,12 @@ struct Common {
     // from the input: a history starts from the input bitstring and ends at
     // the check against the output (the roles of the two swap)
     uint32_t fwd;
+    // affine branching inputs (sources placed by reachability): per form j,
+    // 9 words: input-bit mask [4], output-bit mask [4], constant; and the
+    // per-pair boundary bits the precheck derives from them
+    const uint32_t *aff_tab;
+    uint32_t n_aff;
+    const uint64_t *pair_aff;   // [P] (null when n_aff is 0)
 };
 
 #if !defined(__HIPCC_RTC__)

@@ -43,6 +43,8 @@ enum Op : uint8_t {
     OP_ADDSEL = 11,     // if ((s ^ cv) & cm) == 0: the bit field [a, a+b) += 1 or -= 1 mod 2^b,
                         // -= 1 when zmask bit (bit k of the state) is set (two OP_ADDs on one
                         // field whose controls differ only in bit k, outside the field)
+    OP_BRANCH_AFF = 12, // o = bit a, i = parity(h & S) ^ bit k of the pair's affine constants
+                        // (S = cm[0] | cm[1] << 32): factor U[o][i], bit a := i
 };
 
 // The opcode byte carries the base op in its low 4 bits; bits 4-5 and 6-7
@@ -106,7 +108,8 @@ inline void touched_bits(const Instr &I, uint32_t (&m)[4]) {
         case OP_DET1:
         case OP_DIAG1:
         case OP_BRANCH_SRC:
-        case OP_BRANCH_NAT: bit(a); break;
+        case OP_BRANCH_NAT:
+        case OP_BRANCH_AFF: bit(a); break;
         case OP_DIAG2: bit(a); bit(b); break;
         case OP_MCPHASE: controls(); break;
         case OP_ADDSEL: bit(I.k); [[fallthrough]];
@@ -131,7 +134,8 @@ inline void written_bits(const Instr &I, uint32_t (&m)[4]) {
         case OP_PERM:
         case OP_DET1:
         case OP_BRANCH_SRC:
-        case OP_BRANCH_NAT: bit(a); break;
+        case OP_BRANCH_NAT:
+        case OP_BRANCH_AFF: bit(a); break;
         case OP_SWAP: bit(a); bit(b); break;
         case OP_ADD:
         case OP_ADDSEL:
@@ -200,6 +204,14 @@ struct HostProgram {
     int L = 0;                 // leading source-free gates (evaluation order)
     int n_branch = 0;
     bool forward = false;      // placed by the forward sweep: evaluation order = time order
+    int placement = 0;         // 0 sweep (backward or forward), 1 fewest by reachability, 2 greedy
+    // OP_BRANCH_AFF constants: per affine input j, the input-bit and
+    // output-bit masks and the constant of its form (4 + 4 + 1 words)
+    std::vector<uint32_t> aff;
+    // cut_ok[e]: a cut at evaluation position e keeps every affine input in a
+    // region no earlier than its sources' (a form may use a source whose own
+    // gate lies deeper; the cut may not fall between them)
+    std::vector<uint8_t> cut_ok;
     std::vector<Instr> ins;            // evaluation order, size G (fused gates become OP_NOP)
     int n_fused = 0;                   // ladders folded into OP_ADD
     int n_paired = 0;                  // OP_ADD pairs merged into OP_ADDSEL
@@ -221,6 +233,27 @@ struct HostProgram {
     std::vector<uint16_t> int_cost;    // per evaluation position: algorithmic int32 ops
     std::vector<uint32_t> fac_begin;   // [G+1]: factor-table offset of the first gate at or after e
 };
+
+// Whether a cut may fall at evaluation position c.
+inline bool cut_allowed(const HostProgram &P, uint32_t c) {
+    return P.cut_ok.empty() || c >= P.cut_ok.size() || P.cut_ok[c];
+}
+
+// Whether the last Dp of a prefix of Ap sources may be enumerated depth
+// first: their bits are set only when the walk reaches their gates, so no
+// affine input before cut c1 may use one of them from an earlier position.
+inline bool dfs_allowed(const HostProgram &P, uint32_t c1, uint32_t Ap, uint32_t Dp) {
+    if (P.aff.empty() || Dp == 0) return true;
+    const uint32_t lo_bits = Ap - Dp;
+    for (uint32_t e = 0; e < c1 && e < P.ins.size(); ++e) {
+        const Instr &I = P.ins[e];
+        if (op_base(static_cast<uint8_t>(I.hdr & 0xffu)) != OP_BRANCH_AFF) continue;
+        const uint64_t smask = I.cm[0] | (static_cast<uint64_t>(I.cm[1]) << 32);
+        for (uint32_t k = lo_bits; k < Ap && k < P.src_eval.size(); ++k)
+            if (((smask >> k) & 1u) && P.src_eval[k] > e) return false;
+    }
+    return true;
+}
 #endif  // !__HIPCC_RTC__
 
 }  // namespace fhs

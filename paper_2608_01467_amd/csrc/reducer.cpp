@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/fhs.h"
+#include "placement.hpp"
 #include "program.hpp"
 
 struct fhs_program {
@@ -257,7 +258,63 @@ int flops_of(const std::vector<cd> &tab) {
     return trivial ? 0 : (axis ? 2 : 6);
 }
 
-fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
+// The gate as the placement analysis sees it (placement.hpp).
+PlaceGate place_gate(const Gate &g) {
+    PlaceGate pg;
+    pg.q = g.q;
+    pg.k = g.k ? g.k : static_cast<int>(g.q.size());
+    for (int j = 0; j < pg.k; ++j) pg.preserve.push_back(preserves(g, j));
+    const Role r = role_of(g);
+    pg.branch = r == R_BRANCH;
+    pg.det = r == R_DET;
+    if (!pg.det) return pg;
+    if (g.k == 0) {                        // MCX: target q[0]
+        if (pg.k == 2) {
+            pg.cnot = true;
+            pg.jt = 0;
+            pg.jc = 1;
+            pg.cval = g.neg[1] ? 0 : 1;
+        }
+        return pg;
+    }
+    if (g.k != 2) return pg;
+    if (pg.preserve[0] != pg.preserve[1]) {
+        // one wire kept: a controlled flip of the other when the kept wire
+        // has one value and nothing for the other value
+        const int jc = pg.preserve[0] ? 0 : 1, jt = 1 - jc;
+        int flips_for = -1;
+        bool ok = true;
+        for (int v = 0; v < 2 && ok; ++v) {
+            const int x = v << jc;             // target 0
+            const bool flip = !is_zero(g.m[x | (1 << jt)][x]);
+            const bool stay = !is_zero(g.m[x][x]);
+            if (flip == stay) ok = false;
+            if (flip) flips_for = flips_for < 0 ? v : 2;
+        }
+        if (ok && (flips_for == 0 || flips_for == 1)) {
+            pg.cnot = true;
+            pg.jc = jc;
+            pg.jt = jt;
+            pg.cval = flips_for;
+        }
+        return pg;
+    }
+    bool sw = true;
+    for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+            const int t = ((x & 1) << 1) | ((x >> 1) & 1);
+            if (is_zero(g.m[y][x]) != (y != t)) sw = false;
+        }
+    pg.swap = sw;
+    return pg;
+}
+
+// plan (may be null): how each branching gate (time index) gets its input
+// bit when the sources are placed by reachability, and the sources'
+// evaluation positions; null: the backward sweep.
+fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P,
+                const std::vector<BranchInput> *plan = nullptr,
+                const std::vector<uint32_t> *plan_src = nullptr) {
     const int G = static_cast<int>(gates.size());
     P.n = n;
     P.G = G;
@@ -331,7 +388,25 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
                     if (is_zero(g.m[o][i])) zmask |= 1u << (2 * o + i);
                 }
             qa = static_cast<uint32_t>(q);
-            if (first_np[q] == t) {
+            if (plan) {
+                const BranchInput &b = (*plan)[t];
+                if (b.kind == BranchInput::NATURAL) {
+                    op = OP_BRANCH_NAT;
+                } else if (b.kind == BranchInput::SOURCE) {
+                    op = OP_BRANCH_SRC;
+                    I.k = static_cast<uint32_t>(b.source);
+                } else {
+                    // the input bit is an affine form: parity(h & S) on the
+                    // device, the boundary part a per-pair constant bit
+                    op = OP_BRANCH_AFF;
+                    I.k = static_cast<uint32_t>(P.aff.size() / 9);
+                    I.cm[0] = static_cast<uint32_t>(b.form.s);
+                    I.cm[1] = static_cast<uint32_t>(b.form.s >> 32);
+                    for (int w = 0; w < 4; ++w) P.aff.push_back(b.form.x[w]);
+                    for (int w = 0; w < 4; ++w) P.aff.push_back(b.form.y[w]);
+                    P.aff.push_back(b.form.c);
+                }
+            } else if (first_np[q] == t) {
                 op = OP_BRANCH_NAT;          // input segment is natural: value from b_in
             } else {
                 op = OP_BRANCH_SRC;          // artificial source k, numbered in sweep order
@@ -400,11 +475,15 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
             } else if (base != OP_SWAP && base != OP_DIAG2) {
                 w2 = 0;
             }
+            const bool affine = base == OP_BRANCH_AFF;   // cm holds the source mask, not controls
             I.hdr = pack_hdr(op_code(base, w1, w2), qa, qb, zmask);
             // algorithmic int32 ops of one backward step (fhs_program_work)
-            const int wspan = hiword(I.cm) + 1;
+            const int wspan = affine ? 1 : hiword(I.cm) + 1;
             int ops = 0;
             switch (base) {
+                // the form: the history index masked, its popcount, the
+                // pair's constant bit, the bit into the state
+                case OP_BRANCH_AFF: ops = zmask ? 6 : 4; break;
                 case OP_PERM: ops = (I.cm[0] | I.cm[1] | I.cm[2] | I.cm[3]) ? 3 * wspan + 1 : 1; break;
                 case OP_MCPHASE: ops = 3 * wspan + 1; break;
                 case OP_SWAP: ops = (I.cm[0] | I.cm[1] | I.cm[2] | I.cm[3]) ? 3 * wspan + 4 : 4; break;
@@ -426,8 +505,25 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P) {
         P.final_before[e + 1] = fin;
     }
     P.fac_begin[G] = static_cast<uint32_t>(P.fac.size());
+    if (plan) {
+        P.src_eval = *plan_src;
+        A = static_cast<int>(P.src_eval.size());
+    }
     P.A = A;
     P.L = A > 0 ? static_cast<int>(P.src_eval[0]) : G;
+    // a cut between an affine input and a source its form uses whose own
+    // gate lies deeper would leave the form without that source
+    P.cut_ok.assign(G + 1, 1);
+    for (int e = 0; e < G; ++e) {
+        const Instr &I = P.ins[e];
+        if (op_base(static_cast<uint8_t>(I.hdr & 0xffu)) != OP_BRANCH_AFF) continue;
+        const uint64_t smask = I.cm[0] | (static_cast<uint64_t>(I.cm[1]) << 32);
+        for (int k = 0; k < A; ++k)
+            if ((smask >> k) & 1u)
+                for (uint32_t c = static_cast<uint32_t>(e) + 1; c <= P.src_eval[k]; ++c) P.cut_ok[c] = 0;
+    }
+    // the gates before the first source run once per pair, without sources
+    if (!P.cut_ok[P.L]) P.L = 0;
     return FHS_OK;
 }
 
@@ -700,9 +796,11 @@ extern "C" const char *fhs_status_string(fhs_status s) {
 
 extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags,
                                     fhs_program **out) {
-    if (!text || !out ||
-        (flags & ~static_cast<uint32_t>(FHS_REDUCE_FUSE | FHS_REDUCE_PAIR | FHS_REDUCE_FORWARD)) ||
-        ((flags & FHS_REDUCE_PAIR) && !(flags & FHS_REDUCE_FUSE)))
+    const uint32_t all = FHS_REDUCE_FUSE | FHS_REDUCE_PAIR | FHS_REDUCE_FORWARD | FHS_REDUCE_OPTIMAL |
+                         FHS_REDUCE_GREEDY;
+    const uint32_t reach = flags & (FHS_REDUCE_OPTIMAL | FHS_REDUCE_GREEDY);
+    if (!text || !out || (flags & ~all) || ((flags & FHS_REDUCE_PAIR) && !(flags & FHS_REDUCE_FUSE)) ||
+        reach == (FHS_REDUCE_OPTIMAL | FHS_REDUCE_GREEDY) || (reach && (flags & FHS_REDUCE_FORWARD)))
         return FHS_EINVAL;
     *out = nullptr;
     int n = 0;
@@ -719,10 +817,20 @@ extern "C" fhs_status fhs_reduce_ex(const char *text, size_t len, uint32_t flags
             for (int a = 0; a < (1 << g.k); ++a)
                 for (int b = 0; b < a; ++b) std::swap(g.m[a][b], g.m[b][a]);
     }
+    std::vector<BranchInput> plan;
+    std::vector<uint32_t> plan_src;
+    if (reach) {
+        std::vector<PlaceGate> pg;
+        pg.reserve(gates.size());
+        for (const Gate &g : gates) pg.push_back(place_gate(g));
+        st = place_by_reach(n, pg, (flags & FHS_REDUCE_GREEDY) != 0, plan, plan_src);
+        if (st != FHS_OK) return st;
+    }
     fhs_program *p = new (std::nothrow) fhs_program;
     if (!p) return FHS_ENOMEM;
-    st = emit(n, gates, p->p);
+    st = emit(n, gates, p->p, reach ? &plan : nullptr, reach ? &plan_src : nullptr);
     p->p.forward = (flags & FHS_REDUCE_FORWARD) != 0;
+    p->p.placement = (flags & FHS_REDUCE_OPTIMAL) ? 1 : ((flags & FHS_REDUCE_GREEDY) ? 2 : 0);
     if (st != FHS_OK) {
         delete p;
         return st;
@@ -758,6 +866,13 @@ extern "C" fhs_status fhs_program_sources(const fhs_program *prog, uint32_t *eva
     if (!prog || (!eval_pos && cap)) return FHS_EINVAL;
     const HostProgram &P = prog->p;
     for (uint32_t k = 0; k < cap && k < P.src_eval.size(); ++k) eval_pos[k] = P.src_eval[k];
+    return FHS_OK;
+}
+
+extern "C" fhs_status fhs_cut_allowed(const fhs_program *prog, uint32_t c, int *allowed) {
+    if (!prog || !allowed) return FHS_EINVAL;
+    if (c > static_cast<uint32_t>(prog->p.G)) return FHS_EINVAL;
+    *allowed = cut_allowed(prog->p, c) ? 1 : 0;
     return FHS_OK;
 }
 
@@ -860,7 +975,9 @@ extern "C" fhs_status fhs_candidate_splits(const fhs_program *prog, uint32_t *c1
                                            uint32_t cap, uint32_t *count) {
     if (!prog || !count || ((!c1 || !c2) && cap)) return FHS_EINVAL;
     const HostProgram &P = prog->p;
-    std::vector<uint32_t> cuts(P.src_eval.begin(), P.src_eval.end());
+    std::vector<uint32_t> cuts;
+    for (uint32_t e : P.src_eval)
+        if (cut_allowed(P, e)) cuts.push_back(e);
     cuts.push_back(static_cast<uint32_t>(P.G));
     uint32_t k = 0;
     for (size_t i = 0; i < cuts.size(); ++i)
@@ -885,7 +1002,10 @@ extern "C" fhs_status fhs_choose_partition(const fhs_program *prog, int mode, ui
         return FHS_OK;
     }
     if (mode == FHS_PART_THIRDS) {
-        *c1 = G / 3; *c2 = (2 * G) / 3;
+        uint32_t a = G / 3, b = (2 * G) / 3;
+        while (!cut_allowed(P, a)) --a;      // position 0 is always allowed
+        while (!cut_allowed(P, b)) --b;
+        *c1 = a; *c2 = b;
         return FHS_OK;
     }
     if (mode != FHS_PART_EQ8) return mode == FHS_PART_MODEL ? FHS_ESTATE : FHS_EINVAL;
@@ -900,6 +1020,7 @@ extern "C" fhs_status fhs_choose_partition(const fhs_program *prog, int mode, ui
     const uint32_t A = static_cast<uint32_t>(P.A);
     for (uint32_t x = 0; x <= G; ++x)
         for (uint32_t y = x; y <= G; ++y) {
+            if (!cut_allowed(P, x) || !cut_allowed(P, y)) continue;
             const uint32_t ap = before[x], ar = before[y] - before[x], as = A - before[y];
             const unsigned __int128 v = eq8(ap, ar, as, x, y - x, G - y);
             if (!have || v < best) {

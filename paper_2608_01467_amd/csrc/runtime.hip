@@ -68,7 +68,7 @@ struct Plan {
     uint32_t Dp = 0;         // prefix sources enumerated depth-first inside a lane
     uint32_t bpp = 1;        // plain: blocks per pair
     uint64_t entries = 0;    // table entries per batch
-    size_t off_pre_st = 0, off_pre_amp = 0, off_pre_M = 0, off_pre_ok = 0;
+    size_t off_pre_st = 0, off_pre_amp = 0, off_pre_M = 0, off_pre_ok = 0, off_pre_aff = 0;
     size_t off_res_amp = 0, off_res_st = 0;
     size_t off_counters = 0;
     size_t off_tab_st = 0, off_tab_beta = 0, off_tab_M = 0, off_tab_ok = 0;
@@ -92,6 +92,7 @@ struct fhs_ctx {
     double *d_fac = nullptr;
     Mask4 *d_fin = nullptr;
     uint32_t *d_src = nullptr;   // [max(A,1)] device-program index of each source gate
+    uint32_t *d_aff = nullptr;   // [9 per affine input] the forms of affine branching inputs
     std::vector<uint32_t> pos2ins;   // [G+1] evaluation position -> device-program index
     std::vector<Instr> dev_ins;      // host copy of the device program
     std::vector<uint32_t> src_dev;   // device-program index of each source's gate
@@ -187,12 +188,14 @@ void free_program(fhs_ctx *c) {
     if (c->d_fac) hipFree(c->d_fac);
     if (c->d_fin) hipFree(c->d_fin);
     if (c->d_src) hipFree(c->d_src);
+    if (c->d_aff) hipFree(c->d_aff);
     for (auto &kv : c->compiled) release(kv.second);
     c->compiled.clear();
     c->d_prog = nullptr;
     c->d_fac = nullptr;
     c->d_fin = nullptr;
     c->d_src = nullptr;
+    c->d_aff = nullptr;
     c->loaded = false;
 }
 
@@ -245,6 +248,7 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
     pl.off_pre_amp = take(sizeof(double2) * n_pairs);
     pl.off_pre_M = take(sizeof(double) * n_pairs);
     pl.off_pre_ok = take(sizeof(uint32_t) * n_pairs);
+    pl.off_pre_aff = take(P.aff.empty() ? 0 : sizeof(uint64_t) * n_pairs);
     pl.off_res_amp = take(sizeof(double2) * n_pairs);
     pl.off_res_st = take(sizeof(uint64_t) * 4 * n_pairs);
     const size_t common_end = off;
@@ -269,6 +273,7 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
         // prefix sources enumerated depth-first per lane, keeping enough lanes
         pl.Dp = std::min<uint32_t>(pl.Ap, static_cast<uint32_t>(kDfsMax));
         while (pl.Dp > 0 && (static_cast<uint64_t>(pl.B) << (pl.Ap - pl.Dp)) < want) --pl.Dp;
+        while (!dfs_allowed(P, pl.c1, pl.Ap, pl.Dp)) --pl.Dp;
         pl.off_counters = take(sizeof(uint32_t) * pl.n_batches);
         pl.off_tab_st = take(sizeof(uint32_t) * NW * pl.entries);
         pl.off_tab_beta = take(sizeof(double2) * pl.entries);
@@ -351,7 +356,7 @@ T *at(void *ws, size_t off) {
 }
 
 Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_t S,
-                   const uint64_t *out, uint32_t M, double thr) {
+                   const uint64_t *out, uint32_t M, double thr, void *ws = nullptr) {
     const HostProgram &P = c->prog;
     Common cm{};
     cm.prog = c->d_prog;
@@ -385,12 +390,16 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.f_G = P.fac_begin[P.G];
     cm.thr = thr;
     cm.fwd = P.forward ? 1u : 0u;
+    cm.aff_tab = c->d_aff;
+    cm.n_aff = static_cast<uint32_t>(P.aff.size() / 9);
+    cm.pair_aff = (ws && cm.n_aff) ? at<uint64_t>(ws, pl.off_pre_aff) : nullptr;
     return cm;
 }
 
 PreBufs pre_bufs(void *ws, const Plan &pl) {
     return PreBufs{at<uint32_t>(ws, pl.off_pre_st), at<double2>(ws, pl.off_pre_amp),
-                   at<double>(ws, pl.off_pre_M), at<uint32_t>(ws, pl.off_pre_ok)};
+                   at<double>(ws, pl.off_pre_M), at<uint32_t>(ws, pl.off_pre_ok),
+                   at<uint64_t>(ws, pl.off_pre_aff)};
 }
 
 PairRes pair_res(void *ws, const Plan &pl) {
@@ -603,6 +612,11 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     if (!src_dev.empty())
         FHS_HIP(c, hipMemcpy(c->d_src, src_dev.data(), sizeof(uint32_t) * src_dev.size(),
                              hipMemcpyHostToDevice));
+    if (P.aff.size() / 9 > 64) return fail(c, FHS_ERANGE, "more than 64 affine branching inputs");
+    if (!P.aff.empty()) {
+        FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_aff), sizeof(uint32_t) * P.aff.size()));
+        FHS_HIP(c, hipMemcpy(c->d_aff, P.aff.data(), sizeof(uint32_t) * P.aff.size(), hipMemcpyHostToDevice));
+    }
     c->c1 = c->c2 = 0;
     c->loaded = true;
     ++c->generation;
@@ -758,6 +772,10 @@ extern "C" fhs_status fhs_set_partition(fhs_ctx *c, uint32_t c1, uint32_t c2) {
     if (!c->loaded) return fail(c, FHS_ESTATE, "no program loaded");
     if (c1 > c2 || c2 > static_cast<uint32_t>(c->prog.G))
         return fail(c, FHS_EINVAL, "need c1 <= c2 <= G (%u, %u, %d)", c1, c2, c->prog.G);
+    const uint32_t L = static_cast<uint32_t>(c->prog.L);
+    if (!cut_allowed(c->prog, std::max(c1, L)) || !cut_allowed(c->prog, std::max(c2, L)))
+        return fail(c, FHS_EINVAL, "cut (%u, %u) separates an affine branching input from a source its form uses",
+                    c1, c2);
     c->c1 = c1;
     c->c2 = c2;
     return FHS_OK;
@@ -958,6 +976,8 @@ extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs
     out->items_per_pair = pl.nchunks;
     out->lanes_per_root_task = 1u << pl.ss;
     out->plain_blocks_per_pair = pl.bpp;
+    out->prefix_depth_first = pl.Dp;
+    out->reserved = 0;
     out->table_bytes = pl.entries * (sizeof(uint32_t) * nw_of(c->prog) + sizeof(double2) +
                                      sizeof(double) + sizeof(uint32_t));
     return FHS_OK;
@@ -1040,7 +1060,7 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
         // Timing mode: the same launch sequence, enqueued directly on the
         // caller's stream with events around every consumer launch (events
         // recorded inside a captured graph carry no usable timestamps).
-        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr, d_ws);
         const CompiledConsumer *ck = nullptr;
         if ((st = compiled_consumer(c, cm, pl.Dp, &ck)) != FHS_OK) return st;
         int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
@@ -1068,7 +1088,7 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
     }
     if (!(c->have_graph && c->key == key)) {
         drop_graph(c);
-        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+        const Common cm = make_common(c, pl, d_in, S, d_out, M, thr, d_ws);
         const CompiledConsumer *ck = nullptr;   // compiled before the capture starts
         if ((st = compiled_consumer(c, cm, pl.Dp, &ck)) != FHS_OK) return st;
         int bpc = c->prog.A > 0 ? (ck ? ck->blocks_per_cu : consume_blocks_per_cu(cm, nw_of(c->prog), c->ilp)) : 1;
@@ -1107,7 +1127,7 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
     plain.c1 = plain.c2 = static_cast<uint32_t>(P.L);
     plain.Ap = plain.Ar = 0;
     plain.As = static_cast<uint32_t>(P.A);
-    const Common cm = make_common(c, plain, d_in, S, d_out, M, thr);
+    const Common cm = make_common(c, plain, d_in, S, d_out, M, thr, d_ws);
     PreBufs pre = pre_bufs(d_ws, pl);
     PairRes res = pair_res(d_ws, pl);
     FHS_HIP(c, launch_precheck(cm, NW, pre, pl.P, nullptr, 0, s));
@@ -1141,7 +1161,7 @@ extern "C" fhs_status fhs_evaluate_noalloc(fhs_ctx *c, const uint64_t *d_in, con
     if (st != FHS_OK || M == 0) return st;
     FHS_HIP(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Common cm = make_common(c, pl, d_in, S, d_out, M, thr);
+    const Common cm = make_common(c, pl, d_in, S, d_out, M, thr, c->scratch);
     // A compiled consumer only if one is already cached for this program,
     // split and launch shape (compiling and loading a module allocates);
     // otherwise the interpreting kernels.

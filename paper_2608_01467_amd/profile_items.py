@@ -9,9 +9,10 @@ Eq. (8) split (or --cuts); the persistent consumer's per-item clock stamps
 (fhs_item_stamps) give each output's cost (the summed durations of its
 items), their distribution, and how well the atomic work queue kept the
 workgroups busy: the makespan against the summed item time divided by the
-number of resident workgroups.  `sources`: the walk at 10..20 steps (A = s-1
-sources) with the same output count, consumer time per output and per
-candidate history against A.  One JSON line per result.  Everything here
+number of resident workgroups (the most items in flight at once), and how
+long the tail after the last moment at that count lasts.  `sources`: the
+walk at 10..20 steps (A = s-1 sources) with the same output count,
+consumer time per output and per candidate history against A.  One JSON line per result.  Everything here
 drives the C ABI; no computation of the method happens in Python.
 """
 from __future__ import annotations
@@ -53,6 +54,22 @@ def _histogram(x: np.ndarray, bins: int = 12) -> list:
     counts, _ = np.histogram(x, bins=edges)
     return [{"from": float(edges[i]), "to": float(edges[i + 1]), "count": int(c)}
             for i, c in enumerate(counts)]
+
+
+def _concurrency(start: np.ndarray, end: np.ndarray) -> dict:
+    """Items in flight over the launch: the most at once (the workgroups the
+    device kept resident), the mean (summed item time over the makespan),
+    and when the count first fell below its maximum for good (the tail)."""
+    ev = np.concatenate([np.stack([start, np.ones_like(start)], 1),
+                         np.stack([end, -np.ones_like(end)], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]          # ends before starts at equal times
+    live = np.cumsum(ev[:, 1])
+    peak = int(live.max())
+    t0, t1 = float(start.min()), float(end.max())
+    last_peak = float(ev[np.nonzero(live == peak)[0][-1], 0])
+    mean = float((end - start).sum()) / max(t1 - t0, 1.0)
+    return {"max_in_flight": peak, "mean_in_flight": mean, "busy_frac": mean / peak if peak else 0.0,
+            "tail_frac": (t1 - last_peak) / max(t1 - t0, 1.0)}
 
 
 def timed_evaluation(ctx: Context, prog: Program, cfg: dict, cuts, launch=None, reps: int = 2):
@@ -110,7 +127,8 @@ def items(args) -> int:
             "leaves_per_output": _quantiles(leaves),
             # the queue's balance: summed item time over the workgroups that
             # ran it, against the makespan
-            "sum_item_us": float(dur.sum())}
+            "sum_item_us": float(dur.sum()),
+            "in_flight": _concurrency(start.astype(np.float64), stamps[:, 1].astype(np.float64))}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -138,6 +156,10 @@ def sources(args) -> int:
 
 
 def main() -> int:
+    import torch
+    if not torch.cuda.is_available():      # torch sets the device up before the library does
+        print("profile_items: no GPU visible", file=sys.stderr)
+        return 1
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=["items", "sources"])
     ap.add_argument("--workload", default="walk_99p_20s")

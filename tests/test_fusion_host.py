@@ -79,8 +79,10 @@ def test_mixed_circuits_without_ladders_are_unchanged():
 def test_reduce_ex_rejects_unknown_flags():
     t = b"qubits 2\nH 0\n"
     h = ctypes.c_void_p()
-    assert fhs.lib().fhs_reduce_ex(t, len(t), 8, ctypes.byref(h)) == 1
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 32, ctypes.byref(h)) == 1
     assert fhs.lib().fhs_reduce_ex(t, len(t), 2, ctypes.byref(h)) == 1   # pair needs fuse
-    for flags in (0, 1, 3, 4, 7):
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 8 | 16, ctypes.byref(h)) == 1   # one placement
+    assert fhs.lib().fhs_reduce_ex(t, len(t), 4 | 8, ctypes.byref(h)) == 1
+    for flags in (0, 1, 3, 4, 7, 8, 11, 16, 19):
         assert fhs.lib().fhs_reduce_ex(t, len(t), flags, ctypes.byref(h)) == 0
         fhs.lib().fhs_program_free(h)

@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 import paper_2608_01467_amd as fhs  # noqa: E402
 
 TOL = 1e-12
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 THREADS = min(16, len(os.sched_getaffinity(0)))
 
 
@@ -655,6 +656,96 @@ def test_forward_placement(ctx, case):
         amps, st = gpu_eval(ctx, t, inputs, coeffs, outs, partition=part, plain=plain, prog=prog)
         assert np.abs(amps - ref_a).max() <= TOL, (case, part, plain, dispatch, h)
         assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), (case, part, plain, dispatch)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
+REACH_CASES = ["fig3", "cnot5-optimal", "cnot8-optimal", "cnot11-greedy", "cnot14-greedy", "cnot51-optimal",
+               "cnot103-optimal", "cnot107-optimal", "big-optimal"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", REACH_CASES)
+def test_reach_placement(ctx, case):
+    """Sources placed by determinism reachability (FHS_REDUCE_OPTIMAL /
+    GREEDY, Section IV-B): the plain form and the batched form at allowed
+    cut pairs (interpreted, and compiled at three of them), with and without
+    pruning, against the oracle's Algorithm 1 under the same placement,
+    valid sets included; cuts that would separate an affine input from a
+    source its form uses are refused."""
+    import json
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case == "fig3":
+        with open(os.path.join(ROOT, "tests", "golden", "fig3_three_qubit.json")) as f:
+            t = json.load(f)["circuit"]
+        placement = "optimal"
+    elif case == "big-optimal":
+        t = w.cnot_layers(10, 3, 4700).to_text()
+        placement = "optimal"
+    else:
+        name, placement = case.split("-")
+        seed = int(name[4:])
+        t = w.cnot_layers(2 + seed % 6, 2 + seed % 4, 4400 + seed).to_text()
+    o = oracle.Feynman(t, placement)
+    prog = fhs.Program(t, placement=placement)
+    assert prog.A == o.A and prog.source_eval_positions == o.source_eval_positions
+    n = o.n
+    S = 1 + len(case) % 2
+    inputs = [int(rng.integers(0, 1 << n)) for _ in range(S)]
+    coeffs = [complex(rng.normal(), rng.normal()) for _ in range(S)]
+    outs = list(range(1 << n)) if n <= 8 else [int(rng.integers(0, 1 << n)) for _ in range(64)]
+    allowed = [c for c in range(prog.L, prog.G + 1) if prog.cut_allowed(c)]
+    refused = [c for c in range(prog.L, prog.G + 1) if not prog.cut_allowed(c)]
+    splits = sorted({(a, b) for a in allowed for b in allowed if a <= b})
+    pick = [splits[int(i)] for i in rng.choice(len(splits), size=min(10, len(splits)), replace=False)]
+    # the allowed cuts on both sides of each refused run
+    for c in refused:
+        lo = max([a for a in allowed if a < c], default=None)
+        hi = min([a for a in allowed if a > c], default=None)
+        if lo is not None and hi is not None:
+            pick += [(lo, hi), (lo, lo), (hi, hi)]
+    pick.append(prog.choose_partition(fhs.PART_EQ8))
+    for thr in (0.0, 0.05):
+        ref_a, ref_st = o.evaluate(inputs, coeffs, outs, threshold=thr, threads=THREADS)
+        runs = [((0, 0), True, 0)] + [(p, False, 0) for p in pick] + [(p, False, 3) for p in pick[-3:]]
+        for part, plain, dispatch in runs:
+            ctx.set_launch_config(2 if dispatch else 1, 0, 0, dispatch)
+            amps, st = gpu_eval(ctx, t, inputs, coeffs, outs, thr=thr, partition=part, plain=plain, prog=prog)
+            assert np.abs(amps - ref_a).max() <= TOL, (case, thr, part, plain, dispatch)
+            assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), (case, thr, part, plain, dispatch)
+    ctx.load(prog)
+    for c in refused[:3]:
+        with pytest.raises(fhs.FhsError):
+            ctx.set_partition(c, prog.G)
+        with pytest.raises(fhs.FhsError):
+            ctx.set_partition(prog.L, c)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
+@pytest.mark.gpu
+def test_reach_depth_first_prefix(ctx):
+    """A prefix holding every source, enumerated partly depth first inside a
+    lane (many pairs, few lanes per pair), under a greedy placement whose
+    affine inputs use sources that lie deeper than themselves: the depth-first
+    part is cut back to sources no earlier affine input uses, and the results
+    equal the oracle's Algorithm 1."""
+    t = w.cnot_layers(14, 4, 5002).to_text()
+    o = oracle.Feynman(t, "greedy")
+    prog = fhs.Program(t, placement="greedy")
+    assert prog.A == o.A == 14
+    assert any(not prog.cut_allowed(c) for c in range(prog.G + 1))
+    rng = np.random.default_rng(5002)
+    outs = [int(rng.integers(0, 1 << 14)) for _ in range(256)]
+    ref_a, ref_st = o.evaluate([0], [1.0], outs, threads=THREADS)
+    ctx.set_launch_config(1, 0, 0, 0)
+    ctx.load(prog)
+    for part in ((prog.G, prog.G), (0, 0)):
+        ctx.set_partition(*part)
+        plan = ctx.plan(len(outs), 1)
+        if part[0] == prog.G:
+            assert plan["Ap"] == 14
+        amps, st = gpu_eval(ctx, t, [0], [1.0], outs, partition=part, prog=prog)
+        assert np.abs(amps - ref_a).max() <= TOL, (part, plan)
+        assert np.array_equal(st[:, :3], ref_st[:, :3].astype(np.uint64)), part
     ctx.set_launch_config(0, 0, 0, 0)
 
 

@@ -140,3 +140,59 @@ def test_empty_circuit():
     p = fhs.Program("qubits 5\n")
     assert (p.G, p.A, p.L) == (0, 0, 0)
     assert p.partition_cost(0, 0)[0] == 0
+
+
+
+def _reach_circuits():
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "fig3_three_qubit.json")) as f:
+        yield "fig3", json.load(f)["circuit"]
+    for seed in range(40):
+        n = 2 + seed % 6
+        yield f"cnot{seed}", w.cnot_layers(n, 2 + seed % 4, 4400 + seed).to_text()
+    for n in (4, 6):
+        yield f"qaoa{n}", w.qaoa_maxcut(n, 2, 11, 12)[0].to_text()
+    yield "qft5", w.qft(5).to_text()
+
+
+@pytest.mark.parametrize("placement", ["optimal", "greedy"])
+@pytest.mark.parametrize("name,text", list(_reach_circuits()), ids=[c[0] for c in _reach_circuits()])
+def test_reach_reducer_matches_oracle(name, text, placement):
+    """FHS_REDUCE_OPTIMAL / GREEDY choose the same sources, at the same
+    evaluation positions, as the oracle's placement by reachability; Eq. (8)
+    agrees; every candidate split the library offers keeps 0 <= c1 <= c2 <= G
+    and the full-range cuts (0 and G, which never separate an affine input
+    from its sources) are always among the allowed ones."""
+    p = fhs.Program(text, placement=placement)
+    o = oracle.Feynman(text, placement)
+    assert p.placement == placement
+    assert (p.n, p.G, p.A) == (o.n, o.G, o.A)
+    assert p.source_eval_positions == o.source_eval_positions
+    assert p.A <= fhs.Program(text).A
+    splits = p.candidate_splits()
+    assert all(0 <= a <= b <= p.G for a, b in splits)
+    for c1, c2 in splits[:: max(1, len(splits) // 8)]:
+        assert p.partition_cost(c1, c2)[0] == o.eq8(c1, c2)
+    assert p.cut_allowed(0) and p.cut_allowed(p.G)
+    assert all(p.cut_allowed(a) and p.cut_allowed(b) for a, b in splits)
+    c1, c2 = p.choose_partition(fhs.PART_EQ8)   # cuts below L act at L
+    assert p.cut_allowed(max(c1, p.L)) and p.cut_allowed(max(c2, p.L))
+    if placement == "optimal" and name.startswith("cnot"):
+        # Eq. (8) over the allowed cuts is no better than over all of them
+        assert p.partition_cost(c1, c2)[0] >= o.eq8_argmin()[2]
+
+
+def test_reach_flag_errors():
+    t = w.cnot_layers(4, 2, 4401).to_text()
+    with pytest.raises(ValueError):
+        fhs.Program(t, placement="sideways")
+    lib = fhs.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    b = t.encode()
+    for flags in (fhs.REDUCE_OPTIMAL | fhs.REDUCE_GREEDY, fhs.REDUCE_OPTIMAL | fhs.REDUCE_FORWARD):
+        assert lib.fhs_reduce_ex(b, len(b), flags, ctypes.byref(h)) == 1   # FHS_EINVAL
+    # gates outside the analysed set
+    t2 = "qubits 3\nH 0\nCCX 0 1 2\nH 2\n"
+    with pytest.raises(fhs.FhsError):
+        fhs.Program(t2, placement="optimal")

@@ -478,30 +478,6 @@ def test_fig3_optimal_and_greedy_one_source():
             assert np.array_equal(st[:, 0], stb[:, 0])
 
 
-def _cnot_layers(n, layers, seed):
-    """Random circuit from the gate set the placement analysis covers:
-    Hadamards and RX/RY (branching), X/Z/T/P (one-qubit), CNOT and SWAP."""
-    rng = np.random.default_rng(seed)
-    c = w.Circuit(n)
-    for _ in range(layers):
-        for q in rng.choice(n, size=max(1, n // 2), replace=False):
-            g = str(rng.choice(["H", "H", "RX", "RY"]))
-            if g == "H":
-                c.add(g, int(q))
-            else:
-                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
-        for _ in range(n):
-            a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
-            c.add(str(rng.choice(["CX", "CX", "CX", "SWAP"])), a, b)
-        for q in rng.choice(n, size=max(1, n // 3), replace=False):
-            g = str(rng.choice(["X", "Z", "T", "P"]))
-            if g == "P":
-                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
-            else:
-                c.add(g, int(q))
-    return c
-
-
 @pytest.mark.parametrize("seed", range(40))
 def test_reachability_placement_random(seed):
     """On random CNOT + one-qubit circuits: optimal <= greedy <= backward
@@ -509,7 +485,7 @@ def test_reachability_placement_random(seed):
     valid-history counts of the backward placement and of the naive path
     sum."""
     n = 2 + seed % 4
-    c = _cnot_layers(n, 2 + seed % 3, 4400 + seed)
+    c = w.cnot_layers(n, 2 + seed % 3, 4400 + seed)
     t = c.to_text()
     Fb, Fo, Fg = (oracle.Feynman(t, p) for p in ("backward", "optimal", "greedy"))
     assert Fo.A <= Fg.A <= Fb.A

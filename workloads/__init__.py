@@ -267,6 +267,31 @@ def random_clifford_t(n: int = 10, n_gates: int = 40, seed: int = 101) -> Circui
     return c
 
 
+def cnot_layers(n: int, layers: int, seed: int) -> Circuit:
+    """Random circuit from the gate set the reachability placement covers:
+    per layer, Hadamards and RX/RY on half the qubits (branching), n CNOTs
+    or SWAPs on random pairs, then X/Z/T/P on a third of the qubits."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    for _ in range(layers):
+        for q in rng.choice(n, size=max(1, n // 2), replace=False):
+            g = str(rng.choice(["H", "H", "RX", "RY"]))
+            if g == "H":
+                c.add(g, int(q))
+            else:
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+        for _ in range(n):
+            a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+            c.add(str(rng.choice(["CX", "CX", "CX", "SWAP"])), a, b)
+        for q in rng.choice(n, size=max(1, n // 3), replace=False):
+            g = str(rng.choice(["X", "Z", "T", "P"]))
+            if g == "P":
+                c.add(g, int(q), angle=float(rng.uniform(-np.pi, np.pi)))
+            else:
+                c.add(g, int(q))
+    return c
+
+
 def qft(n: int) -> Circuit:
     """Textbook QFT network in little-endian qubit order: for the most
     significant qubit down to qubit 0, a Hadamard followed by controlled phase
