@@ -248,6 +248,11 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *                       automatic rule).  fhs_evaluate returns
  *                       FHS_EUNSUPPORTED, with the compiler log in
  *                       fhs_last_error, if that compilation fails.
+ *   items_per_claim     work items a consumer workgroup takes from the
+ *                       queue with one atomic, 1..64 (default: automatic,
+ *                       about 2^16 candidate histories per claim, at most
+ *                       16 items and at least 64 claims per compute unit;
+ *                       fhs_get_plan reports the value used).
  * Affects speed and the grouping of the amplitude sums (so their last bits),
  * never the history counts.  FHS_EINVAL for values out of range. */
 typedef struct {
@@ -255,6 +260,7 @@ typedef struct {
     uint32_t chunk;
     uint32_t blocks_per_cu;
     uint32_t dispatch;
+    uint32_t items_per_claim;
 } fhs_launch_config;
 
 fhs_status fhs_set_launch_config(fhs_ctx *ctx, const fhs_launch_config *cfg);
@@ -328,7 +334,7 @@ typedef struct {
     uint32_t plain_blocks_per_pair;
     uint64_t table_bytes;          /* prefix-table bytes per batch */
     uint32_t prefix_depth_first;   /* prefix sources enumerated depth first inside a lane */
-    uint32_t reserved;
+    uint32_t items_per_claim;      /* work items a consumer workgroup takes from the queue at once */
 } fhs_plan;
 
 fhs_status fhs_get_plan(const fhs_ctx *ctx, uint32_t M, uint32_t S, fhs_plan *plan);

@@ -74,7 +74,7 @@ class Plan(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
         "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)] + [
-        ("prefix_depth_first", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+        ("prefix_depth_first", ctypes.c_uint32), ("items_per_claim", ctypes.c_uint32)]
 
 
 class MlpShape(ctypes.Structure):
@@ -83,7 +83,8 @@ class MlpShape(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("histories_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("dispatch", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("dispatch", ctypes.c_uint32),
+                ("items_per_claim", ctypes.c_uint32)]
 
 
 _lib = None
@@ -289,8 +290,8 @@ class Context:
         return c1.value, c2.value
 
     def set_launch_config(self, histories_per_lane: int = 0, chunk: int = 0,
-                          blocks_per_cu: int = 0, dispatch: int = 0) -> None:
-        cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu, dispatch)
+                          blocks_per_cu: int = 0, dispatch: int = 0, items_per_claim: int = 0) -> None:
+        cfg = LaunchConfig(histories_per_lane, chunk, blocks_per_cu, dispatch, items_per_claim)
         _check(lib().fhs_set_launch_config(self._h, ctypes.byref(cfg)), self)
 
     def precompile(self, splits, M: int, S: int, threshold: float = 0.0, threads: int = 16) -> int:
@@ -311,6 +312,13 @@ class Context:
         cfg = LaunchConfig()
         _check(lib().fhs_get_launch_config(self._h, ctypes.byref(cfg)), self)
         return cfg.histories_per_lane, cfg.chunk, cfg.blocks_per_cu, cfg.dispatch
+
+    @property
+    def items_per_claim(self) -> int:
+        """The launch configuration's items per claim (0: automatic)."""
+        cfg = LaunchConfig()
+        _check(lib().fhs_get_launch_config(self._h, ctypes.byref(cfg)), self)
+        return cfg.items_per_claim
 
     def plan(self, M: int, S: int) -> dict:
         p = Plan()

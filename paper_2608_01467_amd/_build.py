@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfhs.so")
 RTC = os.path.join(HERE, "fhs_rtc")
+PROBE = os.path.join(HERE, "probe_valu_issue")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -86,6 +87,10 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, "--offload-arch=gfx950", "-o", out, w, "-L" + HERE, "-lfhs", "-lhiprtc",
               "-Wl,-rpath,$ORIGIN"])
         os.replace(out, RTC)
+        # probe_valu_issue: the VALU issue-rate probe behind the ALU rooflines
+        out = PROBE + f".tmp{os.getpid()}"
+        _run([HIPCC] + HIP_FLAGS + ["-o", out, os.path.join(CSRC, "probe_valu_issue.hip")])
+        os.replace(out, PROBE)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if verbose:

@@ -1028,10 +1028,17 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     const uint32_t sshift = c.Ap + c.Ar;
     const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
 
-    for (;;) {
-        if (t == 0) s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
+    const uint32_t grab = c.grab > 0u ? c.grab : 1u;
+    uint32_t item = 0, left = 0;   // the claimed run of items not yet done (uniform)
+    for (;; ++item, --left) {
+        if (left == 0u) {
+            // the previous claim was last read before the barrier in the
+            // block reduction of its last item
+            if (t == 0) s_item = atomicAdd(counter, grab);
+            __syncthreads();
+            item = s_item;
+            left = grab;
+        }
         if (item >= n_items) break;
         if (part.stamps && t == 0) part.stamps[2ull * item] = wall_clock64();
         const uint32_t pl = item / nchunks, ch = item - pl * nchunks;

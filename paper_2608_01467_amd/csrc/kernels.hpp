@@ -72,6 +72,9 @@ struct Common {
     const uint32_t *aff_tab;
     uint32_t n_aff;
     const uint64_t *pair_aff;   // [P] (null when n_aff is 0)
+    // work items a consumer workgroup claims from the queue at once (>= 1):
+    // short items claimed one by one keep the queue's single counter busy
+    uint32_t grab;
 };
 
 #if !defined(__HIPCC_RTC__)

@@ -65,6 +65,7 @@ struct Plan {
     uint32_t chunk = 1;      // prefix entries per work item
     uint32_t nchunks = 1;    // work items per pair
     uint32_t ss = 0;         // log2 lanes per root task
+    uint32_t grab = 1;       // work items per claim from the consumer's queue
     uint32_t Dp = 0;         // prefix sources enumerated depth-first inside a lane
     uint32_t bpp = 1;        // plain: blocks per pair
     uint64_t entries = 0;    // table entries per batch
@@ -98,6 +99,7 @@ struct fhs_ctx {
     std::vector<uint32_t> src_dev;   // device-program index of each source's gate
     std::map<std::string, CompiledConsumer> compiled;   // consumers compiled for this program
     uint32_t c1 = 0, c2 = 0;
+    uint32_t grab_override = 0;   // items per claim set by the launch config (0: the plan's)
     size_t table_budget = size_t(1) << 30;
     uint64_t generation = 0;
     hipStream_t cap_stream = nullptr;
@@ -281,6 +283,16 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
         pl.off_tab_ok = take(sizeof(uint32_t) * pl.entries);
         const uint64_t items = static_cast<uint64_t>(pl.B) * pl.nchunks;
         if (items > 0xffffffffull) return FHS_ERANGE;
+        // short items are claimed several at a time (one atomic on the
+        // queue's counter per claim): about 2^16 candidate histories per
+        // claim, at most 16 items, and still >= 64 claims per compute unit;
+        // the counter may run past the item count by one claim per workgroup
+        const uint64_t leaves_item = std::max<uint64_t>(static_cast<uint64_t>(pl.chunk) << (pl.Ar + pl.As), 1);
+        uint64_t g = (uint64_t(1) << 16) / leaves_item;
+        g = std::min<uint64_t>(g, items / (static_cast<uint64_t>(std::max(c->num_cu, 1)) * 64));
+        g = std::min<uint64_t>(g, 16);
+        if (items + (g << 20) > 0xffffffffull) g = 1;
+        pl.grab = static_cast<uint32_t>(std::max<uint64_t>(g, 1));
         pl.off_part_amp = take(sizeof(double2) * items);
         pl.off_part_st = take(sizeof(uint64_t) * 4 * items);
     }
@@ -393,6 +405,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.aff_tab = c->d_aff;
     cm.n_aff = static_cast<uint32_t>(P.aff.size() / 9);
     cm.pair_aff = (ws && cm.n_aff) ? at<uint64_t>(ws, pl.off_pre_aff) : nullptr;
+    cm.grab = c->grab_override ? c->grab_override : pl.grab;
     return cm;
 }
 
@@ -939,8 +952,9 @@ extern "C" fhs_status fhs_set_launch_config(fhs_ctx *c, const fhs_launch_config 
     const uint32_t h = cfg->histories_per_lane ? cfg->histories_per_lane : 2;
     const uint32_t ch = cfg->chunk ? cfg->chunk : kMaxChunk;
     if (h > 2 || ch > static_cast<uint32_t>(kMaxChunk) || (ch & (ch - 1)) || cfg->blocks_per_cu > 64 ||
-        cfg->dispatch > 3)
+        cfg->dispatch > 3 || cfg->items_per_claim > 64)
         return fail(c, FHS_EINVAL, "launch config out of range");
+    c->grab_override = cfg->items_per_claim;
     c->ilp = static_cast<int>(h);
     c->chunk_max = ch;
     c->blocks_per_cu = cfg->blocks_per_cu;
@@ -955,6 +969,7 @@ extern "C" fhs_status fhs_get_launch_config(const fhs_ctx *c, fhs_launch_config 
     cfg->chunk = c->chunk_max;
     cfg->blocks_per_cu = c->blocks_per_cu;
     cfg->dispatch = c->dispatch;
+    cfg->items_per_claim = c->grab_override;
     return FHS_OK;
 }
 
@@ -977,7 +992,7 @@ extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs
     out->lanes_per_root_task = 1u << pl.ss;
     out->plain_blocks_per_pair = pl.bpp;
     out->prefix_depth_first = pl.Dp;
-    out->reserved = 0;
+    out->items_per_claim = c->grab_override ? c->grab_override : pl.grab;
     out->table_bytes = pl.entries * (sizeof(uint32_t) * nw_of(c->prog) + sizeof(double2) +
                                      sizeof(double) + sizeof(uint32_t));
     return FHS_OK;

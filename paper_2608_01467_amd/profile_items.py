@@ -107,6 +107,8 @@ def items(args) -> int:
     ctx.set_table_budget(32 << 30)
     cuts = tuple(int(v) for v in args.cuts.split(",")) if args.cuts else prog.choose_partition(PART_EQ8)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.claim is not None:
+        launch = (launch or ctx.launch_config) + (args.claim,)
     ms, stamps, ipp, tps, _, st = timed_evaluation(ctx, prog, cfg, cuts, launch)
     S = len(cfg["inputs"])
     start = stamps[:, 0].astype(np.int64)
@@ -118,6 +120,7 @@ def items(args) -> int:
     lc = ctx.launch_config
     valid = st[:, 0] > 0
     line = {"workload": args.workload, "partition": list(cuts), "launch_config": list(lc),
+            "items_per_claim": plan["items_per_claim"],
             "regions": [plan["Ap"], plan["Ar"], plan["As"]], "items": int(stamps.shape[0]),
             "items_per_pair": ipp, "consumer_ms": ms, "makespan_us": float(makespan),
             "item_us": _quantiles(dur), "output_us": _quantiles(per_out),
@@ -165,6 +168,7 @@ def main() -> int:
     ap.add_argument("--workload", default="walk_99p_20s")
     ap.add_argument("--cuts", default=None, metavar="C1,C2")
     ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC,DISPATCH")
+    ap.add_argument("--claim", type=int, default=None, help="items per claim (0: automatic)")
     ap.add_argument("--steps", default="10-20")
     ap.add_argument("--outputs", type=int, default=8192)
     args = ap.parse_args()

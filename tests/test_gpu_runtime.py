@@ -123,6 +123,27 @@ def test_table_batches_and_timing(ctx):
         ctx.set_table_budget(1 << 30)
 
 
+@pytest.mark.parametrize("case", [0, 1])
+def test_items_per_claim(ctx, case):
+    """A consumer workgroup may take several work items per atomic on the
+    queue's counter: every claim size (and the automatic one) gives the
+    oracle's amplitudes and valid sets, including claims that run past the
+    last item; the plan reports the size in use."""
+    name, text, outs, thr = _cases()[case]
+    prog = fhs.Program(text)
+    part = prog.choose_partition(fhs.PART_EQ8)
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    for dispatch in (0, 3):
+        for claim in (0, 1, 3, 16, 64):
+            ctx.set_launch_config(2, 4, 0, dispatch, claim)
+            assert ctx.items_per_claim == claim
+            amps, st = _run(ctx, prog, outs, thr, part)
+            plan = ctx.plan(len(outs), 1)
+            assert plan["items_per_claim"] == (claim or plan["items_per_claim"]) >= 1
+            _check((name, dispatch, claim), amps, st, ref)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_autotune_launch(ctx):
     name, text, outs, thr = _cases()[1]
     wl = tune.Workload(ctx, text, [0], [1.0], outs, thr)
