@@ -65,6 +65,21 @@ def traffic_from_profile(workload: str, partition):
     return entry.get("bytes_per_launch") if entry else None
 
 
+def pmc_from_profile(workload: str, partition, launch):
+    """Instructions the consumer issued per launch (rocprofv3 PMC summary
+    committed under profiles/), if taken on the current kernels with the same
+    split and launch configuration."""
+    path = os.path.join(ROOT, "profiles", f"consume_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernels_hash") != kernels_hash():
+        return None
+    key = f"{partition[0]},{partition[1]}|{','.join(str(int(v)) for v in launch)}"
+    return d.get("runs", {}).get(key)
+
+
 def cpu_model() -> str:
     """The host CPU's model name (lscpu), for the CPU baseline's record."""
     import subprocess
@@ -435,6 +450,22 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": fp_rate / PEAK_FP64, "operand": "FP64 flops"}
     tb = traffic_from_profile(args.workload, part)
     roof["traffic"] = tb
+    # The work model counts operations; the hardware counters count issued
+    # instructions.  Lane-instructions per second against the 128-lane VALU
+    # issue rate (the int32 peak above), the FP64 share of them, and VALU
+    # busy (wave-instructions per CU-cycle, rocprofv3's VALUBusy), from the
+    # committed PMC summary over this launch's measured duration.
+    pm = pmc_from_profile(args.workload, part, ctx.launch_config)
+    if pm:
+        lane_rate = pm["valu_insts"] * 64 / avg_launch
+        roof["pmc"] = {"valu_lane_instr_per_s": lane_rate,
+                       "valu_issue_frac": lane_rate / PEAK_INT32,
+                       "fp64_instr_share": pm["fp64_insts"] / pm["valu_insts"],
+                       "fp64_executed_tflops": pm["fp64_flops"] / avg_launch / 1e12,
+                       "valu_busy": pm["valu_insts"] / (256 * 2.4e9 * avg_launch),
+                       "salu_per_valu": pm["salu_insts"] / pm["valu_insts"]}
+    else:
+        roof["pmc"] = None
     roof["kernel"] = "fhs_consume_compiled" if ctx.launch_config[3] == 3 else "k_consume"
     roof["avg_launch_ms"] = avg_launch * 1e3
     roof["launches_per_step"] = launches

@@ -151,7 +151,22 @@ struct Lanes {
     uint64_t dx[H];     // factor-table indices recorded for a deferred multiply
     uint64_t hf[H];     // the source bits of the earlier regions (their global positions)
     uint64_t aff;       // the pair's boundary bits of the affine inputs' forms
+    // Wave-uniform parts of this region's source index, on bits disjoint from
+    // hb's and from each other: the region's index is hb | hq | hu.  The
+    // consumer's suffix loop keeps its counter here (hq the base of an
+    // unrolled pass, hu the leaf's offset in it, a compile-time constant
+    // there), so what depends only on those sources is scalar work, and the
+    // offset's share of it is folded at compile time.
+    uint64_t hq;
+    uint32_t hu;
 };
+
+// Source bit k of a region's index (hb, hq and hu hold disjoint bits).
+template <int NW, int H>
+__device__ __forceinline__ uint32_t src_bit(const Lanes<NW, H> &L, int h, uint32_t k) {
+    return static_cast<uint32_t>((L.hb[h] >> k) & 1u) | static_cast<uint32_t>((L.hq >> k) & 1u) |
+           (k < 32u ? (L.hu >> k) & 1u : 0u);
+}
 
 // Factor tables: `fac` points at the slice [lo, ...) of the global table,
 // staged in LDS by the hot kernels; entries are read per lane.
@@ -365,8 +380,18 @@ __device__ __forceinline__ void pend_addsel(const Lanes<NW, H> &L, const Instr &
 // of 1, d1 - d0 = +-2, so together they add kc to pk and the popcount of the
 // source index over `pos` minus that over `neg` to pb (n = pk + 2 pb).
 template <int NW, int H>
-__device__ __forceinline__ void pend_src(const Lanes<NW, H> &L, int32_t (&pk)[H], int32_t (&pb)[H], int32_t kc,
-                                         uint64_t pos, uint64_t neg) {
+__device__ __forceinline__ void pend_src(const Lanes<NW, H> &L, int32_t (&pk)[H], int32_t (&pb)[H], int32_t &pbq,
+                                         int32_t kc, uint64_t pos, uint64_t neg) {
+    // hb and hq hold disjoint bits, so the popcounts split: hb's part per
+    // lane into pb, hq's (the same in every lane) into the scalar pbq
+    if ((pos | neg) >> 32) {
+        pbq += __popcll(L.hq & pos) - __popcll(L.hq & neg);
+    } else {
+        const uint32_t hq = static_cast<uint32_t>(L.hq);
+        if (pos) pbq += __popc(hq & static_cast<uint32_t>(pos));
+        if (neg) pbq -= __popc(hq & static_cast<uint32_t>(neg));
+    }
+    pbq += __popc(L.hu & static_cast<uint32_t>(pos)) - __popc(L.hu & static_cast<uint32_t>(neg));
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         pk[h] += kc;
@@ -382,12 +407,12 @@ __device__ __forceinline__ void pend_src(const Lanes<NW, H> &L, int32_t (&pk)[H]
 
 template <int NW, int H>
 __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H],
-                                            int32_t (&pb)[H]) {
+                                            int32_t (&pb)[H], int32_t &pbq) {
     const FieldMasks f = field_masks(lo, hi);
     const uint32_t wl = lo >> 5, sh = lo & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
-        const int32_t n = pk[h] + 2 * pb[h];
+        const int32_t n = pk[h] + 2 * (pb[h] + pbq);
         // n * 2^lo in two's complement over the state's words
         const int64_t v = static_cast<int64_t>(n) * (static_cast<int64_t>(1) << sh);
         const uint32_t lo32 = static_cast<uint32_t>(static_cast<uint64_t>(v));
@@ -402,6 +427,7 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
         pk[h] = 0;
         pb[h] = 0;
     });
+    pbq = 0;
 }
 
 // The last pending run of a region after which the final check compares
@@ -413,9 +439,13 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
 // compiler computes it once per root history, leaving one compare per
 // history.  The field's bits are left as they were, so the final check that
 // follows must leave them out (nothing else reads them after the region).
+// The count is compared as 2 pbq = residue - pk - 2 pb (mod 2^32): the right
+// side does not depend on the wave-uniform sources, so inside the suffix
+// loop it is computed once per root history and each leaf costs one compare
+// against a scalar.
 template <int NW, int H>
 __device__ __forceinline__ void flush_check(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H],
-                                            int32_t (&pb)[H], const uint32_t (&bin)[NW]) {
+                                            int32_t (&pb)[H], int32_t &pbq, const uint32_t (&bin)[NW]) {
     const FieldMasks f = field_masks(lo, hi);
     const FieldMasks g = field_masks(lo + 32u < hi ? lo + 32u : hi, hi);   // bits [lo+32, hi)
     const uint32_t m = hi - lo, wl = lo >> 5, sh = lo & 31u;
@@ -436,24 +466,28 @@ __device__ __forceinline__ void flush_check(Lanes<NW, H> &L, uint32_t lo, uint32
             ohi |= ~d[w] & g.fm[w];
         });
         const uint32_t e32 = sh ? (x0 >> sh) | (x1 << (32u - sh)) : x0;   // bits [lo, lo+32) of d
-        const int32_t n = pk[h] + 2 * pb[h];
+        // the step count is n = pk + 2 pb + 2 pbq
+        const uint32_t nl = static_cast<uint32_t>(pk[h]) + 2u * static_cast<uint32_t>(pb[h]);
+        const uint32_t nq = 2u * static_cast<uint32_t>(pbq);
         bool hit;
         if (m <= 32u) {
             const uint32_t up = 32u - m;   // only the field's m low bits count
-            hit = (static_cast<uint32_t>(n) << up) == (e32 << up);
+            hit = (nq << up) == ((e32 - nl) << up);
         } else {
             // n sign-extended to m bits equals the residue iff their low 32
             // bits agree and bits [lo+32, hi) all repeat bit 31: the residue
             // as an int32 when it is one, else a value no step count reaches
-            // (|n| is at most the number of steps)
+            // (|n| is at most the number of steps); equal int32 values are
+            // equal mod 2^32
             const bool fits = static_cast<int32_t>(e32) < 0 ? ohi == 0u : zhi == 0u;
-            const int32_t en = fits ? static_cast<int32_t>(e32) : static_cast<int32_t>(0x80000000u);
-            hit = n == en;
+            const uint32_t en = fits ? e32 : 0x80000000u;
+            hit = nq == en - nl;
         }
         L.ok[h] = L.ok[h] && hit;
         pk[h] = 0;
         pb[h] = 0;
     });
+    pbq = 0;
 }
 
 template <int NW, int H, int WA, int WB>
@@ -517,7 +551,7 @@ __device__ __forceinline__ void op_branch(Lanes<NW, H> &L, const Instr &I, const
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         const uint32_t o = (L.s[h][A] >> sh) & 1u;
-        const uint32_t i = SRC ? static_cast<uint32_t>((L.hb[h] >> ks) & 1u) : (bin[A] >> sh) & 1u;
+        const uint32_t i = SRC ? src_bit(L, h, ks) : (bin[A] >> sh) & 1u;
         const uint32_t x = 2u * o + i;
         take_factor<DEFER>(L, h, F, I.fac, x);
         if (PRUNE) {
@@ -580,7 +614,7 @@ __device__ __forceinline__ void op_branch_real(Lanes<NW, H> &L, uint32_t (&sg)[H
         const uint32_t s0 = L.s[h][A];
         uint32_t snew;
         if constexpr (SRC) {
-            const uint32_t i = static_cast<uint32_t>(L.hb[h] >> ks) & 1u;
+            const uint32_t i = src_bit(L, h, ks);
             sg[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + i)) & 1u;   // the entry's sign
             snew = (s0 & ~bit) | (i << sa);
         } else {
@@ -626,7 +660,7 @@ __device__ __forceinline__ void op_branch_aff(Lanes<NW, H> &L, const Instr &I, c
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
         const uint32_t o = (L.s[h][A] >> sh) & 1u;
-        const uint64_t full = L.hf[h] | (L.hb[h] << kbase);
+        const uint64_t full = L.hf[h] | ((L.hb[h] | L.hq | L.hu) << kbase);
         const uint32_t i = (static_cast<uint32_t>(__popcll(full & smask)) & 1u) ^ cbit;
         const uint32_t x = 2u * o + i;
         take_factor<DEFER>(L, h, F, I.fac, x);
@@ -882,6 +916,7 @@ __device__ __forceinline__ void block_reduce_store(Acc a, Acc *lds, Partials par
 template <bool RUNS>
 struct Interp {
     static constexpr bool kDefer = false;   // factors are multiplied as the walk goes
+    static constexpr int kUnroll = 1;       // suffix assignments per pass of the leaf loop
     // prefix region: the gates before the first depth-first source, and the
     // gates of depth-first level l (from its source up to the next level's)
     template <int NW, bool PRUNE>
@@ -969,6 +1004,8 @@ __device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, ui
         L.hb[0] = li & lomask;
         L.dx[0] = 0;
         L.hf[0] = 0;
+        L.hq = 0;
+        L.hu = 0;
         L.aff = c.n_aff ? pre.aff[p] : 0ull;
         Walk::template prefix_head<NW, PRUNE>(c, F, L, bin, e_split);
         const uint64_t ebase = pl << c.Ap;
@@ -1107,6 +1144,8 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
             R.aff = paff;
+            R.hq = 0;
+            R.hu = 0;
             Regions::template root<NW, H, PRUNE>(c, F, R, bin);
             bool any = false;
             unroll<H>([&](auto jj) {
@@ -1117,18 +1156,26 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             if (!__any(any)) continue;   // wave-uniform skip
             // every suffix assignment of a consistent root is a leaf walked
             unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n_suffix : 0u; });
-            for (uint64_t q = 0; q < n_suffix; ++q) {
-                Lanes<NW, H> S2 = R;
+            // one leaf: the suffix region for assignment q (wave-uniform: the
+            // lanes differ in hs0 only), then its final check
+            auto walk_leaf = [&](Lanes<NW, H> &S2, uint64_t q, uint32_t u) {
                 unroll<H>([&](auto jj) {
-                    S2.hb[jj.value] = hs0[jj.value] + q;
+                    S2.hb[jj.value] = hs0[jj.value];   // multiples of n_suffix
                     S2.dx[jj.value] = 0;
                     S2.hf[jj.value] = hbase[jj.value];
                 });
+                S2.hq = q;                              // below n_suffix, the same in every lane
+                S2.hu = u;
                 Regions::template suffix<NW, H, PRUNE>(c, F, S2, bin);
                 unroll<H>([&](auto jj) {
                     constexpr int j = jj.value;
-                    const bool ok2 = S2.ok[j] && Regions::template final_G<NW>(S2.s[j], bin, fin_G);
-                    if (ok2) {
+                    S2.ok[j] = S2.ok[j] && Regions::template final_G<NW>(S2.s[j], bin, fin_G);
+                });
+            };
+            auto count_leaf = [&](Lanes<NW, H> &S2, uint64_t q) {
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    if (S2.ok[j]) {
                         // a policy that deferred the suffix's factors applies them
                         // now, for the histories that count
                         if constexpr (Regions::kDefer) Regions::template suffix_amp<NW, H>(F, S2, j);
@@ -1140,6 +1187,29 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                         acc.xorh ^= mix64(h);
                     }
                 });
+            };
+            constexpr int U = Regions::kUnroll;
+            uint64_t q = 0;
+            if constexpr (U > 1) {
+                // U leaves per pass: their checks first, then one wave-uniform
+                // test skips the pass when no lane has a valid history in it
+                for (; q + U <= n_suffix; q += U) {   // q stays a multiple of U
+                    Lanes<NW, H> S2[U];
+                    bool any = false;
+                    unroll<U>([&](auto uu) {
+                        constexpr int u = uu.value;
+                        S2[u] = R;
+                        walk_leaf(S2[u], q, static_cast<uint32_t>(u));
+                        unroll<H>([&](auto jj) { any = any || S2[u].ok[jj.value]; });
+                    });
+                    if (!__any(any)) continue;
+                    unroll<U>([&](auto uu) { count_leaf(S2[uu.value], q + uu.value); });
+                }
+            }
+            for (; q < n_suffix; ++q) {
+                Lanes<NW, H> S2 = R;
+                walk_leaf(S2, q, 0u);
+                count_leaf(S2, q);
             }
         }
         block_reduce_store<NT>(acc, l_red, part, item);

@@ -107,7 +107,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
     uint64_t spos = 0, sneg = 0;
     auto flush_src = [&]() {
         if (pkc == 0 && spos == 0 && sneg == 0) return;
-        std::snprintf(buf, sizeof(buf), "    pend_src<NW, H>(L, pk, pb, %d, 0x%llxull, 0x%llxull);\n", pkc,
+        std::snprintf(buf, sizeof(buf), "    pend_src<NW, H>(L, pk, pb, pbq, %d, 0x%llxull, 0x%llxull);\n", pkc,
                       static_cast<unsigned long long>(spos), static_cast<unsigned long long>(sneg));
         o += buf;
         pkc = 0;
@@ -116,7 +116,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
     auto flush = [&]() {
         if (!pending) return;
         flush_src();
-        std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk, pb);\n", plo, phi);
+        std::snprintf(buf, sizeof(buf), "    flush_field<NW, H>(L, %uu, %uu, pk, pb, pbq);\n", plo, phi);
         o += buf;
         pending = false;
     };
@@ -232,7 +232,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         for (int w = 0; w < 4; ++w) covered = covered && (fm.w[w] & ~check->w[w]) == 0u;
         if (covered) {
             flush_src();
-            std::snprintf(buf, sizeof(buf), "    flush_check<NW, H>(L, %uu, %uu, pk, pb, bin);\n", plo, phi);
+            std::snprintf(buf, sizeof(buf), "    flush_check<NW, H>(L, %uu, %uu, pk, pb, pbq, bin);\n", plo, phi);
             o += buf;
             pending = false;
             if (checked) *checked = fm;
@@ -292,6 +292,11 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
     o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
+    // a short suffix walks several assignments per pass of the leaf loop
+    // (the loop control and the skip of passes without a valid history are
+    // paid once per pass); longer ones one at a time, keeping registers
+    std::snprintf(buf, sizeof(buf), "static constexpr int kUnroll = %d;\n", iG - i2 <= 24u ? 8 : 1);
+    o += buf;
     // the final-bit masks as constants: fully checked words become one compare
     const Mask4 *fm[2] = {&fin_c2, &fin_rest};
     const char *fname[2] = {"final_c2", "final_G"};
@@ -310,7 +315,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   "__device__ static __forceinline__ void root(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
                   "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
-                  "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
+                  "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n",
                   Ap);
     o += buf;
     emit_region(o, dev, fac, fac_lo, Ap, i1, i2, false, none);
@@ -320,7 +325,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   "__device__ static __forceinline__ void suffix(const Common &c, const FacRef &F, "
                   "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
                   "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
-                  "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n",
+                  "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n",
                   Ap + Ar);
     o += buf;
     o += sfx;
@@ -349,7 +354,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
-             "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n";
+             "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n";
         emit_region(o, dev, fac, pfac_lo, 0u, iL, e_split, false, none);
         o += "}\n";
         o += "template <int NW, bool PRUNE>\n"
@@ -357,7 +362,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
              "Lanes<NW, 1> &L, const uint32_t (&bin)[NW], uint32_t, uint32_t, uint32_t l) {\n"
              "    constexpr int H = 1; constexpr uint32_t kbase = 0u; const double thr = c.thr; "
              "(void)kbase; (void)thr; (void)bin;\n"
-             "    int32_t pk[H] = {}, pb[H] = {}; (void)pk; (void)pb;\n"
+             "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n"
              "    switch (l) {\n";
         for (uint32_t l = 0; l < Dp; ++l) {
             const uint32_t a = src_dev[lo_bits + l], b = (l + 1 < Dp) ? src_dev[lo_bits + l + 1] : i1;

@@ -45,6 +45,8 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     L.ok[0] = !(bad_o || bad_i);
     L.hb[0] = 0;
     L.hf[0] = 0;
+    L.hq = 0;
+    L.hu = 0;
     L.aff = 0;
     if (c.n_aff) {
         L.aff = affine_bits<NW>(c, bin, L.s[0]);   // the start bits, before any gate
@@ -111,6 +113,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
                 L.ok[j] = L.hb[j] < NH;
             });
             L.aff = c.n_aff ? pre.aff[p] : 0ull;
+            L.hq = 0;
+            L.hu = 0;
             run_region<NW, H, PRUNE, RUNS>(c.prog, F, c.iL, c.iG, L, 0, bin, c.thr);
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
