@@ -430,14 +430,18 @@ def main() -> int:
     # region, the suffix region's integer work once per leaf walked (2^As
     # per consistent root) and its factor products once per valid history
     # (a history's amplitude is needed only when it passes the final check).
-    # Redundant evaluations the kernel makes for parallelism (root re-runs
-    # by the lanes that share a root task, lanes that idle inside a wave) do
-    # not count.
+    # The suffix's integer work whose inputs are only the suffix's own source
+    # bits is the same for every root that shares the suffix assignment (the
+    # consumer computes it once per assignment for a whole wave): it is not
+    # counted per leaf.  Redundant evaluations the kernel makes for
+    # parallelism (root re-runs by the lanes that share a root task, lanes
+    # that idle inside a wave) do not count.
     root = prog.work(plan["c1"], plan["c2"])
     suffix = prog.work(plan["c2"], prog.G)
     launches = max(1, len(kt) // max(args.steps, 1))
     n_root = n_valid_entries << plan["Ar"]
-    int_ops = (n_root * root["int_ops"] + leaves * suffix["int_ops"]) / launches
+    suffix_leaf_int = suffix["int_ops"] - suffix["src_int_ops"]
+    int_ops = (n_root * root["int_ops"] + leaves * suffix_leaf_int) / launches
     flops = (n_root * root["fp64_flops"] + valid * suffix["fp64_flops"]) / launches
     avg_launch = sum(kt) / len(kt) / 1e3
     int_rate = int_ops / avg_launch
@@ -472,6 +476,7 @@ def main() -> int:
     roof["work"] = {"prefix_entries": n_entries, "prefix_entries_consistent": n_valid_entries,
                     "root_evaluations": n_root, "leaves": leaves,
                     "root_int_ops": root["int_ops"], "suffix_int_ops": suffix["int_ops"],
+                    "suffix_src_int_ops": suffix["src_int_ops"],
                     "root_fp64_flops": root["fp64_flops"],
                     "suffix_fp64_flops": suffix["fp64_flops"]}
     roof["ms_per_step_timed"] = T_timed * 1e3

@@ -188,6 +188,12 @@ typedef struct {
     uint64_t int_ops;
     uint64_t fp64_flops;
     uint64_t branch;
+    uint64_t src_int_ops;   /* the part of int_ops whose inputs are only the
+                               range's own source bits: a source bit into the
+                               state (without zero entries), a popcount of the
+                               source index, operations on state bits that hold
+                               nothing else; the same for every history that
+                               shares the range's source assignment */
 } fhs_work;
 
 fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1, fhs_work *out);
@@ -230,7 +236,10 @@ fhs_status fhs_set_table_budget(fhs_ctx *ctx, size_t bytes);
  *                       lockstep through one decoded instruction stream
  *                       (default 2);
  *   chunk               prefix entries per work item of the persistent
- *                       consumer, a power of two in [1, 256] (default 256);
+ *                       consumer at most, a power of two in [1, 256]
+ *                       (default 256); the plan halves it, down to 8, while
+ *                       a batch would hold fewer than 128 work items per
+ *                       compute unit (fhs_get_plan reports the value used);
  *   blocks_per_cu       persistent workgroups per compute unit, at most the
  *                       occupancy limit (default: the occupancy limit);
  *   dispatch            how the kernels walk the program: 1 one opcode

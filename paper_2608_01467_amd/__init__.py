@@ -67,7 +67,8 @@ class ProgramInfo(ctypes.Structure):
 
 class Work(ctypes.Structure):
     _fields_ = [("gates", ctypes.c_uint64), ("int_ops", ctypes.c_uint64),
-                ("fp64_flops", ctypes.c_uint64), ("branch", ctypes.c_uint64)]
+                ("fp64_flops", ctypes.c_uint64), ("branch", ctypes.c_uint64),
+                ("src_int_ops", ctypes.c_uint64)]
 
 
 class Plan(ctypes.Structure):
@@ -214,7 +215,8 @@ class Program:
         """Algorithmic work of evaluation positions [e0, e1) per history."""
         w = Work()
         _check(lib().fhs_program_work(self._h, e0, e1, ctypes.byref(w)))
-        return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch)
+        return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch,
+                    src_int_ops=w.src_int_ops)
 
     def split_features(self, c1: int, c2: int, M: int, S: int) -> np.ndarray:
         out = (ctypes.c_double * N_FEATURES)()

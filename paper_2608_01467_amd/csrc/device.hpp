@@ -159,6 +159,7 @@ struct Lanes {
     // offset's share of it is folded at compile time.
     uint64_t hq;
     uint32_t hu;
+    uint32_t sd[H];     // bit 0: the sign of the deferred real factors' product so far
 };
 
 // Source bit k of a region's index (hb, hq and hu hold disjoint bits).
@@ -634,6 +635,25 @@ __device__ __forceinline__ void op_branch_real(Lanes<NW, H> &L, uint32_t (&sg)[H
 
 // The signs op_branch_real collected: negate the amplitude where the parity
 // of sg is odd, and start over.
+// The same gate in a region whose factors are deferred to the histories
+// that pass the final check: only the state and the entry's sign (into
+// L.sd) change here; the magnitude r is the same for every history and is
+// multiplied in once for the valid ones, with the region's other deferred
+// factors.
+template <int NW, int H, int WA, bool SRC>
+__device__ __forceinline__ void op_branch_real_sign(Lanes<NW, H> &L, uint32_t sa, uint32_t ks,
+                                                    const uint32_t (&bin)[NW], uint32_t neg) {
+    constexpr int A = wsel<WA, NW>();
+    const uint32_t bit = 1u << sa;
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t s0 = L.s[h][A];
+        const uint32_t i = SRC ? src_bit(L, h, ks) : (bin[A] >> sa) & 1u;
+        L.sd[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + i)) & 1u;
+        L.s[h][A] = (s0 & ~bit) | (i << sa);
+    });
+}
+
 template <int NW, int H>
 __device__ __forceinline__ void apply_signs(Lanes<NW, H> &L, uint32_t (&sg)[H]) {
     unroll<H>([&](auto hh) {
@@ -1006,6 +1026,7 @@ __device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, ui
         L.hf[0] = 0;
         L.hq = 0;
         L.hu = 0;
+        L.sd[0] = 0;
         L.aff = c.n_aff ? pre.aff[p] : 0ull;
         Walk::template prefix_head<NW, PRUNE>(c, F, L, bin, e_split);
         const uint64_t ebase = pl << c.Ap;
@@ -1141,6 +1162,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 R.ok[j] = valid;
                 R.hb[j] = hr;
                 R.hf[j] = l_hp[jx];
+                R.sd[j] = 0;
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
             R.aff = paff;
@@ -1162,6 +1184,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 unroll<H>([&](auto jj) {
                     S2.hb[jj.value] = hs0[jj.value];   // multiples of n_suffix
                     S2.dx[jj.value] = 0;
+                    S2.sd[jj.value] = 0;
                     S2.hf[jj.value] = hbase[jj.value];
                 });
                 S2.hq = q;                              // below n_suffix, the same in every lane

@@ -88,9 +88,13 @@ FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
 // at the end on a field that mask covers whole is compared with the output
 // instead (flush_check); its field is returned in `checked`, for the final
 // check to leave out.
+// With `defer`, a real-entry branch (FacShape REAL) records only its sign
+// (op_branch_real_sign) and its magnitude joins *rdef, the product the valid
+// histories are multiplied by at the end (*rsign: some sign was recorded).
 void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vector<double> &fac,
                  uint32_t fac_lo, uint32_t kbase, uint32_t lo, uint32_t hi, bool defer,
-                 std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr) {
+                 std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr,
+                 double *rdef = nullptr, bool *rsign = nullptr) {
     char buf[512];
     int off = 0;
     std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n"
@@ -149,14 +153,24 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
                       I.cv[2], I.cv[3]);
         o += buf;
         int d = -1;
+        char call[512];
+        FacShape fs = fac_shape(I, fac);
+        const uint32_t sa = a & 31u, sb = b & 31u;
+        if (defer && rdef && fs.kind == FacShape::REAL) {
+            std::snprintf(call, sizeof(call),
+                          "op_branch_real_sign<NW, H, wsel<%d, NW>(), %s>(L, %uu, I.k - kbase, bin, %uu); }\n", w1,
+                          base == OP_BRANCH_SRC ? "true" : "false", sa, fs.neg);
+            o += call;
+            *rdef *= fs.r;
+            *rsign = true;
+            continue;
+        }
         if (defer && factor_bits(base) > 0) {
             d = off;
             deferred.push_back(Deferred{I.fac, off, factor_bits(base)});
             off += factor_bits(base);
+            fs = FacShape{};
         }
-        char call[512];
-        const FacShape fs = d < 0 ? fac_shape(I, fac) : FacShape{};
-        const uint32_t sa = a & 31u, sb = b & 31u;
         if (fs.kind == FacShape::CONJ) {
             std::snprintf(call, sizeof(call),
                           "(void)I; op_conj<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), %s>(L, %uu, %uu, %a, %a); }\n",
@@ -282,12 +296,16 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // for the histories that pass the final check) when nothing needs them
     // during the walk (pruning does), their indices fit in dx, and a history
     // can still fail after the root; when none can, deferring only adds work.
+    // (real-entry branches defer only a sign and a constant magnitude)
     int bits = 0;
-    for (uint32_t x = i2; x < iG; ++x) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
+    for (uint32_t x = i2; x < iG; ++x)
+        if (fac_shape(dev[x], fac).kind != FacShape::REAL) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
     const bool defer = !prune && bits <= 64 && (check_left || zero_entries);
+    double rdef = 1.0;
+    bool rsign = false;
     if (defer) {
         sfx.clear();
-        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked);
+        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign);
     }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
@@ -341,6 +359,14 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                       "    { const uint32_t x = static_cast<uint32_t>(L.dx[h] >> %d) & %uu; "
                       "const double2 f = Fc.c(%uu + 2u * x); cmul(L.re[h], L.im[h], f.x, f.y); }\n",
                       d.off, (1u << d.bits) - 1u, d.fac);
+        o += buf;
+    }
+    if (rsign) {
+        // the real-entry branches' magnitudes (one constant) and signs
+        std::snprintf(buf, sizeof(buf),
+                      "    { const uint32_t f = (L.sd[h] & 1u) << 31; "
+                      "L.re[h] = flip_sign(L.re[h] * %a, f); L.im[h] = flip_sign(L.im[h] * %a, f); }\n",
+                      rdef, rdef);
         o += buf;
     }
     o += "}\n";

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     L.hf[0] = 0;
     L.hq = 0;
     L.hu = 0;
+    L.sd[0] = 0;
     L.aff = 0;
     if (c.n_aff) {
         L.aff = affine_bits<NW>(c, bin, L.s[0]);   // the start bits, before any gate
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(Common c, PreBufs pre, 
                 L.M[j] = M0;
                 L.hb[j] = h0 + j * stride;
                 L.hf[j] = 0;
+                L.sd[j] = 0;
                 L.ok[j] = L.hb[j] < NH;
             });
             L.aff = c.n_aff ? pre.aff[p] : 0ull;

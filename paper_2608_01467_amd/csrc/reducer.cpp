@@ -722,26 +722,56 @@ constexpr uint64_t kPopcountCost = 2;   // the source index masked, its popcount
 // bit set earlier in the range (SourceBits) adds a constant plus that bit
 // with a fixed sign: such steps cost nothing each, and their run pays one
 // popcount of the source index per sign that occurs.
-uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
-    uint64_t ops = 0;
+// Work of [lo, hi) per history; *uniform (may be null) receives the part
+// whose inputs are only this range's own source bits (and constants): a
+// source bit written into the state, a popcount of the source index, and
+// operations on state bits that hold nothing else.  That part is the same
+// for every history that shares the range's source assignment, whatever
+// came before the range.
+uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi, uint64_t *uniform = nullptr) {
+    uint64_t ops = 0, uni = 0;
     SourceBits sb;
     bool pos_used = false, neg_used = false;
+    // state bits whose value is a function of this range's source bits alone
+    std::vector<uint8_t> src_only(kMaxQubits, 0);
+    auto bits_of = [](const uint32_t (&m)[4], auto &&f) {
+        for (int q = 0; q < kMaxQubits; ++q)
+            if ((m[q >> 5] >> (q & 31)) & 1u) f(q);
+    };
     for (uint32_t e = lo; e < hi; ++e) {
         const Instr &I = P.ins[e];
+        const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
         const bool starts_run = P.flush_cost[e] && (P.run_prev[e] == kNoPrev || P.run_prev[e] < lo);
         if (starts_run) pos_used = neg_used = false;
         const int j = sb.selector_source(I);
         sb.step(I, 0);
+        uint32_t touched[4], written[4];
+        touched_bits(I, touched);
+        written_bits(I, written);
         if (j >= 0) {
             const uint32_t z = I.hdr >> 24;
             const int d0 = (z & 1u) ? -1 : 1, d1 = (z & 2u) ? -1 : 1;
             bool &used = d1 > d0 ? pos_used : neg_used;
             if (d1 != d0 && !used) {
                 ops += kPopcountCost;
+                uni += kPopcountCost;   // the source index alone
                 used = true;
             }
+            bits_of(written, [&](int q) { src_only[q] = 0; });   // the field: the count joins its old value
         } else {
+            bool only = true;   // inputs: this range's sources and source-only bits
+            if (base == OP_BRANCH_SRC) {
+                only = P.int_cost[e] == 1u || src_only[(I.hdr >> 8) & 0xffu];   // with zero entries it reads o
+                bits_of(written, [&](int q) { src_only[q] = 1; });
+            } else if (base == OP_BRANCH_NAT || base == OP_BRANCH_AFF) {
+                only = false;   // the input bitstring, or forms over the boundary bits
+                bits_of(written, [&](int q) { src_only[q] = 0; });
+            } else {
+                bits_of(touched, [&](int q) { only = only && src_only[q]; });
+                bits_of(written, [&](int q) { src_only[q] = only ? 1 : 0; });
+            }
             ops += P.int_cost[e];
+            if (only) uni += P.int_cost[e];
         }
         if (starts_run) ops += P.flush_cost[e];
     }
@@ -752,6 +782,7 @@ uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi) {
         while (P.run_prev[f] != kNoPrev && P.run_prev[f] >= lo) f = P.run_prev[f];
         ops = ops - P.flush_cost[f] + kCheckCost;
     }
+    if (uniform) *uniform = uni;
     return ops;
 }
 
@@ -899,13 +930,13 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     if (!prog || !out) return FHS_EINVAL;
     const HostProgram &P = prog->p;
     if (e0 > e1 || e1 > static_cast<uint32_t>(P.G)) return FHS_EINVAL;
-    fhs_work w{0, 0, 0, 0};
+    fhs_work w{0, 0, 0, 0, 0};
     for (uint32_t e = e0; e < e1; ++e) {
         w.gates += 1;
         w.fp64_flops += P.fp_cost[e];
         w.branch += P.role[e] == 2 ? 1 : 0;
     }
-    w.int_ops = range_int_ops(P, e0, e1);
+    w.int_ops = range_int_ops(P, e0, e1, &w.src_int_ops);
     *out = w;
     return FHS_OK;
 }

@@ -265,7 +265,15 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
         B = std::max<uint64_t>(1, std::min<uint64_t>(B, n_pairs));
         pl.B = static_cast<uint32_t>(B);
         pl.n_batches = (n_pairs + pl.B - 1) / pl.B;
-        pl.chunk = static_cast<uint32_t>(std::min<uint64_t>(per_pair, c->chunk_max));
+        // prefix entries per work item: the configured chunk, halved (down to
+        // 8) while a batch would hold fewer than 128 items per compute unit,
+        // so that when pairs are few and their tables small the costly pairs
+        // (those with many valid histories) still spread over several
+        // workgroups instead of setting the kernel's length alone
+        uint64_t ch = std::min<uint64_t>(per_pair, c->chunk_max);
+        const uint64_t want_items = static_cast<uint64_t>(std::max(c->num_cu, 1)) * 128;
+        while (ch > 8 && B * ((per_pair + ch - 1) / ch) < want_items) ch >>= 1;
+        pl.chunk = static_cast<uint32_t>(ch);
         pl.nchunks = static_cast<uint32_t>((per_pair + pl.chunk - 1) / pl.chunk);
         pl.entries = B * per_pair;
         // lanes sharing one root task: enough root tasks to fill the device

@@ -57,6 +57,13 @@ def test_walk_ladders_fold_to_one_instruction_each():
     assert a.work(0, a.G)["int_ops"] == unfolded
     assert b.work(0, b.G)["int_ops"] == steps * (1 + 2 * (4 + 1)) + 2
     assert c.work(0, c.G)["int_ops"] == steps * 1 + 2 + 2 + 2
+    # the part that depends only on the range's own sources: the 19 source
+    # bits into the state (the coin's first H takes the input bit) and the
+    # popcount of the source index; the compare with the field's residue
+    # reads the state
+    assert c.work(0, c.G)["src_int_ops"] == (steps - 1) + 2
+    assert b.work(0, b.G)["src_int_ops"] == steps - 1
+    assert c.work(half0 := c.source_eval_positions[0], half0 + 1)["src_int_ops"] == 1
     # a range that starts inside the run pays its own popcount and compare,
     # and the range that holds the run's start but stops short of the end
     # applies its part with a carry chain
