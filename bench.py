@@ -440,9 +440,14 @@ def main() -> int:
     suffix = prog.work(plan["c2"], prog.G)
     launches = max(1, len(kt) // max(args.steps, 1))
     n_root = n_valid_entries << plan["Ar"]
-    suffix_leaf_int = suffix["int_ops"] - suffix["src_int_ops"]
-    int_ops = (n_root * root["int_ops"] + leaves * suffix_leaf_int) / launches
-    flops = (n_root * root["fp64_flops"] + valid * suffix["fp64_flops"]) / launches
+    # The suffix instructions the compiled consumer evaluates once per root
+    # (no suffix source influences them) count per root, not per leaf.
+    hoist = ctx.launch_config[3] == 3 and thr == 0.0
+    h_int = suffix["hoist_int_ops"] if hoist else 0
+    h_fp = suffix["hoist_fp64_flops"] if hoist else 0
+    suffix_leaf_int = suffix["int_ops"] - suffix["src_int_ops"] - h_int
+    int_ops = (n_root * (root["int_ops"] + h_int) + leaves * suffix_leaf_int) / launches
+    flops = (n_root * (root["fp64_flops"] + h_fp) + valid * (suffix["fp64_flops"] - h_fp)) / launches
     avg_launch = sum(kt) / len(kt) / 1e3
     int_rate = int_ops / avg_launch
     fp_rate = flops / avg_launch
@@ -477,6 +482,7 @@ def main() -> int:
                     "root_evaluations": n_root, "leaves": leaves,
                     "root_int_ops": root["int_ops"], "suffix_int_ops": suffix["int_ops"],
                     "suffix_src_int_ops": suffix["src_int_ops"],
+                    "suffix_hoisted_int_ops": h_int, "suffix_hoisted_fp64_flops": h_fp,
                     "root_fp64_flops": root["fp64_flops"],
                     "suffix_fp64_flops": suffix["fp64_flops"]}
     roof["ms_per_step_timed"] = T_timed * 1e3

@@ -194,6 +194,14 @@ typedef struct {
                                source index, operations on state bits that hold
                                nothing else; the same for every history that
                                shares the range's source assignment */
+    uint64_t hoist_int_ops; /* taken as a suffix region (without pruning): the
+                               int_ops and fp64_flops of its instructions the
+                               compiled consumer evaluates once per root
+                               history instead of once per leaf: phases and
+                               branching gates on a natural input segment that
+                               no source of the range influences and that
+                               commute with the instructions before them */
+    uint64_t hoist_fp64_flops;
 } fhs_work;
 
 fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1, fhs_work *out);

@@ -68,7 +68,8 @@ class ProgramInfo(ctypes.Structure):
 class Work(ctypes.Structure):
     _fields_ = [("gates", ctypes.c_uint64), ("int_ops", ctypes.c_uint64),
                 ("fp64_flops", ctypes.c_uint64), ("branch", ctypes.c_uint64),
-                ("src_int_ops", ctypes.c_uint64)]
+                ("src_int_ops", ctypes.c_uint64), ("hoist_int_ops", ctypes.c_uint64),
+                ("hoist_fp64_flops", ctypes.c_uint64)]
 
 
 class Plan(ctypes.Structure):
@@ -216,7 +217,8 @@ class Program:
         w = Work()
         _check(lib().fhs_program_work(self._h, e0, e1, ctypes.byref(w)))
         return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch,
-                    src_int_ops=w.src_int_ops)
+                    src_int_ops=w.src_int_ops, hoist_int_ops=w.hoist_int_ops,
+                    hoist_fp64_flops=w.hoist_fp64_flops)
 
     def split_features(self, c1: int, c2: int, M: int, S: int) -> np.ndarray:
         out = (ctypes.c_double * N_FEATURES)()

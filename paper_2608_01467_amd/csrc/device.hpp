@@ -955,6 +955,11 @@ struct Interp {
     }
     template <int NW, int H>
     __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
+    // suffix instructions evaluated once per root history: none here
+    static constexpr bool kHoist = false;
+    template <int NW, int H, bool PRUNE>
+    __device__ static __forceinline__ void suffix_pre(const Common &, const FacRef &, Lanes<NW, H> &,
+                                                      const uint32_t (&)[NW]) {}
     // final-bit checks at c2 and G with the masks read from the program
     template <int NW>
     __device__ static __forceinline__ bool final_c2(const uint32_t (&s)[NW], const uint32_t (&bin)[NW],
@@ -1178,6 +1183,8 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             if (!__any(any)) continue;   // wave-uniform skip
             // every suffix assignment of a consistent root is a leaf walked
             unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n_suffix : 0u; });
+            // the suffix instructions no suffix source influences, once per root
+            if constexpr (Regions::kHoist) Regions::template suffix_pre<NW, H, PRUNE>(c, F, R, bin);
             // one leaf: the suffix region for assignment q (wave-uniform: the
             // lanes differ in hs0 only), then its final check
             auto walk_leaf = [&](Lanes<NW, H> &S2, uint64_t q, uint32_t u) {

@@ -88,13 +88,14 @@ FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
 // at the end on a field that mask covers whole is compared with the output
 // instead (flush_check); its field is returned in `checked`, for the final
 // check to leave out.
+// Instructions marked in `omit` (indexed from lo) are left out.
 // With `defer`, a real-entry branch (FacShape REAL) records only its sign
 // (op_branch_real_sign) and its magnitude joins *rdef, the product the valid
 // histories are multiplied by at the end (*rsign: some sign was recorded).
 void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vector<double> &fac,
                  uint32_t fac_lo, uint32_t kbase, uint32_t lo, uint32_t hi, bool defer,
                  std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr,
-                 double *rdef = nullptr, bool *rsign = nullptr) {
+                 double *rdef = nullptr, bool *rsign = nullptr, const std::vector<uint8_t> *omit = nullptr) {
     char buf[512];
     int off = 0;
     std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n"
@@ -125,6 +126,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         pending = false;
     };
     for (uint32_t x = lo; x < hi; ++x) {
+        if (omit && (*omit)[x - lo]) continue;   // emitted elsewhere
         const Instr &I = dev[x];
         const uint32_t op = I.hdr & 0xffu;
         const int base = op_base(op);
@@ -272,7 +274,15 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // input segment was set from the input and always matches it.
     std::string sfx;
     Mask4 checked{{0u, 0u, 0u, 0u}};
-    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked);
+    // suffix instructions evaluated once per root history (suffix_pre)
+    const std::vector<uint8_t> hoist = hoistable(dev, i2, iG, prune);
+    std::vector<uint8_t> keep(hoist.size());
+    bool any_hoist = false;
+    for (size_t x = 0; x < hoist.size(); ++x) {
+        keep[x] = hoist[x] ? 0 : 1;
+        any_hoist = any_hoist || hoist[x];
+    }
+    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked, nullptr, nullptr, &hoist);
     Mask4 natw{{0u, 0u, 0u, 0u}};
     bool zero_entries = false;
     for (uint32_t x = i2; x < iG; ++x) {
@@ -299,13 +309,14 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // (real-entry branches defer only a sign and a constant magnitude)
     int bits = 0;
     for (uint32_t x = i2; x < iG; ++x)
-        if (fac_shape(dev[x], fac).kind != FacShape::REAL) bits += factor_bits(op_base(dev[x].hdr & 0xffu));
+        if (!hoist[x - i2] && fac_shape(dev[x], fac).kind != FacShape::REAL)
+            bits += factor_bits(op_base(dev[x].hdr & 0xffu));
     const bool defer = !prune && bits <= 64 && (check_left || zero_entries);
     double rdef = 1.0;
     bool rsign = false;
     if (defer) {
         sfx.clear();
-        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign);
+        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign, &hoist);
     }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     o += "struct Compiled {\n";
@@ -347,6 +358,18 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   Ap + Ar);
     o += buf;
     o += sfx;
+    o += "}\n";
+    std::snprintf(buf, sizeof(buf),
+                  "static constexpr bool kHoist = %s;\n"
+                  "template <int NW, int H, bool PRUNE>\n"
+                  "__device__ static __forceinline__ void suffix_pre(const Common &c, const FacRef &F, "
+                  "Lanes<NW, H> &L, const uint32_t (&bin)[NW]) {\n"
+                  "    constexpr uint32_t kbase = %uu; const double thr = c.thr; (void)kbase; (void)thr;\n"
+                  "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n",
+                  any_hoist ? "true" : "false", Ap + Ar);
+    o += buf;
+    if (any_hoist) emit_region(o, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, nullptr, nullptr, nullptr, nullptr,
+                               &keep);
     o += "}\n";
     // the deferred factors, in evaluation order: the same products as the walk
     o += "template <int NW, int H>\n"

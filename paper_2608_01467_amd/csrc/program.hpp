@@ -172,6 +172,44 @@ struct SourceBits {
     }
 };
 
+// The instructions of a suffix region [lo, hi) (device indices; OP_NOP
+// skipped) that can be evaluated once per root history instead of once per
+// leaf: phases (DIAG1, DIAG2, MCPHASE) and, without pruning, branching gates
+// on a natural input segment (BRANCH_NAT) that commute with every
+// instruction before them that stays in the leaf loop (neither writes a
+// state bit the other reads or writes; phases write none).  Only staying
+// instructions write the bits a source of the region influences, so these
+// read none of them.  Their factors are then multiplied before the leaf's
+// other factors instead of between them: the same product up to rounding.
+// With pruning, branches stay in place (the modulus product's order decides
+// pruning).
+inline std::vector<uint8_t> hoistable(const std::vector<Instr> &ins, uint32_t lo, uint32_t hi, bool prune) {
+    std::vector<uint8_t> out(hi > lo ? hi - lo : 0, 0);
+    uint32_t stay_w[4] = {0, 0, 0, 0};   // bits written by an instruction that stays
+    uint32_t stay_t[4] = {0, 0, 0, 0};   // bits touched by an instruction that stays
+    for (uint32_t x = lo; x < hi; ++x) {
+        const Instr &I = ins[x];
+        const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+        if (base == OP_NOP) continue;
+        uint32_t t[4], w[4];
+        touched_bits(I, t);
+        written_bits(I, w);
+        bool conflict = false;
+        for (int k = 0; k < 4; ++k) conflict = conflict || (t[k] & stay_w[k]) || (w[k] & stay_t[k]);
+        const bool kind = base == OP_DIAG1 || base == OP_DIAG2 || base == OP_MCPHASE ||
+                          (base == OP_BRANCH_NAT && !prune);
+        if (kind && !conflict) {
+            out[x - lo] = 1;
+            continue;
+        }
+        for (int k = 0; k < 4; ++k) {
+            stay_w[k] |= w[k];
+            stay_t[k] |= t[k];
+        }
+    }
+    return out;
+}
+
 // Whether `I` ends a pending accumulation of ladder steps on the field
 // [lo, hi): it touches a field bit other than as a further step of the same
 // field (an add on the field itself only reads its controls and selector).

@@ -786,6 +786,19 @@ uint64_t range_int_ops(const HostProgram &P, uint32_t lo, uint32_t hi, uint64_t 
     return ops;
 }
 
+// Work of the suffix instructions [lo, hi) the compiled consumer evaluates
+// once per root history instead of once per leaf (hoistable, without
+// pruning): their integer ops and FP64 flops per evaluation.
+void hoisted_work(const HostProgram &P, uint32_t lo, uint32_t hi, uint64_t &iops, uint64_t &flops) {
+    iops = flops = 0;
+    const std::vector<uint8_t> h = hoistable(P.ins, lo, hi, false);
+    for (uint32_t e = lo; e < hi; ++e)
+        if (h[e - lo]) {
+            iops += P.int_cost[e];
+            flops += P.fp_cost[e];
+        }
+}
+
 // Runs of identical opcodes: the device dispatches once per run.
 void set_runs(HostProgram &P) {
     const int G = P.G;
@@ -930,13 +943,14 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     if (!prog || !out) return FHS_EINVAL;
     const HostProgram &P = prog->p;
     if (e0 > e1 || e1 > static_cast<uint32_t>(P.G)) return FHS_EINVAL;
-    fhs_work w{0, 0, 0, 0, 0};
+    fhs_work w{0, 0, 0, 0, 0, 0, 0};
     for (uint32_t e = e0; e < e1; ++e) {
         w.gates += 1;
         w.fp64_flops += P.fp_cost[e];
         w.branch += P.role[e] == 2 ? 1 : 0;
     }
     w.int_ops = range_int_ops(P, e0, e1, &w.src_int_ops);
+    hoisted_work(P, e0, e1, w.hoist_int_ops, w.hoist_fp64_flops);
     *out = w;
     return FHS_OK;
 }
@@ -974,6 +988,13 @@ extern "C" fhs_status fhs_split_features(const fhs_program *prog, uint32_t c1, u
     work(L, e1, ip, fp);
     work(e1, e2, ir, fr);
     work(e2, G, is, fs);
+    // the suffix instructions the consumer evaluates once per root history
+    uint64_t hi_ops = 0, hi_fl = 0;
+    hoisted_work(P, e2, G, hi_ops, hi_fl);
+    ir += static_cast<double>(hi_ops);
+    fr += static_cast<double>(hi_fl);
+    is -= static_cast<double>(hi_ops);
+    fs -= static_cast<double>(hi_fl);
     decode(L, e1, dp, rp);
     decode(e1, e2, dr, rr);
     decode(e2, G, ds, rs);

@@ -93,3 +93,29 @@ def test_reduce_ex_rejects_unknown_flags():
     for flags in (0, 1, 3, 4, 7, 8, 11, 16, 19):
         assert fhs.lib().fhs_reduce_ex(t, len(t), flags, ctypes.byref(h)) == 0
         fhs.lib().fhs_program_free(h)
+
+
+def test_hoisted_suffix_work_qaoa():
+    """The suffix instructions the compiled consumer evaluates once per root
+    (fhs_work.hoist_*): with the cut after the last two first-layer RX gates
+    in evaluation order (vertices 0 and 1 in time order: the suffix's sources), the
+    first-layer RZZ phases on edges that avoid both vertices and the
+    Hadamards on vertices no remaining gate reads; counted here from the
+    graph alone."""
+    for nv, seed in ((12, 401), (12, 31), (8, 5)):
+        c, edges, _, _ = w.qaoa_maxcut(nv, 2, seed, seed + 1)
+        p = fhs.Program(c.to_text())
+        c2 = p.G - (nv + len(edges) + 2)     # suffix: 2 RX, the first RZZ layer, the H layer
+        src = {0, 1}
+        stay_edges = [e for e in edges if src & set(e)]
+        touched = src | {q for e in stay_edges for q in e}
+        k = len(edges) - len(stay_edges)
+        m = nv - len(touched)
+        wk = p.work(c2, p.G)
+        assert p.source_eval_positions[-2:] == [c2, c2 + 1]
+        assert (wk["hoist_int_ops"], wk["hoist_fp64_flops"]) == (3 * k + m, 6 * k + 2 * m), (nv, seed)
+    # the walk's suffix has nothing to hoist: every gate reads the coin or the field
+    t = w.quantum_walk(20, 6).to_text()
+    q = fhs.Program(t)
+    for c2 in q.source_eval_positions:
+        assert q.work(c2, q.G)["hoist_int_ops"] == 0
