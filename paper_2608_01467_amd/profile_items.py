@@ -3,6 +3,7 @@ artificial sources on the quantum walk; time per requested bitstring).
 
     python -m paper_2608_01467_amd.profile_items items [--workload walk_99p_20s]
     python -m paper_2608_01467_amd.profile_items sources [--steps 10-20]
+    python -m paper_2608_01467_amd.profile_items choice --workload aa_k16_s3
 
 `items`: one batched evaluation of the workload in timing mode at its
 Eq. (8) split (or --cuts); the persistent consumer's per-item clock stamps
@@ -158,13 +159,61 @@ def sources(args) -> int:
     return 0
 
 
+def choice(args) -> int:
+    """The split choice for a workload the method cannot evaluate whole (the
+    amplitude-amplification circuit with 16 search qubits and 14 ancillas:
+    A = 96 sources, 2^96 histories per output): Eq. (8)'s argmin and cost,
+    the plain cost, the cost model's predictions over the candidate splits
+    (how many lie in its training range), its own choice, and what planning
+    the evaluation returns."""
+    import math
+    from . import FhsError, PART_MODEL, tune
+    cfg = w.CONFIGS[args.workload]()
+    prog = Program(cfg["circuit"].to_text())
+    M, S = len(cfg["outputs"]), len(cfg["inputs"])
+    ctx = Context(0)
+    line = {"workload": args.workload, "qubits": prog.n, "gates": prog.G, "sources": prog.A,
+            "outputs": M, "inputs": S}
+    e1, e2 = prog.choose_partition(PART_EQ8)
+    cost, reg = prog.partition_cost(e1, e2)
+    line["eq8"] = {"partition": [e1, e2], "gate_ops_per_pair": str(cost), "log2": math.log2(cost),
+                   "regions": list(reg[3:])}
+    plain = prog.partition_cost(0, 0)[0]
+    line["plain"] = {"gate_ops_per_pair": str(plain), "log2": math.log2(plain), "eq8_gain": plain / cost}
+    blob = tune.load_model()
+    splits = prog.candidate_splits()
+    line["candidate_splits"] = len(splits)
+    if blob is not None:
+        ctx.load_cost_model(blob)
+        ctx.load(prog)
+        pred = ctx.predict_splits(splits, M, S)
+        ok = ~np.isnan(pred)
+        line["model_in_range"] = int(ok.sum())
+        if ok.any():
+            i = int(np.nanargmin(pred))
+            line["model_best_predicted"] = {"partition": list(splits[i]), "log_seconds": float(pred[i])}
+        try:
+            line["model_choice"] = list(ctx.choose_partition(PART_MODEL, M, S))
+        except FhsError as e:
+            line["model_choice"] = str(e)
+    else:
+        ctx.load(prog)
+    ctx.set_partition(e1, e2)
+    try:
+        line["plan"] = ctx.plan(M, S)
+    except FhsError as e:
+        line["plan"] = str(e)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     import torch
     if not torch.cuda.is_available():      # torch sets the device up before the library does
         print("profile_items: no GPU visible", file=sys.stderr)
         return 1
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["items", "sources"])
+    ap.add_argument("mode", choices=["items", "sources", "choice"])
     ap.add_argument("--workload", default="walk_99p_20s")
     ap.add_argument("--cuts", default=None, metavar="C1,C2")
     ap.add_argument("--launch", default=None, metavar="H,CHUNK,BPC,DISPATCH")
@@ -172,7 +221,7 @@ def main() -> int:
     ap.add_argument("--steps", default="10-20")
     ap.add_argument("--outputs", type=int, default=8192)
     args = ap.parse_args()
-    return items(args) if args.mode == "items" else sources(args)
+    return {"items": items, "sources": sources, "choice": choice}[args.mode](args)
 
 
 if __name__ == "__main__":
