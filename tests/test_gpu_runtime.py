@@ -208,3 +208,38 @@ def test_precompile(ctx):
     with pytest.raises(fhs.FhsError):
         ctx.precompile([(5, 2)], len(outs), 1, thr)
     ctx.set_launch_config(0, 0, 0, 0)
+
+
+def test_workspace_too_small(ctx):
+    """fhs_evaluate and fhs_evaluate_plain with a workspace below
+    fhs_workspace_size: FHS_ENOMEM (status 4), nothing launched, the outputs
+    left as they were; with the full size the same call succeeds."""
+    import ctypes
+    name, text, outs, thr = _cases()[0]
+    prog = fhs.Program(text)
+    ctx.load(prog)
+    ctx.set_partition(*prog.choose_partition(fhs.PART_EQ8))
+    d_in, d_out = ctx.device_bits([0]), ctx.device_bits(outs)
+    d_cf = ctx.device_coeffs([1.0])
+    M = len(outs)
+    need = ctx.workspace_size(M, 1)
+    assert need > 256
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    amps = torch.full((M, 2), 7.0, dtype=torch.float64, device="cuda:0")
+    stats = torch.full((M, 4), 7, dtype=torch.int64, device="cuda:0")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = fhs.lib()
+    for fn in (L.fhs_evaluate, L.fhs_evaluate_plain):
+        st = fn(ctx._h, d_in.data_ptr(), d_cf.data_ptr(), 1, d_out.data_ptr(), M, float(thr),
+                amps.data_ptr(), stats.data_ptr(), ws.data_ptr(), need - 256, stream)
+        assert st == 4, st
+        assert b"workspace" in L.fhs_last_error(ctx._h)
+        torch.cuda.synchronize()
+        assert bool((amps == 7.0).all()) and bool((stats == 7).all())
+    st = L.fhs_evaluate(ctx._h, d_in.data_ptr(), d_cf.data_ptr(), 1, d_out.data_ptr(), M, float(thr),
+                        amps.data_ptr(), stats.data_ptr(), ws.data_ptr(), need, stream)
+    assert st == 0
+    torch.cuda.synchronize()
+    ref = oracle.Feynman(text).evaluate([0], [1], outs, threshold=thr, threads=THREADS)
+    a = amps.cpu().numpy()
+    _check("full workspace", a[:, 0] + 1j * a[:, 1], stats.cpu().numpy().view(np.uint64), ref)
