@@ -285,7 +285,15 @@ static int build_relations(const orc_circuit *c, relation *rel, int *nrel) {
             rel[nr].seg[0] = g->in_seg[1]; rel[nr].seg[1] = g->in_seg[0]; rel[nr].seg[2] = g->out_seg[0];
             ++nr;
         } else if (g->k == 2 && g->kind == KIND_DENSE && local_preserved(g, 0) != local_preserved(g, 1)) {
-            int jc = local_preserved(g, 0) ? 0 : 1, jt = 1 - jc;
+            int jc = local_preserved(g, 0) ? 0 : 1, jt = 1 - jc, flips = 0;
+            /* a CNOT: the target flips for exactly one value of the kept
+             * wire (a flip for both would leave the kept wire unfixed by
+             * the other two) */
+            for (int v = 0; v < 2; ++v) {
+                const int x = v << jc;
+                if (!is_zero(M_AT(g, x | (1 << jt), x))) ++flips;
+            }
+            if (flips != 1) return -1;
             rel[nr].n = 3;
             rel[nr].seg[0] = g->in_seg[jc]; rel[nr].seg[1] = g->in_seg[jt]; rel[nr].seg[2] = g->out_seg[jt];
             ++nr;
