@@ -181,7 +181,11 @@ fhs_status fhs_partition_cost(const fhs_program *prog, uint32_t c1, uint32_t c2,
  *               sign of such steps (one popcount of the source index);
  *   fp64_flops: complex multiply of the running amplitude: 6 for a general
  *               factor table, 2 if every entry is purely real or imaginary,
- *               0 if every entry is 0, +-1 or +-i; a negation counts 0;
+ *               0 if every entry is 0, +-1 or +-i; a negation counts 0; a
+ *               branching gate whose four entries are real, nonzero and of
+ *               one magnitude (H) counts 0: the product of such magnitudes
+ *               over a region is one constant for every history, and only
+ *               the sign is per history;
  *   branch:     branching gates (one modulus multiply each when pruning). */
 typedef struct {
     uint64_t gates;

@@ -604,7 +604,10 @@ __device__ __forceinline__ void op_conj(Lanes<NW, H> &L, uint32_t sa, uint32_t s
 // multiplying by the signed entry at the gate.  The input bit comes from the
 // source (SRC) or from the input bitstring and replaces bit a of the state.
 // No entry is zero.
-template <int NW, int H, bool PRUNE, int WA, bool SRC>
+// With MUL false the magnitude is left out too: every such factor's r is
+// the same for every history, so the region multiplies their product in
+// once, at its end with the signs (scale_amp).
+template <int NW, int H, bool PRUNE, int WA, bool SRC, bool MUL = true>
 __device__ __forceinline__ void op_branch_real(Lanes<NW, H> &L, uint32_t (&sg)[H], uint32_t sa, uint32_t ks,
                                                const uint32_t (&bin)[NW], double thr, double r,
                                                uint32_t neg, double m) {
@@ -623,8 +626,10 @@ __device__ __forceinline__ void op_branch_real(Lanes<NW, H> &L, uint32_t (&sg)[H
             else if (neg != 0u) sg[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + ((bin[A] >> sa) & 1u))) & 1u;
             snew = (s0 & ~bit) | (bin[A] & bit);
         }
-        L.re[h] *= r;
-        L.im[h] *= r;
+        if constexpr (MUL) {
+            L.re[h] *= r;
+            L.im[h] *= r;
+        }
         if (PRUNE) {
             L.M[h] = L.M[h] * m;
             L.ok[h] = L.ok[h] && !(L.M[h] < thr);
@@ -651,6 +656,16 @@ __device__ __forceinline__ void op_branch_real_sign(Lanes<NW, H> &L, uint32_t sa
         const uint32_t i = SRC ? src_bit(L, h, ks) : (bin[A] >> sa) & 1u;
         L.sd[h] ^= (neg >> (((s0 >> sa) & 1u) * 2u + i)) & 1u;
         L.s[h][A] = (s0 & ~bit) | (i << sa);
+    });
+}
+
+// The region's real-entry magnitudes, one constant (op_branch_real, MUL
+// false).
+template <int NW, int H>
+__device__ __forceinline__ void scale_amp(Lanes<NW, H> &L, double r) {
+    unroll<H>([&](auto hh) {
+        L.re[hh.value] *= r;
+        L.im[hh.value] *= r;
     });
 }
 

@@ -102,6 +102,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
                                     "    uint32_t sg[H] = {}; (void)sg;\n", fac_lo);
     o += buf;
     bool signs = false;   // a real-entry branch collected a sign to apply at the end
+    double rmag = 1.0;    // and the product of their magnitudes, applied there too
     bool pending = false;
     uint32_t plo = 0, phi = 0;
     // ladder steps of the pending run whose selecting bit holds a source bit
@@ -183,11 +184,12 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         }
         if (fs.kind == FacShape::REAL) {
             std::snprintf(call, sizeof(call),
-                          "op_branch_real<NW, H, PRUNE, wsel<%d, NW>(), %s>(L, sg, %uu, I.k - kbase, bin, thr, "
+                          "op_branch_real<NW, H, PRUNE, wsel<%d, NW>(), %s, false>(L, sg, %uu, I.k - kbase, bin, thr, "
                           "%a, %uu, %a); if constexpr (PRUNE) { if (!wave_alive(L)) return; } }\n",
                           w1, base == OP_BRANCH_SRC ? "true" : "false", sa, fs.r, fs.neg, fs.m);
             o += call;
             signs = true;
+            rmag *= fs.r;
             continue;
         }
         switch (base) {
@@ -255,7 +257,13 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         }
     }
     flush();
-    if (signs) o += "    apply_signs<NW, H>(L, sg);\n";
+    if (signs) {
+        if (rmag != 1.0) {
+            std::snprintf(buf, sizeof(buf), "    scale_amp<NW, H>(L, %a);\n", rmag);
+            o += buf;
+        }
+        o += "    apply_signs<NW, H>(L, sg);\n";
+    }
 }
 
 }  // namespace

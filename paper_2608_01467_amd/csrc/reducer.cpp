@@ -505,6 +505,18 @@ fhs_status emit(int n, const std::vector<Gate> &gates, HostProgram &P,
         P.final_before[e + 1] = fin;
     }
     P.fac_begin[G] = static_cast<uint32_t>(P.fac.size());
+    // A branching gate whose four entries are real, nonzero and of one
+    // magnitude (H) multiplies every history by that magnitude: the product
+    // of those magnitudes over a region is one constant for every history,
+    // and per history only the entry's sign remains (no flops).
+    for (int e = 0; e < G; ++e) {
+        const int base = op_base(static_cast<uint8_t>(P.ins[e].hdr & 0xffu));
+        if ((base != OP_BRANCH_SRC && base != OP_BRANCH_NAT) || (P.ins[e].hdr >> 24)) continue;
+        const double *t = P.fac.data() + P.ins[e].fac;
+        bool real = t[0] != 0.0;
+        for (int x = 0; x < 4; ++x) real = real && t[2 * x + 1] == 0.0 && std::fabs(t[2 * x]) == std::fabs(t[0]);
+        if (real) P.fp_cost[e] = 0;
+    }
     if (plan) {
         P.src_eval = *plan_src;
         A = static_cast<int>(P.src_eval.size());
