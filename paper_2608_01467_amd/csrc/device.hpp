@@ -952,6 +952,8 @@ template <bool RUNS>
 struct Interp {
     static constexpr bool kDefer = false;   // factors are multiplied as the walk goes
     static constexpr int kUnroll = 1;       // suffix assignments per pass of the leaf loop
+    static constexpr int kSS = -1;          // lanes per root task: the launch's
+    static constexpr int kAs = -1;          // suffix sources: the program's
     // prefix region: the gates before the first depth-first source, and the
     // gates of depth-first level l (from its source up to the next level's)
     template <int NW, bool PRUNE>
@@ -1101,8 +1103,10 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     const uint32_t rmask = (1u << c.Ar) - 1u;
+    if constexpr (Regions::kSS >= 0) ss = static_cast<uint32_t>(Regions::kSS);   // compiled for it
     const uint32_t smask = (1u << ss) - 1u;
-    const uint64_t n_suffix = 1ull << (c.As - ss);   // suffix assignments per task
+    const uint32_t As = Regions::kAs >= 0 ? static_cast<uint32_t>(Regions::kAs) : c.As;
+    const uint64_t n_suffix = 1ull << (As - ss);   // suffix assignments per task
     const uint32_t sshift = c.Ap + c.Ar;
     const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
 

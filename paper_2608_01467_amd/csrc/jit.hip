@@ -272,7 +272,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                             uint32_t i2, uint32_t iG, uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2,
                             const Mask4 &fin_G, int NW, int H, bool prune, bool flds, uint32_t fac_lo,
                             bool prefix_ok, uint32_t iL, const std::vector<uint32_t> &src_dev, uint32_t Dp,
-                            bool pflds, uint32_t pfac_lo) {
+                            bool pflds, uint32_t pfac_lo, uint32_t ss) {
     std::vector<Deferred> none, deferred;
     std::string o;
     char buf[512];
@@ -333,6 +333,11 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // (the loop control and the skip of passes without a valid history are
     // paid once per pass); longer ones one at a time, keeping registers
     std::snprintf(buf, sizeof(buf), "static constexpr int kUnroll = %d;\n", iG - i2 <= 24u ? 8 : 1);
+    o += buf;
+    // the lanes per root task as a constant: the suffix sources below As - ss
+    // are then known to live in the leaf loop's wave-uniform counter
+    std::snprintf(buf, sizeof(buf), "static constexpr int kSS = %u;\nstatic constexpr int kAs = %u;\n", ss,
+                  static_cast<uint32_t>(src_dev.size()) - Ap - Ar);
     o += buf;
     // the final-bit masks as constants: fully checked words become one compare
     const Mask4 *fm[2] = {&fin_c2, &fin_rest};

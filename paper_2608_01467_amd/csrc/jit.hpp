@@ -49,7 +49,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                             uint32_t i2, uint32_t iG, uint32_t Ap, uint32_t Ar, const Mask4 &fin_c2,
                             const Mask4 &fin_G, int NW, int H, bool prune, bool flds, uint32_t fac_lo,
                             bool prefix_ok, uint32_t iL, const std::vector<uint32_t> &src_dev, uint32_t Dp,
-                            bool pflds, uint32_t pfac_lo);
+                            bool pflds, uint32_t pfac_lo, uint32_t ss);
 
 // Compile `src` for gfx950 and load it on the current device.  On failure
 // returns false and puts the compiler log in `log`.

@@ -75,6 +75,9 @@ struct Common {
     // work items a consumer workgroup claims from the queue at once (>= 1):
     // short items claimed one by one keep the queue's single counter busy
     uint32_t grab;
+    // log2 of the lanes that share one root task (the plan's; a compiled
+    // consumer is built for one value)
+    uint32_t ss;
 };
 
 #if !defined(__HIPCC_RTC__)

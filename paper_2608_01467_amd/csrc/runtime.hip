@@ -414,6 +414,7 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.n_aff = static_cast<uint32_t>(P.aff.size() / 9);
     cm.pair_aff = (ws && cm.n_aff) ? at<uint64_t>(ws, pl.off_pre_aff) : nullptr;
     cm.grab = c->grab_override ? c->grab_override : pl.grab;
+    cm.ss = pl.ss;
     return cm;
 }
 
@@ -457,19 +458,19 @@ bool consumer_job(const fhs_ctx *c, const Common &cm, uint32_t Dp, std::string &
     const bool prefix_ok = cm.i1 - cm.iL <= kMaxCompiledInstr;
     const bool pflds = cm.f_c1 - cm.f_L <= kMaxLdsFactors;
     const int NW = nw_of(c->prog);
-    char buf[160];
+    char buf[192];
     // the cut positions fix the final-bit masks (two cuts inside one folded
     // ladder share device indices but not masks); Dp fixes the prefix's
-    // depth-first levels
-    std::snprintf(buf, sizeof(buf), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d", cm.i1, cm.i2, cm.iG, cm.c1,
-                  cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0);
+    // depth-first levels; ss which suffix sources the leaf loop's counter holds
+    std::snprintf(buf, sizeof(buf), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d/%u", cm.i1, cm.i2, cm.iG, cm.c1,
+                  cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0, cm.ss);
     key = buf;
     shm = consume_lds_bytes(cm);
     if (src)
         *src = consumer_source(c->dev_ins, c->prog.fac, cm.i1, cm.i2, cm.iG, cm.Ap, cm.Ar,
                                c->prog.final_before[cm.c2], c->prog.final_before[cm.G], NW, c->ilp, prune,
                                flds, flds ? cm.f_c1 : 0u, prefix_ok, cm.iL, c->src_dev, Dp, pflds,
-                               pflds ? cm.f_L : 0u);
+                               pflds ? cm.f_L : 0u, cm.ss);
     return true;
 }
 
