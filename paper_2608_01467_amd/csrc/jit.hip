@@ -334,10 +334,16 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // paid once per pass); longer ones one at a time, keeping registers
     std::snprintf(buf, sizeof(buf), "static constexpr int kUnroll = %d;\n", iG - i2 <= 24u ? 8 : 1);
     o += buf;
-    // the lanes per root task as a constant: the suffix sources below As - ss
-    // are then known to live in the leaf loop's wave-uniform counter
-    std::snprintf(buf, sizeof(buf), "static constexpr int kSS = %u;\nstatic constexpr int kAs = %u;\n", ss,
-                  static_cast<uint32_t>(src_dev.size()) - Ap - Ar);
+    // with one lane per root task, every suffix source lives in the leaf
+    // loop's wave-uniform counter: built for that case as constants (with
+    // several lanes per root task the lanes' share of the suffix index stays
+    // a run-time value; combined with the counter, the compiler then
+    // evaluates the suffix's source-only work per lane and per leaf)
+    if (ss == 0)
+        std::snprintf(buf, sizeof(buf), "static constexpr int kSS = 0;\nstatic constexpr int kAs = %u;\n",
+                      static_cast<uint32_t>(src_dev.size()) - Ap - Ar);
+    else
+        std::snprintf(buf, sizeof(buf), "static constexpr int kSS = -1;\nstatic constexpr int kAs = -1;\n");
     o += buf;
     // the final-bit masks as constants: fully checked words become one compare
     const Mask4 *fm[2] = {&fin_c2, &fin_rest};

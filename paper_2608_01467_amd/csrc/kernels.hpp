@@ -76,7 +76,7 @@ struct Common {
     // short items claimed one by one keep the queue's single counter busy
     uint32_t grab;
     // log2 of the lanes that share one root task (the plan's; a compiled
-    // consumer is built for one value)
+    // consumer is built either for 0 or for any other value)
     uint32_t ss;
 };
 

@@ -461,9 +461,9 @@ bool consumer_job(const fhs_ctx *c, const Common &cm, uint32_t Dp, std::string &
     char buf[192];
     // the cut positions fix the final-bit masks (two cuts inside one folded
     // ladder share device indices but not masks); Dp fixes the prefix's
-    // depth-first levels; ss which suffix sources the leaf loop's counter holds
+    // depth-first levels; whether the leaf loop's counter holds every suffix source
     std::snprintf(buf, sizeof(buf), "%u/%u/%u/%u/%u/%u/%u/%u/%d/%d/%d/%d/%u", cm.i1, cm.i2, cm.iG, cm.c1,
-                  cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0, cm.ss);
+                  cm.c2, cm.Ap, cm.Ar, Dp, NW, c->ilp, prune ? 1 : 0, flds ? 1 : 0, cm.ss == 0 ? 0u : 1u);
     key = buf;
     shm = consume_lds_bytes(cm);
     if (src)
