@@ -613,6 +613,45 @@ def test_compiled_random_mixed(ctx, seed):
     ctx.set_launch_config(0, 0, 0, 0)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", [9112, 9128])
+def test_compiled_uniform_suffix(ctx, seed):
+    """Enough (pair, root) tasks that each lane holds its own root task:
+    every suffix source then lives in the leaf loop's wave-uniform counter
+    and the compiled consumer is built with that as a constant (scalar work
+    over the suffix sources, unrolled passes when the suffix is short, the
+    suffix instructions no suffix source influences once per root).  Random
+    layered circuits on 12 qubits, 2048 outputs, against the oracle, with and
+    without pruning, at splits with 2^8 or more root tasks per pair."""
+    c = _branchy(12, 5, seed)
+    t = c.to_text()
+    o = oracle.Feynman(t)
+    prog = fhs.Program(t)
+    assert prog.A == 12
+    src = list(prog.source_eval_positions)
+    outs = w.random_outputs(12, 2048, seed=seed)
+    # (Ap, Ar, As) = (9, 0, 3), (6, 3, 3), (6, 2, 4): 2^8 or more root tasks
+    # per pair; (3, 3, 6) shares each root task among several lanes
+    parts = [(src[8] + 1, src[9]), (src[5] + 1, src[9]), (src[5] + 1, src[8]), (src[2] + 1, src[5] + 1)]
+    ctx.load(prog)
+    uniform = 0
+    for part in parts:
+        ctx.set_launch_config(2, 0, 0, 3)
+        ctx.set_partition(*part)
+        plan = ctx.plan(len(outs), 1)
+        uniform += plan["lanes_per_root_task"] == 1
+    assert uniform == 3
+    for thr in (0.0, 0.02):
+        ref = o.evaluate([0], [1.0], outs, threshold=thr, threads=THREADS)
+        for h in (1, 2):
+            ctx.set_launch_config(h, 0, 0, 3)
+            for part in parts:
+                amps, st = gpu_eval(ctx, t, [0], [1.0], outs, thr=thr, partition=part, prog=prog)
+                assert np.abs(amps - ref[0]).max() <= TOL, (seed, thr, h, part)
+                assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (seed, thr, h, part)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 @pytest.mark.parametrize("case", ["fig2", "qft8", "qaoa6", "walk_xcoin", "aa3", "branchy1", "branchy3"])
 def test_forward_placement(ctx, case):
     """Sources placed by the forward sweep (FHS_REDUCE_FORWARD, Table I's
