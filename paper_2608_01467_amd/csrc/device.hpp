@@ -160,6 +160,7 @@ struct Lanes {
     uint64_t hq;
     uint32_t hu;
     uint32_t sd[H];     // bit 0: the sign of the deferred real factors' product so far
+    uint32_t ci[H];     // counted factors: the index into their tables (op_count_*)
 };
 
 // Source bit k of a region's index (hb, hq and hu hold disjoint bits).
@@ -680,6 +681,99 @@ __device__ __forceinline__ void apply_signs(Lanes<NW, H> &L, uint32_t (&sg)[H]) 
     });
 }
 
+// ---------------------------------------------------------------------------
+// Counted factors (the compiled consumer without pruning).  A gate whose
+// factor table takes two values, a where bit x of TT is clear and b where it
+// is set (x the table index the gate selects), belongs to the class of the
+// gates with that pair.  A history's product over a class's n gates is
+// a^(n-f) b^f, f the number of b entries it took: the history keeps f, as a
+// field of its index ci (a gate of the class moves it by the class's step
+// d), and the consumer multiplies in the tabulated product once, for the
+// histories that pass the final check.  The same amplitude up to rounding.
+// ---------------------------------------------------------------------------
+
+// Whether bit lo | hi << 1 of TT is set, for the truth tables of the common
+// gates written as the bit operation they are.
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t tt_sel(uint32_t lo, uint32_t hi) {
+    if constexpr (TT == 0x6u) return lo ^ hi;
+    else if constexpr (TT == 0x9u) return (lo ^ hi) ^ 1u;
+    else if constexpr (TT == 0x8u) return lo & hi;
+    else if constexpr (TT == 0x7u) return (lo & hi) ^ 1u;
+    else if constexpr (TT == 0xeu) return lo | hi;
+    else if constexpr (TT == 0x1u) return (lo | hi) ^ 1u;
+    else if constexpr (TT == 0xau) return lo;
+    else if constexpr (TT == 0x5u) return lo ^ 1u;
+    else if constexpr (TT == 0xcu) return hi;
+    else if constexpr (TT == 0x3u) return hi ^ 1u;
+    else return (TT >> (lo | (hi << 1))) & 1u;
+}
+
+// A diagonal gate (DIAG1: x = bit a; DIAG2: x = bit a | bit b << 1), counted.
+template <int NW, int H, int WA, int WB, uint32_t TT, bool TWO>
+__device__ __forceinline__ void op_count_diag(Lanes<NW, H> &L, uint32_t sa, uint32_t sb, uint32_t d) {
+    constexpr int A = wsel<WA, NW>(), B = wsel<WB, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t lo = (L.s[h][A] >> sa) & 1u;
+        const uint32_t hi = TWO ? (L.s[h][B] >> sb) & 1u : 0u;
+        L.ci[h] += tt_sel<TT>(lo, hi) * d;
+    });
+}
+
+// A deterministic one-qubit gate (x = bit a, then bit a flips), counted.
+template <int NW, int H, int WA, uint32_t TT>
+__device__ __forceinline__ void op_det1_count(Lanes<NW, H> &L, uint32_t sa, uint32_t d) {
+    constexpr int A = wsel<WA, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        L.ci[h] += tt_sel<TT>((L.s[h][A] >> sa) & 1u, 0u) * d;
+        L.s[h][A] ^= 1u << sa;
+    });
+}
+
+// A branching gate (x = 2o + i, o the state's bit a, i the source's or the
+// input's), counted; bit a becomes i.  No entry is zero.
+template <int NW, int H, int WA, bool SRC, uint32_t TT>
+__device__ __forceinline__ void op_branch_count(Lanes<NW, H> &L, uint32_t sa, uint32_t ks,
+                                                const uint32_t (&bin)[NW], uint32_t d) {
+    constexpr int A = wsel<WA, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t o = (L.s[h][A] >> sa) & 1u;
+        const uint32_t i = SRC ? src_bit(L, h, ks) : (bin[A] >> sa) & 1u;
+        L.ci[h] += tt_sel<TT>(i, o) * d;
+        L.s[h][A] ^= (o ^ i) << sa;
+    });
+}
+
+// Counted diagonal gates of one class on one state word with no state write
+// between them, grouped: b is taken where bit q and bit q + dist differ
+// (KIND 0), agree (1) or are both set (2), or, for one-bit gates, where bit
+// q is set (3) or clear (4); `mask` has bit q of each gate of the group, and
+// n[h] gains their number of b entries, a population count.
+template <int NW, int H, int W, int KIND>
+__device__ __forceinline__ void count_bits(const Lanes<NW, H> &L, uint32_t (&n)[H], uint32_t dist,
+                                           uint32_t mask) {
+    constexpr int A = wsel<W, NW>();
+    unroll<H>([&](auto hh) {
+        constexpr int h = hh.value;
+        const uint32_t s = L.s[h][A];
+        uint32_t y;
+        if constexpr (KIND == 0) y = s ^ (s >> dist);
+        else if constexpr (KIND == 1) y = ~(s ^ (s >> dist));
+        else if constexpr (KIND == 2) y = s & (s >> dist);
+        else if constexpr (KIND == 3) y = s;
+        else y = ~s;
+        n[h] += static_cast<uint32_t>(__popc(y & mask));
+    });
+}
+
+template <int NW, int H>
+__device__ __forceinline__ void count_take(Lanes<NW, H> &L, const uint32_t (&n)[H], uint32_t d) {
+    unroll<H>([&](auto hh) { L.ci[hh.value] += n[hh.value] * d; });
+}
+
 // Branching gate whose input bit is an affine form (sources placed by
 // reachability): the parity of the history index over the form's sources
 // (cm[0], cm[1]), xor the pair's boundary bit k of the form; otherwise as
@@ -972,6 +1066,11 @@ struct Interp {
     }
     template <int NW, int H>
     __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
+    // counted factors: none here (kNCT table entries)
+    static constexpr uint32_t kNCT = 0;
+    __device__ static __forceinline__ double2 count_entry(uint32_t) { return make_double2(0.0, 0.0); }
+    template <int NW, int H>
+    __device__ static __forceinline__ void count_amp(const double2 *, Lanes<NW, H> &, int) {}
     // suffix instructions evaluated once per root history: none here
     static constexpr bool kHoist = false;
     template <int NW, int H, bool PRUNE>
@@ -1091,6 +1190,10 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     __shared__ uint32_t l_hp[kMaxChunk];
     __shared__ uint32_t l_wcount[NT / 64];
     __shared__ Acc l_red[NT / 64];
+    // the counted factors' products (read before the first claim's barrier)
+    __shared__ double2 l_ct[Regions::kNCT > 0 ? Regions::kNCT : 1];
+    if constexpr (Regions::kNCT > 0)
+        for (uint32_t i = threadIdx.x; i < Regions::kNCT; i += NT) l_ct[i] = Regions::count_entry(i);
 
     FacRef F{c.fac, 0u};
     if constexpr (FLDS) {
@@ -1187,6 +1290,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 R.hb[j] = hr;
                 R.hf[j] = l_hp[jx];
                 R.sd[j] = 0;
+                R.ci[j] = 0;
                 hbase[j] = static_cast<uint64_t>(l_hp[jx]) | (static_cast<uint64_t>(hr) << c.Ap);
             });
             R.aff = paff;
@@ -1228,6 +1332,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                         // a policy that deferred the suffix's factors applies them
                         // now, for the histories that count
                         if constexpr (Regions::kDefer) Regions::template suffix_amp<NW, H>(F, S2, j);
+                        if constexpr (Regions::kNCT > 0) Regions::template count_amp<NW, H>(l_ct, S2, j);
                         const uint64_t h = hbase[j] | ((hs0[j] + q) << sshift);
                         acc.re += S2.re[j];
                         acc.im += S2.im[j];

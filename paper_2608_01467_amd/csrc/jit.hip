@@ -5,7 +5,9 @@
 #include <hip/hiprtc.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
+#include <cstring>
 
 #include "program.hpp"
 
@@ -92,12 +94,49 @@ FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
 // With `defer`, a real-entry branch (FacShape REAL) records only its sign
 // (op_branch_real_sign) and its magnitude joins *rdef, the product the valid
 // histories are multiplied by at the end (*rsign: some sign was recorded).
+// With a count plan, the gates it counts move the history's table index
+// instead of multiplying (diagonal ones of a class on one word grouped into
+// population counts until the next state write), and the real-entry
+// branches' magnitudes are left to the plan's table.
 void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vector<double> &fac,
                  uint32_t fac_lo, uint32_t kbase, uint32_t lo, uint32_t hi, bool defer,
                  std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr,
-                 double *rdef = nullptr, bool *rsign = nullptr, const std::vector<uint8_t> *omit = nullptr) {
+                 double *rdef = nullptr, bool *rsign = nullptr, const std::vector<uint8_t> *omit = nullptr,
+                 const CountPlan *cp = nullptr) {
     char buf[512];
     int off = 0;
+    // grouped counted diagonal gates not yet emitted: class, kind
+    // (count_bits), word, distance of the two bits, and the gates' low bits
+    struct CRun {
+        int cls, kind, word;
+        uint32_t dist, mask;
+    };
+    std::vector<CRun> crun;
+    auto add_run = [&](int cls, int kind, int word, uint32_t dist, uint32_t q) {
+        for (CRun &r : crun)
+            if (r.cls == cls && r.kind == kind && r.word == word && r.dist == dist && !((r.mask >> q) & 1u)) {
+                r.mask |= 1u << q;
+                return;
+            }
+        crun.push_back(CRun{cls, kind, word, dist, 1u << q});
+    };
+    auto flush_count = [&]() {
+        std::vector<uint8_t> done(crun.size(), 0);
+        for (size_t i = 0; i < crun.size(); ++i) {
+            if (done[i]) continue;
+            o += "    { uint32_t n[H] = {};";
+            for (size_t j = i; j < crun.size(); ++j) {
+                if (crun[j].cls != crun[i].cls) continue;
+                done[j] = 1;
+                std::snprintf(buf, sizeof(buf), " count_bits<NW, H, %d, %d>(L, n, %uu, 0x%08xu);", crun[j].word,
+                              crun[j].kind, crun[j].dist, crun[j].mask);
+                o += buf;
+            }
+            std::snprintf(buf, sizeof(buf), " count_take<NW, H>(L, n, %uu); }\n", cp->cls[crun[i].cls].step);
+            o += buf;
+        }
+        crun.clear();
+    };
     std::snprintf(buf, sizeof(buf), "    const FacRefC<%uu> Fc{F.p}; (void)Fc;\n"
                                     "    uint32_t sg[H] = {}; (void)sg;\n", fac_lo);
     o += buf;
@@ -134,6 +173,8 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         const int w1 = static_cast<int>((op >> 4) & 3u), w2 = static_cast<int>((op >> 6) & 3u);
         const bool is_add = base == OP_ADD || base == OP_ADDSEL;
         const uint32_t a = (I.hdr >> 8) & 0xffu, b = (I.hdr >> 16) & 0xffu;
+        // the grouped counted gates read the state as it is here
+        if (!crun.empty() && base != OP_DIAG1 && base != OP_DIAG2 && base != OP_MCPHASE) flush_count();
         if (pending && ends_field_run(I, plo, phi)) flush();
         const int sel_src = sbits.selector_source(I);
         sbits.step(I, kbase);
@@ -147,6 +188,35 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
             pending = true;
             plo = a;
             phi = a + b;
+            continue;
+        }
+        const int cc = cp ? cp->of(x) : -1;
+        if (cc >= 0) {
+            TwoValued tv = two_valued(I, fac);
+            tv.tt = cp->tt(cc, tv);
+            const uint32_t step = cp->cls[cc].step, sa = a & 31u, sb = b & 31u;
+            if (base == OP_DIAG1 && (tv.tt == 0x2u || tv.tt == 0x1u)) {
+                add_run(cc, tv.tt == 0x2u ? 3 : 4, w1, 0u, sa);
+            } else if (base == OP_DIAG2 && w1 == w2 && (tv.tt == 0x6u || tv.tt == 0x9u || tv.tt == 0x8u)) {
+                add_run(cc, tv.tt == 0x6u ? 0 : (tv.tt == 0x9u ? 1 : 2), w1, sa > sb ? sa - sb : sb - sa,
+                        sa < sb ? sa : sb);
+            } else if (base == OP_DIAG1 || base == OP_DIAG2) {
+                std::snprintf(buf, sizeof(buf),
+                              "    op_count_diag<NW, H, wsel<%d, NW>(), wsel<%d, NW>(), 0x%xu, %s>(L, %uu, %uu, %uu);\n",
+                              w1, base == OP_DIAG2 ? w2 : w1, tv.tt, base == OP_DIAG2 ? "true" : "false", sa,
+                              base == OP_DIAG2 ? sb : 0u, step);
+                o += buf;
+            } else if (base == OP_DET1) {
+                std::snprintf(buf, sizeof(buf), "    op_det1_count<NW, H, wsel<%d, NW>(), 0x%xu>(L, %uu, %uu);\n", w1,
+                              tv.tt, sa, step);
+                o += buf;
+            } else {
+                std::snprintf(buf, sizeof(buf),
+                              "    op_branch_count<NW, H, wsel<%d, NW>(), %s, 0x%xu>(L, %uu, %uu, bin, %uu);\n", w1,
+                              base == OP_BRANCH_SRC ? "true" : "false", tv.tt, sa,
+                              base == OP_BRANCH_SRC ? I.k - kbase : 0u, step);
+                o += buf;
+            }
             continue;
         }
         std::snprintf(buf, sizeof(buf),
@@ -243,6 +313,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
             phi = a + b;
         }
     }
+    flush_count();
     if (pending && check) {
         Mask4 fm{{0u, 0u, 0u, 0u}};
         for (uint32_t q = plo; q < phi; ++q) fm.w[q >> 5] |= 1u << (q & 31u);
@@ -258,7 +329,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
     }
     flush();
     if (signs) {
-        if (rmag != 1.0) {
+        if (rmag != 1.0 && !cp) {
             std::snprintf(buf, sizeof(buf), "    scale_amp<NW, H>(L, %a);\n", rmag);
             o += buf;
         }
@@ -290,7 +361,12 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
         keep[x] = hoist[x] ? 0 : 1;
         any_hoist = any_hoist || hoist[x];
     }
-    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked, nullptr, nullptr, &hoist);
+    // two-valued factors counted instead of multiplied (without pruning: the
+    // moduli are then never needed as the walk goes)
+    CountPlan cplan;
+    if (!prune) cplan = count_plan(dev, fac, i1, i2, iG, hoist);
+    const CountPlan *cp = cplan.on() ? &cplan : nullptr;
+    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked, nullptr, nullptr, &hoist, cp);
     Mask4 natw{{0u, 0u, 0u, 0u}};
     bool zero_entries = false;
     for (uint32_t x = i2; x < iG; ++x) {
@@ -317,17 +393,82 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // (real-entry branches defer only a sign and a constant magnitude)
     int bits = 0;
     for (uint32_t x = i2; x < iG; ++x)
-        if (!hoist[x - i2] && fac_shape(dev[x], fac).kind != FacShape::REAL)
+        if (!hoist[x - i2] && fac_shape(dev[x], fac).kind != FacShape::REAL && (!cp || cp->of(x) < 0))
             bits += factor_bits(op_base(dev[x].hdr & 0xffu));
     const bool defer = !prune && bits <= 64 && (check_left || zero_entries);
     double rdef = 1.0;
     bool rsign = false;
     if (defer) {
         sfx.clear();
-        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign, &hoist);
+        emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign, &hoist,
+                    cp);
     }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
+    std::vector<double> ctab;
+    if (cp) {
+        // the counted classes' products, group by group; the first group
+        // also carries the real-entry branches' magnitudes of the regions
+        long double rtotal = 1.0L;
+        for (uint32_t x = i1; x < iG; ++x) {
+            const FacShape f = fac_shape(dev[x], fac);
+            if (f.kind == FacShape::REAL) rtotal *= f.r;
+        }
+        for (size_t g = 0; g < cp->group_size.size(); ++g) {
+            for (uint32_t i = 0; i < cp->group_size[g]; ++i) {
+                std::complex<long double> v = g == 0 ? std::complex<long double>(rtotal, 0.0L)
+                                                     : std::complex<long double>(1.0L, 0.0L);
+                for (const CountPlan::Cls &c : cp->cls) {
+                    if (c.group != g) continue;
+                    const uint32_t f = (i / c.stride) % (c.n + 1u);
+                    double ab[4];
+                    std::memcpy(ab, c.v.a, sizeof c.v.a);
+                    std::memcpy(ab + 2, c.v.b, sizeof c.v.b);
+                    const std::complex<long double> a(ab[0], ab[1]), b(ab[2], ab[3]);
+                    for (uint32_t k = 0; k < c.n - f; ++k) v *= a;
+                    for (uint32_t k = 0; k < f; ++k) v *= b;
+                }
+                ctab.push_back(static_cast<double>(v.real()));
+                ctab.push_back(static_cast<double>(v.imag()));
+            }
+        }
+        std::snprintf(buf, sizeof(buf), "__constant__ double kCountTab[%zu] = {", ctab.size());
+        o += buf;
+        for (size_t i = 0; i < ctab.size(); ++i) {
+            std::snprintf(buf, sizeof(buf), "%s%a", i ? ", " : "", ctab[i]);
+            o += buf;
+        }
+        o += "};\n";
+    }
     o += "struct Compiled {\n";
+    if (cp) {
+        std::snprintf(buf, sizeof(buf),
+                      "static constexpr uint32_t kNCT = %uu;\n"
+                      "__device__ static __forceinline__ double2 count_entry(uint32_t i) "
+                      "{ return make_double2(kCountTab[2u * i], kCountTab[2u * i + 1u]); }\n"
+                      "template <int NW, int H>\n"
+                      "__device__ static __forceinline__ void count_amp(const double2 *T, Lanes<NW, H> &L, int h) {\n",
+                      cp->entries);
+        o += buf;
+        const bool one = cp->group_size.size() == 1;
+        for (size_t g = 0; g < cp->group_size.size(); ++g) {
+            const uint32_t width = (g + 1 < cp->group_shift.size() ? cp->group_shift[g + 1] : 32u) - cp->group_shift[g];
+            if (one)
+                std::snprintf(buf, sizeof(buf), "    { const double2 f = T[L.ci[h]]; cmul(L.re[h], L.im[h], f.x, f.y); }\n");
+            else
+                std::snprintf(buf, sizeof(buf),
+                              "    { const double2 f = T[%uu + ((L.ci[h] >> %uu) & 0x%xu)]; "
+                              "cmul(L.re[h], L.im[h], f.x, f.y); }\n",
+                              cp->group_base[g], cp->group_shift[g],
+                              width >= 32u ? 0xffffffffu : (1u << width) - 1u);
+            o += buf;
+        }
+        o += "}\n";
+    } else {
+        o += "static constexpr uint32_t kNCT = 0;\n"
+             "__device__ static __forceinline__ double2 count_entry(uint32_t) { return make_double2(0.0, 0.0); }\n"
+             "template <int NW, int H>\n"
+             "__device__ static __forceinline__ void count_amp(const double2 *, Lanes<NW, H> &, int) {}\n";
+    }
     o += defer ? "static constexpr bool kDefer = true;\n" : "static constexpr bool kDefer = false;\n";
     // a short suffix walks several assignments per pass of the leaf loop
     // (the loop control and the skip of passes without a valid history are
@@ -366,7 +507,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   "    int32_t pk[H] = {}, pb[H] = {}, pbq = 0; (void)pk; (void)pb; (void)pbq;\n",
                   Ap);
     o += buf;
-    emit_region(o, dev, fac, fac_lo, Ap, i1, i2, false, none);
+    emit_region(o, dev, fac, fac_lo, Ap, i1, i2, false, none, nullptr, nullptr, nullptr, nullptr, nullptr, cp);
     o += "}\n";
     std::snprintf(buf, sizeof(buf),
                   "template <int NW, int H, bool PRUNE>\n"
@@ -388,7 +529,7 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                   any_hoist ? "true" : "false", Ap + Ar);
     o += buf;
     if (any_hoist) emit_region(o, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, nullptr, nullptr, nullptr, nullptr,
-                               &keep);
+                               &keep, cp);
     o += "}\n";
     // the deferred factors, in evaluation order: the same products as the walk
     o += "template <int NW, int H>\n"
@@ -403,7 +544,11 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                       d.off, (1u << d.bits) - 1u, d.fac);
         o += buf;
     }
-    if (rsign) {
+    if (rsign && cp) {
+        // the real-entry branches' signs (their magnitudes are in the count table)
+        o += "    { const uint32_t f = (L.sd[h] & 1u) << 31; "
+             "L.re[h] = flip_sign(L.re[h], f); L.im[h] = flip_sign(L.im[h], f); }\n";
+    } else if (rsign) {
         // the real-entry branches' magnitudes (one constant) and signs
         std::snprintf(buf, sizeof(buf),
                       "    { const uint32_t f = (L.sd[h] & 1u) << 31; "

@@ -18,6 +18,9 @@
 
 #include <cstdint>
 #if !defined(__HIPCC_RTC__)
+#include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 #endif
@@ -208,6 +211,203 @@ inline std::vector<uint8_t> hoistable(const std::vector<Instr> &ins, uint32_t lo
         }
     }
     return out;
+}
+
+// A gate whose factor table takes exactly two values, a at the table
+// indices x where bit x of tt is clear and b where it is set ((a, b) as bit
+// patterns of (re, im), in a fixed order so that the same pair is one
+// class): phases, diagonal two-qubit gates with two distinct entries (RZZ,
+// CZ), branching gates such as RX whose diagonal and off-diagonal entries
+// agree.  Branching gates with a zero entry (their histories can fail) and
+// real-entry branches of one magnitude (H: a sign per history, collected
+// separately) are not counted.
+struct TwoValued {
+    bool ok = false;
+    uint64_t a[2] = {0, 0}, b[2] = {0, 0};
+    uint32_t tt = 0;
+    uint32_t nx = 0;    // table entries: 2 (one selecting bit) or 4
+};
+
+inline TwoValued two_valued(const Instr &I, const std::vector<double> &fac) {
+    TwoValued r;
+    const int base = op_base(static_cast<uint8_t>(I.hdr & 0xffu));
+    const bool branch = base == OP_BRANCH_SRC || base == OP_BRANCH_NAT;
+    if (base == OP_DIAG1 || base == OP_DET1) r.nx = 2;
+    else if (base == OP_DIAG2 || branch) r.nx = 4;
+    else return r;
+    if (branch && (I.hdr >> 24) != 0u) return r;
+    const double *t = fac.data() + I.fac;
+    if (branch) {
+        bool real = t[0] != 0.0;
+        for (int x = 0; x < 4; ++x) real = real && t[2 * x + 1] == 0.0 && std::fabs(t[2 * x]) == std::fabs(t[0]);
+        if (real) return r;
+    }
+    auto pat = [&](uint32_t x, uint64_t (&v)[2]) { std::memcpy(v, t + 2 * x, sizeof v); };
+    uint64_t v0[2], v1[2] = {0, 0};
+    pat(0, v0);
+    bool second = false;
+    uint32_t tt = 0;
+    for (uint32_t x = 1; x < r.nx; ++x) {
+        uint64_t v[2];
+        pat(x, v);
+        if (v[0] == v0[0] && v[1] == v0[1]) continue;
+        if (!second) {
+            v1[0] = v[0];
+            v1[1] = v[1];
+            second = true;
+        } else if (v[0] != v1[0] || v[1] != v1[1]) {
+            return r;   // three or more values
+        }
+        tt |= 1u << x;
+    }
+    if (!second) return r;   // one value: no selection
+    if (v0[0] > v1[0] || (v0[0] == v1[0] && v0[1] > v1[1])) {
+        std::swap(v0[0], v1[0]);
+        std::swap(v0[1], v1[1]);
+        tt = ~tt & ((1u << r.nx) - 1u);
+    }
+    r.ok = true;
+    r.a[0] = v0[0];
+    r.a[1] = v0[1];
+    r.b[0] = v1[0];
+    r.b[1] = v1[1];
+    r.tt = tt;
+    return r;
+}
+
+// Table sizes of the counted factors: entries of one group's table and of
+// all groups' (16 bytes each, staged in LDS), and groups, i.e. table
+// multiplies per valid history.
+constexpr uint32_t kCountGroupMax = 1024;
+constexpr uint32_t kCountTabMax = 1024;
+constexpr uint32_t kCountGroups = 3;
+
+// Which two-valued gates of the consumer's regions (root [i1, i2), suffix
+// [i2, iG); `hoisted[x - i2]` marks the suffix instructions evaluated once
+// per root) the compiled consumer counts instead of multiplying.  A class is
+// the gates with one pair (a, b); its n gates give a history the product
+// a^(n-f) b^f, f the number of b entries taken.  Classes share a group's
+// table (the products over every combination of their f) while it stays
+// within kCountGroupMax entries; a history's index `ci` holds each group's
+// index in a bit field, and a class's gate moves it by its step.  Counting is
+// on only when a class has a gate in the leaf loop (else the table multiply
+// per valid history would cost more than the root's multiplies it saves)
+// and every class fits.
+struct CountPlan {
+    struct Cls {
+        TwoValued v;       // the pair as the class counts it: f = the number of b entries
+        uint32_t n = 0;
+        bool leaf = false;
+        bool flip = false; // the gates' own tt (two_valued) complemented
+        uint32_t group = 0, stride = 0, step = 0;
+    };
+    std::vector<Cls> cls;
+    std::vector<int> cls_of;                    // per instruction of [lo, hi): class or -1
+    std::vector<uint32_t> group_size, group_base, group_shift;
+    uint32_t lo = 0, entries = 0;
+    bool on() const { return entries > 0; }
+    int of(uint32_t x) const {
+        return (on() && x >= lo && x - lo < cls_of.size()) ? cls_of[x - lo] : -1;
+    }
+    // the truth table gate `v` (of class c) selects b with
+    uint32_t tt(int c, const TwoValued &v) const {
+        return cls[c].flip ? ~v.tt & ((1u << v.nx) - 1u) : v.tt;
+    }
+};
+
+inline CountPlan count_plan(const std::vector<Instr> &ins, const std::vector<double> &fac, uint32_t i1,
+                            uint32_t i2, uint32_t iG, const std::vector<uint8_t> &hoisted) {
+    CountPlan P;
+    P.lo = i1;
+    P.cls_of.assign(iG > i1 ? iG - i1 : 0, -1);
+    bool any_leaf = false;
+    for (uint32_t x = i1; x < iG; ++x) {
+        const TwoValued v = two_valued(ins[x], fac);
+        if (!v.ok) continue;
+        int c = -1;
+        for (size_t k = 0; k < P.cls.size() && c < 0; ++k) {
+            const TwoValued &u = P.cls[k].v;
+            if (u.a[0] == v.a[0] && u.a[1] == v.a[1] && u.b[0] == v.b[0] && u.b[1] == v.b[1])
+                c = static_cast<int>(k);
+        }
+        if (c < 0) {
+            c = static_cast<int>(P.cls.size());
+            P.cls.push_back(CountPlan::Cls{});
+            P.cls.back().v = v;
+        }
+        P.cls_of[x - i1] = c;
+        P.cls[c].n += 1;
+        if (x >= i2 && (x - i2 >= hoisted.size() || !hoisted[x - i2])) {
+            P.cls[c].leaf = true;
+            any_leaf = true;
+        }
+    }
+    CountPlan off;
+    off.lo = i1;
+    if (!any_leaf) return off;
+    // count the entry the cheaper form selects (bits that differ, a bit that
+    // is set, both set) where most of a class's gates then have that form
+    {
+        std::vector<int> vote(P.cls.size(), 0);
+        for (uint32_t x = i1; x < iG; ++x) {
+            const int c = P.cls_of[x - i1];
+            if (c < 0) continue;
+            const uint32_t t = two_valued(ins[x], fac).tt;
+            if (t == 0x9u || t == 0x1u || t == 0x7u) vote[c] += 1;
+            else if (t == 0x6u || t == 0x2u || t == 0x8u) vote[c] -= 1;
+        }
+        for (size_t k = 0; k < P.cls.size(); ++k)
+            if (vote[k] > 0) {
+                CountPlan::Cls &c = P.cls[k];
+                c.flip = true;
+                std::swap(c.v.a[0], c.v.b[0]);
+                std::swap(c.v.a[1], c.v.b[1]);
+            }
+    }
+    // leaf classes first, then by size
+    std::vector<uint32_t> order(P.cls.size());
+    for (uint32_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        if (P.cls[x].leaf != P.cls[y].leaf) return P.cls[x].leaf;
+        return P.cls[x].n > P.cls[y].n;
+    });
+    uint64_t total = 0;
+    for (uint32_t k : order) {
+        CountPlan::Cls &c = P.cls[k];
+        const uint64_t m = static_cast<uint64_t>(c.n) + 1u;
+        bool placed = false;
+        for (size_t g = 0; g < P.group_size.size() && !placed; ++g) {
+            const uint64_t s = P.group_size[g];
+            if (s * m <= kCountGroupMax && total + s * (m - 1u) <= kCountTabMax) {
+                c.group = static_cast<uint32_t>(g);
+                c.stride = static_cast<uint32_t>(s);
+                P.group_size[g] = static_cast<uint32_t>(s * m);
+                total += s * (m - 1u);
+                placed = true;
+            }
+        }
+        if (!placed && P.group_size.size() < kCountGroups && m <= kCountGroupMax && total + m <= kCountTabMax) {
+            c.group = static_cast<uint32_t>(P.group_size.size());
+            c.stride = 1u;
+            P.group_size.push_back(static_cast<uint32_t>(m));
+            total += m;
+            placed = true;
+        }
+        if (!placed) return off;
+    }
+    uint32_t base = 0, shift = 0;
+    for (uint32_t s : P.group_size) {
+        P.group_base.push_back(base);
+        P.group_shift.push_back(shift);
+        base += s;
+        uint32_t bits = 0;
+        while ((1u << bits) < s) ++bits;
+        shift += bits;
+    }
+    if (shift > 32u) return off;
+    for (CountPlan::Cls &c : P.cls) c.step = c.stride << P.group_shift[c.group];
+    P.entries = base;
+    return P;
 }
 
 // Whether `I` ends a pending accumulation of ladder steps on the field
