@@ -446,8 +446,23 @@ def main() -> int:
     h_int = suffix["hoist_int_ops"] if hoist else 0
     h_fp = suffix["hoist_fp64_flops"] if hoist else 0
     suffix_leaf_int = suffix["int_ops"] - suffix["src_int_ops"] - h_int
-    int_ops = (n_root * (root["int_ops"] + h_int) + leaves * suffix_leaf_int) / launches
-    flops = (n_root * (root["fp64_flops"] + h_fp) + valid * (suffix["fp64_flops"] - h_fp)) / launches
+    root_int, root_fp = root["int_ops"], root["fp64_flops"]
+    suffix_valid_fp = suffix["fp64_flops"] - h_fp
+    # Two-valued factors the compiled consumer counts instead of multiplying
+    # (same condition): their integer steps join the int32 work, their
+    # multiplies leave the FP64 work, and each valid history takes one
+    # complex multiply per table group.
+    groups = plan["count_groups"] if hoist else 0
+    if groups:
+        root_int += root["count_int_ops"]
+        root_fp -= root["count_fp64_flops"]
+        h_int += suffix["hoist_count_int_ops"]
+        h_fp -= suffix["hoist_count_fp64_flops"]
+        suffix_leaf_int += suffix["count_int_ops"] - suffix["hoist_count_int_ops"]
+        suffix_valid_fp -= suffix["count_fp64_flops"] - suffix["hoist_count_fp64_flops"]
+        suffix_valid_fp += 6 * groups
+    int_ops = (n_root * (root_int + h_int) + leaves * suffix_leaf_int) / launches
+    flops = (n_root * (root_fp + h_fp) + valid * suffix_valid_fp) / launches
     avg_launch = sum(kt) / len(kt) / 1e3
     int_rate = int_ops / avg_launch
     fp_rate = flops / avg_launch
@@ -484,7 +499,11 @@ def main() -> int:
                     "suffix_src_int_ops": suffix["src_int_ops"],
                     "suffix_hoisted_int_ops": h_int, "suffix_hoisted_fp64_flops": h_fp,
                     "root_fp64_flops": root["fp64_flops"],
-                    "suffix_fp64_flops": suffix["fp64_flops"]}
+                    "suffix_fp64_flops": suffix["fp64_flops"],
+                    "count_groups": groups, "count_entries": plan["count_entries"] if groups else 0,
+                    "root_count_int_ops": root["count_int_ops"], "root_count_fp64_flops": root["count_fp64_flops"],
+                    "suffix_count_int_ops": suffix["count_int_ops"],
+                    "suffix_count_fp64_flops": suffix["count_fp64_flops"]}
     roof["ms_per_step_timed"] = T_timed * 1e3
     roof["fp64_tflops"] = fp_rate / 1e12
     roof["int32_tops"] = int_rate / 1e12

@@ -206,6 +206,18 @@ typedef struct {
                                no source of the range influences and that
                                commute with the instructions before them */
     uint64_t hoist_fp64_flops;
+    uint64_t count_int_ops; /* taken as regions of the compiled consumer without
+                               pruning whose plan counts two-valued factors
+                               (fhs_plan.count_groups > 0): the int32 ops the
+                               range's two-valued gates add in their counted
+                               form (the step into the history's table index:
+                               1 for a diagonal or deterministic gate, 2 for a
+                               branching gate, whose selecting bit is then
+                               formed too) and the fp64_flops they no longer
+                               take; the hoisted part of each below */
+    uint64_t count_fp64_flops;
+    uint64_t hoist_count_int_ops;
+    uint64_t hoist_count_fp64_flops;
 } fhs_work;
 
 fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uint32_t e1, fhs_work *out);
@@ -356,6 +368,11 @@ typedef struct {
     uint64_t table_bytes;          /* prefix-table bytes per batch */
     uint32_t prefix_depth_first;   /* prefix sources enumerated depth first inside a lane */
     uint32_t items_per_claim;      /* work items a consumer workgroup takes from the queue at once */
+    uint32_t count_groups;         /* the compiled consumer without pruning: table multiplies per
+                                      valid history of the counted two-valued factors (0: none
+                                      counted; on only when a class has a gate in the leaf loop and
+                                      every class fits the tables) */
+    uint32_t count_entries;        /* their tables' entries (16 bytes each, in LDS) */
 } fhs_plan;
 
 fhs_status fhs_get_plan(const fhs_ctx *ctx, uint32_t M, uint32_t S, fhs_plan *plan);

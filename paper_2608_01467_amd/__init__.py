@@ -69,14 +69,17 @@ class Work(ctypes.Structure):
     _fields_ = [("gates", ctypes.c_uint64), ("int_ops", ctypes.c_uint64),
                 ("fp64_flops", ctypes.c_uint64), ("branch", ctypes.c_uint64),
                 ("src_int_ops", ctypes.c_uint64), ("hoist_int_ops", ctypes.c_uint64),
-                ("hoist_fp64_flops", ctypes.c_uint64)]
+                ("hoist_fp64_flops", ctypes.c_uint64), ("count_int_ops", ctypes.c_uint64),
+                ("count_fp64_flops", ctypes.c_uint64), ("hoist_count_int_ops", ctypes.c_uint64),
+                ("hoist_count_fp64_flops", ctypes.c_uint64)]
 
 
 class Plan(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
         "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)] + [
-        ("prefix_depth_first", ctypes.c_uint32), ("items_per_claim", ctypes.c_uint32)]
+        ("prefix_depth_first", ctypes.c_uint32), ("items_per_claim", ctypes.c_uint32),
+        ("count_groups", ctypes.c_uint32), ("count_entries", ctypes.c_uint32)]
 
 
 class MlpShape(ctypes.Structure):
@@ -216,9 +219,7 @@ class Program:
         """Algorithmic work of evaluation positions [e0, e1) per history."""
         w = Work()
         _check(lib().fhs_program_work(self._h, e0, e1, ctypes.byref(w)))
-        return dict(gates=w.gates, int_ops=w.int_ops, fp64_flops=w.fp64_flops, branch=w.branch,
-                    src_int_ops=w.src_int_ops, hoist_int_ops=w.hoist_int_ops,
-                    hoist_fp64_flops=w.hoist_fp64_flops)
+        return {k: getattr(w, k) for k, _ in Work._fields_}
 
     def split_features(self, c1: int, c2: int, M: int, S: int) -> np.ndarray:
         out = (ctypes.c_double * N_FEATURES)()

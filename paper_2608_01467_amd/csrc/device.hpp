@@ -46,11 +46,17 @@ __device__ __forceinline__ T ld_const(const T *p, size_t i) {
     return ((Const<T> *)p)[i];
 }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    // SplitMix64 finaliser (Steele, Lea, Flood 2014)
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+// SplitMix64 finaliser (Steele, Lea, Flood 2014): mix64_tail after the
+// first multiply.  For z < 2^30 the first shift-xor leaves z unchanged, so
+// the first product is linear in z: the consumer forms it per root history
+// plus a wave-uniform part per leaf.
+constexpr uint64_t kMixC1 = 0xbf58476d1ce4e5b9ULL, kMixC2 = 0x94d049bb133111ebULL;
+__device__ __forceinline__ uint64_t mix64_tail(uint64_t z) {
+    z = (z ^ (z >> 27)) * kMixC2;
     return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    return mix64_tail((z ^ (z >> 30)) * kMixC1);
 }
 
 // State words are only ever indexed with compile-time constants (the word
@@ -769,6 +775,14 @@ __device__ __forceinline__ void count_bits(const Lanes<NW, H> &L, uint32_t (&n)[
     });
 }
 
+// A pure leaf's amplitude is +-1 (its signs) when its counted product is
+// taken: the product with that sign replaces it.
+__device__ __forceinline__ void count_set(double &re, double &im, double2 f) {
+    const uint32_t s = static_cast<uint32_t>(__builtin_bit_cast(uint64_t, re) >> 32) & 0x80000000u;
+    re = flip_sign(f.x, s);
+    im = flip_sign(f.y, s);
+}
+
 template <int NW, int H>
 __device__ __forceinline__ void count_take(Lanes<NW, H> &L, const uint32_t (&n)[H], uint32_t d) {
     unroll<H>([&](auto hh) { L.ci[hh.value] += n[hh.value] * d; });
@@ -1048,6 +1062,7 @@ struct Interp {
     static constexpr int kUnroll = 1;       // suffix assignments per pass of the leaf loop
     static constexpr int kSS = -1;          // lanes per root task: the launch's
     static constexpr int kAs = -1;          // suffix sources: the program's
+    static constexpr int kA = -1;           // sources: the program's
     // prefix region: the gates before the first depth-first source, and the
     // gates of depth-first level l (from its source up to the next level's)
     template <int NW, bool PRUNE>
@@ -1066,8 +1081,10 @@ struct Interp {
     }
     template <int NW, int H>
     __device__ static __forceinline__ void suffix_amp(const FacRef &, Lanes<NW, H> &, int) {}
-    // counted factors: none here (kNCT table entries)
+    // counted factors: none here (kNCT table entries; kLeafPure: the leaf
+    // loop multiplies no factor but the counted ones and signs)
     static constexpr uint32_t kNCT = 0;
+    static constexpr bool kLeafPure = false;
     __device__ static __forceinline__ double2 count_entry(uint32_t) { return make_double2(0.0, 0.0); }
     template <int NW, int H>
     __device__ static __forceinline__ void count_amp(const double2 *, Lanes<NW, H> &, int) {}
@@ -1211,6 +1228,9 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     const uint32_t As = Regions::kAs >= 0 ? static_cast<uint32_t>(Regions::kAs) : c.As;
     const uint64_t n_suffix = 1ull << (As - ss);   // suffix assignments per task
     const uint32_t sshift = c.Ap + c.Ar;
+    // history indices below 2^30: the valid-set hash's first product split
+    // into a per-root and a per-leaf part (mix64)
+    const bool small_h = Regions::kA >= 0 ? Regions::kA <= 30 : sshift + As <= 30u;
     const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
 
     const uint32_t grab = c.grab > 0u ? c.grab : 1u;
@@ -1306,6 +1326,28 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             if (!__any(any)) continue;   // wave-uniform skip
             // every suffix assignment of a consistent root is a leaf walked
             unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n_suffix : 0u; });
+            // a pure leaf loop starts each leaf from amplitude +1: a leaf's
+            // value is then its sign times its counted product, and the
+            // root's amplitude multiplies their sum once
+            double ar[H], ai[H], sre[H], sim[H];
+            if constexpr (Regions::kLeafPure) {
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    ar[j] = R.re[j];
+                    ai[j] = R.im[j];
+                    R.re[j] = 1.0;
+                    R.im[j] = 0.0;
+                    sre[j] = sim[j] = 0.0;
+                });
+            }
+            uint64_t hm[H];   // the root's part of the hash's first product
+            unroll<H>([&](auto jj) {
+                constexpr int j = jj.value;
+                hm[j] = small_h ? (hbase[j] + (hs0[j] << sshift)) * kMixC1 : 0u;
+                // opaque to the compiler, which would otherwise fold the two
+                // parts back into one product per leaf
+                asm volatile("" : "+v"(hm[j]));
+            });
             // the suffix instructions no suffix source influences, once per root
             if constexpr (Regions::kHoist) Regions::template suffix_pre<NW, H, PRUNE>(c, F, R, bin);
             // one leaf: the suffix region for assignment q (wave-uniform: the
@@ -1334,11 +1376,17 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                         if constexpr (Regions::kDefer) Regions::template suffix_amp<NW, H>(F, S2, j);
                         if constexpr (Regions::kNCT > 0) Regions::template count_amp<NW, H>(l_ct, S2, j);
                         const uint64_t h = hbase[j] | ((hs0[j] + q) << sshift);
-                        acc.re += S2.re[j];
-                        acc.im += S2.im[j];
+                        if constexpr (Regions::kLeafPure) {
+                            sre[j] += S2.re[j];
+                            sim[j] += S2.im[j];
+                        } else {
+                            acc.re += S2.re[j];
+                            acc.im += S2.im[j];
+                        }
                         acc.nval += 1;
                         acc.sumh += h;
-                        acc.xorh ^= mix64(h);
+                        if (small_h) acc.xorh ^= mix64_tail(hm[j] + (q << sshift) * kMixC1);
+                        else acc.xorh ^= mix64(h);
                     }
                 });
             };
@@ -1364,6 +1412,13 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 Lanes<NW, H> S2 = R;
                 walk_leaf(S2, q, 0u);
                 count_leaf(S2, q);
+            }
+            if constexpr (Regions::kLeafPure) {
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    acc.re += fma(ar[j], sre[j], -(ai[j] * sim[j]));
+                    acc.im += fma(ar[j], sim[j], ai[j] * sre[j]);
+                });
             }
         }
         block_reduce_store<NT>(acc, l_red, part, item);

@@ -440,31 +440,42 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
         o += "};\n";
     }
     o += "struct Compiled {\n";
+    // a pure leaf loop: every factor its instructions take is counted or a
+    // sign (real-entry branches, MCPHASE), and none is deferred
+    bool pure = cp != nullptr && deferred.empty();
+    for (uint32_t x = i2; x < iG && pure; ++x) {
+        if (hoist[x - i2] || cp->of(x) >= 0) continue;
+        const int base = op_base(dev[x].hdr & 0xffu);
+        const bool factor = factor_bits(base) > 0;
+        if (factor && fac_shape(dev[x], fac).kind != FacShape::REAL) pure = false;
+    }
     if (cp) {
         std::snprintf(buf, sizeof(buf),
                       "static constexpr uint32_t kNCT = %uu;\n"
+                      "static constexpr bool kLeafPure = %s;\n"
                       "__device__ static __forceinline__ double2 count_entry(uint32_t i) "
                       "{ return make_double2(kCountTab[2u * i], kCountTab[2u * i + 1u]); }\n"
                       "template <int NW, int H>\n"
                       "__device__ static __forceinline__ void count_amp(const double2 *T, Lanes<NW, H> &L, int h) {\n",
-                      cp->entries);
+                      cp->entries, pure ? "true" : "false");
         o += buf;
         const bool one = cp->group_size.size() == 1;
         for (size_t g = 0; g < cp->group_size.size(); ++g) {
             const uint32_t width = (g + 1 < cp->group_shift.size() ? cp->group_shift[g + 1] : 32u) - cp->group_shift[g];
+            // a pure leaf's first product replaces its amplitude (+-1)
+            const char *take = (pure && g == 0) ? "count_set(L.re[h], L.im[h], f)" : "cmul(L.re[h], L.im[h], f.x, f.y)";
             if (one)
-                std::snprintf(buf, sizeof(buf), "    { const double2 f = T[L.ci[h]]; cmul(L.re[h], L.im[h], f.x, f.y); }\n");
+                std::snprintf(buf, sizeof(buf), "    { const double2 f = T[L.ci[h]]; %s; }\n", take);
             else
-                std::snprintf(buf, sizeof(buf),
-                              "    { const double2 f = T[%uu + ((L.ci[h] >> %uu) & 0x%xu)]; "
-                              "cmul(L.re[h], L.im[h], f.x, f.y); }\n",
+                std::snprintf(buf, sizeof(buf), "    { const double2 f = T[%uu + ((L.ci[h] >> %uu) & 0x%xu)]; %s; }\n",
                               cp->group_base[g], cp->group_shift[g],
-                              width >= 32u ? 0xffffffffu : (1u << width) - 1u);
+                              width >= 32u ? 0xffffffffu : (1u << width) - 1u, take);
             o += buf;
         }
         o += "}\n";
     } else {
         o += "static constexpr uint32_t kNCT = 0;\n"
+             "static constexpr bool kLeafPure = false;\n"
              "__device__ static __forceinline__ double2 count_entry(uint32_t) { return make_double2(0.0, 0.0); }\n"
              "template <int NW, int H>\n"
              "__device__ static __forceinline__ void count_amp(const double2 *, Lanes<NW, H> &, int) {}\n";
@@ -485,6 +496,8 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
                       static_cast<uint32_t>(src_dev.size()) - Ap - Ar);
     else
         std::snprintf(buf, sizeof(buf), "static constexpr int kSS = -1;\nstatic constexpr int kAs = -1;\n");
+    o += buf;
+    std::snprintf(buf, sizeof(buf), "static constexpr int kA = %u;\n", static_cast<uint32_t>(src_dev.size()));
     o += buf;
     // the final-bit masks as constants: fully checked words become one compare
     const Mask4 *fm[2] = {&fin_c2, &fin_rest};

@@ -955,7 +955,7 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     if (!prog || !out) return FHS_EINVAL;
     const HostProgram &P = prog->p;
     if (e0 > e1 || e1 > static_cast<uint32_t>(P.G)) return FHS_EINVAL;
-    fhs_work w{0, 0, 0, 0, 0, 0, 0};
+    fhs_work w{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t e = e0; e < e1; ++e) {
         w.gates += 1;
         w.fp64_flops += P.fp_cost[e];
@@ -963,6 +963,19 @@ extern "C" fhs_status fhs_program_work(const fhs_program *prog, uint32_t e0, uin
     }
     w.int_ops = range_int_ops(P, e0, e1, &w.src_int_ops);
     hoisted_work(P, e0, e1, w.hoist_int_ops, w.hoist_fp64_flops);
+    // the two-valued gates' counted form (the compiled consumer without pruning)
+    const std::vector<uint8_t> h = hoistable(P.ins, e0, e1, false);
+    for (uint32_t e = e0; e < e1; ++e) {
+        if (!two_valued(P.ins[e], P.fac).ok) continue;
+        const int base = op_base(static_cast<uint8_t>(P.ins[e].hdr & 0xffu));
+        const uint64_t add = (base == OP_BRANCH_SRC || base == OP_BRANCH_NAT) ? 2u : 1u;
+        w.count_int_ops += add;
+        w.count_fp64_flops += P.fp_cost[e];
+        if (h[e - e0]) {
+            w.hoist_count_int_ops += add;
+            w.hoist_count_fp64_flops += P.fp_cost[e];
+        }
+    }
     *out = w;
     return FHS_OK;
 }

@@ -1002,6 +1002,15 @@ extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs
     out->plain_blocks_per_pair = pl.bpp;
     out->prefix_depth_first = pl.Dp;
     out->items_per_claim = c->grab_override ? c->grab_override : pl.grab;
+    out->count_groups = out->count_entries = 0;
+    if (c->prog.A > 0 && pl.c2 <= static_cast<uint32_t>(c->prog.G)) {
+        const uint32_t i1 = c->pos2ins[pl.c1], i2 = c->pos2ins[pl.c2], iG = c->pos2ins[c->prog.G];
+        const CountPlan cp = count_plan(c->dev_ins, c->prog.fac, i1, i2, iG, hoistable(c->dev_ins, i2, iG, false));
+        if (cp.on()) {
+            out->count_groups = static_cast<uint32_t>(cp.group_size.size());
+            out->count_entries = cp.entries;
+        }
+    }
     out->table_bytes = pl.entries * (sizeof(uint32_t) * nw_of(c->prog) + sizeof(double2) +
                                      sizeof(double) + sizeof(uint32_t));
     return FHS_OK;

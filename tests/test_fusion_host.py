@@ -116,8 +116,31 @@ def test_hoisted_suffix_work_qaoa():
         # a phase: 3 int ops, 6 flops; a Hadamard: its input bit (1 op) and a
         # sign, its magnitude being common to every history (0 flops)
         assert (wk["hoist_int_ops"], wk["hoist_fp64_flops"]) == (3 * k + m, 6 * k), (nv, seed)
+        # counted (fhs_work.count_*): every RZZ (two values, e^{+-i gamma}) and
+        # RX (cos on the diagonal, -i sin off it) of the suffix, one int op
+        # per phase and two per branching gate; the Hadamards stay signs
+        assert (wk["count_int_ops"], wk["count_fp64_flops"]) == (len(edges) + 2 * 2, 6 * len(edges) + 2 * 2)
+        assert (wk["hoist_count_int_ops"], wk["hoist_count_fp64_flops"]) == (k, 6 * k)
     # the walk's suffix has nothing to hoist: every gate reads the coin or the field
     t = w.quantum_walk(20, 6).to_text()
     q = fhs.Program(t)
     for c2 in q.source_eval_positions:
         assert q.work(c2, q.G)["hoist_int_ops"] == 0
+        assert q.work(c2, q.G)["count_int_ops"] == 0   # H and permutations: nothing two-valued
+
+
+@pytest.mark.parametrize("gate,extra", [
+    ("T", 1), ("TDG", 1), ("S", 1), ("SDG", 1), ("Z", 1), ("P 0.7", 1), ("RZ 0.7", 1), ("P 0.0", 0),
+    ("RX 0.7", 2), ("RY 0.7", 0), ("H", 0), ("Y", 1), ("X", 0),
+    ("CZ", 1), ("CP 0.7", 1), ("RZZ 0.7", 1), ("CX", 0), ("SWAP", 0)])
+def test_two_valued_gates_counted(gate, extra):
+    """Which gates the compiled consumer can count (fhs_work.count_int_ops):
+    tables with exactly two distinct entries (P(0) has one value, RY three);
+    the Hadamards around the gate are real-entry branches, whose signs are
+    collected instead."""
+    name, *ang = gate.split()
+    qs = "0 1" if name in ("CZ", "CP", "RZZ", "CX", "SWAP") else "0"
+    text = "qubits 2\nH 0\nH 1\nRX 0 0.3\n" + " ".join([name, qs] + ang) + "\nH 0\nH 1\n"
+    p = fhs.Program(text)
+    wk = p.work(0, p.G)
+    assert wk["count_int_ops"] == extra + 2, gate     # + the RX 0.3 before it

@@ -652,6 +652,87 @@ def test_compiled_uniform_suffix(ctx, seed):
     ctx.set_launch_config(0, 0, 0, 0)
 
 
+def _counted(n: int, layers: int, seed: int):
+    """Random layered circuit whose factors mostly take two values, with few
+    distinct angles: RX on a few qubits (the first on each wire on its
+    natural input, the later ones with sources), RZZ with +-gamma (both
+    orientations of one class), CP, CZ, RZ with +-theta, T, TDG, S and Y."""
+    rng = np.random.default_rng(seed)
+    g1, g2, b1, th = (float(x) for x in rng.uniform(-np.pi, np.pi, 4))
+    c = w.Circuit(n)
+
+    def pick(k):
+        return [int(x) for x in rng.choice(n, size=k, replace=False)]
+
+    rxq = pick(4)
+    for q in rxq:
+        c.add("RX", q, angle=b1)
+    for _ in range(layers):
+        for _ in range(6):
+            a, b = pick(2)
+            c.add("RZZ", a, b, angle=g1 if rng.integers(0, 2) else -g1)
+        for _ in range(2):
+            a, b = pick(2)
+            c.add("CP", a, b, angle=g2)
+        a, b = pick(2)
+        c.add("CZ", a, b)
+        for q in pick(3):
+            k = str(rng.choice(["RZ+", "RZ-", "T", "TDG", "S", "Y", "Y"]))
+            if k.startswith("RZ"):
+                c.add("RZ", q, angle=th if k == "RZ+" else -th)
+            else:
+                c.add(k, q)
+        for q in rng.choice(rxq, size=3, replace=False):
+            c.add("RX", int(q), angle=b1)
+        a, b = pick(2)
+        c.add("CX", a, b)
+    return c
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,seed", [(12, 1), (40, 2), (40, 3)])
+def test_compiled_counted_factors(ctx, n, seed):
+    """Two-valued factors counted by the compiled consumer instead of
+    multiplied (without pruning): grouped population counts of each form
+    (bits that differ, agree, are both set, a bit set or clear), single
+    diagonal gates across state words, Y, RX on natural inputs and with
+    sources, one to three table groups, with deferred suffix factors; against
+    the oracle on reachable and random outputs, and with pruning (no
+    counting) as well."""
+    c = _counted(n, 3, seed)
+    t = c.to_text()
+    o = oracle.Feynman(t)
+    prog = fhs.Program(t)
+    assert prog.A == 9
+    rng = np.random.default_rng(seed)
+    outs = set()
+    for _ in range(96):
+        x = 0
+        for g in c.gates:
+            q = g.qubits
+            if g.name == "RX":
+                x = (x & ~(1 << q[0])) | (int(rng.integers(0, 2)) << q[0])
+            elif g.name == "Y":
+                x ^= 1 << q[0]
+            elif g.name == "CX" and (x >> q[0]) & 1:
+                x ^= 1 << q[1]
+        outs.add(x)
+    outs = sorted(outs)[:48] + [int(rng.integers(0, 1 << n)) for _ in range(8)]
+    src = list(prog.source_eval_positions)
+    parts = [(src[3] + 1, src[6] + 1), (src[0] + 1, src[4] + 1), (0, src[4]), (src[2] + 1, src[5] + 1)]
+    for thr in (0.0, 0.02):
+        ref = o.evaluate([0], [1.0], outs, threshold=thr, threads=THREADS)
+        if thr == 0.0:
+            assert np.abs(ref[0]).max() > 1e-3
+        for h in (1, 2):
+            ctx.set_launch_config(h, 0, 0, 3)
+            for part in parts:
+                amps, st = gpu_eval(ctx, t, [0], [1.0], outs, thr=thr, partition=part, prog=prog)
+                assert np.abs(amps - ref[0]).max() <= TOL, (n, seed, thr, h, part)
+                assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (n, seed, thr, h, part)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 @pytest.mark.parametrize("case", ["fig2", "qft8", "qaoa6", "walk_xcoin", "aa3", "branchy1", "branchy3"])
 def test_forward_placement(ctx, case):
     """Sources placed by the forward sweep (FHS_REDUCE_FORWARD, Table I's
