@@ -340,13 +340,14 @@ fhs_status fhs_kernel_counts(fhs_ctx *ctx, uint64_t *prefix_entries, uint64_t *p
 /* Per-work-item timestamps of the most recent fhs_evaluate run in timing
  * mode, for the cost distribution over outputs (Section V: time against the
  * number of sources, time per requested bitstring): the persistent
- * consumer's work item (pair p, chunk j of its prefix entries) has index
+ * consumer's work item (pair p, part j: chunk j / root_parts of its prefix
+ * entries, part j % root_parts of that chunk's root tasks) has index
  * p * items_per_pair + j, pairs numbered p = j_out * S + i_in; stamps[2 k]
  * and stamps[2 k + 1] receive the device's constant-rate clock when a
  * workgroup popped item k and when it stored the item's sums (ticks_per_s
  * ticks per second; comparable across compute units).  Writes min(count,
- * cap) items (blocking copy).  Outputs with no work (a pair rejected before
- * enumeration) still have their items, which take almost no time.
+ * cap) items (blocking copy).  The items of a pair the precheck rejected
+ * are skipped: their stamps stay 0.
  * FHS_ESTATE if timing is off or the last timed call was not a batched
  * evaluation with sources. */
 fhs_status fhs_item_stamps(fhs_ctx *ctx, uint64_t *stamps, size_t cap, size_t *count,
@@ -373,6 +374,14 @@ typedef struct {
                                       counted; on only when a class has a gate in the leaf loop and
                                       every class fits the tables) */
     uint32_t count_entries;        /* their tables' entries (16 bytes each, in LDS) */
+    uint32_t root_parts;           /* work items per chunk: its root tasks in this many parts
+                                      (items_per_pair = chunks per pair * root_parts) */
+    uint32_t pair_filter;          /* 1: the precheck applies the pair-level residue test (every
+                                      write to one bit field after the leading gates is a
+                                      source-selected ladder step and the final check covers it:
+                                      a pair whose residue no history's step count reaches is
+                                      rejected, its amplitude and statistics zero), and the
+                                      consumer skips the items of rejected pairs */
 } fhs_plan;
 
 fhs_status fhs_get_plan(const fhs_ctx *ctx, uint32_t M, uint32_t S, fhs_plan *plan);
@@ -389,7 +398,11 @@ fhs_status fhs_workspace_size(const fhs_ctx *ctx, uint32_t M, uint32_t S, size_t
  *   d_amps    [M*2]  <b_out_j|C|psi>                  (device, written)
  *   d_stats   [M*4]  per output, summed over inputs: number of valid
  *                    histories, sum of their indices h (mod 2^64), xor of
- *                    SplitMix64(h), leaf histories walked (device, written)
+ *                    SplitMix64(h), leaf histories walked: the suffix
+ *                    assignments of consistent roots the consumer evaluated
+ *                    (those the final field check's residue rules out in
+ *                    advance, a pass or a root at a time, are not walked)
+ *                    (device, written)
  *   d_ws, ws_bytes   workspace of at least fhs_workspace_size bytes, 256-byte
  *                    aligned (device, scratch; contents undefined afterwards)
  * Enqueued asynchronously on `stream`: one precheck launch, then per batch of

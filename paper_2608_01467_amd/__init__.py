@@ -79,7 +79,8 @@ class Plan(ctypes.Structure):
         "c1", "c2", "Ap", "Ar", "As", "n_batches", "pairs_per_batch", "chunk", "items_per_pair",
         "lanes_per_root_task", "plain_blocks_per_pair")] + [("table_bytes", ctypes.c_uint64)] + [
         ("prefix_depth_first", ctypes.c_uint32), ("items_per_claim", ctypes.c_uint32),
-        ("count_groups", ctypes.c_uint32), ("count_entries", ctypes.c_uint32)]
+        ("count_groups", ctypes.c_uint32), ("count_entries", ctypes.c_uint32),
+        ("root_parts", ctypes.c_uint32), ("pair_filter", ctypes.c_uint32)]
 
 
 class MlpShape(ctypes.Structure):

@@ -438,6 +438,44 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
     pbq = 0;
 }
 
+// The residue (output - state) on the field [lo, hi) in the form the final
+// check compares it with a step count n: n matches iff (n << up) == (e << up)
+// for the returned e.  For m = hi - lo <= 32 bits, e holds the residue's low 32 bits and
+// up = 32 - m (only the field's m low bits count).  For wider fields up = 0
+// and e is the residue as an int32 when it is one, else a value no step
+// count reaches (|n| is at most the number of steps): n sign-extended to m
+// bits equals the residue iff their low 32 bits agree and bits [lo+32, hi)
+// all repeat bit 31, and equal int32 values are equal mod 2^32.
+template <int NW>
+__device__ __forceinline__ uint32_t field_residue(const uint32_t (&s)[NW], const uint32_t (&bin)[NW], uint32_t lo,
+                                                  uint32_t hi, uint32_t &up) {
+    const FieldMasks f = field_masks(lo, hi);
+    const FieldMasks g = field_masks(lo + 32u < hi ? lo + 32u : hi, hi);   // bits [lo+32, hi)
+    const uint32_t m = hi - lo, wl = lo >> 5, sh = lo & 31u;
+    // bits [lo, hi) of d hold the residue
+    uint32_t d[NW], borrow = 0;
+    unroll<NW>([&](auto ww) {
+        constexpr int w = ww.value;
+        d[w] = __builtin_subc(bin[w] & f.fm[w], s[w] & f.fm[w], borrow, &borrow);
+    });
+    uint32_t x0 = 0, x1 = 0, zhi = 0, ohi = 0;
+    unroll<NW>([&](auto ww) {
+        constexpr uint32_t w = static_cast<uint32_t>(ww.value);
+        if (w == wl) x0 = d[w];
+        if (w == wl + 1u) x1 = d[w];
+        zhi |= d[w] & g.fm[w];
+        ohi |= ~d[w] & g.fm[w];
+    });
+    const uint32_t e32 = sh ? (x0 >> sh) | (x1 << (32u - sh)) : x0;   // bits [lo, lo+32) of d
+    if (m <= 32u) {
+        up = 32u - m;
+        return e32;
+    }
+    up = 0u;
+    const bool fits = static_cast<int32_t>(e32) < 0 ? ohi == 0u : zhi == 0u;
+    return fits ? e32 : 0x80000000u;
+}
+
 // The last pending run of a region after which the final check compares
 // every bit of the field with the output: (x + n) mod 2^m equals the target
 // t iff n = (t - x) mod 2^m, so instead of adding n 2^lo to the field and
@@ -454,44 +492,14 @@ __device__ __forceinline__ void flush_field(Lanes<NW, H> &L, uint32_t lo, uint32
 template <int NW, int H>
 __device__ __forceinline__ void flush_check(Lanes<NW, H> &L, uint32_t lo, uint32_t hi, int32_t (&pk)[H],
                                             int32_t (&pb)[H], int32_t &pbq, const uint32_t (&bin)[NW]) {
-    const FieldMasks f = field_masks(lo, hi);
-    const FieldMasks g = field_masks(lo + 32u < hi ? lo + 32u : hi, hi);   // bits [lo+32, hi)
-    const uint32_t m = hi - lo, wl = lo >> 5, sh = lo & 31u;
     unroll<H>([&](auto hh) {
         constexpr int h = hh.value;
-        // (output - state) on the field bits: bits [lo, hi) of d hold the residue
-        uint32_t d[NW], borrow = 0;
-        unroll<NW>([&](auto ww) {
-            constexpr int w = ww.value;
-            d[w] = __builtin_subc(bin[w] & f.fm[w], L.s[h][w] & f.fm[w], borrow, &borrow);
-        });
-        uint32_t x0 = 0, x1 = 0, zhi = 0, ohi = 0;
-        unroll<NW>([&](auto ww) {
-            constexpr uint32_t w = static_cast<uint32_t>(ww.value);
-            if (w == wl) x0 = d[w];
-            if (w == wl + 1u) x1 = d[w];
-            zhi |= d[w] & g.fm[w];
-            ohi |= ~d[w] & g.fm[w];
-        });
-        const uint32_t e32 = sh ? (x0 >> sh) | (x1 << (32u - sh)) : x0;   // bits [lo, lo+32) of d
+        uint32_t up;
+        const uint32_t e = field_residue<NW>(L.s[h], bin, lo, hi, up);
         // the step count is n = pk + 2 pb + 2 pbq
         const uint32_t nl = static_cast<uint32_t>(pk[h]) + 2u * static_cast<uint32_t>(pb[h]);
         const uint32_t nq = 2u * static_cast<uint32_t>(pbq);
-        bool hit;
-        if (m <= 32u) {
-            const uint32_t up = 32u - m;   // only the field's m low bits count
-            hit = (nq << up) == ((e32 - nl) << up);
-        } else {
-            // n sign-extended to m bits equals the residue iff their low 32
-            // bits agree and bits [lo+32, hi) all repeat bit 31: the residue
-            // as an int32 when it is one, else a value no step count reaches
-            // (|n| is at most the number of steps); equal int32 values are
-            // equal mod 2^32
-            const bool fits = static_cast<int32_t>(e32) < 0 ? ohi == 0u : zhi == 0u;
-            const uint32_t en = fits ? e32 : 0x80000000u;
-            hit = nq == en - nl;
-        }
-        L.ok[h] = L.ok[h] && hit;
+        L.ok[h] = L.ok[h] && (nq << up) == ((e - nl) << up);
         pk[h] = 0;
         pb[h] = 0;
     });
@@ -1088,6 +1096,17 @@ struct Interp {
     __device__ static __forceinline__ double2 count_entry(uint32_t) { return make_double2(0.0, 0.0); }
     template <int NW, int H>
     __device__ static __forceinline__ void count_amp(const double2 *, Lanes<NW, H> &, int) {}
+    // whole passes of leaves rejected by the final field check: not here
+    static constexpr bool kPassFilter = false;
+    static constexpr uint32_t kPassUp = 0u;
+    static constexpr uint32_t kPassSpan = 0u;
+    static constexpr uint32_t kRootQ = 0u;
+    static constexpr int32_t kRootSpan = -1;
+    template <int NW, int H>
+    __device__ static __forceinline__ void pass_res(const Lanes<NW, H> &, const uint64_t (&)[H],
+                                                    const uint32_t (&)[NW], uint32_t (&)[H]) {}
+    template <int UU>
+    __device__ static __forceinline__ uint32_t pass_q(uint64_t) { return 0u; }
     // suffix instructions evaluated once per root history: none here
     static constexpr bool kHoist = false;
     template <int NW, int H, bool PRUNE>
@@ -1219,7 +1238,11 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     }
     const uint32_t per_pair = 1u << c.Ap;
     const uint32_t nchunks = (per_pair + chunk - 1) / chunk;
-    const uint32_t n_items = B * nchunks;
+    const uint32_t rparts = c.rparts > 0u ? c.rparts : 1u;   // items per chunk
+    const uint32_t ipp = nchunks * rparts;                   // items per pair
+    // the batch's pairs the precheck accepted (written before this launch)
+    const uint32_t bidx = p0 / c.acc_B;
+    const uint32_t n_items = c.acc_n[bidx] * ipp;
     const uint64_t E = static_cast<uint64_t>(B) << c.Ap;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     const uint32_t rmask = (1u << c.Ar) - 1u;
@@ -1245,9 +1268,12 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             left = grab;
         }
         if (item >= n_items) break;
-        if (part.stamps && t == 0) part.stamps[2ull * item] = wall_clock64();
-        const uint32_t pl = item / nchunks, ch = item - pl * nchunks;
+        const uint32_t f = item / ipp, rem = item - f * ipp, ch = rem / rparts, rp = rem - ch * rparts;
+        const uint32_t pl = c.acc_list[static_cast<size_t>(bidx) * c.acc_B + f];
         const uint32_t p = p0 + pl;
+        // timing stamps by pair (pair-major), the pair's item rem
+        const uint64_t sidx = static_cast<uint64_t>(pl) * ipp + rem;
+        if (part.stamps && t == 0) part.stamps[2ull * sidx] = wall_clock64();
         const uint32_t hp0 = ch * chunk;
         const uint32_t cnt = min(chunk, per_pair - hp0);
 
@@ -1289,9 +1315,15 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
         load_bits<NW>(check_bits(c, p), c.W, c.n, bin);
         const uint64_t paff = c.n_aff ? c.pair_aff[p] : 0ull;
         Acc acc{0.0, 0.0, 0, 0, 0, 0};
-        const uint64_t ntask = static_cast<uint64_t>(nv) << (c.Ar + ss);
-        // uniform loop bounds: the program counter inside stays wave-uniform
-        for (uint64_t tb = 0; tb < ntask; tb += static_cast<uint64_t>(H) * NT) {
+        // this item's part of the chunk's root tasks: whole passes of the
+        // workgroup (uniform loop bounds: the program counter inside stays
+        // wave-uniform)
+        const uint64_t step = static_cast<uint64_t>(H) * NT;
+        const uint64_t ntask_all = static_cast<uint64_t>(nv) << (c.Ar + ss);
+        const uint64_t per_part = ((ntask_all + rparts - 1u) / rparts + step - 1u) / step * step;
+        const uint64_t t_lo = min(ntask_all, static_cast<uint64_t>(rp) * per_part);
+        const uint64_t ntask = min(ntask_all, t_lo + per_part);
+        for (uint64_t tb = t_lo; tb < ntask; tb += step) {
             Lanes<NW, H> R;
             uint64_t hbase[H], hs0[H];
             unroll<H>([&](auto jj) {
@@ -1324,8 +1356,6 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 any = any || R.ok[j];
             });
             if (!__any(any)) continue;   // wave-uniform skip
-            // every suffix assignment of a consistent root is a leaf walked
-            unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n_suffix : 0u; });
             // a pure leaf loop starts each leaf from amplitude +1: a leaf's
             // value is then its sign times its counted product, and the
             // root's amplitude multiplies their sum once
@@ -1340,6 +1370,41 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                     sre[j] = sim[j] = 0.0;
                 });
             }
+            // a pass of leaves can hold a valid history only where the final
+            // field check's residue v (per root) is within reach of the
+            // pass's source popcounts (the compiled regions' pass_res/pass_q)
+            uint32_t pv[H];
+            if constexpr (Regions::kPassFilter) Regions::template pass_res<NW, H>(R, hs0, bin, pv);
+            auto may_pass = [&](uint64_t qq, auto uu) {
+                constexpr int UU = decltype(uu)::value;
+                constexpr uint32_t up = Regions::kPassUp;
+                constexpr uint32_t span = UU == 1 ? 0u : Regions::kPassSpan;
+                const uint32_t pq = Regions::template pass_q<UU>(qq);
+                bool may = false;
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    const uint32_t D = pv[j] - pq;
+                    may = may || (R.ok[j] && (D & ((2u << up) - 1u)) == 0u && (D >> (up + 1u)) <= span);
+                });
+                return __any(may);
+            };
+            if constexpr (Regions::kPassFilter && Regions::kRootSpan >= 0) {
+                // no suffix assignment at all within reach: skip the root's leaves
+                constexpr uint32_t up = Regions::kPassUp;
+                bool may = false;
+                unroll<H>([&](auto jj) {
+                    constexpr int j = jj.value;
+                    const uint32_t D = pv[j] - Regions::kRootQ;
+                    may = may || (R.ok[j] && (D & ((2u << up) - 1u)) == 0u &&
+                                  (D >> (up + 1u)) <= static_cast<uint32_t>(Regions::kRootSpan));
+                });
+                if (!__any(may)) continue;
+            }
+            // the leaves walked: every suffix assignment of a consistent root
+            // that no filter rejected before its walk
+            auto walked = [&](uint64_t n) {
+                unroll<H>([&](auto jj) { acc.leaves += R.ok[jj.value] ? n : 0u; });
+            };
             uint64_t hm[H];   // the root's part of the hash's first product
             unroll<H>([&](auto jj) {
                 constexpr int j = jj.value;
@@ -1396,6 +1461,10 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 // U leaves per pass: their checks first, then one wave-uniform
                 // test skips the pass when no lane has a valid history in it
                 for (; q + U <= n_suffix; q += U) {   // q stays a multiple of U
+                    if constexpr (Regions::kPassFilter) {
+                        if (!may_pass(q, IC<U>{})) continue;
+                    }
+                    walked(U);
                     Lanes<NW, H> S2[U];
                     bool any = false;
                     unroll<U>([&](auto uu) {
@@ -1409,6 +1478,10 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 }
             }
             for (; q < n_suffix; ++q) {
+                if constexpr (Regions::kPassFilter) {
+                    if (!may_pass(q, IC<1>{})) continue;
+                }
+                walked(1);
                 Lanes<NW, H> S2 = R;
                 walk_leaf(S2, q, 0u);
                 count_leaf(S2, q);
@@ -1422,7 +1495,7 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
             }
         }
         block_reduce_store<NT>(acc, l_red, part, item);
-        if (part.stamps && t == 0) part.stamps[2ull * item + 1] = wall_clock64();
+        if (part.stamps && t == 0) part.stamps[2ull * sidx + 1] = wall_clock64();
     }
 }
 

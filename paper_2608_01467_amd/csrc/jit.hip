@@ -4,6 +4,7 @@
 
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -79,6 +80,19 @@ FacShape fac_shape(const Instr &I, const std::vector<double> &fac) {
     return f;
 }
 
+// The final field check of a suffix region (flush_check) when its residue is
+// the same for every leaf of a root: the run's steps are all selected by
+// source bits (a constant plus popcounts of the source index), and nothing
+// in the region before the run writes the field.  Then whether a leaf can
+// pass depends on the leaf only through the popcounts of its wave-uniform
+// source bits, and the consumer can reject whole passes of leaves at once.
+struct TailCheck {
+    bool ok = false;
+    uint32_t lo = 0, hi = 0;    // the field
+    int32_t kc = 0;             // the run's constant steps
+    std::vector<std::pair<uint64_t, uint64_t>> src;   // (pos, neg) source-bit masks
+};
+
 // One block per instruction: the instruction as a constant and the call of
 // its backward step with the word indices its opcode carries (wsel maps them
 // onto the state registers as the interpreter's dispatch does).  With
@@ -102,9 +116,21 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
                  uint32_t fac_lo, uint32_t kbase, uint32_t lo, uint32_t hi, bool defer,
                  std::vector<Deferred> &deferred, const Mask4 *check = nullptr, Mask4 *checked = nullptr,
                  double *rdef = nullptr, bool *rsign = nullptr, const std::vector<uint8_t> *omit = nullptr,
-                 const CountPlan *cp = nullptr) {
+                 const CountPlan *cp = nullptr, TailCheck *tail = nullptr) {
     char buf[512];
     int off = 0;
+    // the pending run: its first instruction, whether every step is selected
+    // by a source bit, its constant steps and its source popcounts
+    uint32_t run_first = lo;
+    bool run_pure = true;
+    int32_t run_kc = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> run_src;
+    auto run_start = [&](uint32_t x) {
+        run_first = x;
+        run_pure = true;
+        run_kc = 0;
+        run_src.clear();
+    };
     // grouped counted diagonal gates not yet emitted: class, kind
     // (count_bits), word, distance of the two bits, and the gates' low bits
     struct CRun {
@@ -155,6 +181,7 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         std::snprintf(buf, sizeof(buf), "    pend_src<NW, H>(L, pk, pb, pbq, %d, 0x%llxull, 0x%llxull);\n", pkc,
                       static_cast<unsigned long long>(spos), static_cast<unsigned long long>(sneg));
         o += buf;
+        run_src.emplace_back(spos, sneg);
         pkc = 0;
         spos = sneg = 0;
     };
@@ -182,7 +209,9 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
             // a step selected by source bit j: d0 when the bit is 0, d1 when 1
             const uint32_t z = I.hdr >> 24;
             const int32_t d0 = (z & 1u) ? -1 : 1, d1 = (z & 2u) ? -1 : 1;
+            if (!pending) run_start(x);
             pkc += d0;
+            run_kc += d0;
             if (d1 > d0) spos |= 1ull << sel_src;
             if (d1 < d0) sneg |= 1ull << sel_src;
             pending = true;
@@ -308,6 +337,8 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
         }
         o += call;
         if (is_add) {
+            if (!pending) run_start(x);
+            run_pure = false;   // a step whose controls the leaf may change
             pending = true;
             plo = a;
             phi = a + b;
@@ -325,6 +356,20 @@ void emit_region(std::string &o, const std::vector<Instr> &dev, const std::vecto
             o += buf;
             pending = false;
             if (checked) *checked = fm;
+            if (tail) {
+                bool clean = run_pure;
+                for (uint32_t x = lo; x < run_first && clean; ++x) {
+                    if (omit && (*omit)[x - lo]) continue;
+                    uint32_t wm[4];
+                    written_bits(dev[x], wm);
+                    for (int w = 0; w < 4; ++w) clean = clean && (wm[w] & fm.w[w]) == 0u;
+                }
+                tail->ok = clean;
+                tail->lo = plo;
+                tail->hi = phi;
+                tail->kc = run_kc;
+                tail->src = run_src;
+            }
         }
     }
     flush();
@@ -366,7 +411,9 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     CountPlan cplan;
     if (!prune) cplan = count_plan(dev, fac, i1, i2, iG, hoist);
     const CountPlan *cp = cplan.on() ? &cplan : nullptr;
-    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked, nullptr, nullptr, &hoist, cp);
+    TailCheck tail;
+    emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, false, none, &fin_G, &checked, nullptr, nullptr, &hoist, cp,
+                &tail);
     Mask4 natw{{0u, 0u, 0u, 0u}};
     bool zero_entries = false;
     for (uint32_t x = i2; x < iG; ++x) {
@@ -400,8 +447,9 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     bool rsign = false;
     if (defer) {
         sfx.clear();
+        tail = TailCheck{};
         emit_region(sfx, dev, fac, fac_lo, Ap + Ar, i2, iG, true, deferred, &fin_G, &checked, &rdef, &rsign, &hoist,
-                    cp);
+                    cp, &tail);
     }
     o += "#include \"device.hpp\"\nnamespace fhs {\nnamespace {\n";
     std::vector<double> ctab;
@@ -484,8 +532,92 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
     // a short suffix walks several assignments per pass of the leaf loop
     // (the loop control and the skip of passes without a valid history are
     // paid once per pass); longer ones one at a time, keeping registers
-    std::snprintf(buf, sizeof(buf), "static constexpr int kUnroll = %d;\n", iG - i2 <= 24u ? 8 : 1);
+    const int U = iG - i2 <= 24u ? 8 : 1;
+    std::snprintf(buf, sizeof(buf), "static constexpr int kUnroll = %d;\n", U);
     o += buf;
+    // Whole passes of leaves rejected at once (TailCheck): a leaf passes the
+    // final field check only if 2 (P(q) + P(u)) << up equals the root's
+    // residue less its constant and lane steps (v), P the source popcounts
+    // of the pass's wave-uniform base q and of the leaf's offset u < U; with
+    // P(u) in [pmin, pmax], D = v - (2 (P(q) + pmin) << up) must be
+    // 2k << up for some k <= pmax - pmin.
+    {
+        const uint32_t m = tail.hi - tail.lo;
+        const uint32_t up = m <= 32u ? 32u - m : 0u;
+        int32_t pmin = 0, pmax = 0;
+        for (int u = 0; u < U; ++u) {
+            int32_t p = 0;
+            for (const auto &pn : tail.src)
+                p += __builtin_popcountll(static_cast<uint64_t>(u) & pn.first) -
+                     __builtin_popcountll(static_cast<uint64_t>(u) & pn.second);
+            pmin = u ? std::min(pmin, p) : p;
+            pmax = u ? std::max(pmax, p) : p;
+        }
+        const bool filt = tail.ok && m >= 2u && up <= 30u &&
+                          static_cast<uint64_t>(pmax - pmin) + 1u < (1ull << (31u - up));
+        // the same over every suffix assignment: per source bit its weight in
+        // P, the range the sum of the weights of any subset of bits spans
+        int32_t amin = 0, amax = 0;
+        const uint32_t As = static_cast<uint32_t>(src_dev.size()) - Ap - Ar;
+        for (uint32_t k = 0; k < As && k < 64u; ++k) {
+            int32_t wk = 0;
+            for (const auto &pn : tail.src)
+                wk += static_cast<int32_t>((pn.first >> k) & 1u) - static_cast<int32_t>((pn.second >> k) & 1u);
+            if (wk < 0) amin += wk;
+            else amax += wk;
+        }
+        const bool rfilt = filt && static_cast<uint64_t>(amax - amin) + 1u < (1ull << (31u - up));
+        std::snprintf(buf, sizeof(buf), "static constexpr uint32_t kRootQ = %uu;\nstatic constexpr int32_t kRootSpan = %d;\n",
+                      rfilt ? (2u * static_cast<uint32_t>(amin)) << up : 0u, rfilt ? amax - amin : -1);
+        o += buf;
+        if (filt) {
+            std::snprintf(buf, sizeof(buf),
+                          "static constexpr bool kPassFilter = true;\n"
+                          "static constexpr uint32_t kPassUp = %uu;\n"
+                          "static constexpr uint32_t kPassSpan = %uu;\n"
+                          "template <int NW, int H>\n"
+                          "__device__ static __forceinline__ void pass_res(const Lanes<NW, H> &R, const uint64_t (&hs)[H], "
+                          "const uint32_t (&bin)[NW], uint32_t (&v)[H]) {\n"
+                          "    unroll<H>([&](auto hh) {\n"
+                          "        constexpr int h = hh.value;\n"
+                          "        uint32_t up;\n"
+                          "        const uint32_t e = field_residue<NW>(R.s[h], bin, %uu, %uu, up);\n"
+                          "        int32_t pb = 0;\n",
+                          up, static_cast<uint32_t>(pmax - pmin), tail.lo, tail.hi);
+            o += buf;
+            for (const auto &pn : tail.src) {
+                std::snprintf(buf, sizeof(buf),
+                              "        pb += __popcll(hs[h] & 0x%llxull) - __popcll(hs[h] & 0x%llxull);\n",
+                              static_cast<unsigned long long>(pn.first), static_cast<unsigned long long>(pn.second));
+                o += buf;
+            }
+            std::snprintf(buf, sizeof(buf),
+                          "        v[h] = (e - (%uu + 2u * static_cast<uint32_t>(pb))) << up;\n"
+                          "    });\n"
+                          "}\n"
+                          "template <int UU>\n"
+                          "__device__ static __forceinline__ uint32_t pass_q(uint64_t q) {\n"
+                          "    int32_t p = UU == 1 ? 0 : %d;\n",
+                          static_cast<uint32_t>(tail.kc), pmin);
+            o += buf;
+            for (const auto &pn : tail.src) {
+                std::snprintf(buf, sizeof(buf), "    p += __popcll(q & 0x%llxull) - __popcll(q & 0x%llxull);\n",
+                              static_cast<unsigned long long>(pn.first), static_cast<unsigned long long>(pn.second));
+                o += buf;
+            }
+            std::snprintf(buf, sizeof(buf), "    return (2u * static_cast<uint32_t>(p)) << %uu;\n}\n", up);
+            o += buf;
+        } else {
+            o += "static constexpr bool kPassFilter = false;\n"
+                 "static constexpr uint32_t kPassUp = 0u;\n"
+                 "static constexpr uint32_t kPassSpan = 0u;\n"
+                 "template <int NW, int H>\n"
+                 "__device__ static __forceinline__ void pass_res(const Lanes<NW, H> &, const uint64_t (&)[H], "
+                 "const uint32_t (&)[NW], uint32_t (&)[H]) {}\n"
+                 "template <int UU>\n"
+                 "__device__ static __forceinline__ uint32_t pass_q(uint64_t) { return 0u; }\n";
+        }
+    }
     // with one lane per root task, every suffix source lives in the leaf
     // loop's wave-uniform counter: built for that case as constants (with
     // several lanes per root task the lanes' share of the suffix index stays
@@ -618,6 +750,37 @@ std::string consumer_source(const std::vector<Instr> &dev, const std::vector<dou
         o += buf;
     }
     return o;
+}
+
+bool pair_filter(const std::vector<Instr> &dev, const std::vector<double> &fac, uint32_t iL, uint32_t iG,
+                 const Mask4 &fin_G, uint32_t A, PairFilter &out) {
+    if (iL >= iG || A == 0) return false;
+    // the whole program after the leading gates as one region with global
+    // source indices: its final run and what precedes it (the text is not used)
+    std::string text;
+    std::vector<Deferred> none;
+    Mask4 checked{{0u, 0u, 0u, 0u}};
+    TailCheck tail;
+    emit_region(text, dev, fac, 0u, 0u, iL, iG, false, none, &fin_G, &checked, nullptr, nullptr, nullptr, nullptr,
+                &tail);
+    if (!tail.ok) return false;
+    const uint32_t m = tail.hi - tail.lo;
+    const uint32_t up = m <= 32u ? 32u - m : 0u;
+    int64_t amin = 0, amax = 0;
+    for (uint32_t k = 0; k < A && k < 64u; ++k) {
+        int64_t wk = 0;
+        for (const auto &pn : tail.src)
+            wk += static_cast<int64_t>((pn.first >> k) & 1u) - static_cast<int64_t>((pn.second >> k) & 1u);
+        if (wk < 0) amin += wk;
+        else amax += wk;
+    }
+    if (m < 2u || up > 30u || static_cast<uint64_t>(amax - amin) + 1u >= (1ull << (31u - up))) return false;
+    out.lo = tail.lo;
+    out.hi = tail.hi;
+    out.up = up;
+    out.off = static_cast<uint32_t>(static_cast<int64_t>(tail.kc) + 2 * amin);
+    out.span = static_cast<uint32_t>(amax - amin);
+    return true;
 }
 
 bool compile_code(const std::string &src, std::vector<char> &code, std::string &log) {

@@ -59,6 +59,19 @@ bool compile_consumer(const std::string &src, size_t shm, CompiledConsumer &out,
 // calls; safe to run for different sources on several threads at once),
 // then the module load on the calling thread's current device.
 bool compile_code(const std::string &src, std::vector<char> &code, std::string &log);
+
+// A residue test for a whole pair (the precheck): when every write to one
+// bit field after the leading source-free gates is a ladder step selected by
+// a source bit, and the final check covers the field, the field's step count
+// is off0 + 2 P(h) with P(h) in [amin, amax] for every history h.  A pair is
+// then feasible only if D = (e - off) << up, e the field residue after the
+// leading gates (field_residue), is 2k << up for some k <= span; off =
+// off0 + 2 amin.  Returns false when the program has no such field.
+struct PairFilter {
+    uint32_t lo = 0, hi = 0, up = 0, off = 0, span = 0;
+};
+bool pair_filter(const std::vector<Instr> &dev, const std::vector<double> &fac, uint32_t iL, uint32_t iG,
+                 const Mask4 &fin_G, uint32_t A, PairFilter &out);
 bool load_consumer(const std::vector<char> &code, bool has_prefix, size_t shm, CompiledConsumer &out,
                    std::string &log);
 

@@ -55,12 +55,50 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     }
     const FacRef F{c.fac, 0u};
     run_region<NW, 1, PRUNE, true>(c.prog, F, 0, c.iL, L, 0, bin, c.thr);
-    const bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
+    bool ok = L.ok[0] && check_final<NW>(L.s[0], bin, ld_const(c.fin, c.L));
+    if (c.pf_on) {
+        // the field's residue against every step count the histories reach
+        uint32_t up;
+        const uint32_t e = field_residue<NW>(L.s[0], bin, c.pf_lo, c.pf_hi, up);
+        const uint32_t D = (e - c.pf_off) << up;
+        ok = ok && (D & ((2u << up) - 1u)) == 0u && (D >> (up + 1u)) <= c.pf_span;
+    }
 #pragma unroll
     for (int w = 0; w < NW; ++w) pre.st[static_cast<size_t>(w) * P + p] = L.s[0][w];
     pre.amp[p] = make_double2(L.re[0], L.im[0]);
     pre.M[p] = L.M[0];
     pre.ok[p] = (ok ? 1u : 0u) | ((bad_o || bad_i) ? 2u : 0u);
+}
+
+// The accepted pairs of each batch, listed (PreBufs.acc_*): one atomic per
+// wave and batch.
+__global__ __launch_bounds__(256) void k_compact(PreBufs pre, uint32_t P) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool a = pre.ok[p] == 1u;
+    const uint32_t b = p / pre.acc_B, pl = p - b * pre.acc_B;
+    uint32_t slot = 0xffffffffu;
+    bool pending = true;
+    for (;;) {
+        const uint64_t act = __ballot(pending);
+        if (act == 0u) break;
+        const int leader = __ffsll(static_cast<long long>(act)) - 1;
+        const uint32_t lb = __shfl(b, leader);
+        const bool mine = pending && b == lb;
+        const uint64_t take = __ballot(mine && a);
+        uint32_t base = 0;
+        if (static_cast<int>(lane) == leader && take) base = atomicAdd(pre.acc_n + lb, static_cast<uint32_t>(__popcll(take)));
+        base = __shfl(base, leader);
+        if (mine) {
+            if (a) {
+                slot = base + static_cast<uint32_t>(__popcll(take & ((1ull << lane) - 1ull)));
+                pre.acc_list[static_cast<size_t>(lb) * pre.acc_B + slot] = pl;
+            }
+            pending = false;
+        }
+    }
+    pre.acc_pos[p] = slot;
 }
 
 template <int NW, bool PRUNE, bool FLDS, bool RUNS>
@@ -168,9 +206,12 @@ __global__ void k_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t 
             lv = 1;
             xh = mix64(0);
         }
-    } else {
+    } else if (okv == 1u) {
+        // the consumer's items cover only the accepted pairs, listed (the
+        // plain form's blocks cover every pair)
+        const uint32_t f = pre.acc_pos ? pre.acc_pos[p] : pl;
         for (uint32_t k = 0; k < ipp; ++k) {
-            const size_t it = static_cast<size_t>(pl) * ipp + k;
+            const size_t it = static_cast<size_t>(f) * ipp + k;
             const double2 a = part.amp[it];
             re += a.x;
             im += a.y;
@@ -257,6 +298,12 @@ hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uin
             k_precheck<nw.value, pr.value><<<blocks, 256, 0, s>>>(c, pre, P, zero_words, n_zero);
         });
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(PreBufs pre, uint32_t P, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    k_compact<<<(P + 255) / 256, 256, 0, s>>>(pre, P);
     return hipGetLastError();
 }
 

@@ -18,6 +18,14 @@ struct PreBufs {
     double *M;         // [P]     running modulus product
     uint32_t *ok;      // [P]     1 = consistent so far
     uint64_t *aff;     // [P]     bit j: the boundary part of affine input j's form
+    // The pairs the precheck accepted, per batch of acc_B pairs (k_compact):
+    // acc_n[b] of them, listed at acc_list[b acc_B ...] by their index in the
+    // batch (in no particular order); acc_pos[p] is pair p's place in that
+    // list (0xffffffff: rejected).  The consumer's work items cover only them.
+    uint32_t *acc_n;
+    uint32_t *acc_list;
+    uint32_t *acc_pos;
+    uint32_t acc_B;
 };
 
 // One output pair's finished result.
@@ -78,10 +86,23 @@ struct Common {
     // log2 of the lanes that share one root task (the plan's; a compiled
     // consumer is built either for 0 or for any other value)
     uint32_t ss;
+    // The pair-level residue test (pair_filter; pf_on 0: none): the
+    // precheck rejects a pair whose field residue no history's steps reach,
+    // and the consumer skips a rejected pair's items.
+    uint32_t pf_on, pf_lo, pf_hi, pf_up, pf_off, pf_span;
+    // the accepted pairs of each batch (PreBufs.acc_*)
+    const uint32_t *acc_n;
+    const uint32_t *acc_list;
+    uint32_t acc_B;
+    // Work items per chunk of prefix entries: the chunk's root tasks in this
+    // many equal parts, so that one pair's work spreads over several
+    // workgroups (with the pair-level test, rejected pairs' items are free).
+    uint32_t rparts;
 };
 
 #if !defined(__HIPCC_RTC__)
 // Launchers (kernels.hip).  NW and pruning are dispatched inside.
+hipError_t launch_compact(PreBufs pre, uint32_t P, hipStream_t s);
 hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
                            uint32_t n_zero, hipStream_t s);
 // Dp: the last Dp prefix sources are enumerated depth-first inside a lane

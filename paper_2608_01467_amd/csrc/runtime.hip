@@ -63,7 +63,9 @@ struct Plan {
     uint32_t B = 0;          // pairs per batch
     uint32_t n_batches = 0;
     uint32_t chunk = 1;      // prefix entries per work item
-    uint32_t nchunks = 1;    // work items per pair
+    uint32_t nchunks = 1;    // chunks of prefix entries per pair
+    uint32_t rparts = 1;     // work items per chunk (parts of its root tasks)
+    uint32_t ipp = 1;        // work items per pair: nchunks * rparts
     uint32_t ss = 0;         // log2 lanes per root task
     uint32_t grab = 1;       // work items per claim from the consumer's queue
     uint32_t Dp = 0;         // prefix sources enumerated depth-first inside a lane
@@ -71,7 +73,8 @@ struct Plan {
     uint64_t entries = 0;    // table entries per batch
     size_t off_pre_st = 0, off_pre_amp = 0, off_pre_M = 0, off_pre_ok = 0, off_pre_aff = 0;
     size_t off_res_amp = 0, off_res_st = 0;
-    size_t off_counters = 0;
+    size_t off_counters = 0;      // per batch: the queue's counter, then the accepted pairs' count
+    size_t off_acc_list = 0, off_acc_pos = 0;
     size_t off_tab_st = 0, off_tab_beta = 0, off_tab_M = 0, off_tab_ok = 0;
     size_t off_part_amp = 0, off_part_st = 0;   // batched mode
     size_t off_plain_amp = 0, off_plain_st = 0; // plain mode
@@ -126,6 +129,8 @@ struct fhs_ctx {
     unsigned long long *d_valid = nullptr;  // timing mode: consistent prefix entries
     uint64_t n_entries = 0;                 // timing mode: prefix entries built
     void *scratch = nullptr;                // this device's copy of the no-alloc scratch
+    bool pf_on = false;                     // the program's pair-level residue test (pair_filter)
+    PairFilter pf;
     unsigned long long *d_stamps = nullptr; // timing mode: per work item start/end clock
     size_t stamps_cap = 0;                  // items d_stamps holds
     uint64_t n_stamped = 0;                 // items of the last timed evaluation
@@ -251,6 +256,8 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
     pl.off_pre_M = take(sizeof(double) * n_pairs);
     pl.off_pre_ok = take(sizeof(uint32_t) * n_pairs);
     pl.off_pre_aff = take(P.aff.empty() ? 0 : sizeof(uint64_t) * n_pairs);
+    pl.off_acc_list = take(sizeof(uint32_t) * n_pairs);
+    pl.off_acc_pos = take(sizeof(uint32_t) * n_pairs);
     pl.off_res_amp = take(sizeof(double2) * n_pairs);
     pl.off_res_st = take(sizeof(uint64_t) * 4 * n_pairs);
     const size_t common_end = off;
@@ -284,12 +291,23 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
         pl.Dp = std::min<uint32_t>(pl.Ap, static_cast<uint32_t>(kDfsMax));
         while (pl.Dp > 0 && (static_cast<uint64_t>(pl.B) << (pl.Ap - pl.Dp)) < want) --pl.Dp;
         while (!dfs_allowed(P, pl.c1, pl.Ap, pl.Dp)) --pl.Dp;
-        pl.off_counters = take(sizeof(uint32_t) * pl.n_batches);
+        // With the pair-level residue test the pairs it rejects cost nothing
+        // in the consumer, so a chunk's root tasks are split into parts of
+        // at least one pass of the workgroup: the work of the pairs that
+        // remain (often few) spreads over many workgroups.
+        pl.rparts = 1;
+        if (c->pf_on) {
+            const uint64_t tasks = static_cast<uint64_t>(pl.chunk) << (pl.Ar + pl.ss);
+            const uint64_t pass = static_cast<uint64_t>(std::max(c->ilp, 1)) * kConsumeThreads;
+            pl.rparts = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(64, tasks / pass)));
+        }
+        pl.ipp = pl.nchunks * pl.rparts;
+        pl.off_counters = take(sizeof(uint32_t) * 2 * pl.n_batches);
         pl.off_tab_st = take(sizeof(uint32_t) * NW * pl.entries);
         pl.off_tab_beta = take(sizeof(double2) * pl.entries);
         pl.off_tab_M = take(sizeof(double) * pl.entries);
         pl.off_tab_ok = take(sizeof(uint32_t) * pl.entries);
-        const uint64_t items = static_cast<uint64_t>(pl.B) * pl.nchunks;
+        const uint64_t items = static_cast<uint64_t>(pl.B) * pl.ipp;
         if (items > 0xffffffffull) return FHS_ERANGE;
         // short items are claimed several at a time (one atomic on the
         // queue's counter per claim): about 2^16 candidate histories per
@@ -413,15 +431,27 @@ Common make_common(const fhs_ctx *c, const Plan &pl, const uint64_t *in, uint32_
     cm.aff_tab = c->d_aff;
     cm.n_aff = static_cast<uint32_t>(P.aff.size() / 9);
     cm.pair_aff = (ws && cm.n_aff) ? at<uint64_t>(ws, pl.off_pre_aff) : nullptr;
+    cm.acc_n = (ws && P.A > 0) ? at<uint32_t>(ws, pl.off_counters) + pl.n_batches : nullptr;
+    cm.acc_list = ws ? at<uint32_t>(ws, pl.off_acc_list) : nullptr;
+    cm.acc_B = std::max<uint32_t>(pl.B, 1);
     cm.grab = c->grab_override ? c->grab_override : pl.grab;
     cm.ss = pl.ss;
+    cm.rparts = pl.rparts;
+    cm.pf_on = c->pf_on ? 1u : 0u;
+    cm.pf_lo = c->pf.lo;
+    cm.pf_hi = c->pf.hi;
+    cm.pf_up = c->pf.up;
+    cm.pf_off = c->pf.off;
+    cm.pf_span = c->pf.span;
     return cm;
 }
 
 PreBufs pre_bufs(void *ws, const Plan &pl) {
     return PreBufs{at<uint32_t>(ws, pl.off_pre_st), at<double2>(ws, pl.off_pre_amp),
                    at<double>(ws, pl.off_pre_M), at<uint32_t>(ws, pl.off_pre_ok),
-                   at<uint64_t>(ws, pl.off_pre_aff)};
+                   at<uint64_t>(ws, pl.off_pre_aff),
+                   pl.off_counters ? at<uint32_t>(ws, pl.off_counters) + pl.n_batches : nullptr,
+                   at<uint32_t>(ws, pl.off_acc_list), at<uint32_t>(ws, pl.off_acc_pos), std::max<uint32_t>(pl.B, 1)};
 }
 
 PairRes pair_res(void *ws, const Plan &pl) {
@@ -504,8 +534,10 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
     PreBufs pre = pre_bufs(ws, pl);
     PairRes res = pair_res(ws, pl);
     uint32_t *counters = P.A > 0 ? at<uint32_t>(ws, pl.off_counters) : nullptr;
-    hipError_t e = launch_precheck(cm, NW, pre, pl.P, counters, P.A > 0 ? pl.n_batches : 0, s);
+    // (zeroes the queue counters and the accepted pairs' counts)
+    hipError_t e = launch_precheck(cm, NW, pre, pl.P, counters, P.A > 0 ? 2 * pl.n_batches : 0, s);
     if (e != hipSuccess) return e;
+    if (P.A > 0 && (e = launch_compact(pre, pl.P, s)) != hipSuccess) return e;
     if (P.A == 0) {
         e = launch_pair_reduce(pre, Partials{nullptr, nullptr, nullptr}, res, 0, pl.P, 0, 0, s);
         if (e != hipSuccess) return e;
@@ -518,8 +550,8 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
         const uint32_t p0 = b * pl.B;
         const uint32_t B = std::min(pl.B, pl.P - p0);
         // timing mode: this batch's items in the stamp buffer (pair-major)
-        part.stamps = timed && c->d_stamps ? c->d_stamps + 2ull * p0 * pl.nchunks : nullptr;
-        const uint64_t items = static_cast<uint64_t>(B) * pl.nchunks;
+        part.stamps = timed && c->d_stamps ? c->d_stamps + 2ull * p0 * pl.ipp : nullptr;
+        const uint64_t items = static_cast<uint64_t>(B) * pl.ipp;
         uint32_t grid = static_cast<uint32_t>(std::max(c->num_cu, 1)) * static_cast<uint32_t>(bpc);
         if (items < grid) grid = static_cast<uint32_t>(items);
         e = (ck && ck->pfn) ? launch_prefix_compiled(*ck, cm, pre, tab, p0, B, pl.Dp, prefix_lds_bytes(cm), s)
@@ -537,7 +569,7 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
                : launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
         if (timed && (e = hipEventRecord(c->events[2 * b + 1], s)) != hipSuccess) return e;
-        e = launch_pair_reduce(pre, part, res, p0, B, pl.nchunks, cm.A, s);
+        e = launch_pair_reduce(pre, part, res, p0, B, pl.ipp, cm.A, s);
         if (e != hipSuccess) return e;
     }
     return launch_finalize(res, coeffs, cm.S, cm.M, amps, stats, s);
@@ -619,6 +651,9 @@ extern "C" fhs_status fhs_load_program(fhs_ctx *c, const fhs_program *p) {
     for (size_t k = 0; k < P.src_eval.size(); ++k) src_dev[k] = c->pos2ins[P.src_eval[k]];
     c->dev_ins = dev;
     c->src_dev = src_dev;
+    c->pf = PairFilter{};
+    c->pf_on = P.A > 0 && pair_filter(dev, P.fac, c->pos2ins[P.L], c->pos2ins[P.G], P.final_before[P.G],
+                                      static_cast<uint32_t>(P.A), c->pf);
     const size_t ni = std::max<size_t>(dev.size(), 1), nf = std::max<size_t>(P.fac.size(), 1);
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_prog), sizeof(Instr) * ni));
     FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_fac), sizeof(double) * nf));
@@ -997,7 +1032,9 @@ extern "C" fhs_status fhs_get_plan(const fhs_ctx *c, uint32_t M, uint32_t S, fhs
     out->n_batches = pl.n_batches;
     out->pairs_per_batch = pl.B;
     out->chunk = pl.chunk;
-    out->items_per_pair = pl.nchunks;
+    out->items_per_pair = pl.ipp;
+    out->root_parts = pl.rparts;
+    out->pair_filter = c->pf_on ? 1u : 0u;
     out->lanes_per_root_task = 1u << pl.ss;
     out->plain_blocks_per_pair = pl.bpp;
     out->prefix_depth_first = pl.Dp;
@@ -1103,7 +1140,7 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
             // not captured: a plain memset is fine here
             FHS_HIP(c, hipMemsetAsync(c->d_valid, 0, sizeof(unsigned long long), s));
             c->n_entries = 0;
-            const size_t items = static_cast<size_t>(pl.P) * pl.nchunks;
+            const size_t items = static_cast<size_t>(pl.P) * pl.ipp;
             if (items > c->stamps_cap) {
                 FHS_HIP(c, hipStreamSynchronize(s));
                 if (c->d_stamps) FHS_HIP(c, hipFree(c->d_stamps));
@@ -1112,8 +1149,10 @@ extern "C" fhs_status fhs_evaluate(fhs_ctx *c, const uint64_t *d_in, const doubl
                 FHS_HIP(c, hipMalloc(reinterpret_cast<void **>(&c->d_stamps), 2 * sizeof(unsigned long long) * items));
                 c->stamps_cap = items;
             }
+            // items the consumer skips (pairs the precheck rejected) keep zeros
+            if (items) FHS_HIP(c, hipMemsetAsync(c->d_stamps, 0, 2 * sizeof(unsigned long long) * items, s));
             c->n_stamped = items;
-            c->stamp_ipp = pl.nchunks;
+            c->stamp_ipp = pl.ipp;
         }
         FHS_HIP(c, enqueue_batched(c, pl, cm, d_cf, d_amps, d_stats, d_ws, bpc, timed, s, ck));
         c->n_timed = timed ? pl.n_batches : 0;
@@ -1162,6 +1201,7 @@ extern "C" fhs_status fhs_evaluate_plain(fhs_ctx *c, const uint64_t *d_in, const
     plain.As = static_cast<uint32_t>(P.A);
     const Common cm = make_common(c, plain, d_in, S, d_out, M, thr, d_ws);
     PreBufs pre = pre_bufs(d_ws, pl);
+    pre.acc_pos = nullptr;   // the plain form's blocks cover every pair
     PairRes res = pair_res(d_ws, pl);
     FHS_HIP(c, launch_precheck(cm, NW, pre, pl.P, nullptr, 0, s));
     if (P.A == 0) {

@@ -112,19 +112,22 @@ def items(args) -> int:
         launch = (launch or ctx.launch_config) + (args.claim,)
     ms, stamps, ipp, tps, _, st = timed_evaluation(ctx, prog, cfg, cuts, launch)
     S = len(cfg["inputs"])
+    ran = stamps[:, 0] > 0                 # items of pairs the precheck rejected are skipped (stamps 0)
     start = stamps[:, 0].astype(np.int64)
-    dur = (stamps[:, 1].astype(np.int64) - start) / tps * 1e6           # microseconds
+    dur = np.where(ran, (stamps[:, 1].astype(np.int64) - start) / tps * 1e6, 0.0)   # microseconds
     per_out = dur.reshape(-1, S * ipp).sum(axis=1)                       # outputs x (inputs x items)
     leaves = st[:, 3].astype(np.float64)
-    makespan = (stamps[:, 1].max() - stamps[:, 0].min()) / tps * 1e6
+    makespan = (stamps[ran, 1].max() - stamps[ran, 0].min()) / tps * 1e6 if ran.any() else 0.0
     plan = ctx.plan(len(cfg["outputs"]), S)
     lc = ctx.launch_config
     valid = st[:, 0] > 0
     line = {"workload": args.workload, "partition": list(cuts), "launch_config": list(lc),
             "items_per_claim": plan["items_per_claim"],
             "regions": [plan["Ap"], plan["Ar"], plan["As"]], "items": int(stamps.shape[0]),
+            "items_skipped": int((~ran).sum()), "root_parts": plan["root_parts"],
+            "pair_filter": plan["pair_filter"],
             "items_per_pair": ipp, "consumer_ms": ms, "makespan_us": float(makespan),
-            "item_us": _quantiles(dur), "output_us": _quantiles(per_out),
+            "item_us": _quantiles(dur[ran]), "output_us": _quantiles(per_out),
             "output_us_histogram": _histogram(per_out),
             "output_us_valid": _quantiles(per_out[valid]),
             "output_us_no_valid_history": _quantiles(per_out[~valid]),
@@ -132,7 +135,7 @@ def items(args) -> int:
             # the queue's balance: summed item time over the workgroups that
             # ran it, against the makespan
             "sum_item_us": float(dur.sum()),
-            "in_flight": _concurrency(start.astype(np.float64), stamps[:, 1].astype(np.float64))}
+            "in_flight": _concurrency(start[ran].astype(np.float64), stamps[ran, 1].astype(np.float64))}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -149,7 +152,8 @@ def sources(args) -> int:
         prog = Program(c.to_text())
         cuts = prog.choose_partition(PART_EQ8)
         ms, stamps, ipp, tps, _, st = timed_evaluation(ctx, prog, cfg, cuts, launch)
-        dur = (stamps[:, 1].astype(np.int64) - stamps[:, 0].astype(np.int64)) / tps * 1e6
+        ran = stamps[:, 0] > 0
+        dur = np.where(ran, (stamps[:, 1].astype(np.int64) - stamps[:, 0].astype(np.int64)) / tps * 1e6, 0.0)
         per_out = dur.reshape(-1, ipp).sum(axis=1)
         M = len(cfg["outputs"])
         print(json.dumps({"steps": s, "sources": prog.A, "outputs": M, "partition": list(cuts),

@@ -271,6 +271,38 @@ def test_walk_field_widths(ctx, n_pos):
     ctx.set_launch_config(0, 0, 0, 0)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("n_pos", [31, 40])
+def test_walk_pass_filter(ctx, n_pos):
+    """Leaves rejected before they are walked: the suffix ends with the
+    position-count check, whose residue is the same for every leaf of a
+    root, so a pass of leaves (or, with a long suffix walked one leaf at a
+    time, a single leaf) whose source popcounts cannot reach it is skipped.
+    16 steps (A = 15): suffixes of 2 to 15 sources, short (eight leaves per
+    pass) and long (one), fields as wide as a word less one bit and wider;
+    against the position-space closed form and the closed-form valid sets."""
+    steps = 16
+    t = w.quantum_walk(n_pos, steps).to_text()
+    outs = w.walk_outputs(n_pos, steps, 2 * (steps + 1) + 10, seed=n_pos + 1)
+    dp = cf.walk_amplitudes(steps)
+    prog = fhs.Program(t)
+    src = prog.source_eval_positions
+    assert prog.A == 15
+    parts = [(src[0] + 1, src[2]), (src[1], src[1]), (0, src[0]), (src[4], src[7]), (src[6], src[12]),
+             (src[9], src[13])]
+    for h in (1, 2):
+        ctx.set_launch_config(h, 0, 0, 3)
+        for part in parts:
+            amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, prog=prog)
+            for y, a, row in zip(outs, amps, st):
+                x = y >> 1
+                x = x - (1 << n_pos) if x >= (1 << (n_pos - 1)) else x
+                assert abs(a - dp.get((x, y & 1), 0)) <= TOL, (n_pos, h, part, y)
+                assert tuple(int(v) for v in row[:3]) == cf.walk_valid_stats(steps, x, y & 1), \
+                    (n_pos, h, part, y)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_walk_config_full(ctx):
     """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
     against the position-space closed form and the closed-form valid sets
