@@ -303,6 +303,47 @@ def test_walk_pass_filter(ctx, n_pos):
     ctx.set_launch_config(0, 0, 0, 0)
 
 
+@pytest.mark.gpu
+def test_walk_pair_filter_batches(ctx):
+    """Pairs the precheck rejects with the residue test over the whole
+    program (the walk's position count after the leading gates must be
+    reachable by its sources' steps): reachable and unreachable outputs
+    interleaved, two input bitstrings (coin 0 and 1 at position 0, complex
+    coefficients), each batch listing its own accepted pairs (a table budget
+    of 1 MiB: sixteen pairs per batch), and root parts (a pair's root tasks
+    over several items); amplitudes and valid sets against the oracle."""
+    n_pos, steps = 31, 14
+    t = w.quantum_walk(n_pos, steps).to_text()
+    rng = np.random.default_rng(77)
+    outs = w.walk_outputs(n_pos, steps, 60, seed=78)
+    outs = [outs[i] for i in rng.permutation(len(outs))]
+    inputs = [w.walk_state(n_pos, 0, 0), w.walk_state(n_pos, 0, 1)]
+    coeffs = [complex(0.6, 0.0), complex(0.0, 0.8)]
+    ref = oracle.Feynman(t).evaluate(inputs, coeffs, outs, threads=THREADS)
+    assert np.abs(ref[0]).max() > 1e-3
+    prog = fhs.Program(t)
+    src = prog.source_eval_positions
+    assert prog.A == 13
+    seen_batches = seen_parts = 0
+    for part, budget in [((src[11], src[12]), 1 << 20), ((src[11], src[11]), 1 << 20),
+                         ((src[1], src[12]), 1 << 30), ((0, src[6]), 1 << 30)]:
+        ctx.set_table_budget(budget)
+        for h in (1, 2):
+            ctx.set_launch_config(h, 0, 0, 3)
+            ctx.load(prog)
+            ctx.set_partition(*part)
+            plan = ctx.plan(len(outs), len(inputs))
+            assert plan["pair_filter"] == 1
+            seen_batches = max(seen_batches, plan["n_batches"])
+            seen_parts = max(seen_parts, plan["root_parts"])
+            amps, st = gpu_eval(ctx, t, inputs, coeffs, outs, partition=part, prog=prog)
+            assert np.abs(amps - ref[0]).max() <= TOL, (part, budget, h)
+            assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (part, budget, h)
+    assert seen_batches >= 8 and seen_parts >= 8, (seen_batches, seen_parts)
+    ctx.set_table_budget(1 << 30)
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_walk_config_full(ctx):
     """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
     against the position-space closed form and the closed-form valid sets
