@@ -189,10 +189,9 @@ __global__ __launch_bounds__(256) void k_count_valid(const uint32_t *ok, uint64_
     if ((threadIdx.x & 63u) == 0u && cnt) atomicAdd(out, static_cast<unsigned long long>(cnt));
 }
 
-__global__ void k_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
-                              uint32_t ipp, uint32_t A) {
-    const uint32_t pl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pl >= B) return;
+// One pair's sums over its items, in item order.
+__device__ __forceinline__ void pair_sums(const PreBufs &pre, const Partials &part, uint32_t p0, uint32_t pl,
+                                          uint32_t ipp, uint32_t A, double2 &amp, uint64_t (&o)[4]) {
     const uint32_t p = p0 + pl;
     const uint32_t okv = pre.ok[p];
     double re = 0.0, im = 0.0;
@@ -223,28 +222,38 @@ __global__ void k_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t 
         }
     }
     if (okv & 2u) lv = ~0ull;
-    res.amp[p] = make_double2(re, im);
-    uint64_t *o = res.st + 4ull * p;
+    amp = make_double2(re, im);
     o[0] = nv;
     o[1] = sh;
     o[2] = xh;
     o[3] = lv;
 }
 
-__global__ void k_finalize(PairRes res, const double *coeffs, uint32_t S, uint32_t M,
-                           double *amps, uint64_t *stats) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
+__global__ void k_pair_reduce(PreBufs pre, Partials part, PairRes res, uint32_t p0, uint32_t B,
+                              uint32_t ipp, uint32_t A) {
+    const uint32_t pl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pl >= B) return;
+    double2 a;
+    uint64_t o[4];
+    pair_sums(pre, part, p0, pl, ipp, A, a, o);
+    const uint32_t p = p0 + pl;
+    res.amp[p] = a;
+    uint64_t *r = res.st + 4ull * p;
+    for (int k = 0; k < 4; ++k) r[k] = o[k];
+}
+
+// Eq. (2) over the inputs of one output.
+__device__ __forceinline__ void combine(uint32_t j, const double2 *pa, const uint64_t *pst, size_t stride,
+                                        const double *coeffs, uint32_t S, double *amps, uint64_t *stats) {
     double re = 0.0, im = 0.0;
     uint64_t nv = 0, sh = 0, xh = 0, lv = 0;
     bool bad = false;
     for (uint32_t i = 0; i < S; ++i) {
-        const size_t p = static_cast<size_t>(j) * S + i;
-        const double2 a = res.amp[p];
+        const double2 a = pa[i];
         const double cr = coeffs[2 * i], ci = coeffs[2 * i + 1];
         re += cr * a.x - ci * a.y;
         im += cr * a.y + ci * a.x;
-        const uint64_t *st = res.st + 4 * p;
+        const uint64_t *st = pst + stride * i;
         nv += st[0];
         sh += st[1];
         xh ^= st[2];
@@ -257,6 +266,32 @@ __global__ void k_finalize(PairRes res, const double *coeffs, uint32_t S, uint32
     stats[4ull * j + 1] = sh;
     stats[4ull * j + 2] = xh;
     stats[4ull * j + 3] = bad ? ~0ull : lv;
+}
+
+// k_pair_reduce and k_finalize in one launch when every pair is in one
+// batch: the same sums in the same order.
+__global__ void k_reduce_finalize(PreBufs pre, Partials part, uint32_t ipp, uint32_t A, const double *coeffs,
+                                  uint32_t S, uint32_t M, double *amps, uint64_t *stats) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    constexpr uint32_t kMaxS = 8;
+    if (S > kMaxS) return;   // the launcher takes the two-kernel path then
+    double2 pa[kMaxS];
+    uint64_t pst[4 * kMaxS];
+    for (uint32_t i = 0; i < S; ++i) {
+        uint64_t o[4];
+        pair_sums(pre, part, 0u, j * S + i, ipp, A, pa[i], o);
+        for (int k = 0; k < 4; ++k) pst[4 * i + k] = o[k];
+    }
+    combine(j, pa, pst, 4, coeffs, S, amps, stats);
+}
+
+__global__ void k_finalize(PairRes res, const double *coeffs, uint32_t S, uint32_t M,
+                           double *amps, uint64_t *stats) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const size_t p = static_cast<size_t>(j) * S;
+    combine(j, res.amp + p, res.st + 4 * p, 4, coeffs, S, amps, stats);
 }
 
 }  // namespace
@@ -384,6 +419,13 @@ hipError_t launch_count_valid(const uint32_t *ok, uint64_t n, unsigned long long
     if (n == 0) return hipSuccess;
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
     k_count_valid<<<static_cast<uint32_t>(blocks), 256, 0, s>>>(ok, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_finalize(PreBufs pre, Partials part, uint32_t ipp, uint32_t A, const double *coeffs,
+                                  uint32_t S, uint32_t M, double *amps, uint64_t *stats, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    k_reduce_finalize<<<(M + 255) / 256, 256, 0, s>>>(pre, part, ipp, A, coeffs, S, M, amps, stats);
     return hipGetLastError();
 }
 

@@ -103,6 +103,9 @@ struct Common {
 #if !defined(__HIPCC_RTC__)
 // Launchers (kernels.hip).  NW and pruning are dispatched inside.
 hipError_t launch_compact(PreBufs pre, uint32_t P, hipStream_t s);
+// k_pair_reduce + k_finalize in one launch (every pair in one batch, S <= 8)
+hipError_t launch_reduce_finalize(PreBufs pre, Partials part, uint32_t ipp, uint32_t A, const double *coeffs,
+                                  uint32_t S, uint32_t M, double *amps, uint64_t *stats, hipStream_t s);
 hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uint32_t *zero_words,
                            uint32_t n_zero, hipStream_t s);
 // Dp: the last Dp prefix sources are enumerated depth-first inside a lane

@@ -297,8 +297,8 @@ fhs_status make_plan(const fhs_ctx *c, uint32_t M, uint32_t S, Plan &pl, size_t 
         // remain (often few) spreads over many workgroups.
         pl.rparts = 1;
         if (c->pf_on) {
-            const uint64_t tasks = static_cast<uint64_t>(pl.chunk) << (pl.Ar + pl.ss);
             const uint64_t pass = static_cast<uint64_t>(std::max(c->ilp, 1)) * kConsumeThreads;
+            const uint64_t tasks = static_cast<uint64_t>(pl.chunk) << (pl.Ar + pl.ss);
             pl.rparts = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(64, tasks / pass)));
         }
         pl.ipp = pl.nchunks * pl.rparts;
@@ -569,6 +569,9 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
                : launch_consume(cm, NW, c->ilp, tab, part, p0, B, pl.chunk, pl.ss, counters + b, grid, s);
         if (e != hipSuccess) return e;
         if (timed && (e = hipEventRecord(c->events[2 * b + 1], s)) != hipSuccess) return e;
+        // one batch: the pair sums and Eq. (2) in one launch
+        if (pl.n_batches == 1 && cm.S <= 8u)
+            return launch_reduce_finalize(pre, part, pl.ipp, cm.A, coeffs, cm.S, cm.M, amps, stats, s);
         e = launch_pair_reduce(pre, part, res, p0, B, pl.ipp, cm.A, s);
         if (e != hipSuccess) return e;
     }
