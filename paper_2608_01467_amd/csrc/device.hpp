@@ -1261,8 +1261,13 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     for (;; ++item, --left) {
         if (left == 0u) {
             // the previous claim was last read before the barrier in the
-            // block reduction of its last item
-            if (t == 0) s_item = atomicAdd(counter, grab);
+            // block reduction of its last item.  A queue already run dry is
+            // seen with a load: every workgroup's last claim would otherwise
+            // be one more atomic on the one counter.
+            if (t == 0) {
+                const uint32_t cur = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_item = cur >= n_items ? cur : atomicAdd(counter, grab);
+            }
             __syncthreads();
             item = s_item;
             left = grab;
