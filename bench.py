@@ -378,10 +378,12 @@ def main() -> int:
     if args.launch:
         ctx.set_launch_config(*(int(v) for v in args.launch.split(",")))
     elif not args.no_autotune and prog.A > 0:
-        # launch shape (histories per lane, chunk, blocks per CU) swept on a
-        # 1024-output subsample with the chosen split; kept for the full run
+        # launch shape (histories per lane, chunk, blocks per CU) swept with
+        # the chosen split on the workload (on its first 1024 outputs when
+        # it has more than 8192); kept for the full run
+        outs_t = cfg["outputs"] if len(cfg["outputs"]) <= 8192 else cfg["outputs"][:1024]
         sub = tune.Workload(ctx, text, cfg["inputs"], [complex(*z) for z in cfg["coeffs"]],
-                            cfg["outputs"][:1024], thr, fuse=not args.no_fuse)
+                            outs_t, thr, fuse=not args.no_fuse)
         launch, _ = tune.autotune_launch(sub, part, reps=2)
         ctx.load(prog)
         del sub
