@@ -1156,6 +1156,26 @@ __device__ __forceinline__ void prefix_body(Common c, PreBufs pre, Table tab, ui
         stage_factors(l_fac, c.fac, c.f_L, c.f_c1);
         F = FacRef{l_fac, c.f_L};
     }
+    // the batch's pairs the precheck accepted, listed for the consumer
+    // (PreBufs.acc_*; one atomic per wave): the first B threads of the grid
+    if (pre.acc_n && static_cast<uint64_t>(blockIdx.x) * blockDim.x < B) {
+        const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63u;
+        const uint32_t bidx = p0 / pre.acc_B;
+        const bool in = g < B;
+        const bool a = in && pre.ok[p0 + g] == 1u;
+        const uint64_t take = __ballot(a);
+        uint32_t base = 0;
+        if (lane == 0u && take) base = atomicAdd(pre.acc_n + bidx, static_cast<uint32_t>(__popcll(take)));
+        base = __shfl(base, 0);
+        if (in) {
+            uint32_t slot = 0xffffffffu;
+            if (a) {
+                slot = base + static_cast<uint32_t>(__popcll(take & ((1ull << lane) - 1ull)));
+                pre.acc_list[static_cast<size_t>(bidx) * pre.acc_B + slot] = g;
+            }
+            pre.acc_pos[p0 + g] = slot;
+        }
+    }
     const uint32_t lo_bits = c.Ap - Dp;
     const uint64_t NL = static_cast<uint64_t>(B) << lo_bits;
     const uint64_t lomask = (1ull << lo_bits) - 1ull;

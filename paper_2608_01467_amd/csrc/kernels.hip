@@ -70,37 +70,6 @@ __global__ __launch_bounds__(256) void k_precheck(Common c, PreBufs pre, uint32_
     pre.ok[p] = (ok ? 1u : 0u) | ((bad_o || bad_i) ? 2u : 0u);
 }
 
-// The accepted pairs of each batch, listed (PreBufs.acc_*): one atomic per
-// wave and batch.
-__global__ __launch_bounds__(256) void k_compact(PreBufs pre, uint32_t P) {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const uint32_t lane = threadIdx.x & 63u;
-    const bool a = pre.ok[p] == 1u;
-    const uint32_t b = p / pre.acc_B, pl = p - b * pre.acc_B;
-    uint32_t slot = 0xffffffffu;
-    bool pending = true;
-    for (;;) {
-        const uint64_t act = __ballot(pending);
-        if (act == 0u) break;
-        const int leader = __ffsll(static_cast<long long>(act)) - 1;
-        const uint32_t lb = __shfl(b, leader);
-        const bool mine = pending && b == lb;
-        const uint64_t take = __ballot(mine && a);
-        uint32_t base = 0;
-        if (static_cast<int>(lane) == leader && take) base = atomicAdd(pre.acc_n + lb, static_cast<uint32_t>(__popcll(take)));
-        base = __shfl(base, leader);
-        if (mine) {
-            if (a) {
-                slot = base + static_cast<uint32_t>(__popcll(take & ((1ull << lane) - 1ull)));
-                pre.acc_list[static_cast<size_t>(lb) * pre.acc_B + slot] = pl;
-            }
-            pending = false;
-        }
-    }
-    pre.acc_pos[p] = slot;
-}
-
 template <int NW, bool PRUNE, bool FLDS, bool RUNS>
 __global__ __launch_bounds__(256) void k_prefix(Common c, PreBufs pre, Table tab, uint32_t p0,
                                                 uint32_t B, uint32_t P, uint32_t Dp) {
@@ -333,12 +302,6 @@ hipError_t launch_precheck(const Common &c, int NW, PreBufs pre, uint32_t P, uin
             k_precheck<nw.value, pr.value><<<blocks, 256, 0, s>>>(c, pre, P, zero_words, n_zero);
         });
     });
-    return hipGetLastError();
-}
-
-hipError_t launch_compact(PreBufs pre, uint32_t P, hipStream_t s) {
-    if (P == 0) return hipSuccess;
-    k_compact<<<(P + 255) / 256, 256, 0, s>>>(pre, P);
     return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ struct PreBufs {
     double *M;         // [P]     running modulus product
     uint32_t *ok;      // [P]     1 = consistent so far
     uint64_t *aff;     // [P]     bit j: the boundary part of affine input j's form
-    // The pairs the precheck accepted, per batch of acc_B pairs (k_compact):
+    // The pairs the precheck accepted, per batch of acc_B pairs (listed by
+    // the prefix build's first threads):
     // acc_n[b] of them, listed at acc_list[b acc_B ...] by their index in the
     // batch (in no particular order); acc_pos[p] is pair p's place in that
     // list (0xffffffff: rejected).  The consumer's work items cover only them.
@@ -102,7 +103,6 @@ struct Common {
 
 #if !defined(__HIPCC_RTC__)
 // Launchers (kernels.hip).  NW and pruning are dispatched inside.
-hipError_t launch_compact(PreBufs pre, uint32_t P, hipStream_t s);
 // k_pair_reduce + k_finalize in one launch (every pair in one batch, S <= 8)
 hipError_t launch_reduce_finalize(PreBufs pre, Partials part, uint32_t ipp, uint32_t A, const double *coeffs,
                                   uint32_t S, uint32_t M, double *amps, uint64_t *stats, hipStream_t s);

@@ -537,7 +537,6 @@ hipError_t enqueue_batched(fhs_ctx *c, const Plan &pl, const Common &cm, const d
     // (zeroes the queue counters and the accepted pairs' counts)
     hipError_t e = launch_precheck(cm, NW, pre, pl.P, counters, P.A > 0 ? 2 * pl.n_batches : 0, s);
     if (e != hipSuccess) return e;
-    if (P.A > 0 && (e = launch_compact(pre, pl.P, s)) != hipSuccess) return e;
     if (P.A == 0) {
         e = launch_pair_reduce(pre, Partials{nullptr, nullptr, nullptr}, res, 0, pl.P, 0, 0, s);
         if (e != hipSuccess) return e;
