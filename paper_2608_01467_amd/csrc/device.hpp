@@ -1246,10 +1246,12 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     __shared__ uint32_t l_hp[kMaxChunk];
     __shared__ uint32_t l_wcount[NT / 64];
     __shared__ Acc l_red[NT / 64];
-    // the counted factors' products (read before the first claim's barrier)
+    // the counted factors' products
     __shared__ double2 l_ct[Regions::kNCT > 0 ? Regions::kNCT : 1];
-    if constexpr (Regions::kNCT > 0)
+    if constexpr (Regions::kNCT > 0) {
         for (uint32_t i = threadIdx.x; i < Regions::kNCT; i += NT) l_ct[i] = Regions::count_entry(i);
+        __syncthreads();
+    }
 
     FacRef F{c.fac, 0u};
     if constexpr (FLDS) {
@@ -1277,19 +1279,30 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
     const Mask4 fin_c2 = ld_const(c.fin, c.c2), fin_G = ld_const(c.fin, c.G);
 
     const uint32_t grab = c.grab > 0u ? c.grab : 1u;
+    // Each workgroup's first run of items is fixed (workgroup b: items
+    // [b grab, (b + 1) grab)); the counter hands out the items after the
+    // grid's first runs, so a launch starts without one atomic per
+    // workgroup on the one counter.
+    const uint32_t first_runs = gridDim.x * grab;
     uint32_t item = 0, left = 0;   // the claimed run of items not yet done (uniform)
+    bool first = true;
     for (;; ++item, --left) {
         if (left == 0u) {
-            // the previous claim was last read before the barrier in the
-            // block reduction of its last item.  A queue already run dry is
-            // seen with a load: every workgroup's last claim would otherwise
-            // be one more atomic on the one counter.
-            if (t == 0) {
-                const uint32_t cur = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_item = cur >= n_items ? cur : atomicAdd(counter, grab);
+            if (first) {
+                item = blockIdx.x * grab;
+                first = false;
+            } else {
+                // the previous claim was last read before the barrier in the
+                // block reduction of its last item.  A queue already run dry
+                // is seen with a load: every workgroup's last claim would
+                // otherwise be one more atomic on the one counter.
+                if (t == 0) {
+                    const uint32_t cur = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_item = cur + first_runs >= n_items ? cur : atomicAdd(counter, grab);
+                }
+                __syncthreads();
+                item = s_item + first_runs;
             }
-            __syncthreads();
-            item = s_item;
             left = grab;
         }
         if (item >= n_items) break;

@@ -344,6 +344,34 @@ def test_walk_pair_filter_batches(ctx):
     ctx.set_launch_config(0, 0, 0, 0)
 
 
+@pytest.mark.gpu
+def test_walk_filters_with_pruning(ctx):
+    """The residue tests (pair, root, pass) together with threshold pruning:
+    a walk whose histories all have modulus 2^(-A/2) (one Hadamard factor
+    per source), at thresholds below it (nothing pruned) and above it
+    (everything pruned), interpreted and compiled consumers; against the
+    oracle."""
+    n_pos, steps = 20, 9
+    t = w.quantum_walk(n_pos, steps).to_text()
+    outs = w.walk_outputs(n_pos, steps, 40, seed=9)
+    o = oracle.Feynman(t)
+    prog = fhs.Program(t)
+    src = prog.source_eval_positions
+    for thr in (1e-3, 0.3):
+        ref = o.evaluate([0], [1.0], outs, threshold=thr, threads=THREADS)
+        for dispatch in (0, 3):
+            ctx.set_launch_config(2, 0, 0, dispatch)
+            for part in [(src[1], src[4]), (0, src[2]), prog.choose_partition(fhs.PART_EQ8)]:
+                amps, st = gpu_eval(ctx, t, [0], [1], outs, thr=thr, partition=part, prog=prog)
+                assert np.abs(amps - ref[0]).max() <= TOL, (thr, dispatch, part)
+                assert np.array_equal(st[:, :3], ref[1][:, :3].astype(np.uint64)), (thr, dispatch, part)
+        if thr > 0.1:
+            assert not ref[1][:, 0].any()       # every history pruned
+        else:
+            assert ref[1][:, 0].any()
+    ctx.set_launch_config(0, 0, 0, 0)
+
+
 def test_walk_config_full(ctx):
     """100 qubits, 20 steps, the full 8192 outputs: the 42 reachable outputs
     against the position-space closed form and the closed-form valid sets
