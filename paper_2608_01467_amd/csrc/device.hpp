@@ -1292,14 +1292,11 @@ __device__ __forceinline__ void consume_body(Common c, Table tab, Partials part,
                 item = blockIdx.x * grab;
                 first = false;
             } else {
+                // every item was in the grid's first runs: nothing to claim
+                if (first_runs >= n_items) break;
                 // the previous claim was last read before the barrier in the
-                // block reduction of its last item.  A queue already run dry
-                // is seen with a load: every workgroup's last claim would
-                // otherwise be one more atomic on the one counter.
-                if (t == 0) {
-                    const uint32_t cur = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_item = cur + first_runs >= n_items ? cur : atomicAdd(counter, grab);
-                }
+                // block reduction of its last item
+                if (t == 0) s_item = atomicAdd(counter, grab);
                 __syncthreads();
                 item = s_item + first_runs;
             }
