@@ -145,19 +145,29 @@ def test_aa_k4_closed_form(ctx):
 
 
 def test_qaoa12_statevector_and_counts(ctx):
+    """All 4096 outputs of the 12-vertex, p = 2 QAOA circuit against the
+    state vector, every history valid: at Eq. (8)'s split in the default
+    launch shape, and at the split the benchmark times, (35, 40), in the
+    launch shapes its autotuner settles on (1 history per lane, chunk 256,
+    4 blocks per CU or as many as fit; the compiled consumer with counted
+    factors)."""
     cfg = w.CONFIGS["qaoa_12v_p2"]()
     t = cfg["circuit"].to_text()
     prog = fhs.Program(t)
     assert prog.A == 24
     outs = cfg["outputs"]
     ref = sv.amplitudes(t, [0], [1], outs)
-    amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=prog.choose_partition(fhs.PART_EQ8),
-                        prog=prog)
-    assert np.abs(amps - ref).max() <= TOL
-    assert abs(np.sum(np.abs(amps) ** 2) - 1.0) <= 1e-10
     s_all, x_all = _all_h_stats(24)
-    assert (st[:, 0] == (1 << 24)).all()
-    assert (st[:, 1] == s_all).all() and (st[:, 2] == x_all).all()
+    runs = [(prog.choose_partition(fhs.PART_EQ8), (0, 0, 0, 0)),
+            ((35, 40), (1, 256, 0, 3)), ((35, 40), (1, 256, 4, 3))]
+    for part, (h, chunk, bpc, dispatch) in runs:
+        ctx.set_launch_config(h, chunk, bpc, dispatch)
+        amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, prog=prog)
+        assert np.abs(amps - ref).max() <= TOL, (part, h, chunk, bpc, dispatch)
+        assert abs(np.sum(np.abs(amps) ** 2) - 1.0) <= 1e-10
+        assert (st[:, 0] == (1 << 24)).all()
+        assert (st[:, 1] == s_all).all() and (st[:, 2] == x_all).all()
+    ctx.set_launch_config(0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("thr", [1e-5, 3e-5, 1e-3])
@@ -386,17 +396,19 @@ def test_walk_config_full(ctx):
     outs = cfg["outputs"]
     dp = cf.walk_amplitudes(20)
     eq8 = prog.choose_partition(fhs.PART_EQ8)
-    runs = [(prog, eq8, False, (0, 0, 0)), (prog, (0, 0), True, (0, 0, 0)),
-            (prog, (2984, 3581), False, (1, 0, 3)), (prog, (3183, 3581), False, (2, 0, 3)),
-            (prog, eq8, False, (2, 0, 3)), (folded, (2984, 3581), False, (1, 0, 3))]
+    runs = [(prog, eq8, False, (0, 0, 0, 0)), (prog, (0, 0), True, (0, 0, 0, 0)),
+            (prog, (2984, 3581), False, (1, 0, 0, 3)), (prog, (3183, 3581), False, (2, 0, 0, 3)),
+            (prog, eq8, False, (2, 0, 0, 3)), (folded, (2984, 3581), False, (1, 0, 0, 3))]
     # the splits the learned shortlist picks for this workload, in the launch
-    # shape the benchmark's autotuner settles on (2 histories per lane, chunk
-    # 256, compiled consumer and prefix build): each split is its own
-    # compiled module
-    shortlist = [(1989, 2785), (1989, 2984), (2188, 2785), (2188, 2984)]
-    runs += [(prog, p, False, (2, 256, 3)) for p in shortlist]
-    for pg, part, plain, (h, chunk, dispatch) in runs:
-        ctx.set_launch_config(h, chunk, 0, dispatch)
+    # shapes the benchmark's autotuner settles on (1 or 2 histories per lane,
+    # chunk 256, 4 blocks per CU or as many as fit, compiled consumer and
+    # prefix build): each split is its own compiled module
+    shortlist = [(198, 2785), (596, 2785), (198, 2387), (1989, 2785), (2188, 2984)]
+    runs += [(prog, p, False, (2, 256, 4, 3)) for p in shortlist]
+    runs += [(prog, (198, 2785), False, (1, 256, 4, 3)), (prog, (596, 2785), False, (1, 256, 4, 3)),
+             (prog, (198, 2785), False, (1, 256, 0, 3)), (prog, (198, 2387), False, (1, 128, 2, 3))]
+    for pg, part, plain, (h, chunk, bpc, dispatch) in runs:
+        ctx.set_launch_config(h, chunk, bpc, dispatch)
         amps, st = gpu_eval(ctx, t, [0], [1], outs, partition=part, plain=plain, prog=pg)
         for y, a, row in zip(outs[:42], amps[:42], st[:42]):
             x = y >> 1
