@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "histories/s & amplitudes/s, batched+learned vs plain, 1 MI355X, |err|≤1e-12"
 
-# MI355X peaks (AMD published figures; see the design doc for the derivations)
+# MI355X peaks (AMD's published figures)
 SHORTLIST = 5                # the learned split: model predictions timed before the run
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 # 32-bit integer VALU ops/s: simple ops (add, xor, and, or, shifts, compares,
@@ -319,7 +319,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(outputs are independent, see DESIGN.md for how the path would shard)",
+              "(outputs are independent: N GPUs would each evaluate a slice of them)",
               file=sys.stderr)
         return 2
 

@@ -457,7 +457,7 @@ fhs_status fhs_evaluate_noalloc(fhs_ctx *ctx,
  * minimising Eq. (8) (Section IV-C); here a small network, trained on the
  * autotuner's measured times, predicts the log run time of each candidate
  * split from split features, and the argmin is used.  Exhaustive timing
- * remains the fallback and the judge of its regret.
+ * remains the fallback and the measure of its regret.
  * ------------------------------------------------------------------- */
 
 /* Features of the split (c1, c2) for M outputs and S inputs, FHS_N_FEATURES

@@ -119,7 +119,7 @@ def held_out(ctx, blob, args, report) -> None:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "cost_model"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "_build", "cost_model"))
     ap.add_argument("--epochs", type=int, default=4000)
     ap.add_argument("--ratio", type=float, default=16.0,
                     help="time every split whose Eq. (8) cost is within this factor of the best")
