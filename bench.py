@@ -287,8 +287,8 @@ def sweep(args, cfg) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="walk_99p_20s")
     ap.add_argument("--partition", default="model", choices=["model", "eq8", "thirds", "none"],
                     help="model: the learned cost model's split (Eq. (8) if the workload lies "

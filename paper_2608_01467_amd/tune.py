@@ -68,36 +68,57 @@ class Workload:
         return self.ctx.plan(self.M, self.S)["table_bytes"]
 
 
+SHORT_STEP = 1e-3     # seconds: below this one evaluation is timed in batches
+SHORT_BATCH = 32      # back-to-back evaluations per timing of a short step
+CUTOFF_FLOOR = 0.05   # seconds: a first run (graph capture included) this fast is never cut off
+TIE = 0.01            # timings within this fraction of the fastest are a tie
+
+
+def first_within(rows, tie: float = TIE):
+    """The first entry of [(key, seconds)], in the given order, whose time
+    is within `tie` of the fastest: among timings the measurement cannot
+    tell apart, the order decides (the cost model's ranking for splits, the
+    sweep's order for launch shapes), so the same workload gets the same
+    choice from run to run."""
+    fastest = min(t for _, t in rows)
+    return next(k for k, t in rows if t <= fastest * (1.0 + tie))
+
+
 def time_split(wl: Workload, partition, reps: int = 3, plain: bool = False,
                cutoff: Optional[float] = None) -> float:
-    """Best-of-`reps` wall time of one evaluation (graph replay), seconds
-    (at least 10 repetitions when one takes under a millisecond).  The
-    first, untimed-for-the-record run captures the graph; if it already took
-    longer than `cutoff` seconds its time is returned as is (a split that
-    slow is measured once, well enough to rank it last)."""
+    """Time of one evaluation (graph replay), seconds: the best of `reps`
+    timings.  The first run captures the graph; if it already took longer
+    than `cutoff` seconds its time is returned as is (a split that slow is
+    measured once, well enough to rank it last; never below CUTOFF_FLOOR,
+    since a first run also captures the graph).  A second run tells a short
+    step (under SHORT_STEP) from a long one: a short step is timed as the
+    mean of SHORT_BATCH back-to-back evaluations between two
+    synchronisations, best of at least 5 such batches (as the benchmark
+    times its steps; a lone evaluation's launch and synchronisation latency
+    would be most of its timing); a long one evaluation at a time."""
     import torch
-    t0 = time.perf_counter()
-    wl.run(partition, plain)
-    torch.cuda.synchronize()
-    first = time.perf_counter() - t0
-    if cutoff is not None and first > cutoff:
-        return first
-    if first < 1e-3:
-        reps = max(reps, 10)   # a short step: host jitter is a large part of one timing
-    best = math.inf
-    for _ in range(reps):
+
+    def timed(n: int) -> float:
         t0 = time.perf_counter()
-        wl.run(partition, plain)
+        for _ in range(n):
+            wl.run(partition, plain)
         torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
-    return best
+        return (time.perf_counter() - t0) / n
+
+    first = timed(1)
+    if cutoff is not None and first > max(cutoff, CUTOFF_FLOOR):
+        return first
+    one = timed(1)
+    if one < SHORT_STEP:
+        return min(timed(SHORT_BATCH) for _ in range(max(reps, 5)))
+    return min([one] + [timed(1) for _ in range(reps - 1)])
 
 
 def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, int, int, int], List]:
     """Sweep histories per lane x chunk x blocks per CU (automatic dispatch),
     then the explicit dispatch modes (per run, per instruction, compiled) at
     the best shape, then histories per lane x chunk for the compiled
-    consumer; keep the fastest."""
+    consumer; keep the first of the fastest (first_within)."""
     log = []
     best, best_t = None, math.inf
     for h in (1, 2):
@@ -128,6 +149,7 @@ def autotune_launch(wl: Workload, partition, reps: int = 2) -> Tuple[Tuple[int, 
             log.append((cfg, t))
             if t < best_t:
                 best, best_t = cfg, t
+    best = first_within(log)
     wl.ctx.set_launch_config(*best)
     return best, log
 
@@ -164,10 +186,10 @@ PRECOMPILE_BATCH = 32   # splits whose compiled consumers are built together
 def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2, log=None,
                slow_factor: float = 8.0, budget: Optional[float] = None):
     """Time every split (in the given order, best guesses first); returns
-    [(split, seconds)] and the fastest split.  A split whose first run is
-    slower than `slow_factor` x the best so far is timed once; after
-    `budget` seconds the remaining splits are skipped.  `log`, if given, is
-    called with a progress string every few splits."""
+    [(split, seconds)] and the first of the fastest (first_within).  A
+    split whose first run is slower than `slow_factor` x the best so far is
+    timed once; after `budget` seconds the remaining splits are skipped.
+    `log`, if given, is called with a progress string every few splits."""
     rows = []
     t0 = time.perf_counter()
     best = math.inf
@@ -186,8 +208,7 @@ def exhaustive(wl: Workload, splits: Sequence[Tuple[int, int]], reps: int = 2, l
         best = min(best, t)
         if log is not None and (i + 1) % 16 == 0:
             log(f"  {i + 1}/{len(splits)} splits timed, {time.perf_counter() - t0:.1f} s")
-    best = min(rows, key=lambda r: (r[1], r[0]))[0]
-    return rows, best
+    return rows, first_within(rows)
 
 
 def collect(wl: Workload, splits, reps: int = 2, log=None, budget: Optional[float] = None):
