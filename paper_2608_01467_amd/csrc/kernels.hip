@@ -178,16 +178,34 @@ __device__ __forceinline__ void pair_sums(const PreBufs &pre, const Partials &pa
         // the consumer's items cover only the accepted pairs, listed (the
         // plain form's blocks cover every pair)
         const uint32_t f = pre.acc_pos ? pre.acc_pos[p] : pl;
-        for (uint32_t k = 0; k < ipp; ++k) {
-            const size_t it = static_cast<size_t>(f) * ipp + k;
-            const double2 a = part.amp[it];
-            re += a.x;
-            im += a.y;
-            const uint64_t *st = part.st + 4 * it;
-            nv += st[0];
-            sh += st[1];
-            xh ^= st[2];
-            lv += st[3];
+        const double2 *pa = part.amp + static_cast<size_t>(f) * ipp;
+        const uint64_t *ps = part.st + 4ull * f * ipp;
+        // items in groups of 8: a group's loads are all issued before the
+        // first is used (one memory round trip per group, not per item);
+        // the sums still run in item order
+        constexpr uint32_t G = 8;
+        for (uint32_t k0 = 0; k0 < ipp; k0 += G) {
+            const uint32_t n = ipp - k0 < G ? ipp - k0 : G;
+            double2 a[G];
+            ulonglong4 s[G];
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                if (j < n) {
+                    a[j] = pa[k0 + j];
+                    s[j] = *reinterpret_cast<const ulonglong4 *>(ps + 4ull * (k0 + j));
+                }
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                if (j < n) {
+                    re += a[j].x;
+                    im += a[j].y;
+                    nv += s[j].x;
+                    sh += s[j].y;
+                    xh ^= s[j].z;
+                    lv += s[j].w;
+                }
+            }
         }
     }
     if (okv & 2u) lv = ~0ull;
